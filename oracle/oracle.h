@@ -1,0 +1,136 @@
+/*
+ * FP64 CPU oracle for the quasi-static Neo-Hookean indentation solve.
+ *
+ * TEST INFRASTRUCTURE ONLY. This library is the slow, plain reference that the
+ * device path is checked against. It shares no code, header, table or helper
+ * with the device library and must never be linked into, or called by, the
+ * product path; only tests, the smoke check and the CPU-baseline timing of the
+ * benchmark use it.
+ *
+ * Problem (paper Sec. III-A, with the readings stated in the design notes):
+ * linear tetrahedral FEM of a hyperelastic skin (the compressible Neo-Hookean
+ * law that the paper's validated model uses), fixed boundary nodes, and rigid
+ * indenters pushed into the skin; contact is a frictionless node-vs-signed-
+ * distance penalty. Each load step finds a stationary point of
+ *   Pi(u) = sum_e V_e Psi(F_e(u)) + sum_{i eligible} k/2 min(0, phi(X_i+u_i))^2
+ * with the displacement of fixed nodes held at its current value.
+ *
+ * All arrays are row-major, caller-owned, double precision unless stated.
+ */
+#ifndef FEM_ORACLE_H
+#define FEM_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_SPHERE = 0, ORC_CYLINDER = 1, ORC_BOX = 2, ORC_RING = 3 };
+
+enum {
+    ORC_OK = 0,
+    ORC_NOT_CONVERGED = -6,
+    ORC_INVERSION = -7,
+    ORC_BAD_INPUT = -1,
+    ORC_DEGENERATE = -2,
+    ORC_NOT_SPD = -9
+};
+
+typedef struct {
+    int kind;          /* ORC_SPHERE .. ORC_RING */
+    double shape[4];   /* sphere: r; cylinder: radius, height; box: hx,hy,hz; ring: Rmaj, rmin */
+    double R[9];       /* rotation, row-major; local frame -> world: x = R q + c */
+    double c[3];       /* centre */
+    double k;          /* penalty stiffness, N/m per node */
+} orc_indenter;
+
+typedef struct {
+    int n, m;
+    const double *X;              /* n x 3 rest positions */
+    const int *T;                 /* m x 4 node ids */
+    const unsigned char *fixed;   /* n: 1 = displacement prescribed */
+    const unsigned char *eligible;/* n: 1 = contact-eligible (surface, not fixed) */
+    const double *B;              /* m x 9: inverse rest edge matrix, row-major */
+    const double *V;              /* m: rest volumes */
+    double mu, lam;               /* Lame parameters */
+    orc_indenter ind;
+} orc_problem;
+
+typedef struct {
+    double newton_rtol;   /* stop when |g_free| <= max(newton_rtol*r0, newton_atol) */
+    double newton_atol;
+    int max_newton;
+    double cg_rtol;       /* lower bound of the CG forcing term */
+    double cg_eta_max;    /* upper bound of the CG forcing term */
+    int max_cg;
+    int precond;          /* 0 = scalar Jacobi, 1 = 3x3 block Jacobi */
+    double c1;            /* Armijo constant */
+    int max_halvings;
+    int dense;            /* 1: dense Cholesky instead of PCG (tiny meshes) */
+    int contact_hessian;  /* 0: Gauss-Newton k n n^T; 1: exact k (n n^T + phi Hess(phi)) */
+} orc_params;
+
+typedef struct {
+    int status;
+    int newton_iters;
+    int cg_iters;
+    int ls_trials;
+    int grad_passes;      /* gradient evaluations */
+    int energy_passes;    /* energy-only evaluations (line-search trials) */
+    int hv_products;      /* Hessian-vector products */
+    double g0_norm, g_norm, energy, min_J;
+} orc_info;
+
+/* Lame parameters from Young's modulus and Poisson's ratio. */
+void orc_lame(double E, double nu, double *mu, double *lam);
+
+/* Constitutive law at one deformation gradient F (3x3 row-major). */
+double orc_psi(const double F[9], double mu, double lam);
+void orc_pk1(const double F[9], double mu, double lam, double P[9]);
+void orc_dpk1(const double F[9], const double dF[9], double mu, double lam, double dP[9]);
+
+/* Signed distance of world point x to the indenter and its world gradient. */
+double orc_sdf(const orc_indenter *ind, const double x[3], double grad[3]);
+
+/* Mesh precompute: B and V per tet. Returns 0, or -(1+e) for the first tet e
+ * with V <= 0. */
+int orc_precompute(int n, const double *X, int m, const int *T, double *B, double *V);
+
+/* Marks nodes on boundary faces (faces of exactly one tet); returns the number
+ * of boundary faces. */
+int orc_surface_nodes(int n, int m, const int *T, unsigned char *surf);
+
+/* Deformation gradient of tet e at displacement u. */
+void orc_deformation_gradient(const orc_problem *p, const double *u, int e, double F[9]);
+
+/* Total energy; min_J receives the smallest det F (may be NULL). Tets with
+ * det F <= 0 contribute +inf. */
+double orc_energy(const orc_problem *p, const double *u, double *min_J);
+
+/* Full gradient dPi/du (n x 3), fixed nodes included (not masked). */
+void orc_gradient(const orc_problem *p, const double *u, double *g);
+
+/* Dense Hessian (3n x 3n): exact Neo-Hookean tangent plus the contact block on
+ * active contact nodes (Gauss-Newton, or exact when contact_full). Small meshes only. */
+void orc_hessian_dense(const orc_problem *p, const double *u, double *H, int contact_full);
+
+/* q = H(u) v using the assembled block-sparse Hessian (not masked). */
+void orc_hessvec(const orc_problem *p, const double *u, const double *v, double *q, int contact_full);
+
+/* Solves H(u) x = b on the free nodes (fixed rows and columns removed) by PCG
+ * (or dense Cholesky when prm->dense). Returns CG iterations or ORC_NOT_SPD. */
+int orc_linear_solve(const orc_problem *p, const double *u, const double *b, double *x,
+                     const orc_params *prm, double rtol);
+
+/* One load step: Newton from u (in/out) at the problem's indenter pose. */
+int orc_step(const orc_problem *p, const orc_params *prm, double *u, orc_info *info);
+
+/* Contact patch at u: ascending ids of nodes with phi < 0, forces on the skin
+ * -k phi n, penetrations and the resultant. Returns the count (arrays may be
+ * NULL to query it). */
+int orc_contact_patch(const orc_problem *p, const double *u, int *ids, double *f, double *phi,
+                      double F_total[3]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
