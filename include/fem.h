@@ -1,0 +1,189 @@
+/*
+ * libfem: quasi-static Neo-Hookean indentation of a tetrahedral skin mesh on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * The problem is the finite-element contact simulation of paper Sec. III-A: a
+ * volumetric mesh of linear tetrahedra (a soft skin), fixed boundary nodes
+ * (bonded to a rigid core / clamped), rigid indenters driven into the skin,
+ * and, per step, the nodal positions (displacements) and nodal contact forces
+ * with their resultant. The skin is the compressible Neo-Hookean solid that
+ * the paper's validated model uses,
+ *     Psi(F) = mu/2 (tr F^T F - 3) - mu ln J + lam/2 (ln J)^2,
+ * contact is a frictionless per-node penalty k/2 min(0, phi)^2 against the
+ * indenter's signed distance phi, and each load step is solved to a
+ * stationary point of the total energy by Newton's method with matrix-free
+ * Jacobi-preconditioned CG and a backtracking line search.
+ *
+ * Conventions for every call:
+ *   - SI units; all floating-point arguments are double whatever the
+ *     internal precision; all pointers are HOST pointers;
+ *   - node-vector arrays are n x 3, row-major (x, y, z per node);
+ *   - inputs are copied, the caller keeps ownership of its buffers;
+ *   - return value 0 = FEM_OK, negative = error (no exception crosses the
+ *     ABI); fem_last_error() then describes the failure (thread-local);
+ *   - a handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef LIBFEM_FEM_H
+#define LIBFEM_FEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define FEM_OK 0
+#define FEM_E_INVALID (-1)        /* bad argument: null, size, index, non-finite */
+#define FEM_E_DEGENERATE (-2)     /* a tet has rest volume <= 0 */
+#define FEM_E_OOM (-3)            /* device allocation failed */
+#define FEM_E_DEVICE (-4)         /* HIP runtime error, or no usable device */
+#define FEM_E_STATE (-5)          /* call order: material or indenter not set */
+#define FEM_E_NOT_CONVERGED (-6)  /* Newton cap or line-search stall; state kept */
+#define FEM_E_INVERSION (-7)      /* line search could not keep every det F > 0 */
+#define FEM_E_BUFFER (-8)         /* caller buffer too small */
+
+/* ---- enums -------------------------------------------------------------- */
+#define FEM_PREC_FP64 0           /* all arithmetic in double */
+#define FEM_PREC_FP32 1           /* element math and CG vectors in float;
+                                     dot products, norms, energies, the Newton
+                                     test and contact geometry in double */
+
+/* Indenter families (paper Sec. IV-A names spherical, cylindrical and ring
+ * indenters; a box stands for the flat-faced pegs of Fig. 3). The indenter's
+ * local frame q maps to the world as x = R q + c. */
+#define FEM_SPHERE 0              /* shape = {radius} */
+#define FEM_CYLINDER 1            /* shape = {radius, height}; axis = local z, centred */
+#define FEM_BOX 2                 /* shape = {hx, hy, hz} half extents */
+#define FEM_RING 3                /* shape = {major radius, minor radius}; torus about local z */
+
+#define FEM_PRECOND_JACOBI 0      /* scalar Jacobi */
+#define FEM_PRECOND_BLOCK 1       /* 3x3 node-block Jacobi */
+
+typedef struct fem_mesh fem_mesh;
+
+typedef struct {
+    int32_t precision;   /* FEM_PREC_FP64 or FEM_PREC_FP32 */
+    int32_t device;      /* HIP device ordinal */
+    void *stream;        /* hipStream_t to run on; NULL = the library's own stream */
+} fem_config;
+
+typedef struct {
+    double newton_rtol;  /* converged when |g_free| <= max(newton_rtol * |g_free(start)|, newton_atol) */
+    double newton_atol;  /* newtons */
+    int32_t max_newton;
+    double cg_rtol;      /* floor of the CG forcing term eta = clamp(|g|/|g_start|, cg_rtol, cg_eta_max) */
+    double cg_eta_max;
+    int32_t max_cg;      /* per Newton iteration */
+    int32_t precond;     /* FEM_PRECOND_* */
+    int32_t contact_hessian; /* 0: Gauss-Newton k n n^T; 1: exact k (n n^T + phi Hess(phi)) */
+    double c1;           /* Armijo constant */
+    int32_t max_halvings;
+} fem_solve_params;
+
+typedef struct {
+    int32_t status;      /* same value fem_step returned */
+    int32_t newton_iters;
+    int32_t cg_iters;    /* summed over Newton iterations */
+    int32_t ls_trials;   /* line-search energy/gradient evaluations */
+    int32_t grad_passes; /* element passes (gradient or trial), line-search trials included */
+    int32_t hv_products; /* Hessian-vector products */
+    double g0_norm;      /* |g_free| at the start of the step */
+    double g_norm;       /* |g_free| at the end */
+    double energy;       /* total energy at the end */
+    double min_J;        /* smallest det F at the end */
+    int64_t tet_updates; /* m * (grad_passes + hv_products) */
+} fem_step_info;
+
+/* Creates a mesh handle (paper Sec. III-A: volumetric tet mesh with fixed
+ * boundary conditions on some nodes).
+ *   X      n_nodes x 3 rest positions (m);
+ *   tets   n_tets x 4 node ids, 0-based; each tet must have det[X1-X0, X2-X0, X3-X0] > 0;
+ *   fixed  n_nodes flags, 1 = the node's displacement is prescribed (it keeps
+ *          its current value, 0 after creation);
+ *   cfg    precision, device and stream (NULL = FP64 on device 0).
+ * Computes per-tet inverse rest edge matrices and volumes and the
+ * contact-eligible nodes (nodes on boundary faces that are not fixed) on the
+ * device. *out receives the handle, which owns all device memory.
+ * Errors: FEM_E_INVALID (null pointer, n_nodes <= 0, n_tets <= 0,
+ * n_nodes >= 2^21, index out of range, non-finite X), FEM_E_DEGENERATE,
+ * FEM_E_OOM, FEM_E_DEVICE. */
+int fem_create_mesh(const double *X, int32_t n_nodes, const int32_t *tets, int32_t n_tets,
+                    const uint8_t *fixed, const fem_config *cfg, fem_mesh **out);
+
+/* Releases the handle and its device memory; NULL is ignored. */
+void fem_destroy_mesh(fem_mesh *mesh);
+
+/* Sets the skin material (paper Sec. III-A: elastic modulus E and Poisson's
+ * ratio nu are the free material parameters). mu = E / (2 (1 + nu)),
+ * lam = E nu / ((1 + nu)(1 - 2 nu)). density is stored and unused by the
+ * quasi-static solve. Errors: FEM_E_INVALID (E <= 0, nu outside (-1, 0.5),
+ * density < 0, non-finite). */
+int fem_set_material(fem_mesh *mesh, double E, double nu, double density);
+
+/* Sets the rigid indenter pose for the next fem_step (paper Sec. III-A:
+ * rigid objects driven into the skin; here moved kinematically per load step).
+ *   kind     FEM_SPHERE .. FEM_RING; shape/n_shape as listed with the kinds;
+ *   R        3x3 row-major rotation (orthonormal to 1e-9, det +1);
+ *   c        centre; k_penalty  contact stiffness per node (N/m), >= 0.
+ * Errors: FEM_E_INVALID (bad kind, too few or non-positive shape values,
+ * R not a rotation, non-finite values). */
+int fem_set_indenter(fem_mesh *mesh, int32_t kind, const double *shape, int32_t n_shape, const double R[9],
+                     const double c[3], double k_penalty);
+
+/* Fills the default solve parameters for a precision mode. */
+void fem_default_params(fem_solve_params *params, int32_t precision);
+
+/* Solves one quasi-static load step at the current indenter pose, warm-
+ * started from the current displacement: Newton on the total energy
+ * (elastic + contact penalty) over the free nodes. Synchronous: returns when
+ * the step is done. params NULL = defaults; info may be NULL.
+ * Errors: FEM_E_STATE (no material or indenter), FEM_E_NOT_CONVERGED (the
+ * last accepted iterate is kept and usable), FEM_E_INVERSION, FEM_E_DEVICE. */
+int fem_step(fem_mesh *mesh, const fem_solve_params *params, fem_step_info *info);
+
+/* Copies the nodal displacements (paper Sec. III-A: nodal positions / the
+ * deformation field are the simulator's output) into u (capacity doubles,
+ * at least 3 n). Errors: FEM_E_INVALID, FEM_E_BUFFER. */
+int fem_get_displacements(const fem_mesh *mesh, double *u, int64_t capacity);
+
+/* Replaces the nodal displacements (warm start, resume, or prescribed
+ * displacements on fixed nodes); count must equal 3 n. Errors: FEM_E_INVALID. */
+int fem_set_displacements(fem_mesh *mesh, const double *u, int64_t count);
+
+/* Contact patch at the current state (paper Sec. III-A: nodal contact forces,
+ * summed into resultant forces): ids of the eligible nodes with phi < 0 in
+ * ascending order, the force each exerts on the skin f = -k phi grad(phi)
+ * (n_contact x 3), the penetrations phi, and F_total = sum f. Any output
+ * pointer may be NULL except n_contact. If capacity < count, returns
+ * FEM_E_BUFFER with *n_contact = the count needed (F_total still filled). */
+int fem_get_contact_patch(const fem_mesh *mesh, int32_t *ids, double *f, double *phi, int32_t capacity,
+                          int32_t *n_contact, double F_total[3]);
+
+/* Mesh facts computed at creation: node and tet counts, number of
+ * contact-eligible nodes, and (if eligible != NULL, capacity >= n) the
+ * per-node eligibility flags. */
+int fem_get_mesh_info(const fem_mesh *mesh, int32_t *n_nodes, int32_t *n_tets, int32_t *n_eligible,
+                      uint8_t *eligible, int32_t capacity);
+
+/* Evaluates, at the current displacement, the unmasked energy gradient
+ * g = dPi/du (n x 3, fixed nodes included), the total energy and the smallest
+ * det F, running the same element and contact kernels as fem_step. Any output
+ * may be NULL. Errors: FEM_E_STATE, FEM_E_BUFFER (capacity < 3 n). */
+int fem_eval_gradient(fem_mesh *mesh, double *g, int64_t capacity, double *energy, double *min_J);
+
+/* q = H(u) v at the current displacement with the matrix-free Hessian-vector
+ * kernels of fem_step (unmasked; contact block per params->contact_hessian,
+ * params NULL = defaults). v and q are n x 3. Errors: FEM_E_STATE, FEM_E_BUFFER. */
+int fem_eval_hessvec(fem_mesh *mesh, const fem_solve_params *params, const double *v, double *q, int64_t capacity);
+
+/* Static text for a status code. */
+const char *fem_status_string(int status);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *fem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,270 @@
+"""Python binding of libfem (include/fem.h): argument marshalling only.
+
+Every function with an ``fem_`` name calls the C entry point of the same name;
+all arithmetic of the solve runs in the HIP kernels behind it. If libfem.so has
+not been built this module raises on import of the library: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfem.so")
+
+FEM_OK = 0
+FEM_E_INVALID, FEM_E_DEGENERATE, FEM_E_OOM, FEM_E_DEVICE = -1, -2, -3, -4
+FEM_E_STATE, FEM_E_NOT_CONVERGED, FEM_E_INVERSION, FEM_E_BUFFER = -5, -6, -7, -8
+FEM_PREC_FP64, FEM_PREC_FP32 = 0, 1
+FEM_SPHERE, FEM_CYLINDER, FEM_BOX, FEM_RING = 0, 1, 2, 3
+PRECISIONS = {"fp64": FEM_PREC_FP64, "fp32": FEM_PREC_FP32}
+
+# Entry points declared in include/fem.h.
+EXPORTS = ("fem_create_mesh", "fem_destroy_mesh", "fem_set_material", "fem_set_indenter", "fem_default_params",
+           "fem_step", "fem_get_displacements", "fem_set_displacements", "fem_get_contact_patch",
+           "fem_get_mesh_info", "fem_eval_gradient", "fem_eval_hessvec", "fem_status_string", "fem_last_error")
+
+
+class FemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class fem_config(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p)]
+
+
+class fem_solve_params(C.Structure):
+    _fields_ = [("newton_rtol", C.c_double), ("newton_atol", C.c_double), ("max_newton", C.c_int32),
+                ("cg_rtol", C.c_double), ("cg_eta_max", C.c_double), ("max_cg", C.c_int32),
+                ("precond", C.c_int32), ("contact_hessian", C.c_int32), ("c1", C.c_double),
+                ("max_halvings", C.c_int32)]
+
+
+class fem_step_info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("newton_iters", C.c_int32), ("cg_iters", C.c_int32),
+                ("ls_trials", C.c_int32), ("grad_passes", C.c_int32), ("hv_products", C.c_int32),
+                ("g0_norm", C.c_double), ("g_norm", C.c_double), ("energy", C.c_double), ("min_J", C.c_double),
+                ("tet_updates", C.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libfem.so; raises if it is missing (the product path has no
+    fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run paper_2103_16747_amd.build.build()")
+    L = C.CDLL(path)
+    dp, i32p, u8p, vp = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_uint8), C.c_void_p
+    L.fem_create_mesh.argtypes = [dp, C.c_int32, i32p, C.c_int32, u8p, C.POINTER(fem_config), C.POINTER(vp)]
+    L.fem_destroy_mesh.argtypes = [vp]
+    L.fem_destroy_mesh.restype = None
+    L.fem_set_material.argtypes = [vp, C.c_double, C.c_double, C.c_double]
+    L.fem_set_indenter.argtypes = [vp, C.c_int32, dp, C.c_int32, dp, dp, C.c_double]
+    L.fem_default_params.argtypes = [C.POINTER(fem_solve_params), C.c_int32]
+    L.fem_default_params.restype = None
+    L.fem_step.argtypes = [vp, C.POINTER(fem_solve_params), C.POINTER(fem_step_info)]
+    L.fem_get_displacements.argtypes = [vp, dp, C.c_int64]
+    L.fem_set_displacements.argtypes = [vp, dp, C.c_int64]
+    L.fem_get_contact_patch.argtypes = [vp, i32p, dp, dp, C.c_int32, i32p, dp]
+    L.fem_get_mesh_info.argtypes = [vp, i32p, i32p, i32p, u8p, C.c_int32]
+    L.fem_eval_gradient.argtypes = [vp, dp, C.c_int64, dp, dp]
+    L.fem_eval_hessvec.argtypes = [vp, C.POINTER(fem_solve_params), dp, dp, C.c_int64]
+    L.fem_status_string.argtypes = [C.c_int]
+    L.fem_status_string.restype = C.c_char_p
+    L.fem_last_error.argtypes = []
+    L.fem_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _check(rc, allow=()):
+    if rc != FEM_OK and rc not in allow:
+        raise FemError(rc, load().fem_last_error().decode() or load().fem_status_string(rc).decode())
+    return rc
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)   # a torch.cuda.Stream
+
+
+# ---------------------------------------------------------------------------
+# Same names as the C entry points
+# ---------------------------------------------------------------------------
+def fem_default_params(precision: int = FEM_PREC_FP64, **overrides) -> fem_solve_params:
+    p = fem_solve_params()
+    load().fem_default_params(C.byref(p), int(precision))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def fem_create_mesh(X, tets, fixed, precision: int = FEM_PREC_FP64, device: int = 0, stream=None) -> C.c_void_p:
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    T = np.ascontiguousarray(tets, dtype=np.int32)
+    F = np.ascontiguousarray(fixed, dtype=np.uint8)
+    if X.ndim != 2 or X.shape[1] != 3 or T.ndim != 2 or T.shape[1] != 4 or F.shape != (X.shape[0],):
+        raise ValueError("X must be n x 3, tets m x 4, fixed n")
+    cfg = fem_config(int(precision), int(device), _stream_handle(stream))
+    h = C.c_void_p()
+    _check(load().fem_create_mesh(_dp(X), X.shape[0], T.ctypes.data_as(C.POINTER(C.c_int32)), T.shape[0],
+                                  F.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(cfg), C.byref(h)))
+    return h
+
+
+def fem_destroy_mesh(h):
+    load().fem_destroy_mesh(h)
+
+
+def fem_set_material(h, E, nu, density=1100.0):
+    _check(load().fem_set_material(h, float(E), float(nu), float(density)))
+
+
+def fem_set_indenter(h, kind, shape, R, c, k_penalty=1.0e4):
+    sh = np.ascontiguousarray(np.atleast_1d(shape), dtype=np.float64)
+    Rm = np.ascontiguousarray(R, dtype=np.float64).reshape(9)
+    cc = np.ascontiguousarray(c, dtype=np.float64).reshape(3)
+    _check(load().fem_set_indenter(h, int(kind), _dp(sh), sh.size, _dp(Rm), _dp(cc), float(k_penalty)))
+
+
+def fem_step(h, params: fem_solve_params | None = None) -> dict:
+    """One load step. Returns the step info; NOT_CONVERGED and INVERSION are
+    reported in info['status'] rather than raised."""
+    info = fem_step_info()
+    _check(load().fem_step(h, C.byref(params) if params is not None else None, C.byref(info)),
+           allow=(FEM_E_NOT_CONVERGED, FEM_E_INVERSION))
+    return info.as_dict()
+
+
+def fem_get_displacements(h, n: int) -> np.ndarray:
+    u = np.zeros((n, 3))
+    _check(load().fem_get_displacements(h, _dp(u), u.size))
+    return u
+
+
+def fem_set_displacements(h, u):
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    _check(load().fem_set_displacements(h, _dp(uu), uu.size))
+
+
+def fem_get_contact_patch(h):
+    cnt = C.c_int32()
+    Ft = np.zeros(3)
+    rc = load().fem_get_contact_patch(h, None, None, None, 0, C.byref(cnt), _dp(Ft))
+    _check(rc, allow=(FEM_E_BUFFER,))
+    k = max(cnt.value, 1)
+    ids = np.zeros(k, dtype=np.int32)
+    f = np.zeros((k, 3))
+    phi = np.zeros(k)
+    _check(load().fem_get_contact_patch(h, ids.ctypes.data_as(C.POINTER(C.c_int32)), _dp(f), _dp(phi), k,
+                                        C.byref(cnt), _dp(Ft)))
+    c = cnt.value
+    return ids[:c], f[:c], phi[:c], Ft
+
+
+def fem_get_mesh_info(h):
+    n, m, ne = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(load().fem_get_mesh_info(h, C.byref(n), C.byref(m), C.byref(ne), None, 0))
+    elig = np.zeros(n.value, dtype=np.uint8)
+    _check(load().fem_get_mesh_info(h, None, None, None, elig.ctypes.data_as(C.POINTER(C.c_uint8)), n.value))
+    return {"n": n.value, "m": m.value, "n_eligible": ne.value, "eligible": elig}
+
+
+def fem_eval_gradient(h, n: int):
+    g = np.zeros((n, 3))
+    e, mj = C.c_double(), C.c_double()
+    _check(load().fem_eval_gradient(h, _dp(g), g.size, C.byref(e), C.byref(mj)))
+    return g, e.value, mj.value
+
+
+def fem_eval_hessvec(h, v, params: fem_solve_params | None = None):
+    vv = np.ascontiguousarray(v, dtype=np.float64)
+    q = np.zeros_like(vv)
+    _check(load().fem_eval_hessvec(h, C.byref(params) if params is not None else None, _dp(vv), _dp(q), q.size))
+    return q
+
+
+# ---------------------------------------------------------------------------
+# Convenience object
+# ---------------------------------------------------------------------------
+class FemMesh:
+    """Owns one libfem handle."""
+
+    def __init__(self, X, tets, fixed, precision="fp64", device=0, stream=None):
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.n = int(np.asarray(X).shape[0])
+        self.m = int(np.asarray(tets).shape[0])
+        self.h = fem_create_mesh(X, tets, fixed, self.precision, device, stream)
+
+    def close(self):
+        if self.h:
+            fem_destroy_mesh(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def default_params(self, **kw):
+        return fem_default_params(self.precision, **kw)
+
+    def set_material(self, E=0.3e6, nu=0.45, density=1100.0):
+        fem_set_material(self.h, E, nu, density)
+
+    def set_indenter(self, kind, shape, R, c, k_penalty=1.0e4):
+        fem_set_indenter(self.h, kind, shape, R, c, k_penalty)
+
+    def step(self, params=None):
+        return fem_step(self.h, params)
+
+    def displacements(self):
+        return fem_get_displacements(self.h, self.n)
+
+    def set_displacements(self, u):
+        fem_set_displacements(self.h, u)
+
+    def contact_patch(self):
+        return fem_get_contact_patch(self.h)
+
+    def info(self):
+        return fem_get_mesh_info(self.h)
+
+    def gradient(self):
+        return fem_eval_gradient(self.h, self.n)
+
+    def hessvec(self, v, params=None):
+        return fem_eval_hessvec(self.h, v, params)
+
+    def solve_indentation(self, ind, params=None, steps=None, callback=None):
+        """Runs the load steps of a workload Indentation; returns per-step info."""
+        out = []
+        S = ind.steps if steps is None else steps
+        for k in range(1, S + 1):
+            self.set_indenter(ind.kind, ind.shape, ind.R, ind.center(k), ind.k_penalty)
+            info = self.step(params)
+            out.append(info)
+            if callback:
+                callback(k, info)
+        return out
