@@ -177,6 +177,94 @@ int fem_eval_gradient(fem_mesh *mesh, double *g, int64_t capacity, double *energ
  * params NULL = defaults). v and q are n x 3. Errors: FEM_E_STATE, FEM_E_BUFFER. */
 int fem_eval_hessvec(fem_mesh *mesh, const fem_solve_params *params, const double *v, double *q, int64_t capacity);
 
+/* Kernel timing (measurement aid, not part of the solve). With every > 0,
+ * HIP events on the handle's stream bracket every every-th launch of the
+ * timed kernels; every = 0 turns timing off. Counters are cleared on each
+ * call. */
+#define FEM_KERNEL_HV 0           /* Hessian-vector half of a CG iteration */
+#define FEM_KERNEL_CG_UPDATE 1    /* vector-update half of a CG iteration */
+#define FEM_KERNEL_ELEMENT 2      /* element + contact pass (gradient / trial) */
+int fem_set_kernel_timing(fem_mesh *mesh, int32_t every);
+
+/* Sampled launches of one timed kernel so far and their summed event-to-event
+ * milliseconds. Errors: FEM_E_INVALID (null, unknown kernel). */
+int fem_get_kernel_timing(const fem_mesh *mesh, int32_t kernel, int64_t *count, double *total_ms);
+
+/* ---- batches of indentation jobs ------------------------------------------
+ * A batch holds meshes (shared, read-only) and up to max_jobs indentation
+ * jobs, each with its own displacement and solver state resident on the
+ * device. fem_batch_run advances every unfinished job concurrently: one
+ * launch sequence serves all jobs, whichever solver phase each is in, so jobs
+ * of different meshes, indenters and depths progress together and a job
+ * added between runs joins the next round (continuous batching). The
+ * indenters are driven in as in paper Sec. III-A: kinematically, load step s
+ * of S placing the indenter at c0 + depth * s / S * direction.
+ */
+typedef struct fem_batch fem_batch;
+
+typedef struct {
+    int32_t kind;        /* FEM_SPHERE .. FEM_RING */
+    double shape[4];     /* as listed with the kinds; unused entries ignored */
+    double R[9];         /* rotation, row-major */
+    double c0[3];        /* centre at depth 0 (initial contact) */
+    double direction[3]; /* press direction (unit) */
+    double depth;        /* total indentation depth (m) */
+    int32_t steps;       /* quasi-static load steps */
+    double k_penalty;    /* N/m per node */
+} fem_indentation;
+
+typedef struct {
+    int32_t done;        /* 1 when every load step has been taken */
+    int32_t status;      /* FEM_OK, or the status of the first failed load step */
+    int32_t step;        /* current (or last) load step, 1-based */
+    int32_t steps_ok, steps_failed;
+    int64_t newton_iters, cg_iters, hv_products, grad_passes, ls_trials;
+    int64_t tet_updates; /* n_tets * (grad_passes + hv_products) */
+    double energy, min_J, g_norm;
+} fem_job_info;
+
+typedef struct {
+    int32_t n_nodes, n_tets, n_tiles, n_entries, n_eligible;
+} fem_mesh_layout;
+
+/* Creates an empty batch for at most max_jobs (1..65536) concurrent jobs.
+ * Errors: FEM_E_INVALID, FEM_E_OOM, FEM_E_DEVICE. */
+int fem_batch_create(const fem_config *cfg, int32_t max_jobs, fem_batch **out);
+void fem_batch_destroy(fem_batch *batch);
+
+/* Adds a mesh (arguments and errors as fem_create_mesh); *mesh_id names it. */
+int fem_batch_add_mesh(fem_batch *batch, const double *X, int32_t n_nodes, const int32_t *tets, int32_t n_tets,
+                       const uint8_t *fixed, int32_t *mesh_id);
+
+/* Layout facts of a mesh: nodes, tets, tiles, tile entries, contact-eligible nodes. */
+int fem_batch_mesh_info(const fem_batch *batch, int32_t mesh_id, fem_mesh_layout *info);
+
+/* Adds an indentation job on a mesh, starting from rest (u = 0) with material
+ * (E, nu); its device state is allocated now. Errors: FEM_E_INVALID (bad
+ * mesh id, material, indenter or schedule), FEM_E_BUFFER (batch full), FEM_E_OOM. */
+int fem_batch_add_job(fem_batch *batch, int32_t mesh_id, double E, double nu, const fem_indentation *job,
+                      int32_t *job_id);
+
+/* Frees a job's slot and device state. */
+int fem_batch_remove_job(fem_batch *batch, int32_t job_id);
+
+/* Advances all unfinished jobs: until every job is done (max_rounds <= 0) or
+ * for max_rounds rounds. *n_running (may be NULL) receives the number of jobs
+ * still running. Errors: FEM_E_INVALID, FEM_E_DEVICE. */
+int fem_batch_run(fem_batch *batch, const fem_solve_params *params, int32_t max_rounds, int32_t *n_running);
+
+/* Progress and counters of a job (as of the end of the last run). */
+int fem_batch_job_info(const fem_batch *batch, int32_t job_id, fem_job_info *info);
+
+/* A job's displacements (n x 3) and contact patch, as the single-mesh calls. */
+int fem_batch_get_displacements(fem_batch *batch, int32_t job_id, double *u, int64_t capacity);
+int fem_batch_get_contact_patch(fem_batch *batch, int32_t job_id, int32_t *ids, double *f, double *phi,
+                                int32_t capacity, int32_t *n_contact, double F_total[3]);
+
+/* Kernel timing for a batch (as fem_set_kernel_timing). */
+int fem_batch_set_kernel_timing(fem_batch *batch, int32_t every);
+int fem_batch_get_kernel_timing(const fem_batch *batch, int32_t kernel, int64_t *count, double *total_ms);
+
 /* Static text for a status code. */
 const char *fem_status_string(int status);
 

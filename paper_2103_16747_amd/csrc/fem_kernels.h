@@ -1,14 +1,27 @@
 // Device kernels of the indentation solve for gfx950 (CDNA4, wave64).
 //
-// Layout in HBM (per instance): tet connectivity and per-tet constants are
-// SoA (field-major, one coalesced stream per field); node vectors are packed
-// xyz (n x 3) so a tet's four-node gather is four 12- or 24-byte loads. All
-// kernels are bandwidth-bound: the element and Hessian-vector kernels stream
-// per-tet constants once per pass and gather/scatter node data that stays in
-// L2/MALL; the node kernels stream the CG vectors. Reductions are FP64 in
-// both precision modes: per-wave shuffles, per-block LDS, one partial per
-// block, and the last block to finish (ticket counter) sums the partials in a
-// fixed order, so every reduction is deterministic for a given grid.
+// Data layout in HBM.
+//   Topology (shared by every instance of one mesh): tets are ordered along a
+//   Morton curve and cut into tiles of at most kTileTets tets that touch at
+//   most kTileNodes distinct nodes. Per tile: its node list ("entries", global
+//   ids) and the entries' coordinates relative to the tile (ent_x); per tet one
+//   32-bit word of four 8-bit local node indices. Node -> entry CSR lists for
+//   the deterministic gather of tile partial sums.
+//   Instance state: node vectors packed xyz (n x 3), tile partial sums per
+//   entry, contact blocks per contact-eligible node, FP64 solver scalars.
+//
+// Per pass a tile block stages its entries' coordinates and state vectors in
+// LDS, recomputes D_m^-1, V, F for each of its tets (nothing per tet is read
+// from HBM except the packed indices), accumulates nodal contributions with
+// LDS atomics and writes one partial per entry; node kernels gather those
+// partials. Global memory sees no atomics except the reduction tickets.
+//
+// Control: each instance runs a Newton / PCG / line-search state machine whose
+// transitions are taken on the device by the last block of each kernel to
+// finish for that instance (ticket counter). A round of kernels (Hv, update)
+// x C, dot, element, init serves every instance whatever phase it is in;
+// blocks of instances in another phase return at once. All reductions are FP64
+// and summed in a fixed order.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,11 +29,29 @@
 
 namespace fem {
 
-constexpr int kBlock = 256;               // 4 wavefronts of 64
+constexpr int kBlock = 256;       // 4 wavefronts of 64
 constexpr int kWaves = kBlock / 64;
+constexpr int kTileTets = 512;    // tets per tile (2 per thread)
+constexpr int kTileNodes = 256;   // distinct nodes per tile (8-bit local ids)
 
-// CG state codes kept in Scalars::state.
-enum : int { kRunning = 0, kConverged = 1, kNegCurv = 2, kMaxIter = 3 };
+enum Phase : int {
+    PH_IDLE = 0,
+    PH_GRAD = 1,      // element pass at u (start of a load step)
+    PH_INIT = 2,      // gather g and node blocks, Newton test, CG setup
+    PH_CG = 3,        // CG iterations
+    PH_DOT = 4,       // g . dx
+    PH_TRIAL = 5,     // line-search trial: element pass at u + alpha dx
+    PH_DONE = 6,      // all load steps taken
+    PH_EVAL_GRAD = 7, // diagnostics: gradient at u, then idle
+    PH_EVAL_INIT = 8,
+    PH_EVAL_HV = 9,   // diagnostics: q = H z, then idle
+    PH_EVAL_Q = 10
+};
+
+// Status codes (same values as the C ABI).
+enum : int { ST_OK = 0, ST_NOT_CONVERGED = -6, ST_INVERSION = -7 };
+
+enum : int { TK_ELEM = 0, TK_INIT, TK_HV, TK_UPD, TK_DOT, TK_COUNT };
 
 struct Indenter {
     int kind;            // 0 sphere, 1 cylinder, 2 box, 3 ring
@@ -30,40 +61,69 @@ struct Indenter {
     double k;
 };
 
-// Device-resident scalars of one solve.
-struct Scalars {
-    double energy, emag, minJ;   // last element pass
-    double gg;                   // |g_free|^2 at the last Newton init
-    double rz, rr, pq, alpha, beta;
-    double tol2;                 // CG stops when |r|^2 <= tol2
-    double gd;                   // g . dx
-    int it, max_it, state, nhv;  // CG iteration, cap, state, Hv products
+struct SolveParams {
+    double newton_rtol, newton_atol, cg_rtol, cg_eta_max, c1, noise_eps;
+    int max_newton, max_cg, block_jacobi, contact_full, max_halvings, pad;
+};
+
+// Dynamic state of one instance (device-resident; the host reads it).
+struct InstState {
+    int phase, step, steps, step_started;
+    int newton_it, cg_it, halvings, apply;
+    int negcurv, status, last_status, last_cg;   // last_cg: length of the previous CG solve
+    double rz, rr, pq, alpha, beta, tol2;
+    double E, emag, minJ, gg, r0, gd, alpha_ls;
+    double mu, lam, depth;
+    double c0[3], dir[3];
+    Indenter ind;
+    // current load step
+    int st_newton, st_cg, st_hv, st_grad, st_ls, pad1;
+    double st_g0, st_g;
+    // whole job
+    long long tot_newton, tot_cg, tot_hv, tot_grad, tot_ls;
+    int steps_ok, steps_failed, first_fail, pad2;
+    unsigned ticket[TK_COUNT + 3];
 };
 
 template <typename T>
-struct Buffers {
-    int n, m, nc;
-    const int *tet;       // 4 x m
-    const T *B;           // 9 x m  (row-major D_m^-1 entries, field-major)
-    const T *vol;         // m
-    const double *X;      // n x 3
-    const uint8_t *fixed; // n
-    const int *cnodes;    // nc contact-eligible node ids, ascending
-    T *u, *dx, *g, *r, *z, *p, *q;   // n x 3
-    T *diag;              // n x 6 symmetric node blocks (xx yy zz xy xz yz)
-    T *dinv;              // n x 6
-    T *finv;              // 9 x m cached F^-1 (row-major entries)
-    T *c1;                // m cached mu - lam ln J
-    T *chess;             // nc x 6 contact Hessian blocks
-    double *partial;      // 4 x kMaxPartials
-    unsigned *ticket;     // one counter per reduction kernel
-    Scalars *s;
-    double mu, lam;
-    Indenter ind;
+struct Topo {
+    int n, m, ntile, nent, nc, ncb;     // ncb = contact blocks
+    const int *tile_tet;                // ntile + 1
+    const int *tile_ent;                // ntile + 1
+    const int *ent_node;                // nent
+    const T *ent_x;                     // nent x 3, tile-relative rest coordinates
+    const uint32_t *tet_loc;            // m packed local ids
+    const int *node_ent_off;            // n + 1
+    const int *node_ent;                // nent
+    const uint8_t *fixed;               // n
+    const int *cnodes;                  // nc
+    const int *cidx;                    // n: contact slot or -1
+    const double *X;                    // n x 3
 };
 
-constexpr int kMaxPartials = 1 << 16;
-enum : int { kTicketGrad = 0, kTicketInit, kTicketHv, kTicketUpd, kTicketDot, kTicketCount };
+template <typename T>
+struct InstBufs {
+    int topo;
+    int red_stride;                     // partial slots per reduction stream
+    T *u, *dx, *g, *r, *z, *p, *dinv;   // dinv n x 6, others n x 3
+    T *pg;                              // nent x 9: gradient (3) + node block (6) partials
+    T *pq;                              // nent x 3: Hv partials
+    T *cp;                              // nc x 9: contact gradient (3) + block (6)
+    T *qout;                            // n x 3 (diagnostics)
+    double *red;                        // 3 x red_stride
+    InstState *s;
+};
+
+// ---------------------------------------------------------------------------
+// Work mapping: blocks are dealt to the 8 XCDs round-robin, so logical work
+// item L is given to hardware block (L % per) * 8 + L / per; consecutive work
+// items (same tile of consecutive instances) then share an XCD and its L2.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int logical_block() {
+    const int per = gridDim.x >> 3;
+    const int b = blockIdx.x;
+    return (b & 7) * per + (b >> 3);
+}
 
 // ---------------------------------------------------------------------------
 // Reductions
@@ -80,7 +140,6 @@ __device__ __forceinline__ double wave_min(double v) {
     return v;
 }
 
-// Reduces NS sums and (optionally) one min over the block; thread 0 gets them.
 template <int NS, bool MIN>
 __device__ __forceinline__ void block_reduce(double (&v)[NS], double &mn) {
     __shared__ double lds[kWaves][NS + 1];
@@ -110,15 +169,15 @@ __device__ __forceinline__ void block_reduce(double (&v)[NS], double &mn) {
     __syncthreads();
 }
 
-// After thread 0 has written this block's partials: returns true in every
-// thread of the last block to arrive. Release/acquire at agent scope so the
-// partials written on other XCDs are visible to the last block.
-__device__ __forceinline__ bool last_block(unsigned *ticket) {
+// Thread 0 has stored this block's partials; true in every thread of the last
+// of `total` blocks to arrive. Agent-scope release/acquire makes partials
+// written on other XCDs visible to the last block.
+__device__ __forceinline__ bool last_block(unsigned *ticket, int total) {
     __shared__ unsigned s_last;
     if (threadIdx.x == 0) {
         __threadfence();
-        unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (t == gridDim.x - 1) ? 1u : 0u;
+        const unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (t == (unsigned)(total - 1)) ? 1u : 0u;
     }
     __syncthreads();
     const bool last = s_last != 0;
@@ -130,84 +189,116 @@ __device__ __forceinline__ double load_partial(const double *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Sums NS partial streams (stride kMaxPartials) over nb blocks in a fixed
-// order; valid in thread 0. Optionally also the min of stream NS.
+// Sums NS partial streams (stride `stride`) over nb blocks in a fixed order;
+// the result is valid in thread 0. Optionally the min of stream NS.
 template <int NS, bool MIN>
-__device__ __forceinline__ void sum_partials(const double *partial, int nb, double (&out)[NS], double &mn) {
+__device__ __forceinline__ void sum_partials(const double *partial, int stride, int nb, double (&out)[NS], double &mn) {
 #pragma unroll
     for (int i = 0; i < NS; i++) out[i] = 0.0;
     mn = INFINITY;
     for (int b = threadIdx.x; b < nb; b += kBlock) {
 #pragma unroll
-        for (int i = 0; i < NS; i++) out[i] += load_partial(partial + i * kMaxPartials + b);
-        if (MIN) mn = fmin(mn, load_partial(partial + NS * kMaxPartials + b));
+        for (int i = 0; i < NS; i++) out[i] += load_partial(partial + i * stride + b);
+        if (MIN) mn = fmin(mn, load_partial(partial + NS * stride + b));
     }
     block_reduce<NS, MIN>(out, mn);
 }
 
 // ---------------------------------------------------------------------------
-// Small dense helpers
+// Scalar helpers
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ T fma_t(T a, T b, T c);
+template <> __device__ __forceinline__ float fma_t<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> __device__ __forceinline__ double fma_t<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename T> __device__ __forceinline__ T log1p_t(T x);
+template <> __device__ __forceinline__ float log1p_t<float>(float x) { return log1pf(x); }
+template <> __device__ __forceinline__ double log1p_t<double>(double x) { return log1p(x); }
+
+template <typename T> __device__ __forceinline__ T abs_t(T x) { return x < (T)0 ? -x : x; }
+
+template <typename T> __device__ __forceinline__ T safe_recip(T d) {
+    return d > (T)0 ? (T)1 / d : (d < (T)0 ? (T)1 / -d : (T)1);
+}
+
+// ---------------------------------------------------------------------------
+// Element kinematics from LDS-staged tile data.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ T fma_t(T a, T b, T c);
-template <>
-__device__ __forceinline__ float fma_t<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-template <>
-__device__ __forceinline__ double fma_t<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+struct ElemGeo {
+    T Bm[9];   // D_m^-1, row a = shape gradient of local node a+1
+    T V;
+};
 
+// D_m = [X1-X0, X2-X0, X3-X0] (columns), B = D_m^-1 by cofactors, V = det / 6.
 template <typename T>
-__device__ __forceinline__ T log1p_t(T x);
-template <>
-__device__ __forceinline__ float log1p_t<float>(float x) { return log1pf(x); }
-template <>
-__device__ __forceinline__ double log1p_t<double>(double x) { return log1p(x); }
-
-template <typename T>
-__device__ __forceinline__ T abs_t(T x) { return x < (T)0 ? -x : x; }
-
-template <typename T>
-__device__ __forceinline__ void load3(const T *a, int i, T v[3]) {
-    v[0] = a[3 * i]; v[1] = a[3 * i + 1]; v[2] = a[3 * i + 2];
+__device__ __forceinline__ ElemGeo<T> elem_geometry(const T *sx, const int l[4]) {
+    T D[9];
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int i = 0; i < 3; i++) D[3 * i + a] = sx[3 * l[a + 1] + i] - sx[3 * l[0] + i];
+    const T c00 = D[4] * D[8] - D[5] * D[7], c01 = D[5] * D[6] - D[3] * D[8], c02 = D[3] * D[7] - D[4] * D[6];
+    const T det = D[0] * c00 + D[1] * c01 + D[2] * c02;
+    const T id = (T)1 / det;
+    ElemGeo<T> g;
+    g.Bm[0] = c00 * id;
+    g.Bm[1] = (D[2] * D[7] - D[1] * D[8]) * id;
+    g.Bm[2] = (D[1] * D[5] - D[2] * D[4]) * id;
+    g.Bm[3] = c01 * id;
+    g.Bm[4] = (D[0] * D[8] - D[2] * D[6]) * id;
+    g.Bm[5] = (D[2] * D[3] - D[0] * D[5]) * id;
+    g.Bm[6] = c02 * id;
+    g.Bm[7] = (D[1] * D[6] - D[0] * D[7]) * id;
+    g.Bm[8] = (D[0] * D[4] - D[1] * D[3]) * id;
+    g.V = det / (T)6;
+    return g;
 }
 
+// G = sum_a (w_{a+1} - w_0) (x) row_a(D_m^-1), w read from LDS (3 per entry).
 template <typename T>
-__device__ __forceinline__ void atomic_add3(T *a, int i, T x, T y, T z) {
-    atomicAdd(a + 3 * i, x);
-    atomicAdd(a + 3 * i + 1, y);
-    atomicAdd(a + 3 * i + 2, z);
-}
-
-// Shape-function gradient of local node a (a = 0..3) from the SoA rows of
-// D_m^-1: b_{a} = row a-1 for a >= 1, b_0 = -(b_1 + b_2 + b_3).
-template <typename T>
-__device__ __forceinline__ void shape_grad(const T Bm[9], int a, T b[3]) {
-    if (a == 0) {
-        b[0] = -(Bm[0] + Bm[3] + Bm[6]);
-        b[1] = -(Bm[1] + Bm[4] + Bm[7]);
-        b[2] = -(Bm[2] + Bm[5] + Bm[8]);
-    } else {
-        b[0] = Bm[3 * (a - 1)];
-        b[1] = Bm[3 * (a - 1) + 1];
-        b[2] = Bm[3 * (a - 1) + 2];
-    }
-}
-
-// Edge-difference gradient: G = sum_a (w_{a+1} - w_0) (x) row_a(D_m^-1).
-template <typename T>
-__device__ __forceinline__ void edge_gradient(const T w[4][3], const T Bm[9], T G[9]) {
+__device__ __forceinline__ void edge_gradient(const T *sw, const int l[4], const T Bm[9], T G[9]) {
     T d[3][3];
 #pragma unroll
     for (int a = 0; a < 3; a++)
 #pragma unroll
-        for (int i = 0; i < 3; i++) d[a][i] = w[a + 1][i] - w[0][i];
+        for (int i = 0; i < 3; i++) d[a][i] = sw[3 * l[a + 1] + i] - sw[3 * l[0] + i];
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int j = 0; j < 3; j++) G[3 * i + j] = d[0][i] * Bm[j] + d[1][i] * Bm[3 + j] + d[2][i] * Bm[6 + j];
 }
 
-// Nodal vectors of an element first-Piola field: node a+1 receives
-// V * S * row_a(D_m^-1)^T, node 0 the negated sum (the four sum to zero).
+// J - 1 = tr G + (sum of principal 2x2 minors of G) + det G, free of the
+// cancellation of det(I + G) - 1.
+template <typename T>
+__device__ __forceinline__ T det_minus_one(const T G[9]) {
+    const T trG = G[0] + G[4] + G[8];
+    const T m2 = (G[0] * G[4] - G[1] * G[3]) + (G[0] * G[8] - G[2] * G[6]) + (G[4] * G[8] - G[5] * G[7]);
+    const T dG = G[0] * (G[4] * G[8] - G[5] * G[7]) - G[1] * (G[3] * G[8] - G[5] * G[6]) + G[2] * (G[3] * G[7] - G[4] * G[6]);
+    return trG + m2 + dG;
+}
+
+// F^-T = cof(F) / J.
+template <typename T>
+__device__ __forceinline__ void inverse_transpose(const T G[9], T J, T FiT[9]) {
+    T F[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) F[k] = G[k];
+    F[0] += (T)1; F[4] += (T)1; F[8] += (T)1;
+    const T iJ = (T)1 / J;
+    FiT[0] = (F[4] * F[8] - F[5] * F[7]) * iJ;
+    FiT[1] = (F[5] * F[6] - F[3] * F[8]) * iJ;
+    FiT[2] = (F[3] * F[7] - F[4] * F[6]) * iJ;
+    FiT[3] = (F[2] * F[7] - F[1] * F[8]) * iJ;
+    FiT[4] = (F[0] * F[8] - F[2] * F[6]) * iJ;
+    FiT[5] = (F[1] * F[6] - F[0] * F[7]) * iJ;
+    FiT[6] = (F[1] * F[5] - F[2] * F[4]) * iJ;
+    FiT[7] = (F[2] * F[3] - F[0] * F[5]) * iJ;
+    FiT[8] = (F[0] * F[4] - F[1] * F[3]) * iJ;
+}
+
+// Nodal vectors V S row_a(D_m^-1)^T for nodes a+1; node 0 gets minus the sum.
 template <typename T>
 __device__ __forceinline__ void element_nodal(const T S[9], const T Bm[9], T V, T f[4][3]) {
 #pragma unroll
@@ -219,23 +310,30 @@ __device__ __forceinline__ void element_nodal(const T S[9], const T Bm[9], T V, 
     for (int i = 0; i < 3; i++) f[0][i] = -(f[1][i] + f[2][i] + f[3][i]);
 }
 
+__device__ __forceinline__ void unpack_loc(uint32_t w, int l[4]) {
+    l[0] = w & 0xff;
+    l[1] = (w >> 8) & 0xff;
+    l[2] = (w >> 16) & 0xff;
+    l[3] = w >> 24;
+}
+
 // ---------------------------------------------------------------------------
 // Indenter signed distance in double precision: value, unit world gradient
-// and (for points inside) the world Hessian. Medial-axis ties go to the lower
-// axis (x, y, z) and to the radial branch before the axial one.
+// and, inside the indenter, the world Hessian (xx yy zz xy xz yz). Medial
+// ties go to the lower axis (x, y, z) and to the radial branch before the
+// axial one.
 // ---------------------------------------------------------------------------
 __device__ inline void sdf_eval(const Indenter &ind, const double x[3], bool want_h, double &phi, double n[3],
                                 double Hw[6]) {
     const double *R = ind.R;
     const double d0 = x[0] - ind.c[0], d1 = x[1] - ind.c[1], d2 = x[2] - ind.c[2];
-    // q = R^T (x - c)
     double q[3];
 #pragma unroll
     for (int k = 0; k < 3; k++) q[k] = R[k] * d0 + R[3 + k] * d1 + R[6 + k] * d2;
     double gq[3] = {0.0, 0.0, 0.0};
-    double Hq[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // xx yy zz xy xz yz
+    double Hq[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     switch (ind.kind) {
-    case 0: {   // sphere
+    case 0: {
         const double L = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
         phi = L - ind.shape[0];
         if (L > 0.0) {
@@ -251,7 +349,7 @@ __device__ inline void sdf_eval(const Indenter &ind, const double x[3], bool wan
         }
         break;
     }
-    case 1: {   // capped cylinder about local z
+    case 1: {
         const double a = ind.shape[0], hh = 0.5 * ind.shape[1];
         const double rho = sqrt(q[0] * q[0] + q[1] * q[1]);
         const double ex = rho > 0.0 ? q[0] / rho : 1.0, ey = rho > 0.0 ? q[1] / rho : 0.0;
@@ -263,7 +361,7 @@ __device__ inline void sdf_eval(const Indenter &ind, const double x[3], bool wan
         } else if (dr > 0.0 || (dz <= 0.0 && dr >= dz)) {
             phi = dr;
             gq[0] = ex; gq[1] = ey;
-            if (want_h && phi < 0.0 && rho > 0.0) {   // hoop curvature of the side wall
+            if (want_h && phi < 0.0 && rho > 0.0) {
                 const double tx = -ey, ty = ex, ir = 1.0 / rho;
                 Hq[0] = tx * tx * ir; Hq[1] = ty * ty * ir; Hq[3] = tx * ty * ir;
             }
@@ -273,9 +371,8 @@ __device__ inline void sdf_eval(const Indenter &ind, const double x[3], bool wan
         }
         break;
     }
-    case 2: {   // box
-        double o2 = 0.0;
-        double dd[3];
+    case 2: {
+        double o2 = 0.0, dd[3];
         bool outside = false;
 #pragma unroll
         for (int i = 0; i < 3; i++) {
@@ -295,7 +392,7 @@ __device__ inline void sdf_eval(const Indenter &ind, const double x[3], bool wan
         }
         break;
     }
-    default: {  // ring: torus about local z
+    default: {
         const double Rm = ind.shape[0], rm = ind.shape[1];
         const double rho = sqrt(q[0] * q[0] + q[1] * q[1]);
         const double ex = rho > 0.0 ? q[0] / rho : 1.0, ey = rho > 0.0 ? q[1] / rho : 0.0;
@@ -303,11 +400,10 @@ __device__ inline void sdf_eval(const Indenter &ind, const double x[3], bool wan
         const double L = sqrt(wr * wr + wz * wz);
         phi = L - rm;
         if (L > 0.0) {
-            const double cr = wr / L, cz = wz / L;   // gradient in the meridian plane
+            const double cr = wr / L, cz = wz / L;
             gq[0] = cr * ex; gq[1] = cr * ey; gq[2] = cz;
             if (want_h && rho > 0.0) {
-                // meridian tangent t = (-cz e_r + cr e_z), curvature 1/L; hoop
-                // direction e_t = (-ey, ex, 0), curvature cr / rho.
+                // meridian tangent (curvature 1/L) and hoop direction (cr / rho)
                 const double tx = -cz * ex, ty = -cz * ey, tz = cr;
                 const double iL = 1.0 / L, kh = cr / rho;
                 Hq[0] = tx * tx * iL + ey * ey * kh; Hq[1] = ty * ty * iL + ex * ex * kh;
@@ -320,17 +416,15 @@ __device__ inline void sdf_eval(const Indenter &ind, const double x[3], bool wan
         break;
     }
     }
-    // n = R gq ; Hw = R Hq R^T
 #pragma unroll
     for (int i = 0; i < 3; i++) n[i] = R[3 * i] * gq[0] + R[3 * i + 1] * gq[1] + R[3 * i + 2] * gq[2];
     if (want_h) {
-        double Hf[9] = {Hq[0], Hq[3], Hq[4], Hq[3], Hq[1], Hq[5], Hq[4], Hq[5], Hq[2]};
-        double RH[9];
+        const double Hf[9] = {Hq[0], Hq[3], Hq[4], Hq[3], Hq[1], Hq[5], Hq[4], Hq[5], Hq[2]};
+        double RH[9], W[9];
 #pragma unroll
         for (int i = 0; i < 3; i++)
 #pragma unroll
             for (int j = 0; j < 3; j++) RH[3 * i + j] = R[3 * i] * Hf[j] + R[3 * i + 1] * Hf[3 + j] + R[3 * i + 2] * Hf[6 + j];
-        double W[9];
 #pragma unroll
         for (int i = 0; i < 3; i++)
 #pragma unroll
@@ -340,190 +434,265 @@ __device__ inline void sdf_eval(const Indenter &ind, const double x[3], bool wan
 }
 
 // ---------------------------------------------------------------------------
-// Element + contact pass. Blocks [0, tet_blocks) take one tet per thread,
-// blocks after that one contact-eligible node per thread. Evaluates the state
-// u + alpha dx (alpha = 0: the current state). Accumulates the energy, the
-// energy-term magnitudes and min det F; with with_grad also scatters the
-// gradient and the 3x3 node diagonal blocks, and caches F^-1, mu - lam ln J
-// and the contact Hessian blocks for the Hessian-vector kernel.
+// End of a load step (called by a finalising thread): bookkeeping, then the
+// next load step's pose c = c0 + depth * step / steps * dir, or done.
+// ---------------------------------------------------------------------------
+__device__ inline void end_step(InstState *s, int status) {
+    s->last_status = status;
+    s->st_g = sqrt(s->gg);
+    s->tot_newton += s->st_newton;
+    s->tot_cg += s->st_cg;
+    s->tot_hv += s->st_hv;
+    s->tot_grad += s->st_grad;
+    s->tot_ls += s->st_ls;
+    if (status == ST_OK) {
+        s->steps_ok++;
+    } else {
+        s->steps_failed++;
+        if (s->first_fail == 0) s->first_fail = status;
+    }
+    if (s->step >= s->steps) {
+        s->phase = PH_DONE;
+        return;
+    }
+    s->step++;
+    const double f = s->depth * (double)s->step / (double)s->steps;
+    for (int d = 0; d < 3; d++) s->ind.c[d] = s->c0[d] + f * s->dir[d];
+    s->phase = PH_GRAD;
+    s->step_started = 1;
+    s->newton_it = 0;
+    s->st_newton = s->st_cg = s->st_hv = s->st_grad = s->st_ls = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Element + contact pass (phases GRAD, TRIAL, EVAL_GRAD). Tile blocks: energy,
+// magnitude, min J, and per-entry partials of the gradient and of the 3x3
+// node diagonal blocks V (mu |b|^2 I + (mu + lam - lam ln J) c c^T), c = F^-T b.
+// Contact blocks: penalty energy, gradient k phi n and block k n n^T (+ k phi
+// Hess(phi) with the exact contact Hessian) per eligible node.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_element_pass(Buffers<T> b, T alpha, int with_grad, int contact_full,
-                                                          int tet_blocks) {
-    double acc[2] = {0.0, 0.0};   // energy, magnitude
+__global__ __launch_bounds__(kBlock) void k_elem(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
+                                                 int nwork, const SolveParams *P) {
+    const int L = logical_block();
+    if (L >= nwork) return;
+    const int2 w = work[L];
+    const InstBufs<T> &B = bufs[w.x];
+    InstState *s = B.s;
+    const int phase = s->phase;
+    if (phase != PH_GRAD && phase != PH_TRIAL && phase != PH_EVAL_GRAD) return;
+    const Topo<T> &tp = topos[B.topo];
+    const T alpha = phase == PH_TRIAL ? (T)s->alpha_ls : (T)0;
+    const T mu = (T)s->mu, lam = (T)s->lam;
+    double acc[2] = {0.0, 0.0};
     double mnJ = INFINITY;
-    const T mu = (T)b.mu, lam = (T)b.lam;
-    if ((int)blockIdx.x < tet_blocks) {
-        const int e = blockIdx.x * kBlock + threadIdx.x;
-        if (e < b.m) {
-            int v[4];
-            T w[4][3];
+    if (w.y < tp.ntile) {
+        __shared__ T sx[3 * kTileNodes], su[3 * kTileNodes], sa[9 * kTileNodes];
+        const int t = w.y;
+        const int e0 = tp.tile_ent[t], ne = tp.tile_ent[t + 1] - e0;
+        const int k0 = tp.tile_tet[t], nk = tp.tile_tet[t + 1] - k0;
+        for (int l = threadIdx.x; l < ne; l += kBlock) {
+            const int gid = tp.ent_node[e0 + l];
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                sx[3 * l + d] = tp.ent_x[3 * (e0 + l) + d];
+                T uu = B.u[3 * gid + d];
+                if (alpha != (T)0) uu = fma_t(alpha, B.dx[3 * gid + d], uu);
+                su[3 * l + d] = uu;
+            }
+#pragma unroll
+            for (int c = 0; c < 9; c++) sa[9 * l + c] = (T)0;
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nk; k += kBlock) {
+            int l[4];
+            unpack_loc(tp.tet_loc[k0 + k], l);
+            const ElemGeo<T> geo = elem_geometry(sx, l);
+            T G[9];
+            edge_gradient(su, l, geo.Bm, G);
+            const T Jm1 = det_minus_one(G);
+            const T J = (T)1 + Jm1;
+            mnJ = fmin(mnJ, (double)J);
+            if (!(J > (T)0)) {
+                acc[0] = INFINITY;
+                continue;
+            }
+            const T lnJ = log1p_t(Jm1);
+            const T trG = G[0] + G[4] + G[8];
+            T G2 = (T)0;
+#pragma unroll
+            for (int c = 0; c < 9; c++) G2 += G[c] * G[c];
+            const T t1 = (T)0.5 * mu * ((T)2 * trG + G2), t2 = -mu * lnJ, t3 = (T)0.5 * lam * lnJ * lnJ;
+            acc[0] += (double)(geo.V * (t1 + t2 + t3));
+            acc[1] += (double)(geo.V * (abs_t(t1) + abs_t(t2) + abs_t(t3)));
+            T FiT[9];
+            inverse_transpose(G, J, FiT);
+            // P = mu (F - F^-T) + lam ln J F^-T with F - F^-T = G + F^-T G^T, which
+            // keeps full relative precision at small strain.
+            T Pk[9];
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int j = 0; j < 3; j++) {
+                    const T FG = FiT[3 * i] * G[3 * j] + FiT[3 * i + 1] * G[3 * j + 1] + FiT[3 * i + 2] * G[3 * j + 2];
+                    Pk[3 * i + j] = mu * (G[3 * i + j] + FG) + lam * lnJ * FiT[3 * i + j];
+                }
+            T f[4][3];
+            element_nodal(Pk, geo.Bm, geo.V, f);
+            const T kc = mu + lam - lam * lnJ;
 #pragma unroll
             for (int a = 0; a < 4; a++) {
-                v[a] = b.tet[a * b.m + e];
-                T uu[3], dd[3];
-                load3(b.u, v[a], uu);
-                if (alpha != (T)0) {
-                    load3(b.dx, v[a], dd);
-#pragma unroll
-                    for (int i = 0; i < 3; i++) uu[i] = fma_t(alpha, dd[i], uu[i]);
+                T *dst = sa + 9 * l[a];
+                atomicAdd(dst + 0, f[a][0]);
+                atomicAdd(dst + 1, f[a][1]);
+                atomicAdd(dst + 2, f[a][2]);
+                T bb[3];
+                if (a == 0) {
+                    bb[0] = -(geo.Bm[0] + geo.Bm[3] + geo.Bm[6]);
+                    bb[1] = -(geo.Bm[1] + geo.Bm[4] + geo.Bm[7]);
+                    bb[2] = -(geo.Bm[2] + geo.Bm[5] + geo.Bm[8]);
+                } else {
+                    bb[0] = geo.Bm[3 * (a - 1)];
+                    bb[1] = geo.Bm[3 * (a - 1) + 1];
+                    bb[2] = geo.Bm[3 * (a - 1) + 2];
                 }
-#pragma unroll
-                for (int i = 0; i < 3; i++) w[a][i] = uu[i];
-            }
-            T Bm[9];
-#pragma unroll
-            for (int k = 0; k < 9; k++) Bm[k] = b.B[k * b.m + e];
-            const T V = b.vol[e];
-            T G[9];
-            edge_gradient(w, Bm, G);
-            // J - 1 = tr G + (sum of principal 2x2 minors of G) + det G, without cancellation.
-            const T trG = G[0] + G[4] + G[8];
-            const T m2 = (G[0] * G[4] - G[1] * G[3]) + (G[0] * G[8] - G[2] * G[6]) + (G[4] * G[8] - G[5] * G[7]);
-            const T dG = G[0] * (G[4] * G[8] - G[5] * G[7]) - G[1] * (G[3] * G[8] - G[5] * G[6]) +
-                         G[2] * (G[3] * G[7] - G[4] * G[6]);
-            const T Jm1 = trG + m2 + dG;
-            const T J = (T)1 + Jm1;
-            mnJ = (double)J;
-            if (J > (T)0) {
-                const T lnJ = log1p_t(Jm1);
-                T G2 = (T)0;
-#pragma unroll
-                for (int k = 0; k < 9; k++) G2 += G[k] * G[k];
-                // tr(F^T F) - 3 = 2 tr G + |G|^2
-                const T t1 = (T)0.5 * mu * ((T)2 * trG + G2), t2 = -mu * lnJ, t3 = (T)0.5 * lam * lnJ * lnJ;
-                acc[0] = (double)(V * (t1 + t2 + t3));
-                acc[1] = (double)(V * (abs_t(t1) + abs_t(t2) + abs_t(t3)));
-                if (with_grad) {
-                    T F[9];
-#pragma unroll
-                    for (int k = 0; k < 9; k++) F[k] = G[k];
-                    F[0] += (T)1; F[4] += (T)1; F[8] += (T)1;
-                    // cofactor matrix C = J F^-T
-                    T C[9];
-                    C[0] = F[4] * F[8] - F[5] * F[7]; C[1] = F[5] * F[6] - F[3] * F[8]; C[2] = F[3] * F[7] - F[4] * F[6];
-                    C[3] = F[2] * F[7] - F[1] * F[8]; C[4] = F[0] * F[8] - F[2] * F[6]; C[5] = F[1] * F[6] - F[0] * F[7];
-                    C[6] = F[1] * F[5] - F[2] * F[4]; C[7] = F[2] * F[3] - F[0] * F[5]; C[8] = F[0] * F[4] - F[1] * F[3];
-                    const T iJ = (T)1 / J;
-                    T FiT[9];
-#pragma unroll
-                    for (int k = 0; k < 9; k++) FiT[k] = C[k] * iJ;
-                    // P = mu (F - F^-T) + lam ln J F^-T
-                    T P[9];
-#pragma unroll
-                    for (int k = 0; k < 9; k++) P[k] = mu * (F[k] - FiT[k]) + lam * lnJ * FiT[k];
-                    T f[4][3];
-                    element_nodal(P, Bm, V, f);
-#pragma unroll
-                    for (int a = 0; a < 4; a++) atomic_add3(b.g, v[a], f[a][0], f[a][1], f[a][2]);
-                    // node diagonal blocks V (mu |b|^2 I + (mu + lam - lam ln J) c c^T), c = F^-T b
-                    const T kc = mu + lam - lam * lnJ;
-#pragma unroll
-                    for (int a = 0; a < 4; a++) {
-                        T bb[3];
-                        shape_grad(Bm, a, bb);
-                        const T c0 = FiT[0] * bb[0] + FiT[1] * bb[1] + FiT[2] * bb[2];
-                        const T c1v = FiT[3] * bb[0] + FiT[4] * bb[1] + FiT[5] * bb[2];
-                        const T c2 = FiT[6] * bb[0] + FiT[7] * bb[1] + FiT[8] * bb[2];
-                        const T s = V * mu * (bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2]);
-                        const T Vk = V * kc;
-                        T *dg = b.diag + 6 * v[a];
-                        atomicAdd(dg + 0, s + Vk * c0 * c0);
-                        atomicAdd(dg + 1, s + Vk * c1v * c1v);
-                        atomicAdd(dg + 2, s + Vk * c2 * c2);
-                        atomicAdd(dg + 3, Vk * c0 * c1v);
-                        atomicAdd(dg + 4, Vk * c0 * c2);
-                        atomicAdd(dg + 5, Vk * c1v * c2);
-                    }
-                    // cache F^-1 (transpose of F^-T) and mu - lam ln J
-#pragma unroll
-                    for (int i = 0; i < 3; i++)
-#pragma unroll
-                        for (int j = 0; j < 3; j++) b.finv[(3 * i + j) * b.m + e] = FiT[3 * j + i];
-                    b.c1[e] = mu - lam * lnJ;
-                }
-            } else {
-                acc[0] = INFINITY;
+                const T cx = FiT[0] * bb[0] + FiT[1] * bb[1] + FiT[2] * bb[2];
+                const T cy = FiT[3] * bb[0] + FiT[4] * bb[1] + FiT[5] * bb[2];
+                const T cz = FiT[6] * bb[0] + FiT[7] * bb[1] + FiT[8] * bb[2];
+                const T sI = geo.V * mu * (bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2]);
+                const T Vk = geo.V * kc;
+                atomicAdd(dst + 3, sI + Vk * cx * cx);
+                atomicAdd(dst + 4, sI + Vk * cy * cy);
+                atomicAdd(dst + 5, sI + Vk * cz * cz);
+                atomicAdd(dst + 6, Vk * cx * cy);
+                atomicAdd(dst + 7, Vk * cx * cz);
+                atomicAdd(dst + 8, Vk * cy * cz);
             }
         }
+        __syncthreads();
+        for (int i = threadIdx.x; i < 9 * ne; i += kBlock) B.pg[9 * e0 + i] = sa[i];
     } else {
-        const int j = (blockIdx.x - tet_blocks) * kBlock + threadIdx.x;
-        if (j < b.nc) {
-            const int i = b.cnodes[j];
+        const int j = (w.y - tp.ntile) * kBlock + threadIdx.x;
+        if (j < tp.nc) {
+            const int i = tp.cnodes[j];
             double x[3];
 #pragma unroll
             for (int d = 0; d < 3; d++) {
-                T ui = b.u[3 * i + d];
-                if (alpha != (T)0) ui = fma_t(alpha, b.dx[3 * i + d], ui);
-                x[d] = b.X[3 * i + d] + (double)ui;
+                T ui = B.u[3 * i + d];
+                if (alpha != (T)0) ui = fma_t(alpha, B.dx[3 * i + d], ui);
+                x[d] = tp.X[3 * i + d] + (double)ui;
             }
+            const int cf = P->contact_full;
             double phi, nv[3], Hs[6];
-            sdf_eval(b.ind, x, with_grad && contact_full, phi, nv, Hs);
-            T blk[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+            sdf_eval(s->ind, x, cf != 0, phi, nv, Hs);
+            T out[9];
+#pragma unroll
+            for (int c = 0; c < 9; c++) out[c] = (T)0;
             if (phi < 0.0) {
-                const double kp = b.ind.k;
+                const double kp = s->ind.k;
                 const double ec = 0.5 * kp * phi * phi;
                 acc[0] = ec;
                 acc[1] = ec;
-                if (with_grad) {
-                    atomic_add3(b.g, i, (T)(kp * phi * nv[0]), (T)(kp * phi * nv[1]), (T)(kp * phi * nv[2]));
-                    const double hs = contact_full ? phi : 0.0;
-                    double h6[6] = {nv[0] * nv[0], nv[1] * nv[1], nv[2] * nv[2], nv[0] * nv[1], nv[0] * nv[2], nv[1] * nv[2]};
 #pragma unroll
-                    for (int k = 0; k < 6; k++) {
-                        blk[k] = (T)(kp * (h6[k] + (contact_full ? hs * Hs[k] : 0.0)));
-                        atomicAdd(b.diag + 6 * i + k, blk[k]);
-                    }
-                }
-            }
-            if (with_grad) {
+                for (int d = 0; d < 3; d++) out[d] = (T)(kp * phi * nv[d]);
+                const double nn[6] = {nv[0] * nv[0], nv[1] * nv[1], nv[2] * nv[2], nv[0] * nv[1], nv[0] * nv[2], nv[1] * nv[2]};
 #pragma unroll
-                for (int k = 0; k < 6; k++) b.chess[6 * j + k] = blk[k];
+                for (int c = 0; c < 6; c++) out[3 + c] = (T)(kp * (nn[c] + (cf ? phi * Hs[c] : 0.0)));
             }
+#pragma unroll
+            for (int c = 0; c < 9; c++) B.cp[9 * j + c] = out[c];
         }
     }
     block_reduce<2, true>(acc, mnJ);
+    const int S = B.red_stride;
     if (threadIdx.x == 0) {
-        b.partial[blockIdx.x] = acc[0];
-        b.partial[kMaxPartials + blockIdx.x] = acc[1];
-        b.partial[2 * kMaxPartials + blockIdx.x] = mnJ;
+        B.red[w.y] = acc[0];
+        B.red[S + w.y] = acc[1];
+        B.red[2 * S + w.y] = mnJ;
     }
-    if (last_block(b.ticket + kTicketGrad)) {
+    if (last_block(s->ticket + TK_ELEM, tp.ntile + tp.ncb)) {
         double tot[2], mn;
-        sum_partials<2, true>(b.partial, gridDim.x, tot, mn);
+        sum_partials<2, true>(B.red, S, tp.ntile + tp.ncb, tot, mn);
         if (threadIdx.x == 0) {
-            b.s->energy = mn > 0.0 ? tot[0] : INFINITY;
-            b.s->emag = tot[1];
-            b.s->minJ = mn;
-            b.ticket[kTicketGrad] = 0;
+            s->ticket[TK_ELEM] = 0;
+            const double E = mn > 0.0 ? tot[0] : INFINITY;
+            s->st_grad++;
+            if (phase == PH_TRIAL) {
+                s->st_ls++;
+                const double noise = P->noise_eps * s->emag;
+                if (mn > 0.0 && E <= s->E + P->c1 * s->alpha_ls * s->gd + noise) {
+                    s->E = E;
+                    s->emag = tot[1];
+                    s->minJ = mn;
+                    s->apply = 1;
+                    s->phase = PH_INIT;
+                } else if (s->halvings >= P->max_halvings) {
+                    end_step(s, mn > 0.0 ? ST_NOT_CONVERGED : ST_INVERSION);
+                } else {
+                    s->halvings++;
+                    s->alpha_ls *= 0.5;
+                }
+            } else {
+                s->E = E;
+                s->emag = tot[1];
+                s->minJ = mn;
+                s->apply = 0;
+                s->phase = phase == PH_GRAD ? PH_INIT : PH_EVAL_INIT;
+            }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Newton init: r = -g and z = M^-1 r on free nodes, block or scalar Jacobi
-// from the node diagonal blocks; clears dx, p, q; reduces |g_free|^2 and r.z.
+// Newton init (phases INIT, EVAL_INIT), one thread per node: applies an
+// accepted line-search step u += alpha dx, gathers g and the node block from
+// the tile and contact partials, forms the block (or scalar) Jacobi inverse,
+// r = -g and z = M^-1 r on free nodes; reduces |g_free|^2 and r.z. The last
+// block takes the Newton decision and sets up CG (inexact Newton: the CG
+// tolerance follows |g| / |g_step_start|).
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ T safe_recip(T d) {
-    return d > (T)0 ? (T)1 / d : (d < (T)0 ? (T)1 / -d : (T)1);
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_newton_init(Buffers<T> b, int block_jacobi) {
-    double acc[2] = {0.0, 0.0};   // g.g, r.z
+__global__ __launch_bounds__(kBlock) void k_init(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
+                                                 int nwork, const SolveParams *P) {
+    const int L = logical_block();
+    if (L >= nwork) return;
+    const int2 w = work[L];
+    const InstBufs<T> &B = bufs[w.x];
+    InstState *s = B.s;
+    const int phase = s->phase;
+    if (phase != PH_INIT && phase != PH_EVAL_INIT) return;
+    const Topo<T> &tp = topos[B.topo];
+    const bool apply = s->apply != 0;
+    const T alpha = (T)s->alpha_ls;
+    double acc[2] = {0.0, 0.0};
     double unused = 0.0;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < b.n) {
+    const int i = w.y * kBlock + threadIdx.x;
+    if (i < tp.n) {
+        if (apply)
+#pragma unroll
+            for (int d = 0; d < 3; d++) B.u[3 * i + d] = fma_t(alpha, B.dx[3 * i + d], B.u[3 * i + d]);
+        T gsum[9];
+#pragma unroll
+        for (int c = 0; c < 9; c++) gsum[c] = (T)0;
+        for (int q = tp.node_ent_off[i]; q < tp.node_ent_off[i + 1]; q++) {
+            const T *src = B.pg + 9 * tp.node_ent[q];
+#pragma unroll
+            for (int c = 0; c < 9; c++) gsum[c] += src[c];
+        }
+        const int j = tp.cidx[i];
+        if (j >= 0)
+#pragma unroll
+            for (int c = 0; c < 9; c++) gsum[c] += B.cp[9 * j + c];
+#pragma unroll
+        for (int d = 0; d < 3; d++) B.g[3 * i + d] = gsum[d];
         T M[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
         T rr[3] = {(T)0, (T)0, (T)0}, zz[3] = {(T)0, (T)0, (T)0};
-        if (!b.fixed[i]) {
-            const T *D = b.diag + 6 * i;
-            const T a = D[0], bb = D[1], c = D[2], d = D[3], e = D[4], f = D[5];
+        if (!tp.fixed[i]) {
+            const T a = gsum[3], bb = gsum[4], c = gsum[5], d = gsum[6], e = gsum[7], f = gsum[8];
             const T m2 = a * bb - d * d;
             const T c00 = bb * c - f * f, c01 = e * f - d * c, c02 = d * f - bb * e;
             const T det = a * c00 + d * c01 + e * c02;
-            if (block_jacobi && a > (T)0 && m2 > (T)0 && det > (T)0) {
+            if (P->block_jacobi && a > (T)0 && m2 > (T)0 && det > (T)0) {
                 const T id = (T)1 / det;
                 M[0] = c00 * id;
                 M[1] = (a * c - e * e) * id;
@@ -537,283 +706,369 @@ __global__ __launch_bounds__(kBlock) void k_newton_init(Buffers<T> b, int block_
                 M[2] = safe_recip(c);
             }
 #pragma unroll
-            for (int k = 0; k < 3; k++) rr[k] = -b.g[3 * i + k];
+            for (int d2 = 0; d2 < 3; d2++) rr[d2] = -gsum[d2];
             zz[0] = M[0] * rr[0] + M[3] * rr[1] + M[4] * rr[2];
             zz[1] = M[3] * rr[0] + M[1] * rr[1] + M[5] * rr[2];
             zz[2] = M[4] * rr[0] + M[5] * rr[1] + M[2] * rr[2];
 #pragma unroll
-            for (int k = 0; k < 3; k++) {
-                acc[0] += (double)rr[k] * (double)rr[k];
-                acc[1] += (double)rr[k] * (double)zz[k];
+            for (int d2 = 0; d2 < 3; d2++) {
+                acc[0] += (double)rr[d2] * (double)rr[d2];
+                acc[1] += (double)rr[d2] * (double)zz[d2];
             }
         }
 #pragma unroll
-        for (int k = 0; k < 6; k++) b.dinv[6 * i + k] = M[k];
+        for (int c = 0; c < 6; c++) B.dinv[6 * i + c] = M[c];
 #pragma unroll
-        for (int k = 0; k < 3; k++) {
-            b.r[3 * i + k] = rr[k];
-            b.z[3 * i + k] = zz[k];
-            b.dx[3 * i + k] = (T)0;
-            b.p[3 * i + k] = (T)0;
-            b.q[3 * i + k] = (T)0;
+        for (int d = 0; d < 3; d++) {
+            B.r[3 * i + d] = rr[d];
+            B.z[3 * i + d] = zz[d];
+            B.p[3 * i + d] = (T)0;
+            B.dx[3 * i + d] = (T)0;
         }
     }
     block_reduce<2, false>(acc, unused);
+    const int S = B.red_stride;
+    const int nb = (tp.n + kBlock - 1) / kBlock;
     if (threadIdx.x == 0) {
-        b.partial[blockIdx.x] = acc[0];
-        b.partial[kMaxPartials + blockIdx.x] = acc[1];
+        B.red[w.y] = acc[0];
+        B.red[S + w.y] = acc[1];
     }
-    if (last_block(b.ticket + kTicketInit)) {
+    if (last_block(s->ticket + TK_INIT, nb)) {
         double tot[2], mn;
-        sum_partials<2, false>(b.partial, gridDim.x, tot, mn);
+        sum_partials<2, false>(B.red, S, nb, tot, mn);
         if (threadIdx.x == 0) {
-            Scalars *s = b.s;
+            s->ticket[TK_INIT] = 0;
             s->gg = tot[0];
-            s->rr = tot[0];
-            s->rz = tot[1];
-            s->beta = 0.0;
-            s->alpha = 0.0;
-            s->it = 0;
-            s->nhv = 0;
-            s->state = kRunning;
-            b.ticket[kTicketInit] = 0;
+            if (phase == PH_EVAL_INIT) {
+                s->phase = PH_IDLE;
+            } else {
+                const double gn = sqrt(tot[0]);
+                if (s->apply) {
+                    s->newton_it++;
+                    s->st_newton++;
+                    s->apply = 0;
+                }
+                if (s->step_started) {
+                    s->r0 = gn;
+                    s->st_g0 = gn;
+                    s->step_started = 0;
+                }
+                if (gn <= fmax(P->newton_rtol * s->r0, P->newton_atol)) {
+                    end_step(s, ST_OK);
+                } else if (s->newton_it >= P->max_newton) {
+                    end_step(s, ST_NOT_CONVERGED);
+                } else {
+                    const double eta = fmin(P->cg_eta_max, fmax(P->cg_rtol, gn / s->r0));
+                    s->tol2 = eta * eta * tot[0];
+                    s->rz = tot[1];
+                    s->rr = tot[0];
+                    s->beta = 0.0;
+                    s->alpha = 0.0;
+                    s->cg_it = 0;
+                    s->negcurv = 0;
+                    s->phase = PH_CG;
+                }
+            }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// CG, Hessian-vector half: q = H p with p = z + beta p_prev formed on the fly
-// (the update kernel forms the identical value), element part from the cached
-// F^-1 and mu - lam ln J:
-//   dP = mu dG + (mu - lam ln J) (F^-1 dG F^-1)^T + lam tr(F^-1 dG) F^-T,
-// plus the contact blocks; p.q is accumulated element by element, so no
-// second pass over q is needed. force = 1 ignores the CG state (diagnostics).
+// CG, Hessian-vector half (phases CG, EVAL_HV): q = H p with p = z + beta
+// p_prev formed while staging (the update kernel forms the same value). Per
+// tet, with F recomputed from the staged u:
+//   dP = mu dG + (mu - lam ln J) (F^-1 dG F^-1)^T + lam tr(F^-1 dG) F^-T.
+// p.q is accumulated element by element (and over contact blocks), so alpha
+// is known before the update kernel runs.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_hv(Buffers<T> b, int tet_blocks, int force) {
-    if (!force && b.s->state != kRunning) return;
-    const T beta = (T)b.s->beta;
-    const T mu = (T)b.mu, lam = (T)b.lam;
+__global__ __launch_bounds__(kBlock) void k_hv(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
+                                               int nwork, const SolveParams *P) {
+    const int L = logical_block();
+    if (L >= nwork) return;
+    const int2 w = work[L];
+    const InstBufs<T> &B = bufs[w.x];
+    InstState *s = B.s;
+    const int phase = s->phase;
+    if (phase != PH_CG && phase != PH_EVAL_HV) return;
+    if (phase == PH_CG && s->negcurv) return;
+    const Topo<T> &tp = topos[B.topo];
+    const T beta = (T)s->beta;
+    const T mu = (T)s->mu, lam = (T)s->lam;
     double acc[1] = {0.0};
     double unused = 0.0;
-    if ((int)blockIdx.x < tet_blocks) {
-        const int e = blockIdx.x * kBlock + threadIdx.x;
-        if (e < b.m) {
-            int v[4];
-            T w[4][3];
+    if (w.y < tp.ntile) {
+        __shared__ T sx[3 * kTileNodes], su[3 * kTileNodes], sp[3 * kTileNodes], sa[3 * kTileNodes];
+        const int t = w.y;
+        const int e0 = tp.tile_ent[t], ne = tp.tile_ent[t + 1] - e0;
+        const int k0 = tp.tile_tet[t], nk = tp.tile_tet[t + 1] - k0;
+        for (int l = threadIdx.x; l < ne; l += kBlock) {
+            const int gid = tp.ent_node[e0 + l];
 #pragma unroll
-            for (int a = 0; a < 4; a++) {
-                v[a] = b.tet[a * b.m + e];
-#pragma unroll
-                for (int i = 0; i < 3; i++) w[a][i] = fma_t(beta, b.p[3 * v[a] + i], b.z[3 * v[a] + i]);
+            for (int d = 0; d < 3; d++) {
+                sx[3 * l + d] = tp.ent_x[3 * (e0 + l) + d];
+                su[3 * l + d] = B.u[3 * gid + d];
+                sp[3 * l + d] = fma_t(beta, B.p[3 * gid + d], B.z[3 * gid + d]);
+                sa[3 * l + d] = (T)0;
             }
-            T Bm[9], Fi[9];
-#pragma unroll
-            for (int k = 0; k < 9; k++) {
-                Bm[k] = b.B[k * b.m + e];
-                Fi[k] = b.finv[k * b.m + e];
-            }
-            const T V = b.vol[e], cc = b.c1[e];
+        }
+        __syncthreads();
+        double pq = 0.0;
+        for (int k = threadIdx.x; k < nk; k += kBlock) {
+            int l[4];
+            unpack_loc(tp.tet_loc[k0 + k], l);
+            const ElemGeo<T> geo = elem_geometry(sx, l);
+            T G[9];
+            edge_gradient(su, l, geo.Bm, G);
+            const T Jm1 = det_minus_one(G);
+            const T J = (T)1 + Jm1;
+            if (!(J > (T)0)) continue;
+            const T cc = mu - lam * log1p_t(Jm1);
+            T FiT[9];
+            inverse_transpose(G, J, FiT);
             T dG[9];
-            edge_gradient(w, Bm, dG);
-            T A[9];   // F^-1 dG
+            edge_gradient(sp, l, geo.Bm, dG);
+            // A = F^-1 dG (F^-1 = FiT^T)
+            T A[9];
 #pragma unroll
             for (int i = 0; i < 3; i++)
 #pragma unroll
-                for (int j = 0; j < 3; j++) A[3 * i + j] = Fi[3 * i] * dG[j] + Fi[3 * i + 1] * dG[3 + j] + Fi[3 * i + 2] * dG[6 + j];
+                for (int j = 0; j < 3; j++) A[3 * i + j] = FiT[i] * dG[j] + FiT[3 + i] * dG[3 + j] + FiT[6 + i] * dG[6 + j];
             const T tr = A[0] + A[4] + A[8];
-            T Mm[9];  // F^-1 dG F^-1
-#pragma unroll
-            for (int i = 0; i < 3; i++)
-#pragma unroll
-                for (int j = 0; j < 3; j++) Mm[3 * i + j] = A[3 * i] * Fi[j] + A[3 * i + 1] * Fi[3 + j] + A[3 * i + 2] * Fi[6 + j];
+            // Mt = (A F^-1)^T, Mt_ij = sum_k A_jk FiT_ik
             T dP[9];
 #pragma unroll
             for (int i = 0; i < 3; i++)
 #pragma unroll
-                for (int j = 0; j < 3; j++)
-                    dP[3 * i + j] = mu * dG[3 * i + j] + cc * Mm[3 * j + i] + lam * tr * Fi[3 * j + i];
+                for (int j = 0; j < 3; j++) {
+                    const T Mt = A[3 * j] * FiT[3 * i] + A[3 * j + 1] * FiT[3 * i + 1] + A[3 * j + 2] * FiT[3 * i + 2];
+                    dP[3 * i + j] = mu * dG[3 * i + j] + cc * Mt + lam * tr * FiT[3 * i + j];
+                }
             T f[4][3];
-            element_nodal(dP, Bm, V, f);
-            double pq = 0.0;
+            element_nodal(dP, geo.Bm, geo.V, f);
+            T e_pq = (T)0;
 #pragma unroll
             for (int a = 0; a < 4; a++) {
-                atomic_add3(b.q, v[a], f[a][0], f[a][1], f[a][2]);
-                pq += (double)(w[a][0] * f[a][0] + w[a][1] * f[a][1] + w[a][2] * f[a][2]);
+                T *dst = sa + 3 * l[a];
+                atomicAdd(dst + 0, f[a][0]);
+                atomicAdd(dst + 1, f[a][1]);
+                atomicAdd(dst + 2, f[a][2]);
+                e_pq += sp[3 * l[a]] * f[a][0] + sp[3 * l[a] + 1] * f[a][1] + sp[3 * l[a] + 2] * f[a][2];
             }
-            acc[0] = pq;
+            pq += (double)e_pq;
         }
+        acc[0] = pq;
+        __syncthreads();
+        for (int i = threadIdx.x; i < 3 * ne; i += kBlock) B.pq[3 * e0 + i] = sa[i];
     } else {
-        const int j = (blockIdx.x - tet_blocks) * kBlock + threadIdx.x;
-        if (j < b.nc) {
-            const T *H = b.chess + 6 * j;
+        const int j = (w.y - tp.ntile) * kBlock + threadIdx.x;
+        if (j < tp.nc) {
+            const T *H = B.cp + 9 * j + 3;
             if (H[0] != (T)0 || H[1] != (T)0 || H[2] != (T)0 || H[3] != (T)0 || H[4] != (T)0 || H[5] != (T)0) {
-                const int i = b.cnodes[j];
+                const int i = tp.cnodes[j];
                 T pv[3];
 #pragma unroll
-                for (int d = 0; d < 3; d++) pv[d] = fma_t(beta, b.p[3 * i + d], b.z[3 * i + d]);
+                for (int d = 0; d < 3; d++) pv[d] = fma_t(beta, B.p[3 * i + d], B.z[3 * i + d]);
                 const T q0 = H[0] * pv[0] + H[3] * pv[1] + H[4] * pv[2];
                 const T q1 = H[3] * pv[0] + H[1] * pv[1] + H[5] * pv[2];
                 const T q2 = H[4] * pv[0] + H[5] * pv[1] + H[2] * pv[2];
-                atomic_add3(b.q, i, q0, q1, q2);
                 acc[0] = (double)(pv[0] * q0 + pv[1] * q1 + pv[2] * q2);
             }
         }
     }
     block_reduce<1, false>(acc, unused);
-    if (threadIdx.x == 0) b.partial[3 * kMaxPartials + blockIdx.x] = acc[0];
-    if (last_block(b.ticket + kTicketHv)) {
+    const int S = B.red_stride;
+    if (threadIdx.x == 0) B.red[w.y] = acc[0];
+    if (last_block(s->ticket + TK_HV, tp.ntile + tp.ncb)) {
         double tot[1], mn;
-        sum_partials<1, false>(b.partial + 3 * kMaxPartials, gridDim.x, tot, mn);
+        sum_partials<1, false>(B.red, S, tp.ntile + tp.ncb, tot, mn);
         if (threadIdx.x == 0) {
-            Scalars *s = b.s;
+            s->ticket[TK_HV] = 0;
             s->pq = tot[0];
-            if (!force) {
-                s->nhv += 1;
+            if (phase == PH_EVAL_HV) {
+                s->phase = PH_EVAL_Q;
+            } else {
+                s->st_hv++;
                 if (tot[0] > 0.0)
                     s->alpha = s->rz / tot[0];
                 else
-                    s->state = kNegCurv;
+                    s->negcurv = 1;
             }
-            b.ticket[kTicketHv] = 0;
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// CG, update half (free nodes): p = z + beta p_prev; dx += alpha p;
-// r -= alpha q; q = 0; z = M^-1 r; reduces r.z and r.r, then beta and the
-// stopping test. On non-positive curvature at the first iteration the
-// preconditioned residual becomes the Newton direction.
+// CG, update half (phases CG, EVAL_Q), one thread per node: gathers q from
+// the tile partials plus the contact block times p; then on free nodes
+// p = z + beta p_prev, dx += alpha p, r -= alpha q, z = M^-1 r, reducing r.z
+// and r.r. Non-positive curvature ends CG (on its first iteration the
+// preconditioned residual becomes the Newton direction).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_update(Buffers<T> b) {
-    const int state = b.s->state;
-    if (state == kConverged || state == kMaxIter) return;
-    const bool negcurv = state == kNegCurv;
-    const T alpha = (T)b.s->alpha, beta = (T)b.s->beta;
-    double acc[2] = {0.0, 0.0};   // r.z, r.r
+__global__ __launch_bounds__(kBlock) void k_update(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
+                                                   int nwork, const SolveParams *P) {
+    const int L = logical_block();
+    if (L >= nwork) return;
+    const int2 w = work[L];
+    const InstBufs<T> &B = bufs[w.x];
+    InstState *s = B.s;
+    const int phase = s->phase;
+    if (phase != PH_CG && phase != PH_EVAL_Q) return;
+    const Topo<T> &tp = topos[B.topo];
+    const bool negcurv = s->negcurv != 0;
+    const T alpha = (T)s->alpha, beta = (T)s->beta;
+    double acc[2] = {0.0, 0.0};
     double unused = 0.0;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < b.n) {
-        if (negcurv) {
-            if (b.s->it == 0)
+    const int i = w.y * kBlock + threadIdx.x;
+    if (i < tp.n) {
+        T pv[3];
 #pragma unroll
-                for (int k = 0; k < 3; k++) b.dx[3 * i + k] = fma_t(beta, b.p[3 * i + k], b.z[3 * i + k]);
-        } else if (!b.fixed[i]) {
-            T pv[3], rv[3];
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                pv[k] = fma_t(beta, b.p[3 * i + k], b.z[3 * i + k]);
-                b.p[3 * i + k] = pv[k];
-                b.dx[3 * i + k] = fma_t(alpha, pv[k], b.dx[3 * i + k]);
-                rv[k] = fma_t(-alpha, b.q[3 * i + k], b.r[3 * i + k]);
-                b.r[3 * i + k] = rv[k];
-                b.q[3 * i + k] = (T)0;
+        for (int d = 0; d < 3; d++) pv[d] = fma_t(beta, B.p[3 * i + d], B.z[3 * i + d]);
+        if (phase == PH_EVAL_Q || !negcurv) {
+            T qv[3] = {(T)0, (T)0, (T)0};
+            for (int q = tp.node_ent_off[i]; q < tp.node_ent_off[i + 1]; q++) {
+                const T *src = B.pq + 3 * tp.node_ent[q];
+                qv[0] += src[0];
+                qv[1] += src[1];
+                qv[2] += src[2];
             }
-            const T *M = b.dinv + 6 * i;
-            const T z0 = M[0] * rv[0] + M[3] * rv[1] + M[4] * rv[2];
-            const T z1 = M[3] * rv[0] + M[1] * rv[1] + M[5] * rv[2];
-            const T z2 = M[4] * rv[0] + M[5] * rv[1] + M[2] * rv[2];
-            b.z[3 * i] = z0;
-            b.z[3 * i + 1] = z1;
-            b.z[3 * i + 2] = z2;
-            acc[0] = (double)rv[0] * (double)z0 + (double)rv[1] * (double)z1 + (double)rv[2] * (double)z2;
-            acc[1] = (double)rv[0] * (double)rv[0] + (double)rv[1] * (double)rv[1] + (double)rv[2] * (double)rv[2];
-        } else {
+            const int j = tp.cidx[i];
+            if (j >= 0) {
+                const T *H = B.cp + 9 * j + 3;
+                qv[0] += H[0] * pv[0] + H[3] * pv[1] + H[4] * pv[2];
+                qv[1] += H[3] * pv[0] + H[1] * pv[1] + H[5] * pv[2];
+                qv[2] += H[4] * pv[0] + H[5] * pv[1] + H[2] * pv[2];
+            }
+            if (phase == PH_EVAL_Q) {
 #pragma unroll
-            for (int k = 0; k < 3; k++) b.q[3 * i + k] = (T)0;
+                for (int d = 0; d < 3; d++) B.qout[3 * i + d] = qv[d];
+            } else if (!tp.fixed[i]) {
+                T rv[3];
+#pragma unroll
+                for (int d = 0; d < 3; d++) {
+                    B.p[3 * i + d] = pv[d];
+                    B.dx[3 * i + d] = fma_t(alpha, pv[d], B.dx[3 * i + d]);
+                    rv[d] = fma_t(-alpha, qv[d], B.r[3 * i + d]);
+                    B.r[3 * i + d] = rv[d];
+                }
+                const T *M = B.dinv + 6 * i;
+                const T z0 = M[0] * rv[0] + M[3] * rv[1] + M[4] * rv[2];
+                const T z1 = M[3] * rv[0] + M[1] * rv[1] + M[5] * rv[2];
+                const T z2 = M[4] * rv[0] + M[5] * rv[1] + M[2] * rv[2];
+                B.z[3 * i] = z0;
+                B.z[3 * i + 1] = z1;
+                B.z[3 * i + 2] = z2;
+                acc[0] = (double)rv[0] * (double)z0 + (double)rv[1] * (double)z1 + (double)rv[2] * (double)z2;
+                acc[1] = (double)rv[0] * (double)rv[0] + (double)rv[1] * (double)rv[1] + (double)rv[2] * (double)rv[2];
+            }
+        } else if (s->cg_it == 0) {
+#pragma unroll
+            for (int d = 0; d < 3; d++) B.dx[3 * i + d] = pv[d];
         }
     }
     block_reduce<2, false>(acc, unused);
+    const int S = B.red_stride;
+    const int nb = (tp.n + kBlock - 1) / kBlock;
     if (threadIdx.x == 0) {
-        b.partial[blockIdx.x] = acc[0];
-        b.partial[kMaxPartials + blockIdx.x] = acc[1];
+        B.red[w.y] = acc[0];
+        B.red[S + w.y] = acc[1];
     }
-    if (last_block(b.ticket + kTicketUpd)) {
+    if (last_block(s->ticket + TK_UPD, nb)) {
         double tot[2], mn;
-        sum_partials<2, false>(b.partial, gridDim.x, tot, mn);
+        sum_partials<2, false>(B.red, S, nb, tot, mn);
         if (threadIdx.x == 0) {
-            Scalars *s = b.s;
-            if (negcurv) {
-                s->state = kConverged;
+            s->ticket[TK_UPD] = 0;
+            if (phase == PH_EVAL_Q) {
+                s->phase = PH_IDLE;
+            } else if (negcurv) {
+                s->phase = PH_DOT;
             } else {
-                s->it += 1;
+                s->cg_it++;
+                s->st_cg++;
                 s->beta = tot[0] / s->rz;
                 s->rz = tot[0];
                 s->rr = tot[1];
-                if (tot[1] <= s->tol2)
-                    s->state = kConverged;
-                else if (s->it >= s->max_it)
-                    s->state = kMaxIter;
+                if (tot[1] <= s->tol2 || s->cg_it >= P->max_cg) {
+                    s->last_cg = s->cg_it;
+                    s->phase = PH_DOT;
+                }
             }
-            b.ticket[kTicketUpd] = 0;
         }
     }
 }
 
-// g . dx over all nodes (dx is zero on fixed nodes).
+// g . dx (phase DOT), then the line search starts at alpha = 1.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_dot_gdx(Buffers<T> b) {
+__global__ __launch_bounds__(kBlock) void k_dot(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
+                                                int nwork) {
+    const int L = logical_block();
+    if (L >= nwork) return;
+    const int2 w = work[L];
+    const InstBufs<T> &B = bufs[w.x];
+    InstState *s = B.s;
+    if (s->phase != PH_DOT) return;
+    const Topo<T> &tp = topos[B.topo];
     double acc[1] = {0.0};
     double unused = 0.0;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < b.n)
+    const int i = w.y * kBlock + threadIdx.x;
+    if (i < tp.n)
 #pragma unroll
-        for (int k = 0; k < 3; k++) acc[0] += (double)b.g[3 * i + k] * (double)b.dx[3 * i + k];
+        for (int d = 0; d < 3; d++) acc[0] += (double)B.g[3 * i + d] * (double)B.dx[3 * i + d];
     block_reduce<1, false>(acc, unused);
-    if (threadIdx.x == 0) b.partial[blockIdx.x] = acc[0];
-    if (last_block(b.ticket + kTicketDot)) {
+    const int nb = (tp.n + kBlock - 1) / kBlock;
+    if (threadIdx.x == 0) B.red[w.y] = acc[0];
+    if (last_block(s->ticket + TK_DOT, nb)) {
         double tot[1], mn;
-        sum_partials<1, false>(b.partial, gridDim.x, tot, mn);
+        sum_partials<1, false>(B.red, B.red_stride, nb, tot, mn);
         if (threadIdx.x == 0) {
-            b.s->gd = tot[0];
-            b.ticket[kTicketDot] = 0;
+            s->ticket[TK_DOT] = 0;
+            s->gd = tot[0];
+            s->alpha_ls = 1.0;
+            s->halvings = 0;
+            s->phase = PH_TRIAL;
         }
     }
 }
 
-// u = u + alpha dx, with the same rounding as the trial evaluation.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_axpy(T *u, const T *dx, T alpha, int len) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < len) u[i] = fma_t(alpha, dx[i], u[i]);
-}
-
 // ---------------------------------------------------------------------------
-// Contact patch at the current state: one block walks the eligible nodes in
-// ascending order and compacts those with phi < 0 (ordered scan), writing
-// ids, forces on the skin -k phi n, phi, the count and the FP64 resultant.
+// Contact patch of one instance at its current state: one block walks the
+// eligible nodes in ascending order and compacts those with phi < 0 (ordered
+// scan): ids, forces on the skin -k phi n, phi, count and FP64 resultant.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(1024) void k_contact_patch(Buffers<T> b, int *ids, double *f, double *phi_out,
-                                                          int *count, double *Ftot) {
+__global__ __launch_bounds__(1024) void k_contact_patch(const Topo<T> *topos, const InstBufs<T> *bufs, int inst,
+                                                          int *ids, double *f, double *phi_out, int *count,
+                                                          double *Ftot) {
     __shared__ int wave_cnt[16];
     __shared__ double wave_f[16][3];
     __shared__ int base_s;
     __shared__ double F_s[3];
+    const InstBufs<T> &B = bufs[inst];
+    const Topo<T> &tp = topos[B.topo];
+    const Indenter ind = B.s->ind;
     if (threadIdx.x == 0) {
         base_s = 0;
         F_s[0] = F_s[1] = F_s[2] = 0.0;
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int start = 0; start < b.nc; start += 1024) {
+    for (int start = 0; start < tp.nc; start += 1024) {
         const int j = start + threadIdx.x;
         double phi = 0.0, nv[3] = {0.0, 0.0, 0.0}, Hs[6];
         int i = -1;
         bool act = false;
-        if (j < b.nc) {
-            i = b.cnodes[j];
+        if (j < tp.nc) {
+            i = tp.cnodes[j];
             double x[3];
 #pragma unroll
-            for (int d = 0; d < 3; d++) x[d] = b.X[3 * i + d] + (double)b.u[3 * i + d];
-            sdf_eval(b.ind, x, false, phi, nv, Hs);
+            for (int d = 0; d < 3; d++) x[d] = tp.X[3 * i + d] + (double)B.u[3 * i + d];
+            sdf_eval(ind, x, false, phi, nv, Hs);
             act = phi < 0.0;
         }
         double fv[3];
 #pragma unroll
-        for (int d = 0; d < 3; d++) fv[d] = act ? -b.ind.k * phi * nv[d] : 0.0;
+        for (int d = 0; d < 3; d++) fv[d] = act ? -ind.k * phi * nv[d] : 0.0;
         const unsigned long long mask = __ballot(act);
         const int before = __popcll(mask & ((1ull << lane) - 1ull));
         double sf[3];
@@ -854,51 +1109,30 @@ __global__ __launch_bounds__(1024) void k_contact_patch(Buffers<T> b, int *ids, 
 }
 
 // ---------------------------------------------------------------------------
-// Mesh precompute (FP64): D_m = [X1-X0, X2-X0, X3-X0], V = det D_m / 6,
-// D_m^-1 by cofactors; the first tet with V <= 0 is recorded.
+// Mesh set-up kernels.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_precompute(const double *X, const int *tet, int m, T *B, T *vol,
-                                                        int *bad) {
+// Rest volume check (FP64): records the first tet with det D_m <= 0.
+__global__ __launch_bounds__(kBlock) void k_check_volumes(const double *X, const int *tet, int m, int *bad) {
     const int e = blockIdx.x * kBlock + threadIdx.x;
     if (e >= m) return;
-    const int v0 = tet[e];
+    const int v0 = tet[4 * e];
     double D[9];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        const int va = tet[(a + 1) * m + e];
+        const int va = tet[4 * e + a + 1];
 #pragma unroll
         for (int i = 0; i < 3; i++) D[3 * i + a] = X[3 * va + i] - X[3 * v0 + i];
     }
-    const double c00 = D[4] * D[8] - D[5] * D[7], c01 = D[5] * D[6] - D[3] * D[8], c02 = D[3] * D[7] - D[4] * D[6];
-    const double det = D[0] * c00 + D[1] * c01 + D[2] * c02;
-    const double V = det / 6.0;
-    if (!(V > 0.0)) {
-        atomicMin(bad, e);
-        return;
-    }
-    const double id = 1.0 / det;
-    // inverse = adj(D) / det, adj = cofactor^T
-    double inv[9];
-    inv[0] = c00 * id;
-    inv[1] = (D[2] * D[7] - D[1] * D[8]) * id;
-    inv[2] = (D[1] * D[5] - D[2] * D[4]) * id;
-    inv[3] = c01 * id;
-    inv[4] = (D[0] * D[8] - D[2] * D[6]) * id;
-    inv[5] = (D[2] * D[3] - D[0] * D[5]) * id;
-    inv[6] = c02 * id;
-    inv[7] = (D[1] * D[6] - D[0] * D[7]) * id;
-    inv[8] = (D[0] * D[4] - D[1] * D[3]) * id;
-#pragma unroll
-    for (int k = 0; k < 9; k++) B[k * m + e] = (T)inv[k];
-    vol[e] = (T)V;
+    const double det = D[0] * (D[4] * D[8] - D[5] * D[7]) - D[1] * (D[3] * D[8] - D[5] * D[6]) +
+                       D[2] * (D[3] * D[7] - D[4] * D[6]);
+    if (!(det > 0.0)) atomicMin(bad, e);
 }
 
-// Boundary faces by hashing: each of the 4m faces is keyed by its sorted node
-// triple (21 bits per id) and counted in an open-addressing table; faces seen
-// once are boundary faces.
-__device__ __forceinline__ unsigned long long face_key(const int *tet, int m, int e, int f) {
-    int a = tet[((f + 1) & 3) * m + e], b = tet[((f + 2) & 3) * m + e], c = tet[((f + 3) & 3) * m + e];
+// Boundary faces by hashing the sorted node triple (21 bits per id) of each
+// of the 4m faces into an open-addressing table; faces seen once are on the
+// boundary.
+__device__ __forceinline__ unsigned long long face_key(const int *tet, int e, int f) {
+    int a = tet[4 * e + ((f + 1) & 3)], b = tet[4 * e + ((f + 2) & 3)], c = tet[4 * e + ((f + 3) & 3)];
     int t;
     if (a > b) { t = a; a = b; b = t; }
     if (b > c) { t = b; b = c; c = t; }
@@ -919,9 +1153,9 @@ __global__ __launch_bounds__(kBlock) void k_faces_insert(const int *tet, int m, 
                                                          unsigned *cnt, unsigned mask) {
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= 4 * m) return;
-    const unsigned long long k = face_key(tet, m, t >> 2, t & 3);
+    const unsigned long long k = face_key(tet, t >> 2, t & 3);
     unsigned h = face_hash(k) & mask;
-    for (;;) {   // load factor <= 1/2, so a free or matching slot is always found
+    for (;;) {   // load factor <= 1/2: a free or matching slot is always found
         const unsigned long long prev = atomicCAS(keys + h, ~0ull, k);
         if (prev == ~0ull || prev == k) {
             atomicAdd(cnt + h, 1u);
@@ -936,19 +1170,20 @@ __global__ __launch_bounds__(kBlock) void k_faces_mark(const int *tet, int m, co
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= 4 * m) return;
     const int e = t >> 2, f = t & 3;
-    const unsigned long long k = face_key(tet, m, e, f);
+    const unsigned long long k = face_key(tet, e, f);
     unsigned h = face_hash(k) & mask;
     while (keys[h] != k) h = (h + 1) & mask;   // the key was inserted
     if (cnt[h] == 1u) {
-        surf[tet[((f + 1) & 3) * m + e]] = 1;
-        surf[tet[((f + 2) & 3) * m + e]] = 1;
-        surf[tet[((f + 3) & 3) * m + e]] = 1;
+        surf[tet[4 * e + ((f + 1) & 3)]] = 1;
+        surf[tet[4 * e + ((f + 2) & 3)]] = 1;
+        surf[tet[4 * e + ((f + 3) & 3)]] = 1;
     }
 }
 
-// One block: eligible = surface and not fixed; ascending compaction.
+// One block: eligible = surface and not fixed; ascending compaction and the
+// node -> contact slot map.
 __global__ __launch_bounds__(1024) void k_compact_eligible(const uint8_t *surf, const uint8_t *fixed, int n,
-                                                           uint8_t *elig, int *list, int *count) {
+                                                           uint8_t *elig, int *list, int *cidx, int *count) {
     __shared__ int wave_cnt[16];
     __shared__ int base_s;
     if (threadIdx.x == 0) base_s = 0;
@@ -957,13 +1192,17 @@ __global__ __launch_bounds__(1024) void k_compact_eligible(const uint8_t *surf, 
     for (int start = 0; start < n; start += 1024) {
         const int i = start + threadIdx.x;
         const bool act = i < n && surf[i] && !fixed[i];
-        if (i < n) elig[i] = act ? 1 : 0;
         const unsigned long long mask = __ballot(act);
         if (lane == 0) wave_cnt[w] = __popcll(mask);
         __syncthreads();
         int off = base_s;
         for (int k = 0; k < w; k++) off += wave_cnt[k];
-        if (act) list[off + __popcll(mask & ((1ull << lane) - 1ull))] = i;
+        if (i < n) {
+            elig[i] = act ? 1 : 0;
+            const int slot = off + __popcll(mask & ((1ull << lane) - 1ull));
+            cidx[i] = act ? slot : -1;
+            if (act) list[slot] = i;
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
             int tot = 0;

@@ -1,18 +1,20 @@
-// libfem host driver and C ABI (declared in include/fem.h).
+// libfem host side: mesh layout construction, the batch engine and the C ABI
+// (include/fem.h).
 //
-// The host owns control flow only: argument checks, device memory, kernel
-// launches and the Newton / line-search decisions that need the FP64 scalars
-// the kernels reduce. Every arithmetic step of the solve runs in the kernels
-// of fem_kernels.h.
+// The host builds each mesh's tiled layout once, owns device memory, and
+// enqueues rounds of kernels; every arithmetic step of the solve and every
+// solver decision (Newton test, CG stop, line-search acceptance, next load
+// step) is taken on the device by the kernels in fem_kernels.h. A single mesh
+// handle is a batch holding one job.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cfloat>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <limits>
 #include <new>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -38,100 +40,15 @@ int fail(int code, const std::string &msg) {
                         std::string(#expr) + ": " + hipGetErrorString(e_));                        \
     } while (0)
 
-inline int nblocks(long long work, int block = kBlock) { return (int)((work + block - 1) / block); }
+#define TRY(expr)               \
+    do {                        \
+        int rc_ = (expr);       \
+        if (rc_) return rc_;    \
+    } while (0)
 
-// Carves sub-buffers out of one device allocation, 256-byte aligned.
-struct Arena {
-    size_t off = 0;
-    template <typename T>
-    size_t take(size_t count) {
-        size_t at = (off + 255) & ~size_t(255);
-        off = at + count * sizeof(T);
-        return at;
-    }
-};
-
-}  // namespace
-
-struct fem_mesh {
-    int device = 0;
-    int precision = FEM_PREC_FP64;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    int n = 0, m = 0, nc = 0;
-    void *arena = nullptr;
-    size_t arena_bytes = 0;
-    // typed views into the arena (the element type is the precision's)
-    int *tet = nullptr;
-    void *B = nullptr, *vol = nullptr;
-    double *X = nullptr;
-    uint8_t *fixed = nullptr, *eligible = nullptr;
-    int *cnodes = nullptr;
-    void *u = nullptr, *dx = nullptr, *g = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
-    void *diag = nullptr, *dinv = nullptr, *finv = nullptr, *c1 = nullptr, *chess = nullptr;
-    double *partial = nullptr;
-    unsigned *ticket = nullptr;
-    Scalars *s = nullptr;
-    // patch outputs
-    int *patch_ids = nullptr, *patch_count = nullptr;
-    double *patch_f = nullptr, *patch_phi = nullptr, *patch_F = nullptr;
-    // pinned staging
-    Scalars *h_s = nullptr;
-    void *h_stage = nullptr;
-    size_t h_stage_bytes = 0;
-    // problem data
-    bool have_material = false, have_indenter = false;
-    double E = 0, nu = 0, density = 0, mu = 0, lam = 0;
-    Indenter ind{};
-    int last_cg = 0;
-    size_t elem() const { return precision == FEM_PREC_FP32 ? sizeof(float) : sizeof(double); }
-};
-
-namespace {
-
-template <typename T>
-Buffers<T> views(const fem_mesh *M) {
-    Buffers<T> b;
-    b.n = M->n;
-    b.m = M->m;
-    b.nc = M->nc;
-    b.tet = M->tet;
-    b.B = (const T *)M->B;
-    b.vol = (const T *)M->vol;
-    b.X = M->X;
-    b.fixed = M->fixed;
-    b.cnodes = M->cnodes;
-    b.u = (T *)M->u;
-    b.dx = (T *)M->dx;
-    b.g = (T *)M->g;
-    b.r = (T *)M->r;
-    b.z = (T *)M->z;
-    b.p = (T *)M->p;
-    b.q = (T *)M->q;
-    b.diag = (T *)M->diag;
-    b.dinv = (T *)M->dinv;
-    b.finv = (T *)M->finv;
-    b.c1 = (T *)M->c1;
-    b.chess = (T *)M->chess;
-    b.partial = M->partial;
-    b.ticket = M->ticket;
-    b.s = M->s;
-    b.mu = M->mu;
-    b.lam = M->lam;
-    b.ind = M->ind;
-    return b;
-}
-
-int set_device(const fem_mesh *M) {
-    HIP_TRY(hipSetDevice(M->device));
-    return FEM_OK;
-}
-
-int fetch_scalars(fem_mesh *M) {
-    HIP_TRY(hipMemcpyAsync(M->h_s, M->s, sizeof(Scalars), hipMemcpyDeviceToHost, M->stream));
-    HIP_TRY(hipStreamSynchronize(M->stream));
-    return FEM_OK;
-}
+inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+inline int pad8(int x) { return (x + 7) & ~7; }
+bool is_finite(double x) { return std::isfinite(x); }
 
 int launch_check(const char *what) {
     hipError_t e = hipGetLastError();
@@ -139,301 +56,795 @@ int launch_check(const char *what) {
     return FEM_OK;
 }
 
-// Element + contact pass at u + alpha dx; with_grad also rebuilds g, the node
-// diagonal blocks and the Hessian caches.
-template <typename T>
-int element_pass(fem_mesh *M, T alpha, bool with_grad, int contact_full) {
-    Buffers<T> b = views<T>(M);
-    if (with_grad) {
-        HIP_TRY(hipMemsetAsync(M->g, 0, 3 * (size_t)M->n * sizeof(T), M->stream));
-        HIP_TRY(hipMemsetAsync(M->diag, 0, 6 * (size_t)M->n * sizeof(T), M->stream));
+// Sub-allocations of one device allocation, 256-byte aligned.
+struct Arena {
+    size_t off = 0;
+    template <typename T>
+    size_t take(size_t count) {
+        size_t at = (off + 255) & ~size_t(255);
+        off = at + std::max<size_t>(count, 1) * sizeof(T);
+        return at;
     }
-    const int tb = nblocks(M->m), cb = nblocks(M->nc);
-    k_element_pass<T><<<tb + cb, kBlock, 0, M->stream>>>(b, alpha, with_grad ? 1 : 0, contact_full, tb);
-    return launch_check("k_element_pass");
-}
-
-template <typename T>
-int newton_init(fem_mesh *M, int block_jacobi) {
-    k_newton_init<T><<<nblocks(M->n), kBlock, 0, M->stream>>>(views<T>(M), block_jacobi);
-    return launch_check("k_newton_init");
-}
-
-struct Control {
-    double tol2;
-    int max_it;
 };
 
-// Runs CG on H dx = -g from dx = 0 until its device-side state leaves
-// kRunning. Iterations are enqueued in chunks sized from the previous solve;
-// a chunk whose iterations find the state already stopped exits at once.
-template <typename T>
-int run_cg(fem_mesh *M, double tol2, int max_it, int *iters, int *hv) {
-    Buffers<T> b = views<T>(M);
-    // Host-written CG controls (tolerance, cap) live in Scalars.
-    Control *ctl = (Control *)M->h_stage;
-    ctl->tol2 = tol2;
-    ctl->max_it = max_it;
-    HIP_TRY(hipMemcpyAsync(&M->s->tol2, &ctl->tol2, sizeof(double), hipMemcpyHostToDevice, M->stream));
-    HIP_TRY(hipMemcpyAsync(&M->s->max_it, &ctl->max_it, sizeof(int), hipMemcpyHostToDevice, M->stream));
-    const int tb = nblocks(M->m), cb = nblocks(M->nc), nb = nblocks(M->n);
-    int launched = 0;
-    int chunk = std::max(8, (M->last_cg * 3) / 4);
-    for (;;) {
-        const int todo = std::min(chunk, max_it + 1 - launched);
-        for (int k = 0; k < todo; k++) {
-            k_cg_hv<T><<<tb + cb, kBlock, 0, M->stream>>>(b, tb, 0);
-            k_cg_update<T><<<nb, kBlock, 0, M->stream>>>(b);
-        }
-        launched += todo;
-        int rc = launch_check("cg");
-        if (rc) return rc;
-        rc = fetch_scalars(M);
-        if (rc) return rc;
-        if (M->h_s->state != kRunning || launched > max_it) break;
-        chunk = 16;
-    }
-    *iters = M->h_s->it;
-    *hv = M->h_s->nhv;
-    M->last_cg = M->h_s->it;
-    return FEM_OK;
+// ---------------------------------------------------------------------------
+// Tiled layout of one mesh (host construction).
+// ---------------------------------------------------------------------------
+struct HostLayout {
+    int n = 0, m = 0, ntile = 0, nent = 0;
+    std::vector<int> tile_tet, tile_ent, ent_node, node_ent_off, node_ent;
+    std::vector<double> ent_x;   // nent x 3, relative to the tile's mean entry position
+    std::vector<uint32_t> tet_loc;
+};
+
+uint32_t spread_bits(uint32_t v) {   // 10 bits -> every third bit
+    v &= 0x3ff;
+    v = (v | (v << 16)) & 0x030000ff;
+    v = (v | (v << 8)) & 0x0300f00f;
+    v = (v | (v << 4)) & 0x030c30c3;
+    v = (v | (v << 2)) & 0x09249249;
+    return v;
 }
 
-template <typename T>
-int step_impl(fem_mesh *M, const fem_solve_params &P, fem_step_info &info) {
-    const double eps = std::numeric_limits<T>::epsilon();
-    const int contact_full = P.contact_hessian ? 1 : 0;
-    int rc;
-    if ((rc = element_pass<T>(M, (T)0, true, contact_full))) return rc;
-    if ((rc = newton_init<T>(M, P.precond == FEM_PRECOND_BLOCK))) return rc;
-    if ((rc = fetch_scalars(M))) return rc;
-    info.grad_passes = 1;
-    double E = M->h_s->energy, mag = M->h_s->emag, minJ = M->h_s->minJ;
-    double gn = std::sqrt(M->h_s->gg);
-    const double r0 = gn;
-    info.g0_norm = gn;
-    int status = FEM_E_NOT_CONVERGED;
-    for (int it = 0;; it++) {
-        if (gn <= std::max(P.newton_rtol * r0, P.newton_atol)) {
-            status = FEM_OK;
-            break;
+// Tets in Morton order of their centroids, cut greedily into tiles of at most
+// kTileTets tets and kTileNodes distinct nodes.
+void build_layout(const double *X, int n, const int32_t *tets, int m, HostLayout &L) {
+    L.n = n;
+    L.m = m;
+    double lo[3] = {X[0], X[1], X[2]}, hi[3] = {X[0], X[1], X[2]};
+    for (int i = 0; i < n; i++)
+        for (int d = 0; d < 3; d++) {
+            lo[d] = std::min(lo[d], X[3 * i + d]);
+            hi[d] = std::max(hi[d], X[3 * i + d]);
         }
-        if (it == P.max_newton) {
-            status = FEM_E_NOT_CONVERGED;
-            break;
+    double ext = 0.0;
+    for (int d = 0; d < 3; d++) ext = std::max(ext, hi[d] - lo[d]);
+    if (!(ext > 0.0)) ext = 1.0;
+    std::vector<std::pair<uint32_t, int>> key(m);
+    for (int e = 0; e < m; e++) {
+        uint32_t code = 0;
+        for (int d = 0; d < 3; d++) {
+            double c = 0.0;
+            for (int a = 0; a < 4; a++) c += X[3 * tets[4 * e + a] + d];
+            c = 0.25 * c;
+            int q = (int)((c - lo[d]) / ext * 1023.0);
+            q = std::max(0, std::min(1023, q));
+            code |= spread_bits((uint32_t)q) << d;
         }
-        double eta = std::min(P.cg_eta_max, std::max(P.cg_rtol, gn / r0));
-        int cg_it = 0, hv = 0;
-        if ((rc = run_cg<T>(M, eta * eta * gn * gn, P.max_cg, &cg_it, &hv))) return rc;
-        info.cg_iters += cg_it;
-        info.hv_products += hv;
-        k_dot_gdx<T><<<nblocks(M->n), kBlock, 0, M->stream>>>(views<T>(M));
-        if ((rc = launch_check("k_dot_gdx"))) return rc;
-        double gd = 0.0;
-        bool accepted = false, have_gd = false;
-        double alpha = 1.0;
-        double Et = 0.0, magt = 0.0, mjt = 0.0;
-        for (int h = 0; h <= P.max_halvings; h++) {
-            if ((rc = element_pass<T>(M, (T)alpha, true, contact_full))) return rc;
-            if ((rc = fetch_scalars(M))) return rc;
-            if (!have_gd) {
-                gd = M->h_s->gd;
-                have_gd = true;
+        key[e] = {code, e};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<int> stamp(n, -1), local(n, 0);
+    L.tile_tet.assign(1, 0);
+    L.tile_ent.assign(1, 0);
+    L.ent_node.clear();
+    L.ent_x.clear();
+    L.tet_loc.assign(m, 0);
+    int tile = 0, tile_tets = 0, tile_nodes = 0, pos = 0;
+    std::vector<int> tile_list;
+    auto close_tile = [&]() {
+        std::sort(tile_list.begin(), tile_list.end());   // entries in ascending node order
+        for (size_t k = 0; k < tile_list.size(); k++) local[tile_list[k]] = (int)k;
+        for (int k = L.tile_tet.back(); k < pos; k++) {
+            const int e = key[k].second;
+            uint32_t w = 0;
+            for (int a = 0; a < 4; a++) w |= (uint32_t)local[tets[4 * e + a]] << (8 * a);
+            L.tet_loc[k] = w;
+        }
+        double ctr[3] = {0.0, 0.0, 0.0};
+        for (int v : tile_list)
+            for (int d = 0; d < 3; d++) ctr[d] += X[3 * v + d];
+        for (int d = 0; d < 3; d++) ctr[d] /= (double)tile_list.size();
+        for (int v : tile_list) {
+            L.ent_node.push_back(v);
+            for (int d = 0; d < 3; d++) L.ent_x.push_back(X[3 * v + d] - ctr[d]);
+        }
+        L.tile_tet.push_back(pos);
+        L.tile_ent.push_back((int)L.ent_node.size());
+        tile++;
+        tile_tets = 0;
+        tile_nodes = 0;
+        tile_list.clear();
+    };
+    for (int k = 0; k < m; k++) {
+        const int e = key[k].second;
+        int fresh = 0;
+        for (int a = 0; a < 4; a++) {
+            const int v = tets[4 * e + a];
+            if (stamp[v] != tile) fresh++;
+        }
+        if (tile_tets == kTileTets || tile_nodes + fresh > kTileNodes) close_tile();
+        for (int a = 0; a < 4; a++) {
+            const int v = tets[4 * e + a];
+            if (stamp[v] != tile) {
+                stamp[v] = tile;
+                tile_list.push_back(v);
+                tile_nodes++;
             }
-            info.grad_passes++;
-            info.ls_trials++;
-            Et = M->h_s->energy;
-            magt = M->h_s->emag;
-            mjt = M->h_s->minJ;
-            const double noise = 16.0 * eps * mag;
-            if (mjt > 0.0 && Et <= E + P.c1 * alpha * gd + noise) {
-                accepted = true;
-                break;
-            }
-            alpha *= 0.5;
         }
-        if (!accepted) {
-            status = mjt > 0.0 ? FEM_E_NOT_CONVERGED : FEM_E_INVERSION;
-            break;
+        tile_tets++;
+        pos++;
+    }
+    if (tile_tets > 0) close_tile();
+    L.ntile = tile;
+    L.nent = (int)L.ent_node.size();
+    L.node_ent_off.assign(n + 1, 0);
+    for (int v : L.ent_node) L.node_ent_off[v + 1]++;
+    for (int i = 0; i < n; i++) L.node_ent_off[i + 1] += L.node_ent_off[i];
+    L.node_ent.assign(L.nent, 0);
+    std::vector<int> fill(n, 0);
+    for (int q = 0; q < L.nent; q++) {
+        const int v = L.ent_node[q];
+        L.node_ent[L.node_ent_off[v] + fill[v]++] = q;
+    }
+}
+
+// HIP events around every `every`-th launch of the timed kernels, harvested
+// after stream synchronisations.
+struct KernelTimer {
+    static constexpr int kKinds = 3, kPool = 512;
+    int every = 0;
+    long long seen[kKinds] = {0, 0, 0};
+    long long count[kKinds] = {0, 0, 0};
+    double total_ms[kKinds] = {0, 0, 0};
+    hipEvent_t ev[kPool][2] = {};
+    int kind_of[kPool] = {};
+    int used = 0;
+    bool created = false;
+};
+
+struct TopoRec {
+    int n = 0, m = 0, ntile = 0, nent = 0, nc = 0, ncb = 0;
+    void *arena = nullptr;
+    uint8_t *elig = nullptr;   // device, n
+    Topo<float> v32{};
+    Topo<double> v64{};
+};
+
+struct InstRec {
+    bool live = false;
+    int topo = -1;
+    void *arena = nullptr;
+    InstBufs<float> b32{};
+    InstBufs<double> b64{};
+};
+
+}  // namespace
+
+struct fem_batch {
+    int precision = FEM_PREC_FP64;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int capacity = 0;
+    std::vector<TopoRec> topos;
+    std::vector<InstRec> insts;     // size capacity
+    InstState *d_states = nullptr;
+    InstState *h_states = nullptr;  // pinned mirror
+    void *d_topos = nullptr, *d_bufs = nullptr;
+    int2 *d_work_tile = nullptr, *d_work_node = nullptr;
+    int nwork_tile = 0, nwork_node = 0, cap_work_tile = 0, cap_work_node = 0;
+    SolveParams *d_params = nullptr;
+    SolveParams *h_params = nullptr;
+    bool tables_dirty = true;
+    void *patch = nullptr;
+    size_t patch_bytes = 0;
+    void *h_stage = nullptr;
+    size_t h_stage_bytes = 0;
+    KernelTimer timer;
+    size_t elem() const { return precision == FEM_PREC_FP32 ? sizeof(float) : sizeof(double); }
+};
+
+struct fem_mesh {
+    fem_batch *batch = nullptr;
+    int n = 0, m = 0;
+    bool have_material = false, have_indenter = false;
+    double E = 0, nu = 0, density = 0;
+    Indenter ind{};
+};
+
+namespace {
+
+int set_device(const fem_batch *B) {
+    HIP_TRY(hipSetDevice(B->device));
+    return FEM_OK;
+}
+
+int stage(fem_batch *B, size_t bytes) {
+    if (B->h_stage_bytes >= bytes) return FEM_OK;
+    if (B->h_stage) (void)hipHostFree(B->h_stage);
+    B->h_stage = nullptr;
+    B->h_stage_bytes = 0;
+    HIP_TRY(hipHostMalloc(&B->h_stage, bytes));
+    B->h_stage_bytes = bytes;
+    return FEM_OK;
+}
+
+int timer_begin(fem_batch *B, int kind) {
+    KernelTimer &t = B->timer;
+    if (t.every <= 0) return -1;
+    if ((t.seen[kind]++ % t.every) != 0 || t.used >= KernelTimer::kPool) return -1;
+    const int slot = t.used++;
+    t.kind_of[slot] = kind;
+    if (hipEventRecord(t.ev[slot][0], B->stream) != hipSuccess) return -1;
+    return slot;
+}
+
+void timer_end(fem_batch *B, int slot) {
+    if (slot >= 0) (void)hipEventRecord(B->timer.ev[slot][1], B->stream);
+}
+
+void timer_harvest(fem_batch *B) {
+    KernelTimer &t = B->timer;
+    for (int i = 0; i < t.used; i++) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, t.ev[i][0], t.ev[i][1]) == hipSuccess) {
+            t.count[t.kind_of[i]]++;
+            t.total_ms[t.kind_of[i]] += ms;
         }
-        k_axpy<T><<<nblocks(3LL * M->n), kBlock, 0, M->stream>>>((T *)M->u, (const T *)M->dx, (T)alpha, 3 * M->n);
-        if ((rc = launch_check("k_axpy"))) return rc;
-        if ((rc = newton_init<T>(M, P.precond == FEM_PRECOND_BLOCK))) return rc;
-        if ((rc = fetch_scalars(M))) return rc;
-        E = Et;
-        mag = magt;
-        minJ = mjt;
-        gn = std::sqrt(M->h_s->gg);
-        info.newton_iters++;
     }
-    info.status = status;
-    info.g_norm = gn;
-    info.energy = E;
-    info.min_J = minJ;
-    info.tet_updates = (int64_t)M->m * (int64_t)(info.grad_passes + info.hv_products);
-    if (status == FEM_E_NOT_CONVERGED) g_last_error = "Newton did not converge";
-    if (status == FEM_E_INVERSION) g_last_error = "line search could not keep det F > 0";
-    return status;
+    t.used = 0;
 }
 
-bool is_finite(double x) { return std::isfinite(x); }
-
-int stage(fem_mesh *M, size_t bytes) {
-    if (M->h_stage_bytes >= bytes) return FEM_OK;
-    if (M->h_stage) (void)hipHostFree(M->h_stage);
-    M->h_stage = nullptr;
-    M->h_stage_bytes = 0;
-    HIP_TRY(hipHostMalloc(&M->h_stage, bytes));
-    M->h_stage_bytes = bytes;
+int sync(fem_batch *B) {
+    HIP_TRY(hipStreamSynchronize(B->stream));
+    if (B->timer.used) timer_harvest(B);
     return FEM_OK;
 }
 
-// Copies a host double array of len values into a device array of the mesh's
-// precision (through the pinned staging buffer).
-int upload_real(fem_mesh *M, void *dst, const double *src, size_t len) {
-    int rc = stage(M, std::max<size_t>(len * 8, 64));
-    if (rc) return rc;
-    if (M->precision == FEM_PREC_FP32) {
-        float *h = (float *)M->h_stage;
-        for (size_t i = 0; i < len; i++) h[i] = (float)src[i];
-    } else {
-        std::memcpy(M->h_stage, src, len * sizeof(double));
-    }
-    HIP_TRY(hipMemcpyAsync(dst, M->h_stage, len * M->elem(), hipMemcpyHostToDevice, M->stream));
-    HIP_TRY(hipStreamSynchronize(M->stream));
-    return FEM_OK;
-}
-
-int download_real(const fem_mesh *Mc, double *dst, const void *src, size_t len) {
-    fem_mesh *M = const_cast<fem_mesh *>(Mc);
-    int rc = stage(M, std::max<size_t>(len * 8, 64));
-    if (rc) return rc;
-    HIP_TRY(hipMemcpyAsync(M->h_stage, src, len * M->elem(), hipMemcpyDeviceToHost, M->stream));
-    HIP_TRY(hipStreamSynchronize(M->stream));
-    if (M->precision == FEM_PREC_FP32) {
-        const float *h = (const float *)M->h_stage;
-        for (size_t i = 0; i < len; i++) dst[i] = (double)h[i];
-    } else {
-        std::memcpy(dst, M->h_stage, len * sizeof(double));
-    }
-    return FEM_OK;
-}
+// ---------------------------------------------------------------------------
+// Mesh upload: layout, rest volume check, contact-eligible nodes.
+// ---------------------------------------------------------------------------
+template <typename T> Topo<T> &topo_view(TopoRec &R);
+template <> Topo<float> &topo_view<float>(TopoRec &R) { return R.v32; }
+template <> Topo<double> &topo_view<double>(TopoRec &R) { return R.v64; }
 
 template <typename T>
-int create_impl(fem_mesh *M, const double *X, const int32_t *tets, const uint8_t *fixed) {
-    const int n = M->n, m = M->m;
-    // Hash table for boundary faces: power of two >= 8 m slots.
+int add_topology(fem_batch *B, const double *X, int n, const int32_t *tets, int m, const uint8_t *fixed, int *id) {
+    HostLayout L;
+    build_layout(X, n, tets, m, L);
+    TopoRec R;
+    R.n = n;
+    R.m = m;
+    R.ntile = L.ntile;
+    R.nent = L.nent;
+    Arena A;
+    const size_t o_tile_tet = A.take<int>(L.ntile + 1), o_tile_ent = A.take<int>(L.ntile + 1);
+    const size_t o_ent_node = A.take<int>(L.nent), o_ent_x = A.take<T>(3 * (size_t)L.nent);
+    const size_t o_loc = A.take<uint32_t>(m), o_neo = A.take<int>(n + 1), o_ne = A.take<int>(L.nent);
+    const size_t o_fixed = A.take<uint8_t>(n), o_cn = A.take<int>(n), o_cidx = A.take<int>(n);
+    const size_t o_X = A.take<double>(3 * (size_t)n), o_elig = A.take<uint8_t>(n);
+    HIP_TRY(hipMalloc(&R.arena, A.off));
+    char *base = (char *)R.arena;
+    std::vector<T> ex(L.ent_x.size());
+    for (size_t k = 0; k < ex.size(); k++) ex[k] = (T)L.ent_x[k];
+    auto up = [&](size_t off, const void *src, size_t bytes) -> int {
+        HIP_TRY(hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice, B->stream));
+        return FEM_OK;
+    };
+    int rc = FEM_OK;
+    if (!rc) rc = up(o_tile_tet, L.tile_tet.data(), L.tile_tet.size() * sizeof(int));
+    if (!rc) rc = up(o_tile_ent, L.tile_ent.data(), L.tile_ent.size() * sizeof(int));
+    if (!rc) rc = up(o_ent_node, L.ent_node.data(), L.ent_node.size() * sizeof(int));
+    if (!rc) rc = up(o_ent_x, ex.data(), ex.size() * sizeof(T));
+    if (!rc) rc = up(o_loc, L.tet_loc.data(), L.tet_loc.size() * sizeof(uint32_t));
+    if (!rc) rc = up(o_neo, L.node_ent_off.data(), L.node_ent_off.size() * sizeof(int));
+    if (!rc) rc = up(o_ne, L.node_ent.data(), L.node_ent.size() * sizeof(int));
+    if (!rc) rc = up(o_fixed, fixed, n);
+    if (!rc) rc = up(o_X, X, 3 * (size_t)n * sizeof(double));
+    // Rest volumes and boundary faces from the original connectivity.
     unsigned slots = 1;
     while (slots < 8u * (unsigned)m) slots <<= 1;
-    Arena A;
-    const size_t o_tet = A.take<int>(4 * (size_t)m);
-    const size_t o_B = A.take<T>(9 * (size_t)m);
-    const size_t o_vol = A.take<T>(m);
-    const size_t o_X = A.take<double>(3 * (size_t)n);
-    const size_t o_fixed = A.take<uint8_t>(n);
-    const size_t o_elig = A.take<uint8_t>(n);
-    const size_t o_cn = A.take<int>(n);
-    size_t o_vec[7];
-    for (int k = 0; k < 7; k++) o_vec[k] = A.take<T>(3 * (size_t)n);
-    const size_t o_diag = A.take<T>(6 * (size_t)n);
-    const size_t o_dinv = A.take<T>(6 * (size_t)n);
-    const size_t o_finv = A.take<T>(9 * (size_t)m);
-    const size_t o_c1 = A.take<T>(m);
-    const size_t o_chess = A.take<T>(6 * (size_t)n);
-    const size_t o_part = A.take<double>(4 * (size_t)kMaxPartials);
-    const size_t o_ticket = A.take<unsigned>(kTicketCount + 8);
-    const size_t o_s = A.take<Scalars>(1);
-    const size_t o_pid = A.take<int>(n);
-    const size_t o_pcount = A.take<int>(1);
-    const size_t o_pf = A.take<double>(3 * (size_t)n);
-    const size_t o_pphi = A.take<double>(n);
-    const size_t o_pF = A.take<double>(3);
-    const size_t o_bad = A.take<int>(1);
-    M->arena_bytes = A.off;
-    HIP_TRY(hipMalloc(&M->arena, M->arena_bytes));
-    char *base = (char *)M->arena;
-    HIP_TRY(hipMemsetAsync(M->arena, 0, M->arena_bytes, M->stream));
-    M->tet = (int *)(base + o_tet);
-    M->B = base + o_B;
-    M->vol = base + o_vol;
-    M->X = (double *)(base + o_X);
-    M->fixed = (uint8_t *)(base + o_fixed);
-    M->eligible = (uint8_t *)(base + o_elig);
-    M->cnodes = (int *)(base + o_cn);
-    void **vecs[7] = {&M->u, &M->dx, &M->g, &M->r, &M->z, &M->p, &M->q};
-    for (int k = 0; k < 7; k++) *vecs[k] = base + o_vec[k];
-    M->diag = base + o_diag;
-    M->dinv = base + o_dinv;
-    M->finv = base + o_finv;
-    M->c1 = base + o_c1;
-    M->chess = base + o_chess;
-    M->partial = (double *)(base + o_part);
-    M->ticket = (unsigned *)(base + o_ticket);
-    M->s = (Scalars *)(base + o_s);
-    M->patch_ids = (int *)(base + o_pid);
-    M->patch_count = (int *)(base + o_pcount);
-    M->patch_f = (double *)(base + o_pf);
-    M->patch_phi = (double *)(base + o_pphi);
-    M->patch_F = (double *)(base + o_pF);
-    int *bad = (int *)(base + o_bad);
-
-    // Upload: X as is; tets transposed to field-major; fixed flags.
-    std::vector<int> tT(4 * (size_t)m);
-    for (int e = 0; e < m; e++)
-        for (int a = 0; a < 4; a++) tT[(size_t)a * m + e] = tets[4 * (size_t)e + a];
-    HIP_TRY(hipMemcpyAsync(M->X, X, 3 * (size_t)n * sizeof(double), hipMemcpyHostToDevice, M->stream));
-    HIP_TRY(hipMemcpyAsync(M->tet, tT.data(), tT.size() * sizeof(int), hipMemcpyHostToDevice, M->stream));
-    HIP_TRY(hipMemcpyAsync(M->fixed, fixed, n, hipMemcpyHostToDevice, M->stream));
-    const int big = 0x7fffffff;
-    HIP_TRY(hipMemcpyAsync(bad, &big, sizeof(int), hipMemcpyHostToDevice, M->stream));
-    k_precompute<T><<<nblocks(m), kBlock, 0, M->stream>>>(M->X, M->tet, m, (T *)M->B, (T *)M->vol, bad);
-    int rc = launch_check("k_precompute");
-    if (rc) return rc;
-    // Boundary faces -> surface nodes -> contact-eligible list.
+    int *d_tets = nullptr, *d_scalar = nullptr;
     unsigned long long *keys = nullptr;
     unsigned *cnt = nullptr;
     uint8_t *surf = nullptr;
-    HIP_TRY(hipMalloc(&keys, slots * sizeof(unsigned long long)));
-    HIP_TRY(hipMalloc(&cnt, slots * sizeof(unsigned)));
-    HIP_TRY(hipMalloc(&surf, n));
-    HIP_TRY(hipMemsetAsync(keys, 0xff, slots * sizeof(unsigned long long), M->stream));
-    HIP_TRY(hipMemsetAsync(cnt, 0, slots * sizeof(unsigned), M->stream));
-    HIP_TRY(hipMemsetAsync(surf, 0, n, M->stream));
-    k_faces_insert<<<nblocks(4LL * m), kBlock, 0, M->stream>>>(M->tet, m, keys, cnt, slots - 1);
-    k_faces_mark<<<nblocks(4LL * m), kBlock, 0, M->stream>>>(M->tet, m, keys, cnt, slots - 1, surf);
-    k_compact_eligible<<<1, 1024, 0, M->stream>>>(surf, M->fixed, n, M->eligible, M->cnodes, M->patch_count);
-    rc = launch_check("mesh topology");
-    if (rc) return rc;
-    int host[2];
-    HIP_TRY(hipMemcpyAsync(&host[0], bad, sizeof(int), hipMemcpyDeviceToHost, M->stream));
-    HIP_TRY(hipMemcpyAsync(&host[1], M->patch_count, sizeof(int), hipMemcpyDeviceToHost, M->stream));
-    HIP_TRY(hipStreamSynchronize(M->stream));
-    (void)hipFree(keys);
-    (void)hipFree(cnt);
-    (void)hipFree(surf);
-    if (host[0] != big) return fail(FEM_E_DEGENERATE, "tet " + std::to_string(host[0]) + " has rest volume <= 0");
-    M->nc = host[1];
+    const int big = 0x7fffffff;
+    if (!rc && (hipMalloc(&d_tets, 4 * (size_t)m * sizeof(int)) != hipSuccess || hipMalloc(&d_scalar, 2 * sizeof(int)) != hipSuccess ||
+                hipMalloc(&keys, slots * sizeof(unsigned long long)) != hipSuccess ||
+                hipMalloc(&cnt, slots * sizeof(unsigned)) != hipSuccess || hipMalloc(&surf, n) != hipSuccess))
+        rc = fail(FEM_E_OOM, "set-up scratch allocation failed");
+    if (!rc && (hipMemcpyAsync(d_tets, tets, 4 * (size_t)m * sizeof(int), hipMemcpyHostToDevice, B->stream) != hipSuccess ||
+                hipMemcpyAsync(d_scalar, &big, sizeof(int), hipMemcpyHostToDevice, B->stream) != hipSuccess ||
+                hipMemsetAsync(keys, 0xff, slots * sizeof(unsigned long long), B->stream) != hipSuccess ||
+                hipMemsetAsync(cnt, 0, slots * sizeof(unsigned), B->stream) != hipSuccess ||
+                hipMemsetAsync(surf, 0, n, B->stream) != hipSuccess))
+        rc = fail(FEM_E_DEVICE, "set-up copies failed");
+    int host[2] = {0, 0};
+    if (!rc) {
+        k_check_volumes<<<ceil_div(m, kBlock), kBlock, 0, B->stream>>>((const double *)(base + o_X), d_tets, m, d_scalar);
+        k_faces_insert<<<ceil_div(4LL * m, kBlock), kBlock, 0, B->stream>>>(d_tets, m, keys, cnt, slots - 1);
+        k_faces_mark<<<ceil_div(4LL * m, kBlock), kBlock, 0, B->stream>>>(d_tets, m, keys, cnt, slots - 1, surf);
+        k_compact_eligible<<<1, 1024, 0, B->stream>>>(surf, (const uint8_t *)(base + o_fixed), n,
+                                                      (uint8_t *)(base + o_elig), (int *)(base + o_cn),
+                                                      (int *)(base + o_cidx), d_scalar + 1);
+        rc = launch_check("mesh set-up");
+    }
+    if (!rc && hipMemcpyAsync(host, d_scalar, sizeof host, hipMemcpyDeviceToHost, B->stream) != hipSuccess)
+        rc = fail(FEM_E_DEVICE, "copy");
+    if (!rc && hipStreamSynchronize(B->stream) != hipSuccess) rc = fail(FEM_E_DEVICE, "mesh set-up failed");
+    (void)hipStreamSynchronize(B->stream);
+    if (d_tets) (void)hipFree(d_tets);
+    if (d_scalar) (void)hipFree(d_scalar);
+    if (keys) (void)hipFree(keys);
+    if (cnt) (void)hipFree(cnt);
+    if (surf) (void)hipFree(surf);
+    if (!rc && host[0] != big) rc = fail(FEM_E_DEGENERATE, "tet " + std::to_string(host[0]) + " has rest volume <= 0");
+    if (rc) {
+        (void)hipFree(R.arena);
+        return rc;
+    }
+    R.nc = host[1];
+    R.ncb = ceil_div(R.nc, kBlock);
+    R.elig = (uint8_t *)(base + o_elig);
+    Topo<T> &v = topo_view<T>(R);
+    v.n = n;
+    v.m = m;
+    v.ntile = L.ntile;
+    v.nent = L.nent;
+    v.nc = R.nc;
+    v.ncb = R.ncb;
+    v.tile_tet = (const int *)(base + o_tile_tet);
+    v.tile_ent = (const int *)(base + o_tile_ent);
+    v.ent_node = (const int *)(base + o_ent_node);
+    v.ent_x = (const T *)(base + o_ent_x);
+    v.tet_loc = (const uint32_t *)(base + o_loc);
+    v.node_ent_off = (const int *)(base + o_neo);
+    v.node_ent = (const int *)(base + o_ne);
+    v.fixed = (const uint8_t *)(base + o_fixed);
+    v.cnodes = (const int *)(base + o_cn);
+    v.cidx = (const int *)(base + o_cidx);
+    v.X = (const double *)(base + o_X);
+    B->topos.push_back(R);
+    B->tables_dirty = true;
+    *id = (int)B->topos.size() - 1;
     return FEM_OK;
 }
 
-void release(fem_mesh *M) {
-    if (!M) return;
-    (void)hipSetDevice(M->device);
-    if (M->stream) (void)hipStreamSynchronize(M->stream);
-    if (M->arena) (void)hipFree(M->arena);
-    if (M->h_s) (void)hipHostFree(M->h_s);
-    if (M->h_stage) (void)hipHostFree(M->h_stage);
-    if (M->own_stream && M->stream) (void)hipStreamDestroy(M->stream);
-    delete M;
+// ---------------------------------------------------------------------------
+// Instances
+// ---------------------------------------------------------------------------
+template <typename T> InstBufs<T> &inst_view(InstRec &R);
+template <> InstBufs<float> &inst_view<float>(InstRec &R) { return R.b32; }
+template <> InstBufs<double> &inst_view<double>(InstRec &R) { return R.b64; }
+
+template <typename T>
+int alloc_instance(fem_batch *B, int slot, int topo) {
+    const TopoRec &tp = B->topos[topo];
+    const int n = tp.n;
+    const int stride = std::max(tp.ntile + tp.ncb, ceil_div(n, kBlock));
+    Arena A;
+    size_t o[7];
+    for (int k = 0; k < 6; k++) o[k] = A.take<T>(3 * (size_t)n);
+    o[6] = A.take<T>(6 * (size_t)n);
+    const size_t o_pg = A.take<T>(9 * (size_t)tp.nent), o_pq = A.take<T>(3 * (size_t)tp.nent);
+    const size_t o_cp = A.take<T>(9 * (size_t)std::max(tp.nc, 1)), o_q = A.take<T>(3 * (size_t)n);
+    const size_t o_red = A.take<double>(3 * (size_t)stride);
+    InstRec &R = B->insts[slot];
+    HIP_TRY(hipMalloc(&R.arena, A.off));
+    HIP_TRY(hipMemsetAsync(R.arena, 0, A.off, B->stream));
+    char *base = (char *)R.arena;
+    InstBufs<T> &b = inst_view<T>(R);
+    b.topo = topo;
+    b.red_stride = stride;
+    T **vec[6] = {&b.u, &b.dx, &b.g, &b.r, &b.z, &b.p};
+    for (int k = 0; k < 6; k++) *vec[k] = (T *)(base + o[k]);
+    b.dinv = (T *)(base + o[6]);
+    b.pg = (T *)(base + o_pg);
+    b.pq = (T *)(base + o_pq);
+    b.cp = (T *)(base + o_cp);
+    b.qout = (T *)(base + o_q);
+    b.red = (double *)(base + o_red);
+    b.s = B->d_states + slot;
+    R.topo = topo;
+    R.live = true;
+    B->tables_dirty = true;
+    return FEM_OK;
+}
+
+void free_instance(fem_batch *B, int slot) {
+    InstRec &R = B->insts[slot];
+    if (R.arena) (void)hipFree(R.arena);
+    R = InstRec();
+    B->tables_dirty = true;
+}
+
+// Work tables: tile (+ contact) blocks and node blocks of every live
+// instance, ordered tile-major so one tile of consecutive instances is
+// processed back to back (on one XCD, see logical_block()).
+template <typename T>
+int rebuild_tables(fem_batch *B) {
+    std::vector<int2> wt, wn;
+    int max_t = 0, max_nb = 0;
+    for (const InstRec &R : B->insts)
+        if (R.live) {
+            const TopoRec &tp = B->topos[R.topo];
+            max_t = std::max(max_t, tp.ntile + tp.ncb);
+            max_nb = std::max(max_nb, ceil_div(tp.n, kBlock));
+        }
+    for (int t = 0; t < max_t; t++)
+        for (int i = 0; i < B->capacity; i++) {
+            const InstRec &R = B->insts[i];
+            if (R.live && t < B->topos[R.topo].ntile + B->topos[R.topo].ncb) wt.push_back(make_int2(i, t));
+        }
+    for (int t = 0; t < max_nb; t++)
+        for (int i = 0; i < B->capacity; i++) {
+            const InstRec &R = B->insts[i];
+            if (R.live && t < ceil_div(B->topos[R.topo].n, kBlock)) wn.push_back(make_int2(i, t));
+        }
+    auto upload = [&](const std::vector<int2> &v, int2 *&d, int &cap, int &count) -> int {
+        if ((int)v.size() > cap) {
+            if (d) (void)hipFree(d);
+            d = nullptr;
+            cap = std::max<int>((int)v.size(), 64);
+            HIP_TRY(hipMalloc(&d, cap * sizeof(int2)));
+        }
+        if (!v.empty()) HIP_TRY(hipMemcpyAsync(d, v.data(), v.size() * sizeof(int2), hipMemcpyHostToDevice, B->stream));
+        count = (int)v.size();
+        return FEM_OK;
+    };
+    TRY(upload(wt, B->d_work_tile, B->cap_work_tile, B->nwork_tile));
+    TRY(upload(wn, B->d_work_node, B->cap_work_node, B->nwork_node));
+    std::vector<Topo<T>> tv;
+    for (TopoRec &R : B->topos) tv.push_back(topo_view<T>(R));
+    TRY(sync(B));
+    if (B->d_topos) (void)hipFree(B->d_topos);
+    B->d_topos = nullptr;
+    HIP_TRY(hipMalloc(&B->d_topos, std::max<size_t>(tv.size(), 1) * sizeof(Topo<T>)));
+    if (!tv.empty())
+        HIP_TRY(hipMemcpyAsync(B->d_topos, tv.data(), tv.size() * sizeof(Topo<T>), hipMemcpyHostToDevice, B->stream));
+    std::vector<InstBufs<T>> bv(B->capacity);
+    for (int i = 0; i < B->capacity; i++) bv[i] = inst_view<T>(B->insts[i]);
+    HIP_TRY(hipMemcpyAsync(B->d_bufs, bv.data(), bv.size() * sizeof(InstBufs<T>), hipMemcpyHostToDevice, B->stream));
+    TRY(sync(B));
+    B->tables_dirty = false;
+    return FEM_OK;
+}
+
+int params_to_device(fem_batch *B, const fem_solve_params &P) {
+    SolveParams &d = *B->h_params;
+    d.newton_rtol = P.newton_rtol;
+    d.newton_atol = P.newton_atol;
+    d.cg_rtol = P.cg_rtol;
+    d.cg_eta_max = P.cg_eta_max;
+    d.c1 = P.c1;
+    d.noise_eps = 16.0 * (B->precision == FEM_PREC_FP32 ? (double)std::numeric_limits<float>::epsilon()
+                                                        : std::numeric_limits<double>::epsilon());
+    d.max_newton = P.max_newton;
+    d.max_cg = P.max_cg;
+    d.block_jacobi = P.precond == FEM_PRECOND_BLOCK ? 1 : 0;
+    d.contact_full = P.contact_hessian ? 1 : 0;
+    d.max_halvings = P.max_halvings;
+    HIP_TRY(hipMemcpyAsync(B->d_params, B->h_params, sizeof(SolveParams), hipMemcpyHostToDevice, B->stream));
+    return sync(B);
+}
+
+int read_states(fem_batch *B) {
+    HIP_TRY(hipMemcpyAsync(B->h_states, B->d_states, B->capacity * sizeof(InstState), hipMemcpyDeviceToHost, B->stream));
+    return sync(B);
+}
+
+int write_state(fem_batch *B, int slot) {
+    HIP_TRY(hipMemcpyAsync(B->d_states + slot, B->h_states + slot, sizeof(InstState), hipMemcpyHostToDevice, B->stream));
+    return sync(B);
+}
+
+inline bool running_phase(int ph) { return ph != PH_IDLE && ph != PH_DONE; }
+
+// One round: (Hv, update) x C, dot, element pass, init.
+template <typename T>
+int launch_round(fem_batch *B, int chunk) {
+    const Topo<T> *tp = (const Topo<T> *)B->d_topos;
+    const InstBufs<T> *bf = (const InstBufs<T> *)B->d_bufs;
+    const int gt = pad8(B->nwork_tile), gn = pad8(B->nwork_node);
+    if (gt == 0 || gn == 0) return FEM_OK;
+    for (int c = 0; c < chunk; c++) {
+        int slot = timer_begin(B, FEM_KERNEL_HV);
+        k_hv<T><<<gt, kBlock, 0, B->stream>>>(tp, bf, B->d_work_tile, B->nwork_tile, B->d_params);
+        timer_end(B, slot);
+        slot = timer_begin(B, FEM_KERNEL_CG_UPDATE);
+        k_update<T><<<gn, kBlock, 0, B->stream>>>(tp, bf, B->d_work_node, B->nwork_node, B->d_params);
+        timer_end(B, slot);
+    }
+    k_dot<T><<<gn, kBlock, 0, B->stream>>>(tp, bf, B->d_work_node, B->nwork_node);
+    const int slot = timer_begin(B, FEM_KERNEL_ELEMENT);
+    k_elem<T><<<gt, kBlock, 0, B->stream>>>(tp, bf, B->d_work_tile, B->nwork_tile, B->d_params);
+    timer_end(B, slot);
+    k_init<T><<<gn, kBlock, 0, B->stream>>>(tp, bf, B->d_work_node, B->nwork_node, B->d_params);
+    return launch_check("round");
+}
+
+// Advances every running job until all are done or max_rounds rounds ran.
+template <typename T>
+int run_impl(fem_batch *B, int max_rounds, int *n_running) {
+    if (B->tables_dirty) TRY(rebuild_tables<T>(B));
+    int rounds = 0, running = 0;
+    TRY(read_states(B));
+    for (;;) {
+        running = 0;
+        int single = -1;
+        for (int i = 0; i < B->capacity; i++) {
+            if (!B->insts[i].live || !running_phase(B->h_states[i].phase)) continue;
+            running++;
+            single = i;
+        }
+        if (running == 0 || (max_rounds > 0 && rounds >= max_rounds)) break;
+        // CG iterations per round: a fixed 16 for batches; for one job, what
+        // its current CG solve is expected to need from the previous one.
+        int chunk = 16;
+        if (running == 1) {
+            const InstState &s = B->h_states[single];
+            const int expect = s.last_cg > 0 ? s.last_cg : 16;
+            chunk = s.phase == PH_CG ? std::max(4, std::min(64, expect - s.cg_it)) : std::max(4, std::min(64, expect));
+        }
+        TRY(launch_round<T>(B, chunk));
+        TRY(read_states(B));
+        rounds++;
+    }
+    if (n_running) *n_running = running;
+    return FEM_OK;
+}
+
+int run(fem_batch *B, int max_rounds, int *n_running) {
+    return B->precision == FEM_PREC_FP32 ? run_impl<float>(B, max_rounds, n_running)
+                                         : run_impl<double>(B, max_rounds, n_running);
+}
+
+// ---------------------------------------------------------------------------
+// Host <-> device node vectors in the batch precision
+// ---------------------------------------------------------------------------
+int upload_real(fem_batch *B, void *dst, const double *src, size_t len) {
+    TRY(stage(B, std::max<size_t>(len * 8, 64)));
+    if (B->precision == FEM_PREC_FP32) {
+        float *h = (float *)B->h_stage;
+        for (size_t i = 0; i < len; i++) h[i] = (float)src[i];
+    } else {
+        std::memcpy(B->h_stage, src, len * sizeof(double));
+    }
+    HIP_TRY(hipMemcpyAsync(dst, B->h_stage, len * B->elem(), hipMemcpyHostToDevice, B->stream));
+    return sync(B);
+}
+
+int download_real(fem_batch *B, double *dst, const void *src, size_t len) {
+    TRY(stage(B, std::max<size_t>(len * 8, 64)));
+    HIP_TRY(hipMemcpyAsync(B->h_stage, src, len * B->elem(), hipMemcpyDeviceToHost, B->stream));
+    TRY(sync(B));
+    if (B->precision == FEM_PREC_FP32) {
+        const float *h = (const float *)B->h_stage;
+        for (size_t i = 0; i < len; i++) dst[i] = (double)h[i];
+    } else {
+        std::memcpy(dst, B->h_stage, len * sizeof(double));
+    }
+    return FEM_OK;
+}
+
+enum { V_U = 0, V_G, V_Z, V_P, V_Q };
+
+void *inst_ptr(fem_batch *B, int slot, int which) {
+    InstRec &R = B->insts[slot];
+    if (B->precision == FEM_PREC_FP32) {
+        InstBufs<float> &b = R.b32;
+        float *p[] = {b.u, b.g, b.z, b.p, b.qout};
+        return p[which];
+    }
+    InstBufs<double> &b = R.b64;
+    double *p[] = {b.u, b.g, b.z, b.p, b.qout};
+    return p[which];
+}
+
+// ---------------------------------------------------------------------------
+// Batch life cycle
+// ---------------------------------------------------------------------------
+void batch_release(fem_batch *B) {
+    if (!B) return;
+    (void)hipSetDevice(B->device);
+    if (B->stream) (void)hipStreamSynchronize(B->stream);
+    for (int i = 0; i < (int)B->insts.size(); i++) free_instance(B, i);
+    for (TopoRec &R : B->topos)
+        if (R.arena) (void)hipFree(R.arena);
+    if (B->timer.created)
+        for (int i = 0; i < KernelTimer::kPool; i++) {
+            (void)hipEventDestroy(B->timer.ev[i][0]);
+            (void)hipEventDestroy(B->timer.ev[i][1]);
+        }
+    void *dev[] = {B->d_states, B->d_topos, B->d_bufs, B->d_work_tile, B->d_work_node, B->d_params, B->patch};
+    for (void *p : dev)
+        if (p) (void)hipFree(p);
+    if (B->h_states) (void)hipHostFree(B->h_states);
+    if (B->h_params) (void)hipHostFree(B->h_params);
+    if (B->h_stage) (void)hipHostFree(B->h_stage);
+    if (B->own_stream && B->stream) (void)hipStreamDestroy(B->stream);
+    delete B;
+}
+
+int batch_create(const fem_config *cfg, int capacity, fem_batch **out) {
+    *out = nullptr;
+    fem_config c = {FEM_PREC_FP64, 0, nullptr};
+    if (cfg) c = *cfg;
+    if (c.precision != FEM_PREC_FP64 && c.precision != FEM_PREC_FP32) return fail(FEM_E_INVALID, "bad precision");
+    if (capacity < 1 || capacity > 65536) return fail(FEM_E_INVALID, "max_jobs must be in 1..65536");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(FEM_E_DEVICE, "no HIP device");
+    if (c.device < 0 || c.device >= ndev) return fail(FEM_E_INVALID, "bad device ordinal");
+    fem_batch *B = new (std::nothrow) fem_batch();
+    if (!B) return fail(FEM_E_OOM, "host allocation failed");
+    B->precision = c.precision;
+    B->device = c.device;
+    B->capacity = capacity;
+    B->insts.resize(capacity);
+    int rc = set_device(B);
+    if (!rc) {
+        if (c.stream) {
+            B->stream = (hipStream_t)c.stream;
+        } else if (hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking) == hipSuccess) {
+            B->own_stream = true;
+        } else {
+            rc = fail(FEM_E_DEVICE, "stream creation failed");
+        }
+    }
+    const size_t bufs_bytes = (size_t)capacity * std::max(sizeof(InstBufs<float>), sizeof(InstBufs<double>));
+    if (!rc && hipMalloc(&B->d_states, capacity * sizeof(InstState)) != hipSuccess) rc = fail(FEM_E_OOM, "states");
+    if (!rc && hipMemset(B->d_states, 0, capacity * sizeof(InstState)) != hipSuccess) rc = fail(FEM_E_DEVICE, "memset");
+    if (!rc && hipMalloc(&B->d_bufs, bufs_bytes) != hipSuccess) rc = fail(FEM_E_OOM, "views");
+    if (!rc && hipMalloc(&B->d_params, sizeof(SolveParams)) != hipSuccess) rc = fail(FEM_E_OOM, "params");
+    if (!rc && hipHostMalloc(&B->h_states, capacity * sizeof(InstState)) != hipSuccess) rc = fail(FEM_E_OOM, "pinned");
+    if (!rc && hipHostMalloc(&B->h_params, sizeof(SolveParams)) != hipSuccess) rc = fail(FEM_E_OOM, "pinned");
+    if (!rc) {
+        std::memset(B->h_states, 0, capacity * sizeof(InstState));
+        std::memset(B->h_params, 0, sizeof(SolveParams));
+        rc = stage(B, 4096);
+    }
+    if (rc) {
+        std::string msg = g_last_error;
+        batch_release(B);
+        g_last_error = msg;
+        return rc;
+    }
+    *out = B;
+    return FEM_OK;
+}
+
+int check_mesh_args(const double *X, int32_t n_nodes, const int32_t *tets, int32_t n_tets, const uint8_t *fixed) {
+    if (!X || !tets || !fixed) return fail(FEM_E_INVALID, "null input array");
+    if (n_nodes <= 0 || n_tets <= 0) return fail(FEM_E_INVALID, "empty mesh");
+    if (n_nodes >= (1 << 21)) return fail(FEM_E_INVALID, "n_nodes must be below 2^21");
+    if (n_tets >= (1 << 28)) return fail(FEM_E_INVALID, "too many tets");
+    for (long long i = 0; i < 3LL * n_nodes; i++)
+        if (!is_finite(X[i])) return fail(FEM_E_INVALID, "non-finite node coordinate");
+    for (long long i = 0; i < 4LL * n_tets; i++)
+        if (tets[i] < 0 || tets[i] >= n_nodes) return fail(FEM_E_INVALID, "tet index out of range");
+    for (long long e = 0; e < n_tets; e++)
+        for (int a = 0; a < 4; a++)
+            for (int b = 0; b < a; b++)
+                if (tets[4 * e + a] == tets[4 * e + b]) return fail(FEM_E_DEGENERATE, "tet with a repeated node");
+    return FEM_OK;
+}
+
+int check_indenter(int32_t kind, const double *shape, int32_t n_shape, const double *R, const double *c, double k,
+                   Indenter *out) {
+    if (!shape || !R || !c) return fail(FEM_E_INVALID, "null argument");
+    static const int need[4] = {1, 2, 3, 2};
+    if (kind < 0 || kind > 3) return fail(FEM_E_INVALID, "bad indenter kind");
+    if (n_shape < need[kind]) return fail(FEM_E_INVALID, "too few shape values");
+    for (int i = 0; i < need[kind]; i++)
+        if (!is_finite(shape[i]) || !(shape[i] > 0)) return fail(FEM_E_INVALID, "shape values must be positive");
+    if (kind == FEM_RING && !(shape[1] < shape[0])) return fail(FEM_E_INVALID, "ring needs minor < major radius");
+    for (int i = 0; i < 9; i++)
+        if (!is_finite(R[i])) return fail(FEM_E_INVALID, "non-finite rotation");
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            const double s = R[i] * R[j] + R[3 + i] * R[3 + j] + R[6 + i] * R[6 + j];
+            if (std::fabs(s - (i == j ? 1.0 : 0.0)) > 1e-9) return fail(FEM_E_INVALID, "R is not orthonormal");
+        }
+    const double det = R[0] * (R[4] * R[8] - R[5] * R[7]) - R[1] * (R[3] * R[8] - R[5] * R[6]) +
+                       R[2] * (R[3] * R[7] - R[4] * R[6]);
+    if (det < 0) return fail(FEM_E_INVALID, "R is a reflection");
+    if (!is_finite(c[0]) || !is_finite(c[1]) || !is_finite(c[2]) || !is_finite(k) || k < 0)
+        return fail(FEM_E_INVALID, "bad centre or penalty");
+    Indenter ind{};
+    ind.kind = kind;
+    for (int i = 0; i < 4; i++) ind.shape[i] = i < need[kind] ? shape[i] : 0.0;
+    for (int i = 0; i < 9; i++) ind.R[i] = R[i];
+    for (int i = 0; i < 3; i++) ind.c[i] = c[i];
+    ind.k = k;
+    *out = ind;
+    return FEM_OK;
+}
+
+int check_material(double E, double nu, double density) {
+    if (!is_finite(E) || !is_finite(nu) || !is_finite(density) || !(E > 0) || !(nu > -1.0) || !(nu < 0.5) ||
+        density < 0)
+        return fail(FEM_E_INVALID, "need E > 0, -1 < nu < 0.5, density >= 0");
+    return FEM_OK;
 }
 
 int check_params(const fem_solve_params &P) {
     if (!(P.newton_rtol >= 0) || !(P.newton_atol >= 0) || P.max_newton < 0 || !(P.cg_rtol > 0) ||
         !(P.cg_eta_max >= P.cg_rtol) || P.max_cg < 1 || (P.precond != 0 && P.precond != 1) || !(P.c1 >= 0) ||
-        !(P.c1 < 1) || P.max_halvings < 0)
+        !(P.c1 < 1) || P.max_halvings < 0 || P.max_halvings > 200)
         return fail(FEM_E_INVALID, "invalid solve parameters");
     return FEM_OK;
 }
+
+// A job's initial state: material, pose schedule, counters, phase GRAD.
+void init_job_state(InstState &s, double E, double nu, const Indenter &ind, const double c0[3], const double dir[3],
+                    double depth, int steps) {
+    std::memset(&s, 0, sizeof s);
+    s.mu = E / (2.0 * (1.0 + nu));
+    s.lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    s.ind = ind;
+    for (int d = 0; d < 3; d++) {
+        s.c0[d] = c0[d];
+        s.dir[d] = dir[d];
+    }
+    s.depth = depth;
+    s.steps = steps;
+    s.step = 1;
+    const double f = depth / (double)steps;
+    for (int d = 0; d < 3; d++) s.ind.c[d] = c0[d] + f * dir[d];
+    s.step_started = 1;
+    s.phase = PH_GRAD;
+}
+
+void fill_step_info(const InstState &s, int m, fem_step_info *info) {
+    info->status = s.last_status;
+    info->newton_iters = s.st_newton;
+    info->cg_iters = s.st_cg;
+    info->ls_trials = s.st_ls;
+    info->grad_passes = s.st_grad;
+    info->hv_products = s.st_hv;
+    info->g0_norm = s.st_g0;
+    info->g_norm = s.st_g;
+    info->energy = s.E;
+    info->min_J = s.minJ;
+    info->tet_updates = (int64_t)m * (int64_t)(s.st_grad + s.st_hv);
+}
+
+int contact_patch_impl(fem_batch *B, int slot, int32_t *ids, double *f, double *phi, int32_t capacity,
+                       int32_t *n_contact, double F_total[3]) {
+    const int n = B->topos[B->insts[slot].topo].n;
+    const size_t need = 64 + (size_t)n * (sizeof(int) + 4 * sizeof(double)) + 256;
+    if (B->patch_bytes < need) {
+        if (B->patch) (void)hipFree(B->patch);
+        B->patch = nullptr;
+        B->patch_bytes = 0;
+        HIP_TRY(hipMalloc(&B->patch, need));
+        B->patch_bytes = need;
+    }
+    if (B->tables_dirty) TRY(B->precision == FEM_PREC_FP32 ? rebuild_tables<float>(B) : rebuild_tables<double>(B));
+    char *base = (char *)B->patch;
+    double *d_F = (double *)base;
+    int *d_count = (int *)(base + 32);
+    double *d_f = (double *)(base + 64);
+    double *d_phi = d_f + 3 * (size_t)n;
+    int *d_ids = (int *)(d_phi + n);
+    if (B->precision == FEM_PREC_FP32)
+        k_contact_patch<float><<<1, 1024, 0, B->stream>>>((const Topo<float> *)B->d_topos,
+                                                            (const InstBufs<float> *)B->d_bufs, slot, d_ids, d_f,
+                                                            d_phi, d_count, d_F);
+    else
+        k_contact_patch<double><<<1, 1024, 0, B->stream>>>((const Topo<double> *)B->d_topos,
+                                                             (const InstBufs<double> *)B->d_bufs, slot, d_ids, d_f,
+                                                             d_phi, d_count, d_F);
+    TRY(launch_check("k_contact_patch"));
+    int count = 0;
+    double Ft[3];
+    HIP_TRY(hipMemcpyAsync(&count, d_count, sizeof(int), hipMemcpyDeviceToHost, B->stream));
+    HIP_TRY(hipMemcpyAsync(Ft, d_F, sizeof Ft, hipMemcpyDeviceToHost, B->stream));
+    TRY(sync(B));
+    *n_contact = count;
+    if (F_total) std::memcpy(F_total, Ft, sizeof Ft);
+    if (capacity < count) return fail(FEM_E_BUFFER, "capacity below the contact count");
+    if (count > 0) {
+        if (ids) HIP_TRY(hipMemcpyAsync(ids, d_ids, count * sizeof(int), hipMemcpyDeviceToHost, B->stream));
+        if (f) HIP_TRY(hipMemcpyAsync(f, d_f, 3 * (size_t)count * sizeof(double), hipMemcpyDeviceToHost, B->stream));
+        if (phi) HIP_TRY(hipMemcpyAsync(phi, d_phi, count * sizeof(double), hipMemcpyDeviceToHost, B->stream));
+        TRY(sync(B));
+    }
+    return FEM_OK;
+}
+
+bool job_ok(const fem_batch *B, int job) { return B && job >= 0 && job < B->capacity && B->insts[job].live; }
 
 }  // namespace
 
@@ -473,50 +884,30 @@ void fem_default_params(fem_solve_params *P, int32_t precision) {
     P->max_halvings = 40;
 }
 
+// ---- single mesh ----------------------------------------------------------
 int fem_create_mesh(const double *X, int32_t n_nodes, const int32_t *tets, int32_t n_tets, const uint8_t *fixed,
                     const fem_config *cfg, fem_mesh **out) {
     g_last_error.clear();
     if (!out) return fail(FEM_E_INVALID, "out is null");
     *out = nullptr;
-    if (!X || !tets || !fixed) return fail(FEM_E_INVALID, "null input array");
-    if (n_nodes <= 0 || n_tets <= 0) return fail(FEM_E_INVALID, "empty mesh");
-    if (n_nodes >= (1 << 21)) return fail(FEM_E_INVALID, "n_nodes must be below 2^21");
-    if ((long long)n_tets * 4 >= (1LL << 31) / 2) return fail(FEM_E_INVALID, "too many tets");
-    if (nblocks(n_tets) + nblocks(n_nodes) > kMaxPartials) return fail(FEM_E_INVALID, "mesh too large for one launch");
-    for (long long i = 0; i < 3LL * n_nodes; i++)
-        if (!is_finite(X[i])) return fail(FEM_E_INVALID, "non-finite node coordinate");
-    for (long long i = 0; i < 4LL * n_tets; i++)
-        if (tets[i] < 0 || tets[i] >= n_nodes) return fail(FEM_E_INVALID, "tet index out of range");
-    fem_config c = {FEM_PREC_FP64, 0, nullptr};
-    if (cfg) c = *cfg;
-    if (c.precision != FEM_PREC_FP64 && c.precision != FEM_PREC_FP32) return fail(FEM_E_INVALID, "bad precision");
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(FEM_E_DEVICE, "no HIP device");
-    if (c.device < 0 || c.device >= ndev) return fail(FEM_E_INVALID, "bad device ordinal");
+    TRY(check_mesh_args(X, n_nodes, tets, n_tets, fixed));
     fem_mesh *M = new (std::nothrow) fem_mesh();
     if (!M) return fail(FEM_E_OOM, "host allocation failed");
-    M->device = c.device;
-    M->precision = c.precision;
     M->n = n_nodes;
     M->m = n_tets;
-    int rc = set_device(M);
-    if (!rc) {
-        if (c.stream) {
-            M->stream = (hipStream_t)c.stream;
-        } else if (hipStreamCreateWithFlags(&M->stream, hipStreamNonBlocking) == hipSuccess) {
-            M->own_stream = true;
-        } else {
-            rc = fail(FEM_E_DEVICE, "stream creation failed");
-        }
-    }
-    if (!rc && hipHostMalloc(&M->h_s, sizeof(Scalars)) != hipSuccess) rc = fail(FEM_E_OOM, "pinned allocation failed");
-    if (!rc) rc = stage(M, 4096);
+    int rc = batch_create(cfg, 1, &M->batch);
+    int topo = -1;
     if (!rc)
-        rc = M->precision == FEM_PREC_FP32 ? create_impl<float>(M, X, tets, fixed)
-                                           : create_impl<double>(M, X, tets, fixed);
+        rc = M->batch->precision == FEM_PREC_FP32 ? add_topology<float>(M->batch, X, n_nodes, tets, n_tets, fixed, &topo)
+                                                  : add_topology<double>(M->batch, X, n_nodes, tets, n_tets, fixed, &topo);
+    if (!rc)
+        rc = M->batch->precision == FEM_PREC_FP32 ? alloc_instance<float>(M->batch, 0, topo)
+                                                  : alloc_instance<double>(M->batch, 0, topo);
+    if (!rc) rc = sync(M->batch);
     if (rc) {
         std::string msg = g_last_error;
-        release(M);
+        if (M->batch) batch_release(M->batch);
+        delete M;
         g_last_error = msg;
         return rc;
     }
@@ -524,18 +915,19 @@ int fem_create_mesh(const double *X, int32_t n_nodes, const int32_t *tets, int32
     return FEM_OK;
 }
 
-void fem_destroy_mesh(fem_mesh *mesh) { release(mesh); }
+void fem_destroy_mesh(fem_mesh *M) {
+    if (!M) return;
+    batch_release(M->batch);
+    delete M;
+}
 
 int fem_set_material(fem_mesh *M, double E, double nu, double density) {
     g_last_error.clear();
     if (!M) return fail(FEM_E_INVALID, "null mesh");
-    if (!is_finite(E) || !is_finite(nu) || !is_finite(density) || !(E > 0) || !(nu > -1.0) || !(nu < 0.5) || density < 0)
-        return fail(FEM_E_INVALID, "need E > 0, -1 < nu < 0.5, density >= 0");
+    TRY(check_material(E, nu, density));
     M->E = E;
     M->nu = nu;
     M->density = density;
-    M->mu = E / (2.0 * (1.0 + nu));
-    M->lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
     M->have_material = true;
     return FEM_OK;
 }
@@ -543,31 +935,9 @@ int fem_set_material(fem_mesh *M, double E, double nu, double density) {
 int fem_set_indenter(fem_mesh *M, int32_t kind, const double *shape, int32_t n_shape, const double R[9],
                      const double c[3], double k_penalty) {
     g_last_error.clear();
-    if (!M || !shape || !R || !c) return fail(FEM_E_INVALID, "null argument");
-    static const int need[4] = {1, 2, 3, 2};
-    if (kind < 0 || kind > 3) return fail(FEM_E_INVALID, "bad indenter kind");
-    if (n_shape < need[kind]) return fail(FEM_E_INVALID, "too few shape values");
-    for (int i = 0; i < need[kind]; i++)
-        if (!is_finite(shape[i]) || !(shape[i] > 0)) return fail(FEM_E_INVALID, "shape values must be positive");
-    if (kind == FEM_RING && !(shape[1] < shape[0])) return fail(FEM_E_INVALID, "ring needs minor < major radius");
-    for (int i = 0; i < 9; i++)
-        if (!is_finite(R[i])) return fail(FEM_E_INVALID, "non-finite rotation");
-    for (int i = 0; i < 3; i++)
-        for (int j = 0; j < 3; j++) {
-            double s = R[i] * R[j] + R[3 + i] * R[3 + j] + R[6 + i] * R[6 + j];
-            if (std::fabs(s - (i == j ? 1.0 : 0.0)) > 1e-9) return fail(FEM_E_INVALID, "R is not orthonormal");
-        }
-    const double det = R[0] * (R[4] * R[8] - R[5] * R[7]) - R[1] * (R[3] * R[8] - R[5] * R[6]) +
-                       R[2] * (R[3] * R[7] - R[4] * R[6]);
-    if (det < 0) return fail(FEM_E_INVALID, "R is a reflection");
-    if (!is_finite(c[0]) || !is_finite(c[1]) || !is_finite(c[2]) || !is_finite(k_penalty) || k_penalty < 0)
-        return fail(FEM_E_INVALID, "bad centre or penalty");
-    Indenter ind{};
-    ind.kind = kind;
-    for (int i = 0; i < 4; i++) ind.shape[i] = i < need[kind] ? shape[i] : 0.0;
-    for (int i = 0; i < 9; i++) ind.R[i] = R[i];
-    for (int i = 0; i < 3; i++) ind.c[i] = c[i];
-    ind.k = k_penalty;
+    if (!M) return fail(FEM_E_INVALID, "null mesh");
+    Indenter ind;
+    TRY(check_indenter(kind, shape, n_shape, R, c, k_penalty, &ind));
     M->ind = ind;
     M->have_indenter = true;
     return FEM_OK;
@@ -581,24 +951,31 @@ int fem_step(fem_mesh *M, const fem_solve_params *params, fem_step_info *info) {
     if (params)
         P = *params;
     else
-        fem_default_params(&P, M->precision);
-    int rc = check_params(P);
-    if (rc) return rc;
-    if ((rc = set_device(M))) return rc;
+        fem_default_params(&P, M->batch->precision);
+    TRY(check_params(P));
+    fem_batch *B = M->batch;
+    TRY(set_device(B));
+    TRY(params_to_device(B, P));
+    const double zero[3] = {0.0, 0.0, 0.0};
+    const int hint = B->h_states[0].last_cg;
+    init_job_state(B->h_states[0], M->E, M->nu, M->ind, M->ind.c, zero, 0.0, 1);
+    B->h_states[0].last_cg = hint;
+    TRY(write_state(B, 0));
+    TRY(run(B, 0, nullptr));
     fem_step_info local{};
-    rc = M->precision == FEM_PREC_FP32 ? step_impl<float>(M, P, local) : step_impl<double>(M, P, local);
-    local.status = rc;
+    fill_step_info(B->h_states[0], M->m, &local);
     if (info) *info = local;
-    return rc;
+    if (local.status == FEM_E_NOT_CONVERGED) g_last_error = "Newton did not converge";
+    if (local.status == FEM_E_INVERSION) g_last_error = "line search could not keep det F > 0";
+    return local.status;
 }
 
 int fem_get_displacements(const fem_mesh *M, double *u, int64_t capacity) {
     g_last_error.clear();
     if (!M || !u) return fail(FEM_E_INVALID, "null argument");
     if (capacity < 3LL * M->n) return fail(FEM_E_BUFFER, "capacity below 3 n");
-    int rc = set_device(M);
-    if (rc) return rc;
-    return download_real(M, u, M->u, 3 * (size_t)M->n);
+    TRY(set_device(M->batch));
+    return download_real(M->batch, u, inst_ptr(M->batch, 0, V_U), 3 * (size_t)M->n);
 }
 
 int fem_set_displacements(fem_mesh *M, const double *u, int64_t count) {
@@ -607,9 +984,8 @@ int fem_set_displacements(fem_mesh *M, const double *u, int64_t count) {
     if (count != 3LL * M->n) return fail(FEM_E_INVALID, "count must be 3 n");
     for (int64_t i = 0; i < count; i++)
         if (!is_finite(u[i])) return fail(FEM_E_INVALID, "non-finite displacement");
-    int rc = set_device(M);
-    if (rc) return rc;
-    return upload_real(M, M->u, u, (size_t)count);
+    TRY(set_device(M->batch));
+    return upload_real(M->batch, inst_ptr(M->batch, 0, V_U), u, (size_t)count);
 }
 
 int fem_get_contact_patch(const fem_mesh *Mc, int32_t *ids, double *f, double *phi, int32_t capacity,
@@ -618,45 +994,28 @@ int fem_get_contact_patch(const fem_mesh *Mc, int32_t *ids, double *f, double *p
     if (!Mc || !n_contact) return fail(FEM_E_INVALID, "null argument");
     fem_mesh *M = const_cast<fem_mesh *>(Mc);
     if (!M->have_indenter) return fail(FEM_E_STATE, "no indenter");
-    int rc = set_device(M);
-    if (rc) return rc;
-    if (M->precision == FEM_PREC_FP32)
-        k_contact_patch<float><<<1, 1024, 0, M->stream>>>(views<float>(M), M->patch_ids, M->patch_f, M->patch_phi,
-                                                            M->patch_count, M->patch_F);
-    else
-        k_contact_patch<double><<<1, 1024, 0, M->stream>>>(views<double>(M), M->patch_ids, M->patch_f, M->patch_phi,
-                                                             M->patch_count, M->patch_F);
-    if ((rc = launch_check("k_contact_patch"))) return rc;
-    int count = 0;
-    double Ft[3];
-    HIP_TRY(hipMemcpyAsync(&count, M->patch_count, sizeof(int), hipMemcpyDeviceToHost, M->stream));
-    HIP_TRY(hipMemcpyAsync(Ft, M->patch_F, sizeof Ft, hipMemcpyDeviceToHost, M->stream));
-    HIP_TRY(hipStreamSynchronize(M->stream));
-    *n_contact = count;
-    if (F_total) std::memcpy(F_total, Ft, sizeof Ft);
-    if (capacity < count) return fail(FEM_E_BUFFER, "capacity below the contact count");
-    if (count > 0) {
-        if (ids) HIP_TRY(hipMemcpyAsync(ids, M->patch_ids, count * sizeof(int), hipMemcpyDeviceToHost, M->stream));
-        if (f) HIP_TRY(hipMemcpyAsync(f, M->patch_f, 3 * (size_t)count * sizeof(double), hipMemcpyDeviceToHost, M->stream));
-        if (phi) HIP_TRY(hipMemcpyAsync(phi, M->patch_phi, count * sizeof(double), hipMemcpyDeviceToHost, M->stream));
-        HIP_TRY(hipStreamSynchronize(M->stream));
-    }
-    return FEM_OK;
+    fem_batch *B = M->batch;
+    TRY(set_device(B));
+    // The patch is evaluated at the handle's current indenter pose.
+    TRY(read_states(B));
+    B->h_states[0].ind = M->ind;
+    TRY(write_state(B, 0));
+    return contact_patch_impl(B, 0, ids, f, phi, capacity, n_contact, F_total);
 }
 
 int fem_get_mesh_info(const fem_mesh *M, int32_t *n_nodes, int32_t *n_tets, int32_t *n_eligible, uint8_t *eligible,
                       int32_t capacity) {
     g_last_error.clear();
     if (!M) return fail(FEM_E_INVALID, "null mesh");
+    const TopoRec &tp = M->batch->topos[0];
     if (n_nodes) *n_nodes = M->n;
     if (n_tets) *n_tets = M->m;
-    if (n_eligible) *n_eligible = M->nc;
+    if (n_eligible) *n_eligible = tp.nc;
     if (eligible) {
         if (capacity < M->n) return fail(FEM_E_BUFFER, "capacity below n");
-        int rc = set_device(M);
-        if (rc) return rc;
-        HIP_TRY(hipMemcpyAsync(eligible, M->eligible, M->n, hipMemcpyDeviceToHost, M->stream));
-        HIP_TRY(hipStreamSynchronize(M->stream));
+        TRY(set_device(M->batch));
+        HIP_TRY(hipMemcpyAsync(eligible, tp.elig, M->n, hipMemcpyDeviceToHost, M->batch->stream));
+        TRY(sync(M->batch));
     }
     return FEM_OK;
 }
@@ -666,14 +1025,19 @@ int fem_eval_gradient(fem_mesh *M, double *g, int64_t capacity, double *energy, 
     if (!M) return fail(FEM_E_INVALID, "null mesh");
     if (!M->have_material || !M->have_indenter) return fail(FEM_E_STATE, "set material and indenter first");
     if (g && capacity < 3LL * M->n) return fail(FEM_E_BUFFER, "capacity below 3 n");
-    int rc = set_device(M);
-    if (rc) return rc;
-    rc = M->precision == FEM_PREC_FP32 ? element_pass<float>(M, 0.0f, true, 1) : element_pass<double>(M, 0.0, true, 1);
-    if (rc) return rc;
-    if ((rc = fetch_scalars(M))) return rc;
-    if (energy) *energy = M->h_s->energy;
-    if (min_J) *min_J = M->h_s->minJ;
-    if (g) return download_real(M, g, M->g, 3 * (size_t)M->n);
+    fem_batch *B = M->batch;
+    TRY(set_device(B));
+    fem_solve_params P;
+    fem_default_params(&P, B->precision);
+    TRY(params_to_device(B, P));
+    const double zero[3] = {0.0, 0.0, 0.0};
+    init_job_state(B->h_states[0], M->E, M->nu, M->ind, M->ind.c, zero, 0.0, 1);
+    B->h_states[0].phase = PH_EVAL_GRAD;
+    TRY(write_state(B, 0));
+    TRY(run(B, 2, nullptr));
+    if (energy) *energy = B->h_states[0].E;
+    if (min_J) *min_J = B->h_states[0].minJ;
+    if (g) return download_real(B, g, inst_ptr(B, 0, V_G), 3 * (size_t)M->n);
     return FEM_OK;
 }
 
@@ -682,29 +1046,199 @@ int fem_eval_hessvec(fem_mesh *M, const fem_solve_params *params, const double *
     if (!M || !v || !q) return fail(FEM_E_INVALID, "null argument");
     if (!M->have_material || !M->have_indenter) return fail(FEM_E_STATE, "set material and indenter first");
     if (capacity < 3LL * M->n) return fail(FEM_E_BUFFER, "capacity below 3 n");
+    fem_batch *B = M->batch;
     fem_solve_params P;
     if (params)
         P = *params;
     else
-        fem_default_params(&P, M->precision);
-    int rc = set_device(M);
-    if (rc) return rc;
-    const bool f32 = M->precision == FEM_PREC_FP32;
-    const int cf = P.contact_hessian ? 1 : 0;
-    rc = f32 ? element_pass<float>(M, 0.0f, true, cf) : element_pass<double>(M, 0.0, true, cf);
-    if (rc) return rc;
-    // q = H v with p = z + beta p_prev: z = v, p_prev = 0, beta = 0.
-    if ((rc = upload_real(M, M->z, v, 3 * (size_t)M->n))) return rc;
-    HIP_TRY(hipMemsetAsync(M->p, 0, 3 * (size_t)M->n * M->elem(), M->stream));
-    HIP_TRY(hipMemsetAsync(M->q, 0, 3 * (size_t)M->n * M->elem(), M->stream));
-    HIP_TRY(hipMemsetAsync(&M->s->beta, 0, sizeof(double), M->stream));
-    const int tb = nblocks(M->m), cb = nblocks(M->nc);
-    if (f32)
-        k_cg_hv<float><<<tb + cb, kBlock, 0, M->stream>>>(views<float>(M), tb, 1);
+        fem_default_params(&P, B->precision);
+    TRY(check_params(P));
+    TRY(set_device(B));
+    TRY(params_to_device(B, P));
+    const double zero[3] = {0.0, 0.0, 0.0};
+    init_job_state(B->h_states[0], M->E, M->nu, M->ind, M->ind.c, zero, 0.0, 1);
+    B->h_states[0].phase = PH_EVAL_GRAD;
+    TRY(write_state(B, 0));
+    TRY(run(B, 2, nullptr));
+    // q = H v through the CG kernels with z = v, p_prev = 0, beta = 0.
+    std::vector<double> zeros(3 * (size_t)M->n, 0.0);
+    TRY(upload_real(B, inst_ptr(B, 0, V_Z), v, 3 * (size_t)M->n));
+    TRY(upload_real(B, inst_ptr(B, 0, V_P), zeros.data(), 3 * (size_t)M->n));
+    TRY(read_states(B));
+    B->h_states[0].beta = 0.0;
+    B->h_states[0].phase = PH_EVAL_HV;
+    TRY(write_state(B, 0));
+    TRY(run(B, 2, nullptr));
+    return download_real(B, q, inst_ptr(B, 0, V_Q), 3 * (size_t)M->n);
+}
+
+int fem_set_kernel_timing(fem_mesh *M, int32_t every) {
+    return fem_batch_set_kernel_timing(M ? M->batch : nullptr, every);
+}
+
+int fem_get_kernel_timing(const fem_mesh *M, int32_t kernel, int64_t *count, double *total_ms) {
+    return fem_batch_get_kernel_timing(M ? M->batch : nullptr, kernel, count, total_ms);
+}
+
+// ---- batches --------------------------------------------------------------
+int fem_batch_create(const fem_config *cfg, int32_t max_jobs, fem_batch **out) {
+    g_last_error.clear();
+    if (!out) return fail(FEM_E_INVALID, "out is null");
+    return batch_create(cfg, max_jobs, out);
+}
+
+void fem_batch_destroy(fem_batch *B) { batch_release(B); }
+
+int fem_batch_add_mesh(fem_batch *B, const double *X, int32_t n_nodes, const int32_t *tets, int32_t n_tets,
+                       const uint8_t *fixed, int32_t *mesh_id) {
+    g_last_error.clear();
+    if (!B || !mesh_id) return fail(FEM_E_INVALID, "null argument");
+    TRY(check_mesh_args(X, n_nodes, tets, n_tets, fixed));
+    TRY(set_device(B));
+    int id = -1;
+    TRY(B->precision == FEM_PREC_FP32 ? add_topology<float>(B, X, n_nodes, tets, n_tets, fixed, &id)
+                                     : add_topology<double>(B, X, n_nodes, tets, n_tets, fixed, &id));
+    *mesh_id = id;
+    return FEM_OK;
+}
+
+int fem_batch_add_job(fem_batch *B, int32_t mesh_id, double E, double nu, const fem_indentation *job,
+                      int32_t *job_id) {
+    g_last_error.clear();
+    if (!B || !job || !job_id) return fail(FEM_E_INVALID, "null argument");
+    if (mesh_id < 0 || mesh_id >= (int)B->topos.size()) return fail(FEM_E_INVALID, "unknown mesh id");
+    TRY(check_material(E, nu, 0.0));
+    Indenter ind;
+    TRY(check_indenter(job->kind, job->shape, 4, job->R, job->c0, job->k_penalty, &ind));
+    if (job->steps < 1 || !is_finite(job->depth) || job->depth < 0) return fail(FEM_E_INVALID, "bad schedule");
+    for (int d = 0; d < 3; d++)
+        if (!is_finite(job->direction[d])) return fail(FEM_E_INVALID, "bad direction");
+    int slot = -1;
+    for (int i = 0; i < B->capacity; i++)
+        if (!B->insts[i].live) {
+            slot = i;
+            break;
+        }
+    if (slot < 0) return fail(FEM_E_BUFFER, "batch is full");
+    TRY(set_device(B));
+    TRY(B->precision == FEM_PREC_FP32 ? alloc_instance<float>(B, slot, mesh_id)
+                                     : alloc_instance<double>(B, slot, mesh_id));
+    init_job_state(B->h_states[slot], E, nu, ind, job->c0, job->direction, job->depth, job->steps);
+    TRY(write_state(B, slot));
+    *job_id = slot;
+    return FEM_OK;
+}
+
+int fem_batch_remove_job(fem_batch *B, int32_t job) {
+    g_last_error.clear();
+    if (!job_ok(B, job)) return fail(FEM_E_INVALID, "unknown job");
+    TRY(set_device(B));
+    TRY(sync(B));
+    free_instance(B, job);
+    std::memset(B->h_states + job, 0, sizeof(InstState));
+    return write_state(B, job);
+}
+
+int fem_batch_run(fem_batch *B, const fem_solve_params *params, int32_t max_rounds, int32_t *n_running) {
+    g_last_error.clear();
+    if (!B) return fail(FEM_E_INVALID, "null batch");
+    fem_solve_params P;
+    if (params)
+        P = *params;
     else
-        k_cg_hv<double><<<tb + cb, kBlock, 0, M->stream>>>(views<double>(M), tb, 1);
-    if ((rc = launch_check("k_cg_hv"))) return rc;
-    return download_real(M, q, M->q, 3 * (size_t)M->n);
+        fem_default_params(&P, B->precision);
+    TRY(check_params(P));
+    TRY(set_device(B));
+    TRY(params_to_device(B, P));
+    int running = 0;
+    TRY(run(B, max_rounds, &running));
+    if (n_running) *n_running = running;
+    return FEM_OK;
+}
+
+int fem_batch_job_info(const fem_batch *B, int32_t job, fem_job_info *info) {
+    g_last_error.clear();
+    if (!info || !job_ok(B, job)) return fail(FEM_E_INVALID, "unknown job");
+    const InstState &s = B->h_states[job];
+    const int m = B->topos[B->insts[job].topo].m;
+    const bool done = s.phase == PH_DONE;
+    fem_job_info J{};
+    J.done = done ? 1 : 0;
+    J.status = s.first_fail;
+    J.step = s.step;
+    J.steps_ok = s.steps_ok;
+    J.steps_failed = s.steps_failed;
+    J.newton_iters = s.tot_newton + (done ? 0 : s.st_newton);
+    J.cg_iters = s.tot_cg + (done ? 0 : s.st_cg);
+    J.hv_products = s.tot_hv + (done ? 0 : s.st_hv);
+    J.grad_passes = s.tot_grad + (done ? 0 : s.st_grad);
+    J.ls_trials = s.tot_ls + (done ? 0 : s.st_ls);
+    J.tet_updates = (int64_t)m * (J.grad_passes + J.hv_products);
+    J.energy = s.E;
+    J.min_J = s.minJ;
+    J.g_norm = s.st_g;
+    *info = J;
+    return FEM_OK;
+}
+
+int fem_batch_get_displacements(fem_batch *B, int32_t job, double *u, int64_t capacity) {
+    g_last_error.clear();
+    if (!u || !job_ok(B, job)) return fail(FEM_E_INVALID, "unknown job");
+    const int n = B->topos[B->insts[job].topo].n;
+    if (capacity < 3LL * n) return fail(FEM_E_BUFFER, "capacity below 3 n");
+    TRY(set_device(B));
+    return download_real(B, u, inst_ptr(B, job, V_U), 3 * (size_t)n);
+}
+
+int fem_batch_get_contact_patch(fem_batch *B, int32_t job, int32_t *ids, double *f, double *phi, int32_t capacity,
+                                int32_t *n_contact, double F_total[3]) {
+    g_last_error.clear();
+    if (!n_contact || !job_ok(B, job)) return fail(FEM_E_INVALID, "unknown job");
+    TRY(set_device(B));
+    return contact_patch_impl(B, job, ids, f, phi, capacity, n_contact, F_total);
+}
+
+int fem_batch_set_kernel_timing(fem_batch *B, int32_t every) {
+    g_last_error.clear();
+    if (!B || every < 0) return fail(FEM_E_INVALID, "bad argument");
+    TRY(set_device(B));
+    KernelTimer &t = B->timer;
+    if (every > 0 && !t.created) {
+        for (int i = 0; i < KernelTimer::kPool; i++) {
+            HIP_TRY(hipEventCreate(&t.ev[i][0]));
+            HIP_TRY(hipEventCreate(&t.ev[i][1]));
+        }
+        t.created = true;
+    }
+    TRY(sync(B));
+    t.used = 0;
+    t.every = every;
+    for (int k = 0; k < KernelTimer::kKinds; k++) {
+        t.seen[k] = 0;
+        t.count[k] = 0;
+        t.total_ms[k] = 0.0;
+    }
+    return FEM_OK;
+}
+
+int fem_batch_get_kernel_timing(const fem_batch *B, int32_t kernel, int64_t *count, double *total_ms) {
+    g_last_error.clear();
+    if (!B || kernel < 0 || kernel >= KernelTimer::kKinds) return fail(FEM_E_INVALID, "bad argument");
+    if (count) *count = B->timer.count[kernel];
+    if (total_ms) *total_ms = B->timer.total_ms[kernel];
+    return FEM_OK;
+}
+
+int fem_batch_mesh_info(const fem_batch *B, int32_t mesh_id, fem_mesh_layout *info) {
+    g_last_error.clear();
+    if (!B || !info || mesh_id < 0 || mesh_id >= (int)B->topos.size()) return fail(FEM_E_INVALID, "unknown mesh");
+    const TopoRec &tp = B->topos[mesh_id];
+    info->n_nodes = tp.n;
+    info->n_tets = tp.m;
+    info->n_tiles = tp.ntile;
+    info->n_entries = tp.nent;
+    info->n_eligible = tp.nc;
+    return FEM_OK;
 }
 
 }  // extern "C"

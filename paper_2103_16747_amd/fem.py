@@ -25,7 +25,12 @@ PRECISIONS = {"fp64": FEM_PREC_FP64, "fp32": FEM_PREC_FP32}
 # Entry points declared in include/fem.h.
 EXPORTS = ("fem_create_mesh", "fem_destroy_mesh", "fem_set_material", "fem_set_indenter", "fem_default_params",
            "fem_step", "fem_get_displacements", "fem_set_displacements", "fem_get_contact_patch",
-           "fem_get_mesh_info", "fem_eval_gradient", "fem_eval_hessvec", "fem_status_string", "fem_last_error")
+           "fem_get_mesh_info", "fem_eval_gradient", "fem_eval_hessvec", "fem_set_kernel_timing",
+           "fem_get_kernel_timing", "fem_batch_create", "fem_batch_destroy", "fem_batch_add_mesh",
+           "fem_batch_mesh_info", "fem_batch_add_job", "fem_batch_remove_job", "fem_batch_run", "fem_batch_job_info",
+           "fem_batch_get_displacements", "fem_batch_get_contact_patch", "fem_batch_set_kernel_timing",
+           "fem_batch_get_kernel_timing", "fem_status_string", "fem_last_error")
+FEM_KERNEL_HV, FEM_KERNEL_CG_UPDATE, FEM_KERNEL_ELEMENT = 0, 1, 2
 
 
 class FemError(RuntimeError):
@@ -55,6 +60,26 @@ class fem_step_info(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class fem_indentation(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("shape", C.c_double * 4), ("R", C.c_double * 9), ("c0", C.c_double * 3),
+                ("direction", C.c_double * 3), ("depth", C.c_double), ("steps", C.c_int32), ("k_penalty", C.c_double)]
+
+
+class fem_job_info(C.Structure):
+    _fields_ = [("done", C.c_int32), ("status", C.c_int32), ("step", C.c_int32), ("steps_ok", C.c_int32),
+                ("steps_failed", C.c_int32), ("newton_iters", C.c_int64), ("cg_iters", C.c_int64),
+                ("hv_products", C.c_int64), ("grad_passes", C.c_int64), ("ls_trials", C.c_int64),
+                ("tet_updates", C.c_int64), ("energy", C.c_double), ("min_J", C.c_double), ("g_norm", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class fem_mesh_layout(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_tets", C.c_int32), ("n_tiles", C.c_int32), ("n_entries", C.c_int32),
+                ("n_eligible", C.c_int32)]
+
+
 _lib = None
 
 
@@ -82,6 +107,21 @@ def load(path: str = LIB_PATH):
     L.fem_get_mesh_info.argtypes = [vp, i32p, i32p, i32p, u8p, C.c_int32]
     L.fem_eval_gradient.argtypes = [vp, dp, C.c_int64, dp, dp]
     L.fem_eval_hessvec.argtypes = [vp, C.POINTER(fem_solve_params), dp, dp, C.c_int64]
+    L.fem_set_kernel_timing.argtypes = [vp, C.c_int32]
+    L.fem_get_kernel_timing.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+    L.fem_batch_create.argtypes = [C.POINTER(fem_config), C.c_int32, C.POINTER(vp)]
+    L.fem_batch_destroy.argtypes = [vp]
+    L.fem_batch_destroy.restype = None
+    L.fem_batch_add_mesh.argtypes = [vp, dp, C.c_int32, i32p, C.c_int32, u8p, i32p]
+    L.fem_batch_mesh_info.argtypes = [vp, C.c_int32, C.POINTER(fem_mesh_layout)]
+    L.fem_batch_add_job.argtypes = [vp, C.c_int32, C.c_double, C.c_double, C.POINTER(fem_indentation), i32p]
+    L.fem_batch_remove_job.argtypes = [vp, C.c_int32]
+    L.fem_batch_run.argtypes = [vp, C.POINTER(fem_solve_params), C.c_int32, i32p]
+    L.fem_batch_job_info.argtypes = [vp, C.c_int32, C.POINTER(fem_job_info)]
+    L.fem_batch_get_displacements.argtypes = [vp, C.c_int32, dp, C.c_int64]
+    L.fem_batch_get_contact_patch.argtypes = [vp, C.c_int32, i32p, dp, dp, C.c_int32, i32p, dp]
+    L.fem_batch_set_kernel_timing.argtypes = [vp, C.c_int32]
+    L.fem_batch_get_kernel_timing.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
     L.fem_status_string.argtypes = [C.c_int]
     L.fem_status_string.restype = C.c_char_p
     L.fem_last_error.argtypes = []
@@ -204,6 +244,17 @@ def fem_eval_hessvec(h, v, params: fem_solve_params | None = None):
     return q
 
 
+def fem_set_kernel_timing(h, every: int):
+    _check(load().fem_set_kernel_timing(h, int(every)))
+
+
+def fem_get_kernel_timing(h, kernel: int):
+    """(sampled launches, summed milliseconds) of one timed kernel."""
+    cnt, ms = C.c_int64(), C.c_double()
+    _check(load().fem_get_kernel_timing(h, int(kernel), C.byref(cnt), C.byref(ms)))
+    return cnt.value, ms.value
+
+
 # ---------------------------------------------------------------------------
 # Convenience object
 # ---------------------------------------------------------------------------
@@ -257,6 +308,12 @@ class FemMesh:
     def hessvec(self, v, params=None):
         return fem_eval_hessvec(self.h, v, params)
 
+    def set_kernel_timing(self, every):
+        fem_set_kernel_timing(self.h, every)
+
+    def kernel_timing(self, kernel):
+        return fem_get_kernel_timing(self.h, kernel)
+
     def solve_indentation(self, ind, params=None, steps=None, callback=None):
         """Runs the load steps of a workload Indentation; returns per-step info."""
         out = []
@@ -268,3 +325,166 @@ class FemMesh:
             if callback:
                 callback(k, info)
         return out
+
+
+# ---------------------------------------------------------------------------
+# Batches
+# ---------------------------------------------------------------------------
+def fem_batch_create(max_jobs: int, precision: int = FEM_PREC_FP64, device: int = 0, stream=None) -> C.c_void_p:
+    cfg = fem_config(int(precision), int(device), _stream_handle(stream))
+    h = C.c_void_p()
+    _check(load().fem_batch_create(C.byref(cfg), int(max_jobs), C.byref(h)))
+    return h
+
+
+def fem_batch_destroy(h):
+    load().fem_batch_destroy(h)
+
+
+def fem_batch_add_mesh(h, X, tets, fixed) -> int:
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    T = np.ascontiguousarray(tets, dtype=np.int32)
+    F = np.ascontiguousarray(fixed, dtype=np.uint8)
+    mid = C.c_int32()
+    _check(load().fem_batch_add_mesh(h, _dp(X), X.shape[0], T.ctypes.data_as(C.POINTER(C.c_int32)), T.shape[0],
+                                     F.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(mid)))
+    return mid.value
+
+
+def fem_batch_mesh_info(h, mesh_id: int) -> dict:
+    info = fem_mesh_layout()
+    _check(load().fem_batch_mesh_info(h, int(mesh_id), C.byref(info)))
+    return {name: getattr(info, name) for name, _ in info._fields_}
+
+
+def make_indentation(ind) -> fem_indentation:
+    """fem_indentation from a workload Indentation (or anything with the same
+    attributes)."""
+    j = fem_indentation()
+    j.kind = int(ind.kind)
+    sh = list(np.asarray(ind.shape, dtype=np.float64).ravel()) + [0.0] * 4
+    for i in range(4):
+        j.shape[i] = sh[i]
+    for i, v in enumerate(np.asarray(ind.R, dtype=np.float64).ravel()):
+        j.R[i] = v
+    for i in range(3):
+        j.c0[i] = float(ind.c0[i])
+        j.direction[i] = float(ind.direction[i])
+    j.depth = float(ind.depth)
+    j.steps = int(ind.steps)
+    j.k_penalty = float(ind.k_penalty)
+    return j
+
+
+def fem_batch_add_job(h, mesh_id: int, E: float, nu: float, ind) -> int:
+    job = ind if isinstance(ind, fem_indentation) else make_indentation(ind)
+    jid = C.c_int32()
+    _check(load().fem_batch_add_job(h, int(mesh_id), float(E), float(nu), C.byref(job), C.byref(jid)))
+    return jid.value
+
+
+def fem_batch_remove_job(h, job: int):
+    _check(load().fem_batch_remove_job(h, int(job)))
+
+
+def fem_batch_run(h, params: fem_solve_params | None = None, max_rounds: int = 0) -> int:
+    running = C.c_int32()
+    _check(load().fem_batch_run(h, C.byref(params) if params is not None else None, int(max_rounds),
+                                C.byref(running)))
+    return running.value
+
+
+def fem_batch_job_info(h, job: int) -> dict:
+    info = fem_job_info()
+    _check(load().fem_batch_job_info(h, int(job), C.byref(info)))
+    return info.as_dict()
+
+
+def fem_batch_get_displacements(h, job: int, n: int) -> np.ndarray:
+    u = np.zeros((n, 3))
+    _check(load().fem_batch_get_displacements(h, int(job), _dp(u), u.size))
+    return u
+
+
+def fem_batch_get_contact_patch(h, job: int):
+    cnt = C.c_int32()
+    Ft = np.zeros(3)
+    _check(load().fem_batch_get_contact_patch(h, int(job), None, None, None, 0, C.byref(cnt), _dp(Ft)),
+           allow=(FEM_E_BUFFER,))
+    k = max(cnt.value, 1)
+    ids = np.zeros(k, dtype=np.int32)
+    f = np.zeros((k, 3))
+    phi = np.zeros(k)
+    _check(load().fem_batch_get_contact_patch(h, int(job), ids.ctypes.data_as(C.POINTER(C.c_int32)), _dp(f),
+                                              _dp(phi), k, C.byref(cnt), _dp(Ft)))
+    c = cnt.value
+    return ids[:c], f[:c], phi[:c], Ft
+
+
+def fem_batch_set_kernel_timing(h, every: int):
+    _check(load().fem_batch_set_kernel_timing(h, int(every)))
+
+
+def fem_batch_get_kernel_timing(h, kernel: int):
+    cnt, ms = C.c_int64(), C.c_double()
+    _check(load().fem_batch_get_kernel_timing(h, int(kernel), C.byref(cnt), C.byref(ms)))
+    return cnt.value, ms.value
+
+
+class FemBatch:
+    """Owns one libfem batch handle: meshes plus concurrently solved jobs."""
+
+    def __init__(self, max_jobs, precision="fp32", device=0, stream=None):
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.h = fem_batch_create(max_jobs, self.precision, device, stream)
+        self.mesh_nodes = {}
+        self.job_mesh = {}
+
+    def close(self):
+        if self.h:
+            fem_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def default_params(self, **kw):
+        return fem_default_params(self.precision, **kw)
+
+    def add_mesh(self, X, tets, fixed):
+        mid = fem_batch_add_mesh(self.h, X, tets, fixed)
+        self.mesh_nodes[mid] = int(np.asarray(X).shape[0])
+        return mid
+
+    def mesh_info(self, mesh_id):
+        return fem_batch_mesh_info(self.h, mesh_id)
+
+    def add_job(self, mesh_id, ind, E=0.3e6, nu=0.45):
+        jid = fem_batch_add_job(self.h, mesh_id, E, nu, ind)
+        self.job_mesh[jid] = mesh_id
+        return jid
+
+    def remove_job(self, job):
+        fem_batch_remove_job(self.h, job)
+        self.job_mesh.pop(job, None)
+
+    def run(self, params=None, max_rounds=0):
+        return fem_batch_run(self.h, params, max_rounds)
+
+    def job_info(self, job):
+        return fem_batch_job_info(self.h, job)
+
+    def displacements(self, job):
+        return fem_batch_get_displacements(self.h, job, self.mesh_nodes[self.job_mesh[job]])
+
+    def contact_patch(self, job):
+        return fem_batch_get_contact_patch(self.h, job)
+
+    def set_kernel_timing(self, every):
+        fem_batch_set_kernel_timing(self.h, every)
+
+    def kernel_timing(self, kernel):
+        return fem_batch_get_kernel_timing(self.h, kernel)

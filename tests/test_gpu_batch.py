@@ -1,0 +1,139 @@
+"""Batched indentation jobs on an MI355X: parity with the FP64 oracle, the same
+result alone and in a mix of jobs (uneven meshes, different indenters), and
+jobs joining a batch that is already running (continuous batching).
+
+Tolerances: FP64 jobs against the oracle e_inf <= 1e-8 (both converged to a
+1e-10 relative residual); FP32 jobs <= 1e-4. Alone vs in the mix: the two runs
+execute the same kernels on the same state except for the order of LDS
+atomic additions inside a tile, so they agree to the solve tolerance: 1e-9
+(FP64) and 1e-5 (FP32) relative to max |u|.
+"""
+import numpy as np
+import pytest
+
+from paper_2103_16747_amd import fem, workload as W
+
+pytestmark = pytest.mark.gpu
+E0, NU0 = 0.3e6, 0.45
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def e_inf(u, ref):
+    return float(np.abs(u - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def tight(batch, precision):
+    if precision == "fp64":
+        return batch.default_params(newton_rtol=1e-10, cg_rtol=1e-10)
+    return batch.default_params()
+
+
+def cube_jobs():
+    """The block-and-sphere schedule plus three other indenters on the block."""
+    base = W.cube_sphere_indentation()
+    jobs = [base]
+    shapes = {W.CYLINDER: [1.5e-3, 2e-3], W.BOX: [1.5e-3, 1.2e-3, 1.0e-3], W.RING: [2.0e-3, 0.8e-3]}
+    lead = {W.CYLINDER: 1e-3, W.BOX: 1.0e-3, W.RING: 0.8e-3}
+    for kind in (W.CYLINDER, W.BOX, W.RING):
+        c0 = np.array([5.2e-3, 4.9e-3, 10e-3 + lead[kind]])
+        jobs.append(W.Indentation(kind, np.array(shapes[kind]), np.eye(3), c0, np.array([0.0, 0.0, -1.0]),
+                                  0.8e-3, 8))
+    return jobs
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_matches_oracle(oracle_lib, precision):
+    mesh = W.cube_block_mesh()
+    jobs = cube_jobs()
+    batch = fem.FemBatch(len(jobs), precision)
+    mid = batch.add_mesh(mesh.X, mesh.tets, mesh.fixed)
+    ids = [batch.add_job(mid, j, E0, NU0) for j in jobs]
+    say("batch", precision, "jobs", ids)
+    assert batch.run(tight(batch, precision)) == 0
+    orc = oracle_lib.Solver(mesh.X, mesh.tets, mesh.fixed, E=E0, nu=NU0)
+    for jid, job in zip(ids, jobs):
+        info = batch.job_info(jid)
+        assert info["done"] == 1 and info["status"] == 0 and info["steps_ok"] == job.steps, info
+        ref = orc.solve_indentation(job, params=oracle_lib.default_params(newton_rtol=1e-11, cg_rtol=1e-11))
+        err = e_inf(batch.displacements(jid), ref[-1][0])
+        say(W.KIND_NAMES[job.kind], "e_inf %.3e" % err, "newton", info["newton_iters"], "cg", info["cg_iters"])
+        assert err <= (1e-8 if precision == "fp64" else 1e-4)
+        ids_d, f, phi, Ft = batch.contact_patch(jid)
+        ids_r, f_r, phi_r, Ft_r = orc.contact_patch(ref[-1][0])
+        np.testing.assert_array_equal(ids_d, ids_r)
+    batch.close()
+
+
+def run_alone(mesh, job, precision, params_fn):
+    b = fem.FemBatch(1, precision)
+    mid = b.add_mesh(mesh.X, mesh.tets, mesh.fixed)
+    jid = b.add_job(mid, job, E0, NU0)
+    b.run(params_fn(b, precision))
+    u = b.displacements(jid)
+    b.close()
+    return u
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_alone_equals_in_uneven_mix(precision):
+    cube = W.cube_block_mesh()
+    tip = W.fingertip_mesh(5000)
+    tip_jobs = [W.seat_on_mesh(W.random_indentation(4000 + s, steps=6), tip) for s in range(3)]
+    cjobs = cube_jobs()[:2]
+    batch = fem.FemBatch(8, precision)
+    m_cube = batch.add_mesh(cube.X, cube.tets, cube.fixed)
+    m_tip = batch.add_mesh(tip.X, tip.tets, tip.fixed)
+    mix = [(m_cube, cube, j) for j in cjobs] + [(m_tip, tip, j) for j in tip_jobs]
+    ids = [batch.add_job(mid, j, E0, NU0) for mid, _, j in mix]
+    batch.run(tight(batch, precision))
+    tol = 1e-9 if precision == "fp64" else 1e-5
+    for jid, (mid, mesh, job) in zip(ids, mix):
+        info = batch.job_info(jid)
+        assert info["done"] == 1 and info["steps_failed"] == 0, info
+        alone = run_alone(mesh, job, precision, tight)
+        err = e_inf(batch.displacements(jid), alone)
+        say(precision, mesh.name, W.KIND_NAMES[job.kind], "alone vs mix %.3e" % err)
+        assert err <= tol
+    batch.close()
+
+
+def test_job_joins_running_batch_and_slot_reuse():
+    mesh = W.cube_block_mesh()
+    jobs = cube_jobs()
+    batch = fem.FemBatch(2, "fp64")
+    mid = batch.add_mesh(mesh.X, mesh.tets, mesh.fixed)
+    P = tight(batch, "fp64")
+    a = batch.add_job(mid, jobs[0], E0, NU0)
+    running = batch.run(P, max_rounds=3)
+    assert running == 1
+    assert batch.job_info(a)["done"] == 0
+    b = batch.add_job(mid, jobs[1], E0, NU0)
+    with pytest.raises(fem.FemError) as ei:
+        batch.add_job(mid, jobs[2], E0, NU0)
+    assert ei.value.code == fem.FEM_E_BUFFER
+    assert batch.run(P) == 0
+    for jid, job in ((a, jobs[0]), (b, jobs[1])):
+        alone = run_alone(mesh, job, "fp64", tight)
+        assert e_inf(batch.displacements(jid), alone) <= 1e-9
+    batch.remove_job(a)
+    c = batch.add_job(mid, jobs[2], E0, NU0)
+    assert c == a
+    assert batch.run(P) == 0
+    alone = run_alone(mesh, jobs[2], "fp64", tight)
+    assert e_inf(batch.displacements(c), alone) <= 1e-9
+    batch.close()
+
+
+def test_layout_covers_mesh():
+    mesh = W.fingertip_mesh(50000)
+    batch = fem.FemBatch(1, "fp32")
+    mid = batch.add_mesh(mesh.X, mesh.tets, mesh.fixed)
+    info = batch.mesh_info(mid)
+    say(info)
+    assert info["n_nodes"] == mesh.n and info["n_tets"] == mesh.m
+    assert info["n_tiles"] >= mesh.m // 512
+    assert mesh.n <= info["n_entries"] <= 2 * mesh.n
+    batch.close()
