@@ -1,22 +1,23 @@
 #!/usr/bin/env python3
-"""Benchmark of the indentation solve on one MI355X.
+"""Benchmark of batched indentation solves on one MI355X.
 
-A step is one complete indentation job: a seeded rigid indenter (sphere,
-cylinder, box or ring; random surface point, tilt and depth) pressed into the
-synthetic 50k-tet fingertip in 100 quasi-static load steps, each solved by
-Newton + matrix-free block-Jacobi PCG on the device, starting from rest. The
-mesh is resident in HBM before the timed region; every timed step runs a
-different seed.
+A step is one batch: 256 independent indentation jobs on the synthetic
+50k-tet fingertip, each with its own seeded rigid indenter (sphere, cylinder,
+box or ring; random surface point, tilt up to 30 degrees and depth up to
+3 mm), pressed in over 100 quasi-static load steps and solved to the end.
+All jobs run concurrently through one launch sequence (FP32 element math and
+CG vectors, FP64 reductions); the mesh and every job's state are resident in
+HBM before the timed region.
 
-Prints one JSON line: solves/s of the FP32 path (FP32 element math and CG
-vectors, FP64 reductions) with tet-updates/s, per-solve latency percentiles,
-the plain FP64 path on the same seeds, the roofline of the Hessian-vector
-kernel (event-timed on the library's stream during the timed region), and the
-FP64 CPU oracle timed on a bounded sample of the same workload.
+Printed as one JSON line: solves/s and tet-updates/s of the batched FP32
+path; per-job completion latency p50/p99 within the batch; the same batch on
+the FP64 path; the plain FP64 single-instance path (one job at a time) for
+comparison; the roofline of the dominant kernel, event-timed on the library's
+stream during the timed region; and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -30,66 +31,104 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "FEM indentation solves/s + tet-updates/s, FP32 vs FP64 path; p50/p99 latency"
 
 
-def hv_bytes_per_launch(m, n, nc, word):
-    """Algorithmic HBM bytes of one Hessian-vector launch: per tet the four
-    node ids (16 B), D_m^-1 (9 words), V, the cached F^-1 (9 words) and
-    mu - lam ln J; per node the reads of z and p_prev (6 words) and the
-    read-modify-write of q (6 words); per contact-eligible node its id and
-    contact block (6 words)."""
-    return m * (16 + 20 * word) + n * 12 * word + nc * (4 + 6 * word)
+def algorithmic_bytes(kernel, info, word, jobs):
+    """Algorithmic HBM bytes of one launch of a CG kernel over `jobs` jobs of
+    one mesh (ideal reuse: every node value read once per job, every tile
+    entry partial written or read once).
+
+    Hessian-vector (k_hv): shared per launch the packed local ids (4 B/tet)
+    and per tile entry its node id and tile coordinates (4 + 3 words); per job
+    the reads of u, z and p_prev (9 words per node), the write of the q
+    partial (3 words per entry) and the contact blocks (6 words per
+    contact-eligible node).
+    CG update (k_update): shared the node -> entry CSR (4 B per entry and per
+    node) and the fixed / contact-slot maps (5 B per node); per job the reads
+    of p, z, r, dx (12 words per node), the block-Jacobi inverse (6 words per
+    node), the q partials (3 words per entry), the contact blocks (6 words per
+    eligible node) and the writes of p, dx, r, z (12 words per node).
+    """
+    n, m, nent, nc = info["n_nodes"], info["n_tets"], info["n_entries"], info["n_eligible"]
+    if kernel == "hv":
+        shared = 4 * m + nent * (4 + 3 * word)
+        per_job = 9 * word * n + 3 * word * nent + 6 * word * nc
+    else:
+        shared = 4 * nent + 4 * (n + 1) + 5 * n
+        per_job = 30 * word * n + 3 * word * nent + 6 * word * nc
+    return shared + jobs * per_job
 
 
-def run_solves(mesh, inds, precision, stream, timing_every=0):
+def progress(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_batched(mesh, inds, precision, timed_steps, warm_steps, timing_every=0, track_latency=True):
     from paper_2103_16747_amd import fem
 
-    dev = fem.FemMesh(mesh.X, mesh.tets, mesh.fixed, precision=precision, device=0, stream=stream)
-    dev.set_material(0.3e6, 0.45, 1100.0)
-    zeros = np.zeros((mesh.n, 3))
-    return dev, zeros
-
-
-def solve_one(dev, zeros, ind):
-    dev.set_displacements(zeros)
-    tet_updates = 0
-    statuses = []
-    for k in range(1, ind.steps + 1):
-        dev.set_indenter(ind.kind, ind.shape, ind.R, ind.center(k), ind.k_penalty)
-        info = dev.step()
-        tet_updates += info["tet_updates"]
-        statuses.append(info["status"])
-    return tet_updates, statuses
-
-
-def time_path(mesh, warm, timed, precision, torch, timing_every):
-    from paper_2103_16747_amd import fem
-
-    stream = torch.cuda.Stream()
-    dev, zeros = run_solves(mesh, timed, precision, stream)
-    for ind in warm:
-        solve_one(dev, zeros, ind)
+    batch = fem.FemBatch(len(inds), precision)
+    mid = batch.add_mesh(mesh.X, mesh.tets, mesh.fixed)
+    info = batch.mesh_info(mid)
+    jobs = [batch.add_job(mid, ind) for ind in inds]
+    P = batch.default_params()
+    for _ in range(warm_steps):
+        for j, ind in zip(jobs, inds):
+            batch.restart_job(j, ind)
+        batch.run(P)
+        progress(f"warm-up batch {precision} done")
     if timing_every:
-        dev.set_kernel_timing(timing_every)
-    torch.cuda.synchronize()
-    lat, tu, bad = [], 0, 0
-    finals = []
-    t0 = time.perf_counter()
-    for ind in timed:
-        s0 = time.perf_counter()
-        n_tu, st = solve_one(dev, zeros, ind)
-        lat.append(time.perf_counter() - s0)
-        tu += n_tu
-        bad += sum(1 for s in st if s != 0)
-        finals.append(dev.displacements())
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+        batch.set_kernel_timing(timing_every)
+    walls, lat, tu, failed = [], [], 0, 0
+    for _ in range(timed_steps):
+        for j, ind in zip(jobs, inds):
+            batch.restart_job(j, ind)
+        t0 = time.perf_counter()
+        done_at = {}
+        running = len(jobs)
+        while running:
+            running = batch.run(P, max_rounds=8 if track_latency else 0)
+            now = time.perf_counter() - t0
+            if track_latency:
+                for j in jobs:
+                    if j not in done_at and batch.job_info(j)["done"]:
+                        done_at[j] = now
+        walls.append(time.perf_counter() - t0)
+        progress(f"batched {precision}: {len(jobs)} jobs in {walls[-1]:.2f} s")
+        infos = [batch.job_info(j) for j in jobs]
+        tu += sum(i["tet_updates"] for i in infos)
+        failed += sum(i["steps_failed"] for i in infos)
+        lat += list(done_at.values())
     timing = None
     if timing_every:
-        timing = {k: dev.kernel_timing(k) for k in (fem.FEM_KERNEL_HV, fem.FEM_KERNEL_CG_UPDATE, fem.FEM_KERNEL_ELEMENT)}
-        dev.set_kernel_timing(0)
-    n_elig = dev.info()["n_eligible"]
+        timing = {k: batch.kernel_timing(k) for k in (fem.FEM_KERNEL_HV, fem.FEM_KERNEL_CG_UPDATE,
+                                                      fem.FEM_KERNEL_ELEMENT)}
+        batch.set_kernel_timing(0)
+    finals = [batch.displacements(j) for j in jobs[:4]]
+    stats = [batch.job_info(j) for j in jobs]
+    batch.close()
+    return {"walls": walls, "lat": lat, "tet_updates": tu, "failed_steps": failed, "timing": timing,
+            "layout": info, "finals": finals, "stats": stats}
+
+
+def run_single(mesh, inds, precision):
+    """One job at a time through the single-mesh API (create once, then
+    100 fem_step calls per job)."""
+    from paper_2103_16747_amd import fem
+
+    dev = fem.FemMesh(mesh.X, mesh.tets, mesh.fixed, precision=precision)
+    dev.set_material(0.3e6, 0.45, 1100.0)
+    zeros = np.zeros((mesh.n, 3))
+    walls, tu, failed = [], 0, 0
+    for ind in inds:
+        t0 = time.perf_counter()
+        dev.set_displacements(zeros)
+        for k in range(1, ind.steps + 1):
+            dev.set_indenter(ind.kind, ind.shape, ind.R, ind.center(k), ind.k_penalty)
+            info = dev.step()
+            tu += info["tet_updates"]
+            failed += info["status"] != 0
+        walls.append(time.perf_counter() - t0)
+        progress(f"single {precision}: job {ind.seed} in {walls[-1]:.2f} s")
     dev.close()
-    return {"wall": wall, "lat": lat, "tet_updates": tu, "failed_steps": bad, "finals": finals, "timing": timing,
-            "n_eligible": n_elig}
+    return {"walls": walls, "tet_updates": tu, "failed_steps": failed}
 
 
 def cpu_baseline(mesh, ind, seconds):
@@ -106,26 +145,54 @@ def cpu_baseline(mesh, ind, seconds):
         passes += info["grad_passes"] + info["energy_passes"] + info["hv_products"]
         if time.perf_counter() - t0 >= seconds:
             break
+        if steps % 10 == 0:
+            progress(f"cpu oracle: {steps} load steps")
     el = time.perf_counter() - t0
     return {"value": (steps / ind.steps) / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
             "tet_updates_per_s": mesh.m * passes / el,
-            "sample": f"FP64 oracle, one thread, first {steps} of {ind.steps} load steps of seed {ind.seed} "
+            "sample": f"FP64 oracle, one thread, the first {steps} of {ind.steps} load steps of job seed {ind.seed} "
                       f"on the {mesh.m}-tet fingertip ({el:.1f} s); solves/s = ({steps}/{ind.steps}) / time"}
+
+
+def roofline(r, word, jobs):
+    from paper_2103_16747_amd import fem
+
+    tm = r["timing"]
+    if not tm:
+        return None, None
+    per = {}
+    for name, k in (("hv", fem.FEM_KERNEL_HV), ("update", fem.FEM_KERNEL_CG_UPDATE), ("element", fem.FEM_KERNEL_ELEMENT)):
+        cnt, ms = tm[k]
+        per[name] = {"sampled_launches": cnt, "avg_us": (ms / cnt * 1e3) if cnt else None, "total_ms": ms}
+    # Dominant CG kernel: the larger summed event time.
+    dom = max(("hv", "update"), key=lambda k: per[k]["total_ms"])
+    avg_s = per[dom]["avg_us"] * 1e-6
+    byts = algorithmic_bytes(dom, r["layout"], word, jobs)
+    achieved = byts / avg_s / 1e9
+    kname = {"hv": "k_hv", "update": "k_update"}[dom] + ("<float>" if word == 4 else "<double>")
+    return ({"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_launch_us": per[dom]["avg_us"],
+             "sampled_launches": per[dom]["sampled_launches"], "algorithmic_bytes_per_launch": byts,
+             "jobs_per_launch": jobs, "bytes_per_tet_update": byts / (jobs * r["layout"]["n_tets"])},
+            {k: v["avg_us"] for k, v in per.items()})
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5, help="timed indentation solves")
+    ap.add_argument("--steps", type=int, default=2, help="timed batches")
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--jobs", type=int, default=256)
+    ap.add_argument("--single-jobs", type=int, default=3, help="jobs timed one at a time on the FP64 path")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--timing-every", type=int, default=4)
+    ap.add_argument("--no-single", action="store_true")
+    ap.add_argument("--timing-every", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this solver runs each indentation job on a single MI355X and has "
-              "no multi-GPU path; run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: each batch of indentation jobs runs on a single MI355X and this build "
+              "has no multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -133,65 +200,67 @@ def main():
     from paper_2103_16747_amd import fem, workload as W
 
     assert torch.cuda.is_available(), "no GPU visible"
-    torch.cuda.set_device(0)
     fem.load()
     mesh = W.fingertip_mesh(50000)
-    timed = [W.seat_on_mesh(W.random_indentation(W.instance_seed(2, i)), mesh) for i in range(1, args.steps + 1)]
-    warm = [W.seat_on_mesh(W.random_indentation(W.instance_seed(2, 900 + i)), mesh) for i in range(args.warmup)]
+    inds = [W.seat_on_mesh(W.random_indentation(3000 + i), mesh) for i in range(args.jobs)]
 
-    r32 = time_path(mesh, warm, timed, "fp32", torch, args.timing_every)
-    r64 = None if args.no_fp64 else time_path(mesh, warm, timed, "fp64", torch, 0)
-
-    K = args.steps
-    value = K / r32["wall"]
+    torch.cuda.synchronize()
+    r32 = run_batched(mesh, inds, "fp32", args.steps, args.warmup, args.timing_every)
+    torch.cuda.synchronize()
+    K, J = args.steps, args.jobs
+    wall = sum(r32["walls"])
     lat_ms = np.array(r32["lat"]) * 1e3
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": K * J / wall,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": r32["wall"] / K * 1e3,
+        "ms_per_step": wall / K * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "synthetic fingertip, 50k tets, one seeded indenter per solve, 100 quasi-static load steps",
-            "mesh_tets": mesh.m, "mesh_nodes": mesh.n, "contact_eligible_nodes": r32["n_eligible"],
-            "seeds": [ind.seed for ind in timed],
-            "indenters": [W.KIND_NAMES[ind.kind] for ind in timed],
+            "workload": f"batched indentation: {J} jobs on the synthetic 50k-tet fingertip, seeded indenters "
+                        f"(seeds 3000..{3000 + J - 1}), 100 quasi-static load steps each, all jobs concurrent",
+            "jobs_per_step": J, "mesh_tets": mesh.m, "mesh_nodes": mesh.n,
+            "tiles": r32["layout"]["n_tiles"], "tile_entries": r32["layout"]["n_entries"],
+            "contact_eligible_nodes": r32["layout"]["n_eligible"],
             "precision": "fp32 element math and CG vectors; fp64 dots, norms, energies, Newton test, contact",
             "solver": "Newton + block-Jacobi PCG (matrix-free), Armijo line search, exact contact Hessian",
         },
-        "tet_updates_per_s": r32["tet_updates"] / r32["wall"],
+        "tet_updates_per_s": r32["tet_updates"] / wall,
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
-                       "mode": "one job at a time"},
+                       "mode": "job completion time from batch start, all jobs submitted together"},
         "failed_load_steps": r32["failed_steps"],
+        "cg_iters_per_job": float(np.mean([s["cg_iters"] for s in r32["stats"]])),
+        "newton_iters_per_job": float(np.mean([s["newton_iters"] for s in r32["stats"]])),
     }
-    if r64 is not None:
-        errs = [float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)) for a, b in zip(r32["finals"], r64["finals"])]
-        out["fp64_path"] = {"solves_per_s": K / r64["wall"], "tet_updates_per_s": r64["tet_updates"] / r64["wall"],
-                            "ms_per_step": r64["wall"] / K * 1e3, "failed_load_steps": r64["failed_steps"]}
-        out["e_inf_fp32_vs_fp64_path"] = errs
-    tm = r32["timing"]
-    if tm and tm[fem.FEM_KERNEL_HV][0] > 0:
-        cnt, ms = tm[fem.FEM_KERNEL_HV]
-        avg_s = ms / cnt * 1e-3
-        byts = hv_bytes_per_launch(mesh.m, mesh.n, r32["n_eligible"], 4)
-        achieved = byts / avg_s / 1e9
-        out["roofline"] = {"bound": "hbm", "kernel": "k_cg_hv<float>", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                           "avg_launch_us": avg_s * 1e6, "sampled_launches": cnt,
-                           "algorithmic_bytes_per_launch": byts,
-                           "bytes_per_tet_update": byts / mesh.m}
-        out["kernel_avg_us"] = {name: (tm[k][1] / tm[k][0] * 1e3 if tm[k][0] else None)
-                                for name, k in (("hv", fem.FEM_KERNEL_HV), ("cg_update", fem.FEM_KERNEL_CG_UPDATE),
-                                                ("element", fem.FEM_KERNEL_ELEMENT))}
+    rl, kav = roofline(r32, 4, J)
+    if rl:
+        out["roofline"] = rl
+        out["kernel_avg_us"] = kav
+    if not args.no_fp64:
+        r64 = run_batched(mesh, inds, "fp64", 1, 0, 0, track_latency=False)
+        w64 = sum(r64["walls"])
+        out["fp64_batched"] = {"solves_per_s": J / w64, "tet_updates_per_s": r64["tet_updates"] / w64,
+                               "ms_per_step": w64 * 1e3, "failed_load_steps": r64["failed_steps"]}
+        out["e_inf_fp32_vs_fp64"] = [float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+                                     for a, b in zip(r32["finals"], r64["finals"])]
+    if not args.no_single:
+        s64 = run_single(mesh, inds[:args.single_jobs], "fp64")
+        w = sum(s64["walls"])
+        out["fp64_single_instance"] = {"solves_per_s": len(s64["walls"]) / w,
+                                       "tet_updates_per_s": s64["tet_updates"] / w,
+                                       "ms_per_job": w / len(s64["walls"]) * 1e3,
+                                       "failed_load_steps": s64["failed_steps"],
+                                       "jobs": len(s64["walls"])}
+        out["speedup_vs_fp64_single_instance"] = out["value"] / out["fp64_single_instance"]["solves_per_s"]
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(mesh, timed[0], args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(mesh, inds[0], args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -179,8 +179,9 @@ int fem_eval_hessvec(fem_mesh *mesh, const fem_solve_params *params, const doubl
 
 /* Kernel timing (measurement aid, not part of the solve). With every > 0,
  * HIP events on the handle's stream bracket every every-th launch of the
- * timed kernels; every = 0 turns timing off. Counters are cleared on each
- * call. */
+ * timed kernels (with graphs on: the first Hv and update launch and the
+ * element launch of every round); every = 0 turns timing off. Counters are
+ * cleared on each call. */
 #define FEM_KERNEL_HV 0           /* Hessian-vector half of a CG iteration */
 #define FEM_KERNEL_CG_UPDATE 1    /* vector-update half of a CG iteration */
 #define FEM_KERNEL_ELEMENT 2      /* element + contact pass (gradient / trial) */
@@ -245,6 +246,10 @@ int fem_batch_mesh_info(const fem_batch *batch, int32_t mesh_id, fem_mesh_layout
 int fem_batch_add_job(fem_batch *batch, int32_t mesh_id, double E, double nu, const fem_indentation *job,
                       int32_t *job_id);
 
+/* Restarts a job in its existing slot from rest with a new material and
+ * schedule, allocating nothing (arguments and errors as fem_batch_add_job). */
+int fem_batch_restart_job(fem_batch *batch, int32_t job_id, double E, double nu, const fem_indentation *job);
+
 /* Frees a job's slot and device state. */
 int fem_batch_remove_job(fem_batch *batch, int32_t job_id);
 
@@ -264,6 +269,12 @@ int fem_batch_get_contact_patch(fem_batch *batch, int32_t job_id, int32_t *ids, 
 /* Kernel timing for a batch (as fem_set_kernel_timing). */
 int fem_batch_set_kernel_timing(fem_batch *batch, int32_t every);
 int fem_batch_get_kernel_timing(const fem_batch *batch, int32_t kernel, int64_t *count, double *total_ms);
+
+/* Launch mode: with enable != 0 (the default) each round of kernels is
+ * captured once per CG chunk length into a HIP graph and replayed; 0 launches
+ * the kernels one by one. Results are the same either way. */
+int fem_set_graphs(fem_mesh *mesh, int32_t enable);
+int fem_batch_set_graphs(fem_batch *batch, int32_t enable);
 
 /* Static text for a status code. */
 const char *fem_status_string(int status);

@@ -4,24 +4,27 @@
 //   Topology (shared by every instance of one mesh): tets are ordered along a
 //   Morton curve and cut into tiles of at most kTileTets tets that touch at
 //   most kTileNodes distinct nodes. Per tile: its node list ("entries", global
-//   ids) and the entries' coordinates relative to the tile (ent_x); per tet one
-//   32-bit word of four 8-bit local node indices. Node -> entry CSR lists for
-//   the deterministic gather of tile partial sums.
+//   ids); per tet one 32-bit word of four 8-bit local node indices and the
+//   rest-shape constants D_m^-1 and V (computed once in FP64). Node -> entry
+//   CSR lists for the deterministic gather of tile partial sums.
 //   Instance state: node vectors packed xyz (n x 3), tile partial sums per
 //   entry, contact blocks per contact-eligible node, FP64 solver scalars.
 //
-// Per pass a tile block stages its entries' coordinates and state vectors in
-// LDS, recomputes D_m^-1, V, F for each of its tets (nothing per tet is read
-// from HBM except the packed indices), accumulates nodal contributions with
-// LDS atomics and writes one partial per entry; node kernels gather those
-// partials. Global memory sees no atomics except the reduction tickets.
+// Per pass a tile block stages its entries' state vectors in LDS, reads each
+// tet's packed indices and rest constants (shared by every job on the mesh, so
+// a tile's constants are fetched once per XCD and reused from L2 by the other
+// jobs), recomputes F from u, accumulates nodal contributions with FP64 LDS
+// atomics and writes one partial per entry; node kernels gather those
+// partials. Global memory sees no atomics in the solve kernels.
 //
-// Control: each instance runs a Newton / PCG / line-search state machine whose
-// transitions are taken on the device by the last block of each kernel to
-// finish for that instance (ticket counter). A round of kernels (Hv, update)
-// x C, dot, element, init serves every instance whatever phase it is in;
-// blocks of instances in another phase return at once. All reductions are FP64
-// and summed in a fixed order.
+// Control: each instance runs a Newton / PCG / line-search state machine on
+// the device. Work kernels write one FP64 partial per block and per reduced
+// quantity; a finalize kernel (one wavefront per instance) sums them in a
+// fixed order and takes the transition, so no kernel needs cross-block
+// synchronisation (an agent-scope fence per block costs an L2 write-back on
+// this part). A round (Hv, update, finalize) x C, dot, element, finalize,
+// init, finalize serves every instance whatever phase it is in; blocks of
+// instances in another phase return at once.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -44,14 +47,17 @@ enum Phase : int {
     PH_DONE = 6,      // all load steps taken
     PH_EVAL_GRAD = 7, // diagnostics: gradient at u, then idle
     PH_EVAL_INIT = 8,
-    PH_EVAL_HV = 9,   // diagnostics: q = H z, then idle
-    PH_EVAL_Q = 10
+    PH_EVAL_HV = 9    // diagnostics: q = H z, then idle
 };
 
 // Status codes (same values as the C ABI).
 enum : int { ST_OK = 0, ST_NOT_CONVERGED = -6, ST_INVERSION = -7 };
 
-enum : int { TK_ELEM = 0, TK_INIT, TK_HV, TK_UPD, TK_DOT, TK_COUNT };
+// Partial-sum streams of an instance (each red_stride doubles).
+enum : int { RS_PQ = 0, RS_RZ, RS_RR, RS_GD, RS_E, RS_MAG, RS_MINJ, RS_GG, RS_IRZ, RS_COUNT };
+
+// Finalize stages.
+enum : int { FIN_CG = 0, FIN_ELEM = 1, FIN_INIT = 2 };
 
 struct Indenter {
     int kind;            // 0 sphere, 1 cylinder, 2 box, 3 ring
@@ -70,7 +76,7 @@ struct SolveParams {
 struct InstState {
     int phase, step, steps, step_started;
     int newton_it, cg_it, halvings, apply;
-    int negcurv, status, last_status, last_cg;   // last_cg: length of the previous CG solve
+    int status, last_status, last_cg, pad0;   // last_cg: length of the previous CG solve
     double rz, rr, pq, alpha, beta, tol2;
     double E, emag, minJ, gg, r0, gd, alpha_ls;
     double mu, lam, depth;
@@ -82,7 +88,6 @@ struct InstState {
     // whole job
     long long tot_newton, tot_cg, tot_hv, tot_grad, tot_ls;
     int steps_ok, steps_failed, first_fail, pad2;
-    unsigned ticket[TK_COUNT + 3];
 };
 
 template <typename T>
@@ -91,7 +96,8 @@ struct Topo {
     const int *tile_tet;                // ntile + 1
     const int *tile_ent;                // ntile + 1
     const int *ent_node;                // nent
-    const T *ent_x;                     // nent x 3, tile-relative rest coordinates
+    const T *Bt;                        // 9 x m: D_m^-1 per tet in tile order (field-major)
+    const T *Vt;                        // m: rest volume per tet in tile order
     const uint32_t *tet_loc;            // m packed local ids
     const int *node_ent_off;            // n + 1
     const int *node_ent;                // nent
@@ -110,7 +116,7 @@ struct InstBufs {
     T *pq;                              // nent x 3: Hv partials
     T *cp;                              // nc x 9: contact gradient (3) + block (6)
     T *qout;                            // n x 3 (diagnostics)
-    double *red;                        // 3 x red_stride
+    double *red;                        // RS_COUNT x red_stride
     InstState *s;
 };
 
@@ -169,39 +175,34 @@ __device__ __forceinline__ void block_reduce(double (&v)[NS], double &mn) {
     __syncthreads();
 }
 
-// Thread 0 has stored this block's partials; true in every thread of the last
-// of `total` blocks to arrive. Agent-scope release/acquire makes partials
-// written on other XCDs visible to the last block.
-__device__ __forceinline__ bool last_block(unsigned *ticket, int total) {
-    __shared__ unsigned s_last;
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (t == (unsigned)(total - 1)) ? 1u : 0u;
-    }
+// Sum of nb partials (stride 1) in a fixed order, valid in every thread of
+// the block (all threads take part).
+__device__ __forceinline__ double block_sum_partials(const double *part, int nb) {
+    double v[1] = {0.0};
+    double unused = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) v[0] += part[b];
+    block_reduce<1, false>(v, unused);
+    __shared__ double bcast;
+    if (threadIdx.x == 0) bcast = v[0];
     __syncthreads();
-    const bool last = s_last != 0;
-    if (last) __threadfence();
-    return last;
+    const double r = bcast;
+    __syncthreads();
+    return r;
 }
 
-__device__ __forceinline__ double load_partial(const double *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Wavefront sum / min of nb partials in a fixed order (finalize kernel).
+__device__ __forceinline__ double wave_sum_partials(const double *part, int nb) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 64) v += part[b];
+    v = wave_sum(v);
+    return __shfl(v, 0, 64);
 }
 
-// Sums NS partial streams (stride `stride`) over nb blocks in a fixed order;
-// the result is valid in thread 0. Optionally the min of stream NS.
-template <int NS, bool MIN>
-__device__ __forceinline__ void sum_partials(const double *partial, int stride, int nb, double (&out)[NS], double &mn) {
-#pragma unroll
-    for (int i = 0; i < NS; i++) out[i] = 0.0;
-    mn = INFINITY;
-    for (int b = threadIdx.x; b < nb; b += kBlock) {
-#pragma unroll
-        for (int i = 0; i < NS; i++) out[i] += load_partial(partial + i * stride + b);
-        if (MIN) mn = fmin(mn, load_partial(partial + NS * stride + b));
-    }
-    block_reduce<NS, MIN>(out, mn);
+__device__ __forceinline__ double wave_min_partials(const double *part, int nb) {
+    double v = INFINITY;
+    for (int b = threadIdx.x; b < nb; b += 64) v = fmin(v, part[b]);
+    v = wave_min(v);
+    return __shfl(v, 0, 64);
 }
 
 // ---------------------------------------------------------------------------
@@ -230,29 +231,52 @@ struct ElemGeo {
     T V;
 };
 
-// D_m = [X1-X0, X2-X0, X3-X0] (columns), B = D_m^-1 by cofactors, V = det / 6.
+// Rest constants of tet k (tile order) from the per-mesh cache.
 template <typename T>
-__device__ __forceinline__ ElemGeo<T> elem_geometry(const T *sx, const int l[4]) {
-    T D[9];
-#pragma unroll
-    for (int a = 0; a < 3; a++)
-#pragma unroll
-        for (int i = 0; i < 3; i++) D[3 * i + a] = sx[3 * l[a + 1] + i] - sx[3 * l[0] + i];
-    const T c00 = D[4] * D[8] - D[5] * D[7], c01 = D[5] * D[6] - D[3] * D[8], c02 = D[3] * D[7] - D[4] * D[6];
-    const T det = D[0] * c00 + D[1] * c01 + D[2] * c02;
-    const T id = (T)1 / det;
+__device__ __forceinline__ ElemGeo<T> load_geometry(const Topo<T> &tp, int k) {
     ElemGeo<T> g;
-    g.Bm[0] = c00 * id;
-    g.Bm[1] = (D[2] * D[7] - D[1] * D[8]) * id;
-    g.Bm[2] = (D[1] * D[5] - D[2] * D[4]) * id;
-    g.Bm[3] = c01 * id;
-    g.Bm[4] = (D[0] * D[8] - D[2] * D[6]) * id;
-    g.Bm[5] = (D[2] * D[3] - D[0] * D[5]) * id;
-    g.Bm[6] = c02 * id;
-    g.Bm[7] = (D[1] * D[6] - D[0] * D[7]) * id;
-    g.Bm[8] = (D[0] * D[4] - D[1] * D[3]) * id;
-    g.V = det / (T)6;
+#pragma unroll
+    for (int c = 0; c < 9; c++) g.Bm[c] = tp.Bt[c * tp.m + k];
+    g.V = tp.Vt[k];
     return g;
+}
+
+// Hessian-path helpers: the Hessian only steers the Newton direction (the
+// solution is fixed by the gradient), so the tangent's ln J and 1/J use a
+// short series and the hardware reciprocal instead of the correctly rounded
+// library routines; ~1e-7 relative in FP32, ~1e-13 in FP64 for |J - 1| < 1/2.
+template <typename T> __device__ __forceinline__ T fast_rcp(T x);
+template <> __device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double fast_rcp<double>(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    return r;
+}
+
+// ln(1 + x) = 2 atanh(s), s = x / (2 + x); |s| <= 0.2 for |x| <= 1/2.
+template <typename T>
+__device__ __forceinline__ T fast_log1p(T x) {
+    if (!(x > (T)-0.5 && x < (T)0.5)) return log1p_t(x);
+    const T s = x * fast_rcp((T)2 + x);
+    const T s2 = s * s;
+    T p;
+    if (sizeof(T) == 4) {
+        p = fma_t(s2, (T)(1.0 / 9.0), (T)(1.0 / 7.0));
+        p = fma_t(s2, p, (T)(1.0 / 5.0));
+    } else {
+        p = fma_t(s2, (T)(1.0 / 21.0), (T)(1.0 / 19.0));
+        p = fma_t(s2, p, (T)(1.0 / 17.0));
+        p = fma_t(s2, p, (T)(1.0 / 15.0));
+        p = fma_t(s2, p, (T)(1.0 / 13.0));
+        p = fma_t(s2, p, (T)(1.0 / 11.0));
+        p = fma_t(s2, p, (T)(1.0 / 9.0));
+        p = fma_t(s2, p, (T)(1.0 / 7.0));
+        p = fma_t(s2, p, (T)(1.0 / 5.0));
+    }
+    p = fma_t(s2, p, (T)(1.0 / 3.0));
+    p = fma_t(s2, p, (T)1);
+    return (T)2 * s * p;
 }
 
 // G = sum_a (w_{a+1} - w_0) (x) row_a(D_m^-1), w read from LDS (3 per entry).
@@ -279,14 +303,14 @@ __device__ __forceinline__ T det_minus_one(const T G[9]) {
     return trG + m2 + dG;
 }
 
-// F^-T = cof(F) / J.
-template <typename T>
+// F^-T = cof(F) / J (FAST: hardware reciprocal, Hessian path only).
+template <typename T, bool FAST = false>
 __device__ __forceinline__ void inverse_transpose(const T G[9], T J, T FiT[9]) {
     T F[9];
 #pragma unroll
     for (int k = 0; k < 9; k++) F[k] = G[k];
     F[0] += (T)1; F[4] += (T)1; F[8] += (T)1;
-    const T iJ = (T)1 / J;
+    const T iJ = FAST ? fast_rcp(J) : (T)1 / J;
     FiT[0] = (F[4] * F[8] - F[5] * F[7]) * iJ;
     FiT[1] = (F[5] * F[6] - F[3] * F[8]) * iJ;
     FiT[2] = (F[3] * F[7] - F[4] * F[6]) * iJ;
@@ -434,7 +458,7 @@ __device__ inline void sdf_eval(const Indenter &ind, const double x[3], bool wan
 }
 
 // ---------------------------------------------------------------------------
-// End of a load step (called by a finalising thread): bookkeeping, then the
+// End of a load step (called by the finalising thread): bookkeeping, then the
 // next load step's pose c = c0 + depth * step / steps * dir, or done.
 // ---------------------------------------------------------------------------
 __device__ inline void end_step(InstState *s, int status) {
@@ -464,12 +488,22 @@ __device__ inline void end_step(InstState *s, int status) {
     s->st_newton = s->st_cg = s->st_hv = s->st_grad = s->st_ls = 0;
 }
 
+// Block-level partial sums of a work kernel: thread 0 stores them.
+template <int NS>
+__device__ __forceinline__ void store_partials(double *red, int stride, const int (&streams)[NS], int slot,
+                                               double (&v)[NS]) {
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < NS; i++) red[streams[i] * stride + slot] = v[i];
+}
+
 // ---------------------------------------------------------------------------
-// Element + contact pass (phases GRAD, TRIAL, EVAL_GRAD). Tile blocks: energy,
-// magnitude, min J, and per-entry partials of the gradient and of the 3x3
-// node diagonal blocks V (mu |b|^2 I + (mu + lam - lam ln J) c c^T), c = F^-T b.
-// Contact blocks: penalty energy, gradient k phi n and block k n n^T (+ k phi
-// Hess(phi) with the exact contact Hessian) per eligible node.
+// Element + contact pass (phases GRAD, EVAL_GRAD, DOT = first line-search
+// trial at alpha = 1, TRIAL). Tile blocks: energy, magnitude, min J, and per
+// entry partials of the gradient and of the 3x3 node diagonal blocks
+// V (mu |b|^2 I + (mu + lam - lam ln J) c c^T), c = F^-T b. Contact blocks:
+// penalty energy, gradient k phi n and block k n n^T (+ k phi Hess(phi) with
+// the exact contact Hessian) per eligible node.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_elem(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
@@ -478,16 +512,16 @@ __global__ __launch_bounds__(kBlock) void k_elem(const Topo<T> *topos, const Ins
     if (L >= nwork) return;
     const int2 w = work[L];
     const InstBufs<T> &B = bufs[w.x];
-    InstState *s = B.s;
+    const InstState *s = B.s;
     const int phase = s->phase;
-    if (phase != PH_GRAD && phase != PH_TRIAL && phase != PH_EVAL_GRAD) return;
+    if (phase != PH_GRAD && phase != PH_TRIAL && phase != PH_DOT && phase != PH_EVAL_GRAD) return;
     const Topo<T> &tp = topos[B.topo];
-    const T alpha = phase == PH_TRIAL ? (T)s->alpha_ls : (T)0;
+    const T alpha = phase == PH_TRIAL ? (T)s->alpha_ls : (phase == PH_DOT ? (T)1 : (T)0);
     const T mu = (T)s->mu, lam = (T)s->lam;
-    double acc[2] = {0.0, 0.0};
-    double mnJ = INFINITY;
+    double acc[3] = {0.0, 0.0, INFINITY};   // energy, magnitude, min J
     if (w.y < tp.ntile) {
-        __shared__ T sx[3 * kTileNodes], su[3 * kTileNodes], sa[9 * kTileNodes];
+        __shared__ T su[3 * kTileNodes];
+        __shared__ double sa[9 * kTileNodes];   // FP64 accumulation in both precisions
         const int t = w.y;
         const int e0 = tp.tile_ent[t], ne = tp.tile_ent[t + 1] - e0;
         const int k0 = tp.tile_tet[t], nk = tp.tile_tet[t + 1] - k0;
@@ -495,24 +529,23 @@ __global__ __launch_bounds__(kBlock) void k_elem(const Topo<T> *topos, const Ins
             const int gid = tp.ent_node[e0 + l];
 #pragma unroll
             for (int d = 0; d < 3; d++) {
-                sx[3 * l + d] = tp.ent_x[3 * (e0 + l) + d];
                 T uu = B.u[3 * gid + d];
                 if (alpha != (T)0) uu = fma_t(alpha, B.dx[3 * gid + d], uu);
                 su[3 * l + d] = uu;
             }
 #pragma unroll
-            for (int c = 0; c < 9; c++) sa[9 * l + c] = (T)0;
+            for (int c = 0; c < 9; c++) sa[9 * l + c] = 0.0;
         }
         __syncthreads();
         for (int k = threadIdx.x; k < nk; k += kBlock) {
             int l[4];
             unpack_loc(tp.tet_loc[k0 + k], l);
-            const ElemGeo<T> geo = elem_geometry(sx, l);
+            const ElemGeo<T> geo = load_geometry(tp, k0 + k);
             T G[9];
             edge_gradient(su, l, geo.Bm, G);
             const T Jm1 = det_minus_one(G);
             const T J = (T)1 + Jm1;
-            mnJ = fmin(mnJ, (double)J);
+            acc[2] = fmin(acc[2], (double)J);
             if (!(J > (T)0)) {
                 acc[0] = INFINITY;
                 continue;
@@ -542,10 +575,10 @@ __global__ __launch_bounds__(kBlock) void k_elem(const Topo<T> *topos, const Ins
             const T kc = mu + lam - lam * lnJ;
 #pragma unroll
             for (int a = 0; a < 4; a++) {
-                T *dst = sa + 9 * l[a];
-                atomicAdd(dst + 0, f[a][0]);
-                atomicAdd(dst + 1, f[a][1]);
-                atomicAdd(dst + 2, f[a][2]);
+                double *dst = sa + 9 * l[a];
+                atomicAdd(dst + 0, (double)f[a][0]);
+                atomicAdd(dst + 1, (double)f[a][1]);
+                atomicAdd(dst + 2, (double)f[a][2]);
                 T bb[3];
                 if (a == 0) {
                     bb[0] = -(geo.Bm[0] + geo.Bm[3] + geo.Bm[6]);
@@ -561,16 +594,16 @@ __global__ __launch_bounds__(kBlock) void k_elem(const Topo<T> *topos, const Ins
                 const T cz = FiT[6] * bb[0] + FiT[7] * bb[1] + FiT[8] * bb[2];
                 const T sI = geo.V * mu * (bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2]);
                 const T Vk = geo.V * kc;
-                atomicAdd(dst + 3, sI + Vk * cx * cx);
-                atomicAdd(dst + 4, sI + Vk * cy * cy);
-                atomicAdd(dst + 5, sI + Vk * cz * cz);
-                atomicAdd(dst + 6, Vk * cx * cy);
-                atomicAdd(dst + 7, Vk * cx * cz);
-                atomicAdd(dst + 8, Vk * cy * cz);
+                atomicAdd(dst + 3, (double)(sI + Vk * cx * cx));
+                atomicAdd(dst + 4, (double)(sI + Vk * cy * cy));
+                atomicAdd(dst + 5, (double)(sI + Vk * cz * cz));
+                atomicAdd(dst + 6, (double)(Vk * cx * cy));
+                atomicAdd(dst + 7, (double)(Vk * cx * cz));
+                atomicAdd(dst + 8, (double)(Vk * cy * cz));
             }
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < 9 * ne; i += kBlock) B.pg[9 * e0 + i] = sa[i];
+        for (int i = threadIdx.x; i < 9 * ne; i += kBlock) B.pg[9 * e0 + i] = (T)sa[i];
     } else {
         const int j = (w.y - tp.ntile) * kBlock + threadIdx.x;
         if (j < tp.nc) {
@@ -603,53 +636,19 @@ __global__ __launch_bounds__(kBlock) void k_elem(const Topo<T> *topos, const Ins
             for (int c = 0; c < 9; c++) B.cp[9 * j + c] = out[c];
         }
     }
-    block_reduce<2, true>(acc, mnJ);
-    const int S = B.red_stride;
-    if (threadIdx.x == 0) {
-        B.red[w.y] = acc[0];
-        B.red[S + w.y] = acc[1];
-        B.red[2 * S + w.y] = mnJ;
-    }
-    if (last_block(s->ticket + TK_ELEM, tp.ntile + tp.ncb)) {
-        double tot[2], mn;
-        sum_partials<2, true>(B.red, S, tp.ntile + tp.ncb, tot, mn);
-        if (threadIdx.x == 0) {
-            s->ticket[TK_ELEM] = 0;
-            const double E = mn > 0.0 ? tot[0] : INFINITY;
-            s->st_grad++;
-            if (phase == PH_TRIAL) {
-                s->st_ls++;
-                const double noise = P->noise_eps * s->emag;
-                if (mn > 0.0 && E <= s->E + P->c1 * s->alpha_ls * s->gd + noise) {
-                    s->E = E;
-                    s->emag = tot[1];
-                    s->minJ = mn;
-                    s->apply = 1;
-                    s->phase = PH_INIT;
-                } else if (s->halvings >= P->max_halvings) {
-                    end_step(s, mn > 0.0 ? ST_NOT_CONVERGED : ST_INVERSION);
-                } else {
-                    s->halvings++;
-                    s->alpha_ls *= 0.5;
-                }
-            } else {
-                s->E = E;
-                s->emag = tot[1];
-                s->minJ = mn;
-                s->apply = 0;
-                s->phase = phase == PH_GRAD ? PH_INIT : PH_EVAL_INIT;
-            }
-        }
-    }
+    double sums[2] = {acc[0], acc[1]};
+    double mn = acc[2];
+    block_reduce<2, true>(sums, mn);
+    double v[3] = {sums[0], sums[1], mn};
+    const int streams[3] = {RS_E, RS_MAG, RS_MINJ};
+    store_partials<3>(B.red, B.red_stride, streams, w.y, v);
 }
 
 // ---------------------------------------------------------------------------
 // Newton init (phases INIT, EVAL_INIT), one thread per node: applies an
 // accepted line-search step u += alpha dx, gathers g and the node block from
 // the tile and contact partials, forms the block (or scalar) Jacobi inverse,
-// r = -g and z = M^-1 r on free nodes; reduces |g_free|^2 and r.z. The last
-// block takes the Newton decision and sets up CG (inexact Newton: the CG
-// tolerance follows |g| / |g_step_start|).
+// r = -g and z = M^-1 r on free nodes; partial sums of |g_free|^2 and r.z.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_init(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
@@ -658,7 +657,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const Topo<T> *topos, const Ins
     if (L >= nwork) return;
     const int2 w = work[L];
     const InstBufs<T> &B = bufs[w.x];
-    InstState *s = B.s;
+    const InstState *s = B.s;
     const int phase = s->phase;
     if (phase != PH_INIT && phase != PH_EVAL_INIT) return;
     const Topo<T> &tp = topos[B.topo];
@@ -727,50 +726,8 @@ __global__ __launch_bounds__(kBlock) void k_init(const Topo<T> *topos, const Ins
         }
     }
     block_reduce<2, false>(acc, unused);
-    const int S = B.red_stride;
-    const int nb = (tp.n + kBlock - 1) / kBlock;
-    if (threadIdx.x == 0) {
-        B.red[w.y] = acc[0];
-        B.red[S + w.y] = acc[1];
-    }
-    if (last_block(s->ticket + TK_INIT, nb)) {
-        double tot[2], mn;
-        sum_partials<2, false>(B.red, S, nb, tot, mn);
-        if (threadIdx.x == 0) {
-            s->ticket[TK_INIT] = 0;
-            s->gg = tot[0];
-            if (phase == PH_EVAL_INIT) {
-                s->phase = PH_IDLE;
-            } else {
-                const double gn = sqrt(tot[0]);
-                if (s->apply) {
-                    s->newton_it++;
-                    s->st_newton++;
-                    s->apply = 0;
-                }
-                if (s->step_started) {
-                    s->r0 = gn;
-                    s->st_g0 = gn;
-                    s->step_started = 0;
-                }
-                if (gn <= fmax(P->newton_rtol * s->r0, P->newton_atol)) {
-                    end_step(s, ST_OK);
-                } else if (s->newton_it >= P->max_newton) {
-                    end_step(s, ST_NOT_CONVERGED);
-                } else {
-                    const double eta = fmin(P->cg_eta_max, fmax(P->cg_rtol, gn / s->r0));
-                    s->tol2 = eta * eta * tot[0];
-                    s->rz = tot[1];
-                    s->rr = tot[0];
-                    s->beta = 0.0;
-                    s->alpha = 0.0;
-                    s->cg_it = 0;
-                    s->negcurv = 0;
-                    s->phase = PH_CG;
-                }
-            }
-        }
-    }
+    const int streams[2] = {RS_GG, RS_IRZ};
+    store_partials<2>(B.red, B.red_stride, streams, w.y, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -779,7 +736,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const Topo<T> *topos, const Ins
 // tet, with F recomputed from the staged u:
 //   dP = mu dG + (mu - lam ln J) (F^-1 dG F^-1)^T + lam tr(F^-1 dG) F^-T.
 // p.q is accumulated element by element (and over contact blocks), so alpha
-// is known before the update kernel runs.
+// is known to the update kernel without a pass over q.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_hv(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
@@ -788,17 +745,17 @@ __global__ __launch_bounds__(kBlock) void k_hv(const Topo<T> *topos, const InstB
     if (L >= nwork) return;
     const int2 w = work[L];
     const InstBufs<T> &B = bufs[w.x];
-    InstState *s = B.s;
+    const InstState *s = B.s;
     const int phase = s->phase;
     if (phase != PH_CG && phase != PH_EVAL_HV) return;
-    if (phase == PH_CG && s->negcurv) return;
     const Topo<T> &tp = topos[B.topo];
     const T beta = (T)s->beta;
     const T mu = (T)s->mu, lam = (T)s->lam;
     double acc[1] = {0.0};
     double unused = 0.0;
     if (w.y < tp.ntile) {
-        __shared__ T sx[3 * kTileNodes], su[3 * kTileNodes], sp[3 * kTileNodes], sa[3 * kTileNodes];
+        __shared__ T su[3 * kTileNodes], sp[3 * kTileNodes];
+        __shared__ double sa[3 * kTileNodes];   // FP64 accumulation in both precisions
         const int t = w.y;
         const int e0 = tp.tile_ent[t], ne = tp.tile_ent[t + 1] - e0;
         const int k0 = tp.tile_tet[t], nk = tp.tile_tet[t + 1] - k0;
@@ -806,10 +763,9 @@ __global__ __launch_bounds__(kBlock) void k_hv(const Topo<T> *topos, const InstB
             const int gid = tp.ent_node[e0 + l];
 #pragma unroll
             for (int d = 0; d < 3; d++) {
-                sx[3 * l + d] = tp.ent_x[3 * (e0 + l) + d];
                 su[3 * l + d] = B.u[3 * gid + d];
                 sp[3 * l + d] = fma_t(beta, B.p[3 * gid + d], B.z[3 * gid + d]);
-                sa[3 * l + d] = (T)0;
+                sa[3 * l + d] = 0.0;
             }
         }
         __syncthreads();
@@ -817,15 +773,15 @@ __global__ __launch_bounds__(kBlock) void k_hv(const Topo<T> *topos, const InstB
         for (int k = threadIdx.x; k < nk; k += kBlock) {
             int l[4];
             unpack_loc(tp.tet_loc[k0 + k], l);
-            const ElemGeo<T> geo = elem_geometry(sx, l);
+            const ElemGeo<T> geo = load_geometry(tp, k0 + k);
             T G[9];
             edge_gradient(su, l, geo.Bm, G);
             const T Jm1 = det_minus_one(G);
             const T J = (T)1 + Jm1;
             if (!(J > (T)0)) continue;
-            const T cc = mu - lam * log1p_t(Jm1);
+            const T cc = mu - lam * fast_log1p(Jm1);
             T FiT[9];
-            inverse_transpose(G, J, FiT);
+            inverse_transpose<T, true>(G, J, FiT);
             T dG[9];
             edge_gradient(sp, l, geo.Bm, dG);
             // A = F^-1 dG (F^-1 = FiT^T)
@@ -835,7 +791,7 @@ __global__ __launch_bounds__(kBlock) void k_hv(const Topo<T> *topos, const InstB
 #pragma unroll
                 for (int j = 0; j < 3; j++) A[3 * i + j] = FiT[i] * dG[j] + FiT[3 + i] * dG[3 + j] + FiT[6 + i] * dG[6 + j];
             const T tr = A[0] + A[4] + A[8];
-            // Mt = (A F^-1)^T, Mt_ij = sum_k A_jk FiT_ik
+            // (A F^-1)^T_ij = sum_k A_jk FiT_ik
             T dP[9];
 #pragma unroll
             for (int i = 0; i < 3; i++)
@@ -849,17 +805,17 @@ __global__ __launch_bounds__(kBlock) void k_hv(const Topo<T> *topos, const InstB
             T e_pq = (T)0;
 #pragma unroll
             for (int a = 0; a < 4; a++) {
-                T *dst = sa + 3 * l[a];
-                atomicAdd(dst + 0, f[a][0]);
-                atomicAdd(dst + 1, f[a][1]);
-                atomicAdd(dst + 2, f[a][2]);
+                double *dst = sa + 3 * l[a];
+                atomicAdd(dst + 0, (double)f[a][0]);
+                atomicAdd(dst + 1, (double)f[a][1]);
+                atomicAdd(dst + 2, (double)f[a][2]);
                 e_pq += sp[3 * l[a]] * f[a][0] + sp[3 * l[a] + 1] * f[a][1] + sp[3 * l[a] + 2] * f[a][2];
             }
             pq += (double)e_pq;
         }
         acc[0] = pq;
         __syncthreads();
-        for (int i = threadIdx.x; i < 3 * ne; i += kBlock) B.pq[3 * e0 + i] = sa[i];
+        for (int i = threadIdx.x; i < 3 * ne; i += kBlock) B.pq[3 * e0 + i] = (T)sa[i];
     } else {
         const int j = (w.y - tp.ntile) * kBlock + threadIdx.x;
         if (j < tp.nc) {
@@ -877,33 +833,18 @@ __global__ __launch_bounds__(kBlock) void k_hv(const Topo<T> *topos, const InstB
         }
     }
     block_reduce<1, false>(acc, unused);
-    const int S = B.red_stride;
-    if (threadIdx.x == 0) B.red[w.y] = acc[0];
-    if (last_block(s->ticket + TK_HV, tp.ntile + tp.ncb)) {
-        double tot[1], mn;
-        sum_partials<1, false>(B.red, S, tp.ntile + tp.ncb, tot, mn);
-        if (threadIdx.x == 0) {
-            s->ticket[TK_HV] = 0;
-            s->pq = tot[0];
-            if (phase == PH_EVAL_HV) {
-                s->phase = PH_EVAL_Q;
-            } else {
-                s->st_hv++;
-                if (tot[0] > 0.0)
-                    s->alpha = s->rz / tot[0];
-                else
-                    s->negcurv = 1;
-            }
-        }
-    }
+    const int streams[1] = {RS_PQ};
+    store_partials<1>(B.red, B.red_stride, streams, w.y, acc);
 }
 
 // ---------------------------------------------------------------------------
-// CG, update half (phases CG, EVAL_Q), one thread per node: gathers q from
-// the tile partials plus the contact block times p; then on free nodes
-// p = z + beta p_prev, dx += alpha p, r -= alpha q, z = M^-1 r, reducing r.z
-// and r.r. Non-positive curvature ends CG (on its first iteration the
-// preconditioned residual becomes the Newton direction).
+// CG, update half (phases CG, EVAL_HV), one thread per node. Every block sums
+// the Hv kernel's p.q partials (fixed order, so all blocks agree) and forms
+// alpha = r.z / p.q; then it gathers q from the tile partials plus the contact
+// block times p and, on free nodes, sets p = z + beta p_prev, dx += alpha p,
+// r -= alpha q, z = M^-1 r, with partial sums of r.z and r.r. At p.q <= 0 CG
+// stops (on its first iteration the preconditioned residual becomes the
+// Newton direction).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
@@ -912,20 +853,22 @@ __global__ __launch_bounds__(kBlock) void k_update(const Topo<T> *topos, const I
     if (L >= nwork) return;
     const int2 w = work[L];
     const InstBufs<T> &B = bufs[w.x];
-    InstState *s = B.s;
+    const InstState *s = B.s;
     const int phase = s->phase;
-    if (phase != PH_CG && phase != PH_EVAL_Q) return;
+    if (phase != PH_CG && phase != PH_EVAL_HV) return;
     const Topo<T> &tp = topos[B.topo];
-    const bool negcurv = s->negcurv != 0;
-    const T alpha = (T)s->alpha, beta = (T)s->beta;
-    double acc[2] = {0.0, 0.0};
+    const double pq = block_sum_partials(B.red + RS_PQ * B.red_stride, tp.ntile + tp.ncb);
+    const bool negcurv = !(pq > 0.0);
+    const T alpha = negcurv ? (T)0 : (T)(s->rz / pq);
+    const T beta = (T)s->beta;
+    double acc[2] = {0.0, 0.0};   // r.z, r.r
     double unused = 0.0;
     const int i = w.y * kBlock + threadIdx.x;
     if (i < tp.n) {
         T pv[3];
 #pragma unroll
         for (int d = 0; d < 3; d++) pv[d] = fma_t(beta, B.p[3 * i + d], B.z[3 * i + d]);
-        if (phase == PH_EVAL_Q || !negcurv) {
+        if (phase == PH_EVAL_HV || !negcurv) {
             T qv[3] = {(T)0, (T)0, (T)0};
             for (int q = tp.node_ent_off[i]; q < tp.node_ent_off[i + 1]; q++) {
                 const T *src = B.pq + 3 * tp.node_ent[q];
@@ -940,7 +883,7 @@ __global__ __launch_bounds__(kBlock) void k_update(const Topo<T> *topos, const I
                 qv[1] += H[3] * pv[0] + H[1] * pv[1] + H[5] * pv[2];
                 qv[2] += H[4] * pv[0] + H[5] * pv[1] + H[2] * pv[2];
             }
-            if (phase == PH_EVAL_Q) {
+            if (phase == PH_EVAL_HV) {
 #pragma unroll
                 for (int d = 0; d < 3; d++) B.qout[3 * i + d] = qv[d];
             } else if (!tp.fixed[i]) {
@@ -968,37 +911,11 @@ __global__ __launch_bounds__(kBlock) void k_update(const Topo<T> *topos, const I
         }
     }
     block_reduce<2, false>(acc, unused);
-    const int S = B.red_stride;
-    const int nb = (tp.n + kBlock - 1) / kBlock;
-    if (threadIdx.x == 0) {
-        B.red[w.y] = acc[0];
-        B.red[S + w.y] = acc[1];
-    }
-    if (last_block(s->ticket + TK_UPD, nb)) {
-        double tot[2], mn;
-        sum_partials<2, false>(B.red, S, nb, tot, mn);
-        if (threadIdx.x == 0) {
-            s->ticket[TK_UPD] = 0;
-            if (phase == PH_EVAL_Q) {
-                s->phase = PH_IDLE;
-            } else if (negcurv) {
-                s->phase = PH_DOT;
-            } else {
-                s->cg_it++;
-                s->st_cg++;
-                s->beta = tot[0] / s->rz;
-                s->rz = tot[0];
-                s->rr = tot[1];
-                if (tot[1] <= s->tol2 || s->cg_it >= P->max_cg) {
-                    s->last_cg = s->cg_it;
-                    s->phase = PH_DOT;
-                }
-            }
-        }
-    }
+    const int streams[2] = {RS_RZ, RS_RR};
+    store_partials<2>(B.red, B.red_stride, streams, w.y, acc);
 }
 
-// g . dx (phase DOT), then the line search starts at alpha = 1.
+// Partial sums of g . dx (phase DOT).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dot(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
                                                 int nwork) {
@@ -1006,8 +923,7 @@ __global__ __launch_bounds__(kBlock) void k_dot(const Topo<T> *topos, const Inst
     if (L >= nwork) return;
     const int2 w = work[L];
     const InstBufs<T> &B = bufs[w.x];
-    InstState *s = B.s;
-    if (s->phase != PH_DOT) return;
+    if (B.s->phase != PH_DOT) return;
     const Topo<T> &tp = topos[B.topo];
     double acc[1] = {0.0};
     double unused = 0.0;
@@ -1016,17 +932,129 @@ __global__ __launch_bounds__(kBlock) void k_dot(const Topo<T> *topos, const Inst
 #pragma unroll
         for (int d = 0; d < 3; d++) acc[0] += (double)B.g[3 * i + d] * (double)B.dx[3 * i + d];
     block_reduce<1, false>(acc, unused);
-    const int nb = (tp.n + kBlock - 1) / kBlock;
-    if (threadIdx.x == 0) B.red[w.y] = acc[0];
-    if (last_block(s->ticket + TK_DOT, nb)) {
-        double tot[1], mn;
-        sum_partials<1, false>(B.red, B.red_stride, nb, tot, mn);
-        if (threadIdx.x == 0) {
-            s->ticket[TK_DOT] = 0;
-            s->gd = tot[0];
+    const int streams[1] = {RS_GD};
+    store_partials<1>(B.red, B.red_stride, streams, w.y, acc);
+}
+
+// ---------------------------------------------------------------------------
+// Finalize: one wavefront per live instance sums the partials of the stage's
+// work kernel in a fixed order and takes the state-machine transition.
+//   FIN_CG   after Hv + update: alpha, beta, r.z, CG stop or negative
+//            curvature -> DOT; EVAL_HV -> IDLE.
+//   FIN_ELEM after the element pass: GRAD/EVAL_GRAD record the energy;
+//            DOT (trial at alpha = 1) and TRIAL take the Armijo test with the
+//            rounding floor noise_eps * sum of energy-term magnitudes.
+//   FIN_INIT after init: Newton test on |g_free| against the step's first
+//            residual; CG set-up with the inexact-Newton tolerance.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(64) void k_finalize(const Topo<T> *topos, const InstBufs<T> *bufs, const int *live,
+                                                 int nlive, const SolveParams *P, int stage) {
+    if ((int)blockIdx.x >= nlive) return;
+    const InstBufs<T> &B = bufs[live[blockIdx.x]];
+    InstState *s = B.s;
+    const int phase = s->phase;
+    const Topo<T> &tp = topos[B.topo];
+    const int S = B.red_stride;
+    const int nt = tp.ntile + tp.ncb, nn = (tp.n + kBlock - 1) / kBlock;
+    if (stage == FIN_CG) {
+        if (phase != PH_CG && phase != PH_EVAL_HV) return;
+        const double pq = wave_sum_partials(B.red + RS_PQ * S, nt);
+        const double rz = wave_sum_partials(B.red + RS_RZ * S, nn);
+        const double rr = wave_sum_partials(B.red + RS_RR * S, nn);
+        if (threadIdx.x != 0) return;
+        s->pq = pq;
+        if (phase == PH_EVAL_HV) {
+            s->phase = PH_IDLE;
+            return;
+        }
+        s->st_hv++;
+        if (!(pq > 0.0)) {
+            s->last_cg = s->cg_it;
+            s->phase = PH_DOT;
+            return;
+        }
+        s->alpha = s->rz / pq;
+        s->cg_it++;
+        s->st_cg++;
+        s->beta = rz / s->rz;
+        s->rz = rz;
+        s->rr = rr;
+        if (rr <= s->tol2 || s->cg_it >= P->max_cg) {
+            s->last_cg = s->cg_it;
+            s->phase = PH_DOT;
+        }
+    } else if (stage == FIN_ELEM) {
+        if (phase != PH_GRAD && phase != PH_TRIAL && phase != PH_DOT && phase != PH_EVAL_GRAD) return;
+        const double E = wave_sum_partials(B.red + RS_E * S, nt);
+        const double mag = wave_sum_partials(B.red + RS_MAG * S, nt);
+        const double mn = wave_min_partials(B.red + RS_MINJ * S, nt);
+        const double gd = phase == PH_DOT ? wave_sum_partials(B.red + RS_GD * S, nn) : 0.0;
+        if (threadIdx.x != 0) return;
+        const double Et = mn > 0.0 ? E : INFINITY;
+        s->st_grad++;
+        if (phase == PH_GRAD || phase == PH_EVAL_GRAD) {
+            s->E = Et;
+            s->emag = mag;
+            s->minJ = mn;
+            s->apply = 0;
+            s->phase = phase == PH_GRAD ? PH_INIT : PH_EVAL_INIT;
+            return;
+        }
+        if (phase == PH_DOT) {
+            s->gd = gd;
             s->alpha_ls = 1.0;
             s->halvings = 0;
+        }
+        s->st_ls++;
+        const double noise = P->noise_eps * s->emag;
+        if (mn > 0.0 && Et <= s->E + P->c1 * s->alpha_ls * s->gd + noise) {
+            s->E = Et;
+            s->emag = mag;
+            s->minJ = mn;
+            s->apply = 1;
+            s->phase = PH_INIT;
+        } else if (s->halvings >= P->max_halvings) {
+            end_step(s, mn > 0.0 ? ST_NOT_CONVERGED : ST_INVERSION);
+        } else {
+            s->halvings++;
+            s->alpha_ls *= 0.5;
             s->phase = PH_TRIAL;
+        }
+    } else {
+        if (phase != PH_INIT && phase != PH_EVAL_INIT) return;
+        const double gg = wave_sum_partials(B.red + RS_GG * S, nn);
+        const double rz = wave_sum_partials(B.red + RS_IRZ * S, nn);
+        if (threadIdx.x != 0) return;
+        s->gg = gg;
+        if (phase == PH_EVAL_INIT) {
+            s->phase = PH_IDLE;
+            return;
+        }
+        const double gn = sqrt(gg);
+        if (s->apply) {
+            s->newton_it++;
+            s->st_newton++;
+            s->apply = 0;
+        }
+        if (s->step_started) {
+            s->r0 = gn;
+            s->st_g0 = gn;
+            s->step_started = 0;
+        }
+        if (gn <= fmax(P->newton_rtol * s->r0, P->newton_atol)) {
+            end_step(s, ST_OK);
+        } else if (s->newton_it >= P->max_newton) {
+            end_step(s, ST_NOT_CONVERGED);
+        } else {
+            const double eta = fmin(P->cg_eta_max, fmax(P->cg_rtol, gn / s->r0));
+            s->tol2 = eta * eta * gg;
+            s->rz = rz;
+            s->rr = gg;
+            s->beta = 0.0;
+            s->alpha = 0.0;
+            s->cg_it = 0;
+            s->phase = PH_CG;
         }
     }
 }
@@ -1126,6 +1154,33 @@ __global__ __launch_bounds__(kBlock) void k_check_volumes(const double *X, const
     const double det = D[0] * (D[4] * D[8] - D[5] * D[7]) - D[1] * (D[3] * D[8] - D[5] * D[6]) +
                        D[2] * (D[3] * D[7] - D[4] * D[6]);
     if (!(det > 0.0)) atomicMin(bad, e);
+}
+
+// Rest constants per tet in tile order (FP64, stored in the path precision):
+// D_m = [X1-X0, X2-X0, X3-X0], D_m^-1 by cofactors, V = det D_m / 6.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_rest_constants(const double *X, const int *tet, const int *order, int m,
+                                                           T *Bt, T *Vt) {
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= m) return;
+    const int e = order[k];
+    const int v0 = tet[4 * e];
+    double D[9];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const int va = tet[4 * e + a + 1];
+#pragma unroll
+        for (int i = 0; i < 3; i++) D[3 * i + a] = X[3 * va + i] - X[3 * v0 + i];
+    }
+    const double c00 = D[4] * D[8] - D[5] * D[7], c01 = D[5] * D[6] - D[3] * D[8], c02 = D[3] * D[7] - D[4] * D[6];
+    const double det = D[0] * c00 + D[1] * c01 + D[2] * c02;
+    const double id = 1.0 / det;
+    const double inv[9] = {c00 * id, (D[2] * D[7] - D[1] * D[8]) * id, (D[1] * D[5] - D[2] * D[4]) * id,
+                           c01 * id, (D[0] * D[8] - D[2] * D[6]) * id, (D[2] * D[3] - D[0] * D[5]) * id,
+                           c02 * id, (D[1] * D[6] - D[0] * D[7]) * id, (D[0] * D[4] - D[1] * D[3]) * id};
+#pragma unroll
+    for (int c = 0; c < 9; c++) Bt[c * m + k] = (T)inv[c];
+    Vt[k] = (T)(det / 6.0);
 }
 
 // Boundary faces by hashing the sorted node triple (21 bits per id) of each

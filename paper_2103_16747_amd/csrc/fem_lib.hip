@@ -73,7 +73,7 @@ struct Arena {
 struct HostLayout {
     int n = 0, m = 0, ntile = 0, nent = 0;
     std::vector<int> tile_tet, tile_ent, ent_node, node_ent_off, node_ent;
-    std::vector<double> ent_x;   // nent x 3, relative to the tile's mean entry position
+    std::vector<int> order;      // tile order -> input tet index
     std::vector<uint32_t> tet_loc;
 };
 
@@ -118,8 +118,9 @@ void build_layout(const double *X, int n, const int32_t *tets, int m, HostLayout
     L.tile_tet.assign(1, 0);
     L.tile_ent.assign(1, 0);
     L.ent_node.clear();
-    L.ent_x.clear();
     L.tet_loc.assign(m, 0);
+    L.order.resize(m);
+    for (int k = 0; k < m; k++) L.order[k] = key[k].second;
     int tile = 0, tile_tets = 0, tile_nodes = 0, pos = 0;
     std::vector<int> tile_list;
     auto close_tile = [&]() {
@@ -131,14 +132,7 @@ void build_layout(const double *X, int n, const int32_t *tets, int m, HostLayout
             for (int a = 0; a < 4; a++) w |= (uint32_t)local[tets[4 * e + a]] << (8 * a);
             L.tet_loc[k] = w;
         }
-        double ctr[3] = {0.0, 0.0, 0.0};
-        for (int v : tile_list)
-            for (int d = 0; d < 3; d++) ctr[d] += X[3 * v + d];
-        for (int d = 0; d < 3; d++) ctr[d] /= (double)tile_list.size();
-        for (int v : tile_list) {
-            L.ent_node.push_back(v);
-            for (int d = 0; d < 3; d++) L.ent_x.push_back(X[3 * v + d] - ctr[d]);
-        }
+        for (int v : tile_list) L.ent_node.push_back(v);
         L.tile_tet.push_back(pos);
         L.tile_ent.push_back((int)L.ent_node.size());
         tile++;
@@ -193,6 +187,15 @@ struct KernelTimer {
     bool created = false;
 };
 
+// A captured round of kernels for one CG chunk length (optionally with event
+// records around the first Hv, update and element launches).
+struct RoundGraph {
+    int chunk = 0;
+    bool timed = false;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev[3][2] = {};
+};
+
 struct TopoRec {
     int n = 0, m = 0, ntile = 0, nent = 0, nc = 0, ncb = 0;
     void *arena = nullptr;
@@ -224,6 +227,8 @@ struct fem_batch {
     void *d_topos = nullptr, *d_bufs = nullptr;
     int2 *d_work_tile = nullptr, *d_work_node = nullptr;
     int nwork_tile = 0, nwork_node = 0, cap_work_tile = 0, cap_work_node = 0;
+    int *d_live = nullptr;
+    int nlive = 0;
     SolveParams *d_params = nullptr;
     SolveParams *h_params = nullptr;
     bool tables_dirty = true;
@@ -232,6 +237,9 @@ struct fem_batch {
     void *h_stage = nullptr;
     size_t h_stage_bytes = 0;
     KernelTimer timer;
+    bool use_graphs = true;
+    std::vector<RoundGraph> graphs;
+    int pending_graph = -1;   // timed graph launched since the last harvest
     size_t elem() const { return precision == FEM_PREC_FP32 ? sizeof(float) : sizeof(double); }
 };
 
@@ -276,6 +284,17 @@ void timer_end(fem_batch *B, int slot) {
 
 void timer_harvest(fem_batch *B) {
     KernelTimer &t = B->timer;
+    if (B->pending_graph >= 0) {
+        RoundGraph &G = B->graphs[B->pending_graph];
+        for (int k = 0; k < 3; k++) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, G.ev[k][0], G.ev[k][1]) == hipSuccess) {
+                t.count[k]++;
+                t.total_ms[k] += ms;
+            }
+        }
+        B->pending_graph = -1;
+    }
     for (int i = 0; i < t.used; i++) {
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, t.ev[i][0], t.ev[i][1]) == hipSuccess) {
@@ -288,8 +307,21 @@ void timer_harvest(fem_batch *B) {
 
 int sync(fem_batch *B) {
     HIP_TRY(hipStreamSynchronize(B->stream));
-    if (B->timer.used) timer_harvest(B);
+    if (B->timer.used || B->pending_graph >= 0) timer_harvest(B);
     return FEM_OK;
+}
+
+void drop_graphs(fem_batch *B) {
+    for (RoundGraph &G : B->graphs) {
+        if (G.exec) (void)hipGraphExecDestroy(G.exec);
+        if (G.timed)
+            for (int k = 0; k < 3; k++) {
+                (void)hipEventDestroy(G.ev[k][0]);
+                (void)hipEventDestroy(G.ev[k][1]);
+            }
+    }
+    B->graphs.clear();
+    B->pending_graph = -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -310,14 +342,12 @@ int add_topology(fem_batch *B, const double *X, int n, const int32_t *tets, int 
     R.nent = L.nent;
     Arena A;
     const size_t o_tile_tet = A.take<int>(L.ntile + 1), o_tile_ent = A.take<int>(L.ntile + 1);
-    const size_t o_ent_node = A.take<int>(L.nent), o_ent_x = A.take<T>(3 * (size_t)L.nent);
+    const size_t o_ent_node = A.take<int>(L.nent), o_Bt = A.take<T>(9 * (size_t)m), o_Vt = A.take<T>(m);
     const size_t o_loc = A.take<uint32_t>(m), o_neo = A.take<int>(n + 1), o_ne = A.take<int>(L.nent);
     const size_t o_fixed = A.take<uint8_t>(n), o_cn = A.take<int>(n), o_cidx = A.take<int>(n);
     const size_t o_X = A.take<double>(3 * (size_t)n), o_elig = A.take<uint8_t>(n);
     HIP_TRY(hipMalloc(&R.arena, A.off));
     char *base = (char *)R.arena;
-    std::vector<T> ex(L.ent_x.size());
-    for (size_t k = 0; k < ex.size(); k++) ex[k] = (T)L.ent_x[k];
     auto up = [&](size_t off, const void *src, size_t bytes) -> int {
         HIP_TRY(hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice, B->stream));
         return FEM_OK;
@@ -326,7 +356,6 @@ int add_topology(fem_batch *B, const double *X, int n, const int32_t *tets, int 
     if (!rc) rc = up(o_tile_tet, L.tile_tet.data(), L.tile_tet.size() * sizeof(int));
     if (!rc) rc = up(o_tile_ent, L.tile_ent.data(), L.tile_ent.size() * sizeof(int));
     if (!rc) rc = up(o_ent_node, L.ent_node.data(), L.ent_node.size() * sizeof(int));
-    if (!rc) rc = up(o_ent_x, ex.data(), ex.size() * sizeof(T));
     if (!rc) rc = up(o_loc, L.tet_loc.data(), L.tet_loc.size() * sizeof(uint32_t));
     if (!rc) rc = up(o_neo, L.node_ent_off.data(), L.node_ent_off.size() * sizeof(int));
     if (!rc) rc = up(o_ne, L.node_ent.data(), L.node_ent.size() * sizeof(int));
@@ -335,16 +364,18 @@ int add_topology(fem_batch *B, const double *X, int n, const int32_t *tets, int 
     // Rest volumes and boundary faces from the original connectivity.
     unsigned slots = 1;
     while (slots < 8u * (unsigned)m) slots <<= 1;
-    int *d_tets = nullptr, *d_scalar = nullptr;
+    int *d_tets = nullptr, *d_scalar = nullptr, *d_order = nullptr;
     unsigned long long *keys = nullptr;
     unsigned *cnt = nullptr;
     uint8_t *surf = nullptr;
     const int big = 0x7fffffff;
     if (!rc && (hipMalloc(&d_tets, 4 * (size_t)m * sizeof(int)) != hipSuccess || hipMalloc(&d_scalar, 2 * sizeof(int)) != hipSuccess ||
+                hipMalloc(&d_order, (size_t)m * sizeof(int)) != hipSuccess ||
                 hipMalloc(&keys, slots * sizeof(unsigned long long)) != hipSuccess ||
                 hipMalloc(&cnt, slots * sizeof(unsigned)) != hipSuccess || hipMalloc(&surf, n) != hipSuccess))
         rc = fail(FEM_E_OOM, "set-up scratch allocation failed");
     if (!rc && (hipMemcpyAsync(d_tets, tets, 4 * (size_t)m * sizeof(int), hipMemcpyHostToDevice, B->stream) != hipSuccess ||
+                hipMemcpyAsync(d_order, L.order.data(), (size_t)m * sizeof(int), hipMemcpyHostToDevice, B->stream) != hipSuccess ||
                 hipMemcpyAsync(d_scalar, &big, sizeof(int), hipMemcpyHostToDevice, B->stream) != hipSuccess ||
                 hipMemsetAsync(keys, 0xff, slots * sizeof(unsigned long long), B->stream) != hipSuccess ||
                 hipMemsetAsync(cnt, 0, slots * sizeof(unsigned), B->stream) != hipSuccess ||
@@ -353,6 +384,8 @@ int add_topology(fem_batch *B, const double *X, int n, const int32_t *tets, int 
     int host[2] = {0, 0};
     if (!rc) {
         k_check_volumes<<<ceil_div(m, kBlock), kBlock, 0, B->stream>>>((const double *)(base + o_X), d_tets, m, d_scalar);
+        k_rest_constants<T><<<ceil_div(m, kBlock), kBlock, 0, B->stream>>>((const double *)(base + o_X), d_tets, d_order, m,
+                                                                           (T *)(base + o_Bt), (T *)(base + o_Vt));
         k_faces_insert<<<ceil_div(4LL * m, kBlock), kBlock, 0, B->stream>>>(d_tets, m, keys, cnt, slots - 1);
         k_faces_mark<<<ceil_div(4LL * m, kBlock), kBlock, 0, B->stream>>>(d_tets, m, keys, cnt, slots - 1, surf);
         k_compact_eligible<<<1, 1024, 0, B->stream>>>(surf, (const uint8_t *)(base + o_fixed), n,
@@ -365,6 +398,7 @@ int add_topology(fem_batch *B, const double *X, int n, const int32_t *tets, int 
     if (!rc && hipStreamSynchronize(B->stream) != hipSuccess) rc = fail(FEM_E_DEVICE, "mesh set-up failed");
     (void)hipStreamSynchronize(B->stream);
     if (d_tets) (void)hipFree(d_tets);
+    if (d_order) (void)hipFree(d_order);
     if (d_scalar) (void)hipFree(d_scalar);
     if (keys) (void)hipFree(keys);
     if (cnt) (void)hipFree(cnt);
@@ -387,7 +421,8 @@ int add_topology(fem_batch *B, const double *X, int n, const int32_t *tets, int 
     v.tile_tet = (const int *)(base + o_tile_tet);
     v.tile_ent = (const int *)(base + o_tile_ent);
     v.ent_node = (const int *)(base + o_ent_node);
-    v.ent_x = (const T *)(base + o_ent_x);
+    v.Bt = (const T *)(base + o_Bt);
+    v.Vt = (const T *)(base + o_Vt);
     v.tet_loc = (const uint32_t *)(base + o_loc);
     v.node_ent_off = (const int *)(base + o_neo);
     v.node_ent = (const int *)(base + o_ne);
@@ -419,7 +454,7 @@ int alloc_instance(fem_batch *B, int slot, int topo) {
     o[6] = A.take<T>(6 * (size_t)n);
     const size_t o_pg = A.take<T>(9 * (size_t)tp.nent), o_pq = A.take<T>(3 * (size_t)tp.nent);
     const size_t o_cp = A.take<T>(9 * (size_t)std::max(tp.nc, 1)), o_q = A.take<T>(3 * (size_t)n);
-    const size_t o_red = A.take<double>(3 * (size_t)stride);
+    const size_t o_red = A.take<double>(RS_COUNT * (size_t)stride);
     InstRec &R = B->insts[slot];
     HIP_TRY(hipMalloc(&R.arena, A.off));
     HIP_TRY(hipMemsetAsync(R.arena, 0, A.off, B->stream));
@@ -483,8 +518,15 @@ int rebuild_tables(fem_batch *B) {
         count = (int)v.size();
         return FEM_OK;
     };
+    drop_graphs(B);
     TRY(upload(wt, B->d_work_tile, B->cap_work_tile, B->nwork_tile));
     TRY(upload(wn, B->d_work_node, B->cap_work_node, B->nwork_node));
+    std::vector<int> live;
+    for (int i = 0; i < B->capacity; i++)
+        if (B->insts[i].live) live.push_back(i);
+    B->nlive = (int)live.size();
+    if (!live.empty())
+        HIP_TRY(hipMemcpyAsync(B->d_live, live.data(), live.size() * sizeof(int), hipMemcpyHostToDevice, B->stream));
     std::vector<Topo<T>> tv;
     for (TopoRec &R : B->topos) tv.push_back(topo_view<T>(R));
     TRY(sync(B));
@@ -531,27 +573,75 @@ int write_state(fem_batch *B, int slot) {
 
 inline bool running_phase(int ph) { return ph != PH_IDLE && ph != PH_DONE; }
 
-// One round: (Hv, update) x C, dot, element pass, init.
+// One round: (Hv, update, finalize) x C, dot, element pass, finalize, init,
+// finalize. ev (optional) brackets the first Hv, first update and the element
+// launch with event records.
 template <typename T>
-int launch_round(fem_batch *B, int chunk) {
+int enqueue_round(fem_batch *B, int chunk, hipEvent_t (*ev)[2]) {
     const Topo<T> *tp = (const Topo<T> *)B->d_topos;
     const InstBufs<T> *bf = (const InstBufs<T> *)B->d_bufs;
-    const int gt = pad8(B->nwork_tile), gn = pad8(B->nwork_node);
-    if (gt == 0 || gn == 0) return FEM_OK;
+    const int gt = pad8(B->nwork_tile), gn = pad8(B->nwork_node), nl = B->nlive;
     for (int c = 0; c < chunk; c++) {
-        int slot = timer_begin(B, FEM_KERNEL_HV);
+        int slot = ev ? -1 : timer_begin(B, FEM_KERNEL_HV);
+        if (ev && c == 0) HIP_TRY(hipEventRecord(ev[FEM_KERNEL_HV][0], B->stream));
         k_hv<T><<<gt, kBlock, 0, B->stream>>>(tp, bf, B->d_work_tile, B->nwork_tile, B->d_params);
+        if (ev && c == 0) HIP_TRY(hipEventRecord(ev[FEM_KERNEL_HV][1], B->stream));
         timer_end(B, slot);
-        slot = timer_begin(B, FEM_KERNEL_CG_UPDATE);
+        slot = ev ? -1 : timer_begin(B, FEM_KERNEL_CG_UPDATE);
+        if (ev && c == 0) HIP_TRY(hipEventRecord(ev[FEM_KERNEL_CG_UPDATE][0], B->stream));
         k_update<T><<<gn, kBlock, 0, B->stream>>>(tp, bf, B->d_work_node, B->nwork_node, B->d_params);
+        if (ev && c == 0) HIP_TRY(hipEventRecord(ev[FEM_KERNEL_CG_UPDATE][1], B->stream));
         timer_end(B, slot);
+        k_finalize<T><<<nl, 64, 0, B->stream>>>(tp, bf, B->d_live, nl, B->d_params, FIN_CG);
     }
     k_dot<T><<<gn, kBlock, 0, B->stream>>>(tp, bf, B->d_work_node, B->nwork_node);
-    const int slot = timer_begin(B, FEM_KERNEL_ELEMENT);
+    const int slot = ev ? -1 : timer_begin(B, FEM_KERNEL_ELEMENT);
+    if (ev) HIP_TRY(hipEventRecord(ev[FEM_KERNEL_ELEMENT][0], B->stream));
     k_elem<T><<<gt, kBlock, 0, B->stream>>>(tp, bf, B->d_work_tile, B->nwork_tile, B->d_params);
+    if (ev) HIP_TRY(hipEventRecord(ev[FEM_KERNEL_ELEMENT][1], B->stream));
     timer_end(B, slot);
+    k_finalize<T><<<nl, 64, 0, B->stream>>>(tp, bf, B->d_live, nl, B->d_params, FIN_ELEM);
     k_init<T><<<gn, kBlock, 0, B->stream>>>(tp, bf, B->d_work_node, B->nwork_node, B->d_params);
+    k_finalize<T><<<nl, 64, 0, B->stream>>>(tp, bf, B->d_live, nl, B->d_params, FIN_INIT);
     return launch_check("round");
+}
+
+// Launches a round, replaying a captured graph for the chunk length when
+// graphs are on (chunks are powers of two from 4 to 64).
+template <typename T>
+int launch_round(fem_batch *B, int chunk) {
+    if (pad8(B->nwork_tile) == 0 || pad8(B->nwork_node) == 0 || B->nlive == 0) return FEM_OK;
+    if (!B->use_graphs) return enqueue_round<T>(B, chunk, nullptr);
+    int c = 4;
+    while (c < chunk && c < 64) c <<= 1;
+    const bool timed = B->timer.every > 0;
+    int gi = -1;
+    for (int i = 0; i < (int)B->graphs.size(); i++)
+        if (B->graphs[i].chunk == c && B->graphs[i].timed == timed) gi = i;
+    if (gi < 0) {
+        RoundGraph G;
+        G.chunk = c;
+        G.timed = timed;
+        if (timed)
+            for (int k = 0; k < 3; k++) {
+                HIP_TRY(hipEventCreate(&G.ev[k][0]));
+                HIP_TRY(hipEventCreate(&G.ev[k][1]));
+            }
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue_round<T>(B, c, timed ? G.ev : nullptr);
+        const hipError_t ec = hipStreamEndCapture(B->stream, &graph);
+        if (rc) return rc;
+        if (ec != hipSuccess) return fail(FEM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+        const hipError_t ei = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return fail(FEM_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+        B->graphs.push_back(G);
+        gi = (int)B->graphs.size() - 1;
+    }
+    HIP_TRY(hipGraphLaunch(B->graphs[gi].exec, B->stream));
+    if (timed) B->pending_graph = gi;
+    return FEM_OK;
 }
 
 // Advances every running job until all are done or max_rounds rounds ran.
@@ -639,6 +729,7 @@ void batch_release(fem_batch *B) {
     if (!B) return;
     (void)hipSetDevice(B->device);
     if (B->stream) (void)hipStreamSynchronize(B->stream);
+    drop_graphs(B);
     for (int i = 0; i < (int)B->insts.size(); i++) free_instance(B, i);
     for (TopoRec &R : B->topos)
         if (R.arena) (void)hipFree(R.arena);
@@ -647,7 +738,8 @@ void batch_release(fem_batch *B) {
             (void)hipEventDestroy(B->timer.ev[i][0]);
             (void)hipEventDestroy(B->timer.ev[i][1]);
         }
-    void *dev[] = {B->d_states, B->d_topos, B->d_bufs, B->d_work_tile, B->d_work_node, B->d_params, B->patch};
+    void *dev[] = {B->d_states, B->d_topos, B->d_bufs, B->d_work_tile, B->d_work_node, B->d_live, B->d_params,
+                   B->patch};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (B->h_states) (void)hipHostFree(B->h_states);
@@ -687,6 +779,7 @@ int batch_create(const fem_config *cfg, int capacity, fem_batch **out) {
     if (!rc && hipMemset(B->d_states, 0, capacity * sizeof(InstState)) != hipSuccess) rc = fail(FEM_E_DEVICE, "memset");
     if (!rc && hipMalloc(&B->d_bufs, bufs_bytes) != hipSuccess) rc = fail(FEM_E_OOM, "views");
     if (!rc && hipMalloc(&B->d_params, sizeof(SolveParams)) != hipSuccess) rc = fail(FEM_E_OOM, "params");
+    if (!rc && hipMalloc(&B->d_live, capacity * sizeof(int)) != hipSuccess) rc = fail(FEM_E_OOM, "live list");
     if (!rc && hipHostMalloc(&B->h_states, capacity * sizeof(InstState)) != hipSuccess) rc = fail(FEM_E_OOM, "pinned");
     if (!rc && hipHostMalloc(&B->h_params, sizeof(SolveParams)) != hipSuccess) rc = fail(FEM_E_OOM, "pinned");
     if (!rc) {
@@ -1129,6 +1222,28 @@ int fem_batch_add_job(fem_batch *B, int32_t mesh_id, double E, double nu, const 
     return FEM_OK;
 }
 
+int fem_batch_restart_job(fem_batch *B, int32_t job_id, double E, double nu, const fem_indentation *job) {
+    g_last_error.clear();
+    if (!job || !job_ok(B, job_id)) return fail(FEM_E_INVALID, "unknown job");
+    TRY(check_material(E, nu, 0.0));
+    Indenter ind;
+    TRY(check_indenter(job->kind, job->shape, 4, job->R, job->c0, job->k_penalty, &ind));
+    if (job->steps < 1 || !is_finite(job->depth) || job->depth < 0) return fail(FEM_E_INVALID, "bad schedule");
+    for (int d = 0; d < 3; d++)
+        if (!is_finite(job->direction[d])) return fail(FEM_E_INVALID, "bad direction");
+    TRY(set_device(B));
+    const int n = B->topos[B->insts[job_id].topo].n;
+    HIP_TRY(hipMemsetAsync(inst_ptr(B, job_id, V_U), 0, 3 * (size_t)n * B->elem(), B->stream));
+    const int hint = B->h_states[job_id].last_cg;
+    init_job_state(B->h_states[job_id], E, nu, ind, job->c0, job->direction, job->depth, job->steps);
+    B->h_states[job_id].last_cg = hint;
+    // Stream-ordered before any later kernel or state read; the pinned source
+    // slot is not written again until the host has synchronised.
+    HIP_TRY(hipMemcpyAsync(B->d_states + job_id, B->h_states + job_id, sizeof(InstState), hipMemcpyHostToDevice,
+                           B->stream));
+    return FEM_OK;
+}
+
 int fem_batch_remove_job(fem_batch *B, int32_t job) {
     g_last_error.clear();
     if (!job_ok(B, job)) return fail(FEM_E_INVALID, "unknown job");
@@ -1212,6 +1327,7 @@ int fem_batch_set_kernel_timing(fem_batch *B, int32_t every) {
     }
     TRY(sync(B));
     t.used = 0;
+    B->pending_graph = -1;
     t.every = every;
     for (int k = 0; k < KernelTimer::kKinds; k++) {
         t.seen[k] = 0;
@@ -1228,6 +1344,18 @@ int fem_batch_get_kernel_timing(const fem_batch *B, int32_t kernel, int64_t *cou
     if (total_ms) *total_ms = B->timer.total_ms[kernel];
     return FEM_OK;
 }
+
+int fem_batch_set_graphs(fem_batch *B, int32_t enable) {
+    g_last_error.clear();
+    if (!B) return fail(FEM_E_INVALID, "null batch");
+    TRY(set_device(B));
+    TRY(sync(B));
+    drop_graphs(B);
+    B->use_graphs = enable != 0;
+    return FEM_OK;
+}
+
+int fem_set_graphs(fem_mesh *M, int32_t enable) { return fem_batch_set_graphs(M ? M->batch : nullptr, enable); }
 
 int fem_batch_mesh_info(const fem_batch *B, int32_t mesh_id, fem_mesh_layout *info) {
     g_last_error.clear();

@@ -27,9 +27,10 @@ EXPORTS = ("fem_create_mesh", "fem_destroy_mesh", "fem_set_material", "fem_set_i
            "fem_step", "fem_get_displacements", "fem_set_displacements", "fem_get_contact_patch",
            "fem_get_mesh_info", "fem_eval_gradient", "fem_eval_hessvec", "fem_set_kernel_timing",
            "fem_get_kernel_timing", "fem_batch_create", "fem_batch_destroy", "fem_batch_add_mesh",
-           "fem_batch_mesh_info", "fem_batch_add_job", "fem_batch_remove_job", "fem_batch_run", "fem_batch_job_info",
+           "fem_batch_mesh_info", "fem_batch_add_job", "fem_batch_restart_job", "fem_batch_remove_job", "fem_batch_run", "fem_batch_job_info",
            "fem_batch_get_displacements", "fem_batch_get_contact_patch", "fem_batch_set_kernel_timing",
-           "fem_batch_get_kernel_timing", "fem_status_string", "fem_last_error")
+           "fem_batch_get_kernel_timing", "fem_set_graphs", "fem_batch_set_graphs", "fem_status_string",
+           "fem_last_error")
 FEM_KERNEL_HV, FEM_KERNEL_CG_UPDATE, FEM_KERNEL_ELEMENT = 0, 1, 2
 
 
@@ -115,6 +116,7 @@ def load(path: str = LIB_PATH):
     L.fem_batch_add_mesh.argtypes = [vp, dp, C.c_int32, i32p, C.c_int32, u8p, i32p]
     L.fem_batch_mesh_info.argtypes = [vp, C.c_int32, C.POINTER(fem_mesh_layout)]
     L.fem_batch_add_job.argtypes = [vp, C.c_int32, C.c_double, C.c_double, C.POINTER(fem_indentation), i32p]
+    L.fem_batch_restart_job.argtypes = [vp, C.c_int32, C.c_double, C.c_double, C.POINTER(fem_indentation)]
     L.fem_batch_remove_job.argtypes = [vp, C.c_int32]
     L.fem_batch_run.argtypes = [vp, C.POINTER(fem_solve_params), C.c_int32, i32p]
     L.fem_batch_job_info.argtypes = [vp, C.c_int32, C.POINTER(fem_job_info)]
@@ -122,6 +124,8 @@ def load(path: str = LIB_PATH):
     L.fem_batch_get_contact_patch.argtypes = [vp, C.c_int32, i32p, dp, dp, C.c_int32, i32p, dp]
     L.fem_batch_set_kernel_timing.argtypes = [vp, C.c_int32]
     L.fem_batch_get_kernel_timing.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+    L.fem_set_graphs.argtypes = [vp, C.c_int32]
+    L.fem_batch_set_graphs.argtypes = [vp, C.c_int32]
     L.fem_status_string.argtypes = [C.c_int]
     L.fem_status_string.restype = C.c_char_p
     L.fem_last_error.argtypes = []
@@ -311,6 +315,9 @@ class FemMesh:
     def set_kernel_timing(self, every):
         fem_set_kernel_timing(self.h, every)
 
+    def set_graphs(self, enable):
+        _check(load().fem_set_graphs(self.h, int(enable)))
+
     def kernel_timing(self, kernel):
         return fem_get_kernel_timing(self.h, kernel)
 
@@ -381,6 +388,11 @@ def fem_batch_add_job(h, mesh_id: int, E: float, nu: float, ind) -> int:
     jid = C.c_int32()
     _check(load().fem_batch_add_job(h, int(mesh_id), float(E), float(nu), C.byref(job), C.byref(jid)))
     return jid.value
+
+
+def fem_batch_restart_job(h, job: int, E: float, nu: float, ind):
+    j = ind if isinstance(ind, fem_indentation) else make_indentation(ind)
+    _check(load().fem_batch_restart_job(h, int(job), float(E), float(nu), C.byref(j)))
 
 
 def fem_batch_remove_job(h, job: int):
@@ -467,6 +479,9 @@ class FemBatch:
         self.job_mesh[jid] = mesh_id
         return jid
 
+    def restart_job(self, job, ind, E=0.3e6, nu=0.45):
+        fem_batch_restart_job(self.h, job, E, nu, ind)
+
     def remove_job(self, job):
         fem_batch_remove_job(self.h, job)
         self.job_mesh.pop(job, None)
@@ -485,6 +500,9 @@ class FemBatch:
 
     def set_kernel_timing(self, every):
         fem_batch_set_kernel_timing(self.h, every)
+
+    def set_graphs(self, enable):
+        _check(load().fem_batch_set_graphs(self.h, int(enable)))
 
     def kernel_timing(self, kernel):
         return fem_batch_get_kernel_timing(self.h, kernel)

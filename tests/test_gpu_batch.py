@@ -137,3 +137,27 @@ def test_layout_covers_mesh():
     assert info["n_tiles"] >= mesh.m // 512
     assert mesh.n <= info["n_entries"] <= 2 * mesh.n
     batch.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_graph_replay_matches_stream_launches(precision):
+    """Rounds replayed from captured graphs (many replays, with host state
+    writes and synchronisations between them) give the results of rounds
+    launched kernel by kernel; kernel timing in graph mode records events."""
+    mesh = W.cube_block_mesh()
+    jobs = cube_jobs()
+    out = {}
+    for graphs in (1, 0):
+        batch = fem.FemBatch(len(jobs), precision)
+        batch.set_graphs(graphs)
+        batch.set_kernel_timing(4)
+        mid = batch.add_mesh(mesh.X, mesh.tets, mesh.fixed)
+        ids = [batch.add_job(mid, j, E0, NU0) for j in jobs]
+        assert batch.run(tight(batch, precision)) == 0
+        out[graphs] = [batch.displacements(j) for j in ids]
+        cnt, ms = batch.kernel_timing(fem.FEM_KERNEL_HV)
+        assert cnt > 0 and ms > 0
+        batch.close()
+    tol = 1e-9 if precision == "fp64" else 1e-5
+    for a, b in zip(out[1], out[0]):
+        assert e_inf(a, b) <= tol
