@@ -177,6 +177,105 @@ def roofline(r, word, jobs):
             {k: v["avg_us"] for k, v in per.items()})
 
 
+RESOLUTIONS = (5000, 20000, 50000, 120000)
+
+
+def uneven_jobs(count, seed0):
+    """Seeded mix: each job's resolution uniform over RESOLUTIONS, then its
+    indenter from the job seed."""
+    from paper_2103_16747_amd import workload as W
+
+    meshes = {r: W.fingertip_mesh(r) for r in RESOLUTIONS}
+    rng = W.Xoshiro256ss(seed0)
+    jobs = []
+    for i in range(count):
+        res = RESOLUTIONS[rng.below(len(RESOLUTIONS))]
+        jobs.append((res, W.seat_on_mesh(W.random_indentation(seed0 + 1 + i), meshes[res])))
+    return meshes, jobs
+
+
+def bench_uneven(args):
+    """64 jobs at mixed resolution in one batch, shapes from the autotuner,
+    against the same jobs solved one at a time (FP32 path both)."""
+    from paper_2103_16747_amd import autotune, fem
+
+    meshes, jobs = uneven_jobs(64, 4000)
+    tuned = autotune.tune([meshes[r] for r in RESOLUTIONS], "fp32", log=progress)
+    progress(f"autotune: tile {tuned['tile_tets']} chunk {tuned['chunk']}")
+    batch = fem.FemBatch(len(jobs), "fp32")
+    batch.set_option(fem.FEM_OPT_TILE_TETS, tuned["tile_tets"])
+    batch.set_option(fem.FEM_OPT_CG_CHUNK, tuned["chunk"])
+    mids = {r: batch.add_mesh(meshes[r].X, meshes[r].tets, meshes[r].fixed) for r in RESOLUTIONS}
+    ids = [batch.add_job(mids[r], ind) for r, ind in jobs]
+    batch.run()
+    for j, (r, ind) in zip(ids, jobs):
+        batch.restart_job(j, ind)
+    t0 = time.perf_counter()
+    batch.run()
+    wall = time.perf_counter() - t0
+    infos = [batch.job_info(j) for j in ids]
+    batch.close()
+    progress(f"uneven batch: {len(jobs)} jobs in {wall:.2f} s")
+    # unbatched reference: the first job of each resolution, one at a time
+    solo = {}
+    for r in RESOLUTIONS:
+        ind = next(ind for rr, ind in jobs if rr == r)
+        single = run_single(meshes[r], [ind], "fp32")
+        solo[r] = single["walls"][0]
+    per_job_solo = sum(solo[r] for r, _ in jobs)
+    tu = sum(i["tet_updates"] for i in infos)
+    return {"metric": METRIC, "value": len(jobs) / wall, "unit": "solves/s", "n_gpus": 1, "steps": 1,
+            "warmup": 1, "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "uneven batch: 64 synthetic-fingertip jobs at 5k/20k/50k/120k tets (uniform mix), "
+                                   "seeded indenters, 100 load steps each",
+                       "mix": {str(r): sum(1 for rr, _ in jobs if rr == r) for r in RESOLUTIONS},
+                       "autotuned": {"tile_tets": tuned["tile_tets"], "chunk": tuned["chunk"]}},
+            "tet_updates_per_s": tu / wall, "failed_load_steps": sum(i["steps_failed"] for i in infos),
+            "unbatched_estimate": {"solves_per_s": len(jobs) / per_job_solo,
+                                   "per_resolution_s": {str(r): solo[r] for r in RESOLUTIONS},
+                                   "note": "one job per resolution timed alone; the batch's jobs summed at those times"},
+            "speedup_vs_unbatched": per_job_solo / wall,
+            "autotune_table": tuned["table"]}
+
+
+def bench_serving(args):
+    """Poisson streams of mixed-resolution jobs through the serving loop
+    (admission by HBM footprint, continuous batching); p50/p99 latency and
+    solves/s per arrival rate, against one-at-a-time FP64 solves."""
+    from paper_2103_16747_amd import fem, workload as W
+    from paper_2103_16747_amd.serve import IndentationServer, Request, latency_summary
+
+    meshes, jobs = uneven_jobs(args.requests, 5000)
+    keyed = {str(r): meshes[r] for r in RESOLUTIONS}
+    out = {"metric": METRIC, "unit": "ms", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+           "dtype": "f32", "config": {"workload": f"serving: Poisson arrivals of {args.requests} mixed-resolution "
+                                                  "fingertip jobs per rate, 100 load steps each",
+                                      "hbm_budget_GiB": 64}, "rates": {}}
+    for rate in [float(x) for x in args.rates.split(",")]:
+        arrivals = W.poisson_arrivals(int(rate * 1000), rate, len(jobs))
+        reqs = [Request(i, float(t), str(r), ind) for i, (t, (r, ind)) in enumerate(zip(arrivals, jobs))]
+        batch = fem.FemBatch(len(jobs), "fp32")
+        srv = IndentationServer(batch, keyed, hbm_budget=64 << 30, max_jobs=len(jobs), rounds_per_poll=2)
+        res = srv.serve(reqs, timeout=600)
+        summ = latency_summary(res)
+        summ["peak_running"] = srv.stats.peak_running
+        out["rates"][str(rate)] = summ
+        batch.close()
+        progress(f"serving rate {rate}: p50 {summ['p50_ms']:.0f} ms p99 {summ['p99_ms']:.0f} ms "
+                 f"{summ['solves_per_s']:.1f} solves/s")
+    # one-at-a-time FP64 reference on the first job of each resolution
+    ref = {}
+    for r in RESOLUTIONS:
+        ind = next(ind for rr, ind in jobs if rr == r)
+        ref[str(r)] = run_single(meshes[r], [ind], "fp64")["walls"][0]
+    mean_one = sum(ref[str(r)] for r, _ in jobs) / len(jobs)
+    out["fp64_one_at_a_time"] = {"solves_per_s": 1.0 / mean_one, "per_resolution_s": ref}
+    last = out["rates"][max(out["rates"], key=float)]
+    out["value"] = last["p99_ms"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +288,13 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--timing-every", type=int, default=8)
+    ap.add_argument("--config", choices=("batched", "uneven", "serving"), default="batched",
+                    help="batched: 256 jobs on the 50k fingertip (default); uneven: 64 jobs at 5k-120k tets with "
+                         "autotuned shapes; serving: Poisson request streams through the serving loop")
+    ap.add_argument("--rates", default="10,50,200", help="serving: arrival rates (req/s)")
+    ap.add_argument("--requests", type=int, default=48, help="serving: requests per rate")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="before the solves, one device copy of this many MiB (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: each batch of indentation jobs runs on a single MI355X and this build "
@@ -201,6 +307,18 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU visible"
     fem.load()
+    if args.copy_mb > 0:
+        src = torch.ones(args.copy_mb << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.config == "uneven":
+        print(json.dumps(bench_uneven(args)), flush=True)
+        return
+    if args.config == "serving":
+        print(json.dumps(bench_serving(args)), flush=True)
+        return
     mesh = W.fingertip_mesh(50000)
     inds = [W.seat_on_mesh(W.random_indentation(3000 + i), mesh) for i in range(args.jobs)]
 
@@ -239,6 +357,16 @@ def main():
         "cg_iters_per_job": float(np.mean([s["cg_iters"] for s in r32["stats"]])),
         "newton_iters_per_job": float(np.mean([s["newton_iters"] for s in r32["stats"]])),
     }
+    gold_path = os.path.join(ROOT, "tests", "golden", "fingertip50k_oracle.npz")
+    if os.path.exists(gold_path):
+        gold = np.load(gold_path)
+        errs = {}
+        for i, u in enumerate(r32["finals"]):
+            key = f"u100_{3000 + i}"
+            st = gold.get(f"status_{3000 + i}")
+            if key in gold and st is not None and not np.any(st != 0):
+                errs[str(3000 + i)] = float(np.abs(u - gold[key]).max() / np.abs(gold[key]).max())
+        out["e_inf_vs_fp64_oracle"] = errs
     rl, kav = roofline(r32, 4, J)
     if rl:
         out["roofline"] = rl

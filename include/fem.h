@@ -276,6 +276,21 @@ int fem_batch_get_kernel_timing(const fem_batch *batch, int32_t kernel, int64_t 
 int fem_set_graphs(fem_mesh *mesh, int32_t enable);
 int fem_batch_set_graphs(fem_batch *batch, int32_t enable);
 
+/* Batch tuning options (set before fem_batch_run; tile limits apply to meshes
+ * added afterwards):
+ *   FEM_OPT_CG_CHUNK   CG iterations per round, 1..64 (0 = automatic);
+ *   FEM_OPT_TILE_TETS  tets per tile, 64..512 (default 512);
+ *   FEM_OPT_TILE_NODES distinct nodes per tile, 16..256 (default 256).
+ * Errors: FEM_E_INVALID (unknown option, value out of range). */
+#define FEM_OPT_CG_CHUNK 0
+#define FEM_OPT_TILE_TETS 1
+#define FEM_OPT_TILE_NODES 2
+int fem_batch_set_option(fem_batch *batch, int32_t option, int32_t value);
+
+/* Device bytes one job on mesh mesh_id allocates (for admission by HBM
+ * footprint); the mesh itself is shared and not included. */
+int fem_batch_job_footprint(const fem_batch *batch, int32_t mesh_id, int64_t *bytes);
+
 /* Static text for a status code. */
 const char *fem_status_string(int status);
 

@@ -88,7 +88,7 @@ uint32_t spread_bits(uint32_t v) {   // 10 bits -> every third bit
 
 // Tets in Morton order of their centroids, cut greedily into tiles of at most
 // kTileTets tets and kTileNodes distinct nodes.
-void build_layout(const double *X, int n, const int32_t *tets, int m, HostLayout &L) {
+void build_layout(const double *X, int n, const int32_t *tets, int m, int max_tets, int max_nodes, HostLayout &L) {
     L.n = n;
     L.m = m;
     double lo[3] = {X[0], X[1], X[2]}, hi[3] = {X[0], X[1], X[2]};
@@ -147,7 +147,7 @@ void build_layout(const double *X, int n, const int32_t *tets, int m, HostLayout
             const int v = tets[4 * e + a];
             if (stamp[v] != tile) fresh++;
         }
-        if (tile_tets == kTileTets || tile_nodes + fresh > kTileNodes) close_tile();
+        if (tile_tets == max_tets || tile_nodes + fresh > max_nodes) close_tile();
         for (int a = 0; a < 4; a++) {
             const int v = tets[4 * e + a];
             if (stamp[v] != tile) {
@@ -238,6 +238,8 @@ struct fem_batch {
     size_t h_stage_bytes = 0;
     KernelTimer timer;
     bool use_graphs = true;
+    int chunk = 0;                          // CG iterations per round (0 = automatic)
+    int tile_tets = kTileTets, tile_nodes = kTileNodes;   // layout limits for meshes added next
     std::vector<RoundGraph> graphs;
     int pending_graph = -1;   // timed graph launched since the last harvest
     size_t elem() const { return precision == FEM_PREC_FP32 ? sizeof(float) : sizeof(double); }
@@ -334,7 +336,7 @@ template <> Topo<double> &topo_view<double>(TopoRec &R) { return R.v64; }
 template <typename T>
 int add_topology(fem_batch *B, const double *X, int n, const int32_t *tets, int m, const uint8_t *fixed, int *id) {
     HostLayout L;
-    build_layout(X, n, tets, m, L);
+    build_layout(X, n, tets, m, B->tile_tets, B->tile_nodes, L);
     TopoRec R;
     R.n = n;
     R.m = m;
@@ -661,8 +663,8 @@ int run_impl(fem_batch *B, int max_rounds, int *n_running) {
         if (running == 0 || (max_rounds > 0 && rounds >= max_rounds)) break;
         // CG iterations per round: a fixed 16 for batches; for one job, what
         // its current CG solve is expected to need from the previous one.
-        int chunk = 16;
-        if (running == 1) {
+        int chunk = B->chunk > 0 ? B->chunk : 16;
+        if (running == 1 && B->chunk <= 0) {
             const InstState &s = B->h_states[single];
             const int expect = s.last_cg > 0 ? s.last_cg : 16;
             chunk = s.phase == PH_CG ? std::max(4, std::min(64, expect - s.cg_it)) : std::max(4, std::min(64, expect));
@@ -1356,6 +1358,46 @@ int fem_batch_set_graphs(fem_batch *B, int32_t enable) {
 }
 
 int fem_set_graphs(fem_mesh *M, int32_t enable) { return fem_batch_set_graphs(M ? M->batch : nullptr, enable); }
+
+int fem_batch_set_option(fem_batch *B, int32_t option, int32_t value) {
+    g_last_error.clear();
+    if (!B) return fail(FEM_E_INVALID, "null batch");
+    switch (option) {
+    case FEM_OPT_CG_CHUNK:
+        if (value < 0 || value > 64) return fail(FEM_E_INVALID, "chunk must be 0..64");
+        B->chunk = value;
+        return FEM_OK;
+    case FEM_OPT_TILE_TETS:
+        if (value < 64 || value > kTileTets) return fail(FEM_E_INVALID, "tile tets must be 64..512");
+        B->tile_tets = value;
+        return FEM_OK;
+    case FEM_OPT_TILE_NODES:
+        if (value < 16 || value > kTileNodes) return fail(FEM_E_INVALID, "tile nodes must be 16..256");
+        B->tile_nodes = value;
+        return FEM_OK;
+    default:
+        return fail(FEM_E_INVALID, "unknown option");
+    }
+}
+
+int fem_batch_job_footprint(const fem_batch *B, int32_t mesh_id, int64_t *bytes) {
+    g_last_error.clear();
+    if (!B || !bytes || mesh_id < 0 || mesh_id >= (int)B->topos.size()) return fail(FEM_E_INVALID, "unknown mesh");
+    const TopoRec &tp = B->topos[mesh_id];
+    const size_t w = B->elem();
+    const size_t stride = std::max(tp.ntile + tp.ncb, ceil_div(tp.n, kBlock));
+    // the arena of alloc_instance, with its 256-byte alignment padding
+    size_t total = 0;
+    auto add = [&](size_t b) { total += (b + 255) & ~size_t(255); };
+    for (int k = 0; k < 7; k++) add(3 * (size_t)tp.n * w);
+    add(6 * (size_t)tp.n * w);
+    add(9 * (size_t)tp.nent * w);
+    add(3 * (size_t)tp.nent * w);
+    add(9 * (size_t)std::max(tp.nc, 1) * w);
+    add(RS_COUNT * stride * sizeof(double));
+    *bytes = (int64_t)total;
+    return FEM_OK;
+}
 
 int fem_batch_mesh_info(const fem_batch *B, int32_t mesh_id, fem_mesh_layout *info) {
     g_last_error.clear();

@@ -29,9 +29,11 @@ EXPORTS = ("fem_create_mesh", "fem_destroy_mesh", "fem_set_material", "fem_set_i
            "fem_get_kernel_timing", "fem_batch_create", "fem_batch_destroy", "fem_batch_add_mesh",
            "fem_batch_mesh_info", "fem_batch_add_job", "fem_batch_restart_job", "fem_batch_remove_job", "fem_batch_run", "fem_batch_job_info",
            "fem_batch_get_displacements", "fem_batch_get_contact_patch", "fem_batch_set_kernel_timing",
-           "fem_batch_get_kernel_timing", "fem_set_graphs", "fem_batch_set_graphs", "fem_status_string",
+           "fem_batch_get_kernel_timing", "fem_set_graphs", "fem_batch_set_graphs", "fem_batch_set_option",
+           "fem_batch_job_footprint", "fem_status_string",
            "fem_last_error")
 FEM_KERNEL_HV, FEM_KERNEL_CG_UPDATE, FEM_KERNEL_ELEMENT = 0, 1, 2
+FEM_OPT_CG_CHUNK, FEM_OPT_TILE_TETS, FEM_OPT_TILE_NODES = 0, 1, 2
 
 
 class FemError(RuntimeError):
@@ -126,6 +128,8 @@ def load(path: str = LIB_PATH):
     L.fem_batch_get_kernel_timing.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
     L.fem_set_graphs.argtypes = [vp, C.c_int32]
     L.fem_batch_set_graphs.argtypes = [vp, C.c_int32]
+    L.fem_batch_set_option.argtypes = [vp, C.c_int32, C.c_int32]
+    L.fem_batch_job_footprint.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64)]
     L.fem_status_string.argtypes = [C.c_int]
     L.fem_status_string.restype = C.c_char_p
     L.fem_last_error.argtypes = []
@@ -503,6 +507,14 @@ class FemBatch:
 
     def set_graphs(self, enable):
         _check(load().fem_batch_set_graphs(self.h, int(enable)))
+
+    def set_option(self, option, value):
+        _check(load().fem_batch_set_option(self.h, int(option), int(value)))
+
+    def job_footprint(self, mesh_id):
+        b = C.c_int64()
+        _check(load().fem_batch_job_footprint(self.h, int(mesh_id), C.byref(b)))
+        return b.value
 
     def kernel_timing(self, kernel):
         return fem_batch_get_kernel_timing(self.h, kernel)

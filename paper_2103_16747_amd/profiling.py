@@ -1,0 +1,115 @@
+"""Summaries of rocprofv3 CSV output for the indentation kernels.
+
+    python -m paper_2103_16747_amd.profiling stats  <rocprof dir> [--kernel REGEX]
+    python -m paper_2103_16747_amd.profiling traffic <fetch dir> <write dir> --copy-bytes N [--kernel REGEX]
+
+`stats` reads a --kernel-trace --stats run (kernel_stats.csv / kernel_trace.csv)
+and prints per-kernel calls and durations. `traffic` reads two --pmc runs, one
+with FETCH_SIZE and one with WRITE_SIZE (KiB per dispatch), and converts them
+to bytes with the ratio the same counters give for a plain device copy of
+N bytes in the same process (the benchmark's --copy-mb option), reporting the
+per-dispatch HBM traffic of the matching kernels.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import os
+import re
+import statistics
+import sys
+
+
+def _find(d, suffix):
+    hits = sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def kernel_stats(d, pattern=None):
+    rows = list(csv.DictReader(open(_find(d, "kernel_stats.csv"))))
+    out = []
+    for r in rows:
+        if pattern and not re.search(pattern, r["Name"]):
+            continue
+        out.append({"name": r["Name"], "calls": int(r["Calls"]), "avg_us": float(r["AverageNs"]) / 1e3,
+                    "min_us": float(r["MinNs"]) / 1e3, "max_us": float(r["MaxNs"]) / 1e3,
+                    "total_ms": float(r["TotalDurationNs"]) / 1e6, "pct": float(r["Percentage"])})
+    return out
+
+
+def busy_kernel_stats(d, pattern, floor_us):
+    """Durations of dispatches of `pattern` longer than floor_us (dispatches
+    whose jobs were all in other solver phases exit at once and are left
+    out), from kernel_trace.csv."""
+    durs = []
+    for r in csv.DictReader(open(_find(d, "kernel_trace.csv"))):
+        if re.search(pattern, r["Kernel_Name"]):
+            us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            if us >= floor_us:
+                durs.append(us)
+    if not durs:
+        return None
+    return {"dispatches": len(durs), "avg_us": statistics.mean(durs), "median_us": statistics.median(durs)}
+
+
+def counters(d):
+    per = {}
+    for r in csv.DictReader(open(_find(d, "counter_collection.csv"))):
+        per.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return per
+
+
+def traffic(fetch_dir, write_dir, copy_bytes, pattern, copy_pattern=r"copy|elementwise|Copy"):
+    fc, wc = counters(fetch_dir), counters(write_dir)
+
+    def pick(cs, name, pat):
+        vals = [v for k, m in cs.items() if re.search(pat, k) for v in m.get(name, [])]
+        return vals
+
+    cf = pick(fc, "FETCH_SIZE", copy_pattern)
+    cw = pick(wc, "WRITE_SIZE", copy_pattern)
+    if not cf or not cw:
+        raise RuntimeError("no copy-kernel counters found")
+    # the largest copy dispatch is the calibration copy
+    f_scale = copy_bytes / (max(cf) * 1024.0)
+    w_scale = copy_bytes / (max(cw) * 1024.0)
+    kf = pick(fc, "FETCH_SIZE", pattern)
+    kw = pick(wc, "WRITE_SIZE", pattern)
+    kf_busy = [v for v in kf if v > 0.05 * max(kf)] if kf else []
+    kw_busy = [v for v in kw if v > 0.05 * max(kw)] if kw else []
+    return {"copy_fetch_KiB": max(cf), "copy_write_KiB": max(cw), "fetch_scale": f_scale, "write_scale": w_scale,
+            "dispatches": len(kf_busy),
+            "fetch_bytes_per_dispatch": statistics.mean(kf_busy) * 1024.0 * f_scale if kf_busy else None,
+            "write_bytes_per_dispatch": statistics.mean(kw_busy) * 1024.0 * w_scale if kw_busy else None}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("dir")
+    a.add_argument("--kernel", default=None)
+    a.add_argument("--busy-floor-us", type=float, default=0.0)
+    b = sub.add_parser("traffic")
+    b.add_argument("fetch_dir")
+    b.add_argument("write_dir")
+    b.add_argument("--copy-bytes", type=float, required=True)
+    b.add_argument("--kernel", required=True)
+    args = ap.parse_args(argv)
+    if args.cmd == "stats":
+        for r in kernel_stats(args.dir, args.kernel):
+            print(f"{r['name'][:72]:72s} calls={r['calls']:7d} avg={r['avg_us']:9.2f}us min={r['min_us']:8.2f}us "
+                  f"max={r['max_us']:9.2f}us total={r['total_ms']:9.2f}ms {r['pct']:5.1f}%")
+        if args.kernel and args.busy_floor_us > 0:
+            print("busy dispatches:", busy_kernel_stats(args.dir, args.kernel, args.busy_floor_us))
+    else:
+        t = traffic(args.fetch_dir, args.write_dir, args.copy_bytes, args.kernel)
+        for k, v in t.items():
+            print(f"{k}: {v}")
+
+
+if __name__ == "__main__":
+    sys.exit(main())
