@@ -179,9 +179,9 @@ int fem_eval_hessvec(fem_mesh *mesh, const fem_solve_params *params, const doubl
 
 /* Kernel timing (measurement aid, not part of the solve). With every > 0,
  * HIP events on the handle's stream bracket every every-th launch of the
- * timed kernels (with graphs on: the first Hv and update launch and the
- * element launch of every round); every = 0 turns timing off. Counters are
- * cleared on each call. */
+ * timed kernels, and rounds are launched kernel by kernel rather than from a
+ * captured graph; every = 0 turns timing off. Counters are cleared on each
+ * call. */
 #define FEM_KERNEL_HV 0           /* Hessian-vector half of a CG iteration */
 #define FEM_KERNEL_CG_UPDATE 1    /* vector-update half of a CG iteration */
 #define FEM_KERNEL_ELEMENT 2      /* element + contact pass (gradient / trial) */

@@ -187,13 +187,10 @@ struct KernelTimer {
     bool created = false;
 };
 
-// A captured round of kernels for one CG chunk length (optionally with event
-// records around the first Hv, update and element launches).
+// A captured round of kernels for one CG chunk length.
 struct RoundGraph {
     int chunk = 0;
-    bool timed = false;
     hipGraphExec_t exec = nullptr;
-    hipEvent_t ev[3][2] = {};
 };
 
 struct TopoRec {
@@ -241,7 +238,6 @@ struct fem_batch {
     int chunk = 0;                          // CG iterations per round (0 = automatic)
     int tile_tets = kTileTets, tile_nodes = kTileNodes;   // layout limits for meshes added next
     std::vector<RoundGraph> graphs;
-    int pending_graph = -1;   // timed graph launched since the last harvest
     size_t elem() const { return precision == FEM_PREC_FP32 ? sizeof(float) : sizeof(double); }
 };
 
@@ -286,17 +282,6 @@ void timer_end(fem_batch *B, int slot) {
 
 void timer_harvest(fem_batch *B) {
     KernelTimer &t = B->timer;
-    if (B->pending_graph >= 0) {
-        RoundGraph &G = B->graphs[B->pending_graph];
-        for (int k = 0; k < 3; k++) {
-            float ms = 0.0f;
-            if (hipEventElapsedTime(&ms, G.ev[k][0], G.ev[k][1]) == hipSuccess) {
-                t.count[k]++;
-                t.total_ms[k] += ms;
-            }
-        }
-        B->pending_graph = -1;
-    }
     for (int i = 0; i < t.used; i++) {
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, t.ev[i][0], t.ev[i][1]) == hipSuccess) {
@@ -309,21 +294,14 @@ void timer_harvest(fem_batch *B) {
 
 int sync(fem_batch *B) {
     HIP_TRY(hipStreamSynchronize(B->stream));
-    if (B->timer.used || B->pending_graph >= 0) timer_harvest(B);
+    if (B->timer.used) timer_harvest(B);
     return FEM_OK;
 }
 
 void drop_graphs(fem_batch *B) {
-    for (RoundGraph &G : B->graphs) {
+    for (RoundGraph &G : B->graphs)
         if (G.exec) (void)hipGraphExecDestroy(G.exec);
-        if (G.timed)
-            for (int k = 0; k < 3; k++) {
-                (void)hipEventDestroy(G.ev[k][0]);
-                (void)hipEventDestroy(G.ev[k][1]);
-            }
-    }
     B->graphs.clear();
-    B->pending_graph = -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -576,8 +554,7 @@ int write_state(fem_batch *B, int slot) {
 inline bool running_phase(int ph) { return ph != PH_IDLE && ph != PH_DONE; }
 
 // One round: (Hv, update, finalize) x C, dot, element pass, finalize, init,
-// finalize. ev (optional) brackets the first Hv, first update and the element
-// launch with event records.
+// finalize. With kernel timing on, sampled launches are bracketed by events.
 template <typename T>
 int enqueue_round(fem_batch *B, int chunk, hipEvent_t (*ev)[2]) {
     const Topo<T> *tp = (const Topo<T> *)B->d_topos;
@@ -609,29 +586,24 @@ int enqueue_round(fem_batch *B, int chunk, hipEvent_t (*ev)[2]) {
 }
 
 // Launches a round, replaying a captured graph for the chunk length when
-// graphs are on (chunks are powers of two from 4 to 64).
+// graphs are on (chunks are powers of two from 4 to 64). With kernel timing
+// on, rounds are launched kernel by kernel so events can bracket single
+// kernels (event records cannot be captured into the graph here).
 template <typename T>
 int launch_round(fem_batch *B, int chunk) {
     if (pad8(B->nwork_tile) == 0 || pad8(B->nwork_node) == 0 || B->nlive == 0) return FEM_OK;
-    if (!B->use_graphs) return enqueue_round<T>(B, chunk, nullptr);
+    if (!B->use_graphs || B->timer.every > 0) return enqueue_round<T>(B, chunk, nullptr);
     int c = 4;
     while (c < chunk && c < 64) c <<= 1;
-    const bool timed = B->timer.every > 0;
     int gi = -1;
     for (int i = 0; i < (int)B->graphs.size(); i++)
-        if (B->graphs[i].chunk == c && B->graphs[i].timed == timed) gi = i;
+        if (B->graphs[i].chunk == c) gi = i;
     if (gi < 0) {
         RoundGraph G;
         G.chunk = c;
-        G.timed = timed;
-        if (timed)
-            for (int k = 0; k < 3; k++) {
-                HIP_TRY(hipEventCreate(&G.ev[k][0]));
-                HIP_TRY(hipEventCreate(&G.ev[k][1]));
-            }
         hipGraph_t graph = nullptr;
         HIP_TRY(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
-        const int rc = enqueue_round<T>(B, c, timed ? G.ev : nullptr);
+        const int rc = enqueue_round<T>(B, c, nullptr);
         const hipError_t ec = hipStreamEndCapture(B->stream, &graph);
         if (rc) return rc;
         if (ec != hipSuccess) return fail(FEM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
@@ -642,7 +614,6 @@ int launch_round(fem_batch *B, int chunk) {
         gi = (int)B->graphs.size() - 1;
     }
     HIP_TRY(hipGraphLaunch(B->graphs[gi].exec, B->stream));
-    if (timed) B->pending_graph = gi;
     return FEM_OK;
 }
 
@@ -1329,7 +1300,6 @@ int fem_batch_set_kernel_timing(fem_batch *B, int32_t every) {
     }
     TRY(sync(B));
     t.used = 0;
-    B->pending_graph = -1;
     t.every = every;
     for (int k = 0; k < KernelTimer::kKinds; k++) {
         t.seen[k] = 0;

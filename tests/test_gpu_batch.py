@@ -143,7 +143,7 @@ def test_layout_covers_mesh():
 def test_graph_replay_matches_stream_launches(precision):
     """Rounds replayed from captured graphs (many replays, with host state
     writes and synchronisations between them) give the results of rounds
-    launched kernel by kernel; kernel timing in graph mode records events."""
+    launched kernel by kernel; kernel timing (which launches kernel by kernel) records events."""
     mesh = W.cube_block_mesh()
     jobs = cube_jobs()
     out = {}
