@@ -31,30 +31,39 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "FEM indentation solves/s + tet-updates/s, FP32 vs FP64 path; p50/p99 latency"
 
 
-def algorithmic_bytes(kernel, info, word, jobs):
-    """Algorithmic HBM bytes of one launch of a CG kernel over `jobs` jobs of
-    one mesh (ideal reuse: every node value read once per job, every tile
-    entry partial written or read once).
+# Algorithmic arithmetic per tet of the two tile-kernel paths (an FMA counts
+# two; one transcendental counts one; FP64 LDS accumulation and conversions
+# are not counted; the derivation is in the design notes):
+#   Hessian-vector: G from u (54), J - 1 (30), ln J series and c (16),
+#   F^-T (40), dG from p (54), A = F^-1 dG and its trace (47), dP (91),
+#   nodal forces (60), p.q (25)                                  -> 417
+#   element: G (54), J - 1 (30), ln J (1), energy and magnitude (36),
+#   F^-T (40), P (82), nodal forces (60), node diagonal blocks (161) -> 464
+FLOPS_PER_TET = {"hv": 417, "element": 464}
+FP32_VECTOR_PEAK_TFLOPS = 157.3      # 256 CU x 64 lanes x 2 x 2.4 GHz x 2 (packed FP32)
+FP32_NONPACKED_PEAK_TFLOPS = 78.6    # the same without packed FP32, which this build does not emit
 
-    Hessian-vector (k_hv): shared per launch the packed local ids (4 B/tet)
-    and per tile entry its node id and tile coordinates (4 + 3 words); per job
-    the reads of u, z and p_prev (9 words per node), the write of the q
-    partial (3 words per entry) and the contact blocks (6 words per
-    contact-eligible node).
-    CG update (k_update): shared the node -> entry CSR (4 B per entry and per
-    node) and the fixed / contact-slot maps (5 B per node); per job the reads
-    of p, z, r, dx (12 words per node), the block-Jacobi inverse (6 words per
-    node), the q partials (3 words per entry), the contact blocks (6 words per
-    eligible node) and the writes of p, dx, r, z (12 words per node).
+
+def tile_bytes(info, word, hv_passes, el_passes, launches):
+    """Algorithmic HBM bytes per launch of the tile kernel, averaged over
+    `launches` launches that made hv_passes Hessian-vector passes and
+    el_passes element passes in all (ideal reuse: every value read or written
+    once per pass; the mesh constants once per launch).
+
+    Shared per launch: packed local ids (4 B/tet), D_m^-1 and V (10 words per
+    tet), the entry -> node map (4 B per entry).
+    Hessian-vector pass, per job: reads of u, z, p_prev (9 words per node),
+    write of the q partials (3 words per entry), contact blocks (6 words per
+    eligible node).
+    Element pass, per job: reads of u and dx (6 words per node), write of the
+    gradient + block partials (9 words per entry), contact node coordinates
+    (3 doubles) and contact outputs (9 words) per eligible node.
     """
     n, m, nent, nc = info["n_nodes"], info["n_tets"], info["n_entries"], info["n_eligible"]
-    if kernel == "hv":
-        shared = 4 * m + nent * (4 + 3 * word)
-        per_job = 9 * word * n + 3 * word * nent + 6 * word * nc
-    else:
-        shared = 4 * nent + 4 * (n + 1) + 5 * n
-        per_job = 30 * word * n + 3 * word * nent + 6 * word * nc
-    return shared + jobs * per_job
+    shared = m * (4 + 10 * word) + 4 * nent
+    hv = 9 * word * n + 3 * word * nent + 6 * word * nc
+    el = 6 * word * n + 9 * word * nent + (24 + 9 * word) * nc
+    return shared + (hv_passes * hv + el_passes * el) / max(launches, 1)
 
 
 def progress(*a):
@@ -76,7 +85,7 @@ def run_batched(mesh, inds, precision, timed_steps, warm_steps, timing_every=0, 
         progress(f"warm-up batch {precision} done")
     if timing_every:
         batch.set_kernel_timing(timing_every)
-    walls, lat, tu, failed = [], [], 0, 0
+    walls, lat, tu, failed, hv, gp = [], [], 0, 0, 0, 0
     for _ in range(timed_steps):
         for j, ind in zip(jobs, inds):
             batch.restart_job(j, ind)
@@ -95,17 +104,19 @@ def run_batched(mesh, inds, precision, timed_steps, warm_steps, timing_every=0, 
         infos = [batch.job_info(j) for j in jobs]
         tu += sum(i["tet_updates"] for i in infos)
         failed += sum(i["steps_failed"] for i in infos)
+        hv += sum(i["hv_products"] for i in infos)
+        gp += sum(i["grad_passes"] for i in infos)
         lat += list(done_at.values())
     timing = None
     if timing_every:
-        timing = {k: batch.kernel_timing(k) for k in (fem.FEM_KERNEL_HV, fem.FEM_KERNEL_CG_UPDATE,
-                                                      fem.FEM_KERNEL_ELEMENT)}
+        timing = {k: batch.kernel_timing(k) + (batch.kernel_launches(k),)
+                  for k in (fem.FEM_KERNEL_TILE, fem.FEM_KERNEL_NODE, fem.FEM_KERNEL_FINALIZE)}
         batch.set_kernel_timing(0)
     finals = [batch.displacements(j) for j in jobs[:4]]
     stats = [batch.job_info(j) for j in jobs]
     batch.close()
     return {"walls": walls, "lat": lat, "tet_updates": tu, "failed_steps": failed, "timing": timing,
-            "layout": info, "finals": finals, "stats": stats}
+            "hv_passes": hv, "grad_passes": gp, "layout": info, "finals": finals, "stats": stats}
 
 
 def run_single(mesh, inds, precision):
@@ -154,26 +165,38 @@ def cpu_baseline(mesh, ind, seconds):
                       f"on the {mesh.m}-tet fingertip ({el:.1f} s); solves/s = ({steps}/{ind.steps}) / time"}
 
 
-def roofline(r, word, jobs):
+def roofline(r, word):
+    """Roofline of the tile kernel (the dominant one) over the timed region:
+    algorithmic flops per launch (the passes the jobs made, times the tets per
+    pass and FLOPS_PER_TET, over the number of launches) divided by the mean
+    event-timed duration of the sampled launches."""
     from paper_2103_16747_amd import fem
 
     tm = r["timing"]
     if not tm:
         return None, None
     per = {}
-    for name, k in (("hv", fem.FEM_KERNEL_HV), ("update", fem.FEM_KERNEL_CG_UPDATE), ("element", fem.FEM_KERNEL_ELEMENT)):
-        cnt, ms = tm[k]
-        per[name] = {"sampled_launches": cnt, "avg_us": (ms / cnt * 1e3) if cnt else None, "total_ms": ms}
-    # Dominant CG kernel: the larger summed event time.
-    dom = max(("hv", "update"), key=lambda k: per[k]["total_ms"])
-    avg_s = per[dom]["avg_us"] * 1e-6
-    byts = algorithmic_bytes(dom, r["layout"], word, jobs)
-    achieved = byts / avg_s / 1e9
-    kname = {"hv": "k_hv", "update": "k_update"}[dom] + ("<float>" if word == 4 else "<double>")
-    return ({"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-             "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_launch_us": per[dom]["avg_us"],
-             "sampled_launches": per[dom]["sampled_launches"], "algorithmic_bytes_per_launch": byts,
-             "jobs_per_launch": jobs, "bytes_per_tet_update": byts / (jobs * r["layout"]["n_tets"])},
+    for name, k in (("tile", fem.FEM_KERNEL_TILE), ("node", fem.FEM_KERNEL_NODE), ("finalize", fem.FEM_KERNEL_FINALIZE)):
+        cnt, ms, launches = tm[k]
+        per[name] = {"sampled": cnt, "launches": launches, "avg_us": (ms / cnt * 1e3) if cnt else None}
+    t = per["tile"]
+    if not t["sampled"]:
+        return None, None
+    m = r["layout"]["n_tets"]
+    flops = m * (r["hv_passes"] * FLOPS_PER_TET["hv"] + r["grad_passes"] * FLOPS_PER_TET["element"])
+    per_launch = flops / t["launches"]
+    avg_s = t["avg_us"] * 1e-6
+    achieved = per_launch / avg_s / 1e12
+    byts = tile_bytes(r["layout"], word, r["hv_passes"], r["grad_passes"], t["launches"])
+    kname = "k_tile<float>" if word == 4 else "k_tile<double>"
+    return ({"bound": "alu", "kernel": kname, "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+             "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+             "frac_of_non_packed_peak": achieved / FP32_NONPACKED_PEAK_TFLOPS,
+             "avg_launch_us": t["avg_us"], "sampled_launches": t["sampled"], "launches": t["launches"],
+             "flops_per_launch": per_launch,
+             "tet_updates_per_launch": m * (r["hv_passes"] + r["grad_passes"]) / t["launches"],
+             "hbm_model": {"algorithmic_bytes_per_launch": byts, "GB_per_s": byts / avg_s / 1e9,
+                           "frac_of_hbm_peak": byts / avg_s / 1e9 / HBM_PEAK_GBS}},
             {k: v["avg_us"] for k, v in per.items()})
 
 
@@ -204,7 +227,7 @@ def bench_uneven(args):
     progress(f"autotune: tile {tuned['tile_tets']} chunk {tuned['chunk']}")
     batch = fem.FemBatch(len(jobs), "fp32")
     batch.set_option(fem.FEM_OPT_TILE_TETS, tuned["tile_tets"])
-    batch.set_option(fem.FEM_OPT_CG_CHUNK, tuned["chunk"])
+    batch.set_option(fem.FEM_OPT_ROUND_STEPS, tuned["chunk"])
     mids = {r: batch.add_mesh(meshes[r].X, meshes[r].tets, meshes[r].fixed) for r in RESOLUTIONS}
     ids = [batch.add_job(mids[r], ind) for r, ind in jobs]
     batch.run()
@@ -367,7 +390,7 @@ def main():
             if key in gold and st is not None and not np.any(st != 0):
                 errs[str(3000 + i)] = float(np.abs(u - gold[key]).max() / np.abs(gold[key]).max())
         out["e_inf_vs_fp64_oracle"] = errs
-    rl, kav = roofline(r32, 4, J)
+    rl, kav = roofline(r32, 4)
     if rl:
         out["roofline"] = rl
         out["kernel_avg_us"] = kav

@@ -177,14 +177,17 @@ int fem_eval_gradient(fem_mesh *mesh, double *g, int64_t capacity, double *energ
  * params NULL = defaults). v and q are n x 3. Errors: FEM_E_STATE, FEM_E_BUFFER. */
 int fem_eval_hessvec(fem_mesh *mesh, const fem_solve_params *params, const double *v, double *q, int64_t capacity);
 
-/* Kernel timing (measurement aid, not part of the solve). With every > 0,
- * HIP events on the handle's stream bracket every every-th launch of the
- * timed kernels, and rounds are launched kernel by kernel rather than from a
- * captured graph; every = 0 turns timing off. Counters are cleared on each
- * call. */
-#define FEM_KERNEL_HV 0           /* Hessian-vector half of a CG iteration */
-#define FEM_KERNEL_CG_UPDATE 1    /* vector-update half of a CG iteration */
-#define FEM_KERNEL_ELEMENT 2      /* element + contact pass (gradient / trial) */
+/* Kernel timing (measurement aid, not part of the solve). A solver step is
+ * three kernels over every live job: the tile pass (per job the matrix-free
+ * Hessian-vector product during CG, the element + contact pass of a gradient
+ * or line-search trial otherwise), the node pass (CG update, Newton init,
+ * line-search directional derivative) and the finalize. With every > 0, HIP
+ * events on the handle's stream bracket every every-th launch of each, and
+ * rounds are launched kernel by kernel rather than from a captured graph;
+ * every = 0 turns timing off. Counters are cleared on each call. */
+#define FEM_KERNEL_TILE 0
+#define FEM_KERNEL_NODE 1
+#define FEM_KERNEL_FINALIZE 2
 int fem_set_kernel_timing(fem_mesh *mesh, int32_t every);
 
 /* Sampled launches of one timed kernel so far and their summed event-to-event
@@ -270,19 +273,24 @@ int fem_batch_get_contact_patch(fem_batch *batch, int32_t job_id, int32_t *ids, 
 int fem_batch_set_kernel_timing(fem_batch *batch, int32_t every);
 int fem_batch_get_kernel_timing(const fem_batch *batch, int32_t kernel, int64_t *count, double *total_ms);
 
+/* Launches of one timed kernel since timing was turned on (sampled or not). */
+int fem_batch_get_kernel_launches(const fem_batch *batch, int32_t kernel, int64_t *launches);
+
 /* Launch mode: with enable != 0 (the default) each round of kernels is
- * captured once per CG chunk length into a HIP graph and replayed; 0 launches
+ * captured once per round length into a HIP graph and replayed; 0 launches
  * the kernels one by one. Results are the same either way. */
 int fem_set_graphs(fem_mesh *mesh, int32_t enable);
 int fem_batch_set_graphs(fem_batch *batch, int32_t enable);
 
 /* Batch tuning options (set before fem_batch_run; tile limits apply to meshes
  * added afterwards):
- *   FEM_OPT_CG_CHUNK   CG iterations per round, 1..64 (0 = automatic);
+ *   FEM_OPT_ROUND_STEPS solver steps per round between host polls, 1..64
+ *                      (0 = automatic: 16 for batches, the expected length
+ *                      of the Newton iteration for a single job);
  *   FEM_OPT_TILE_TETS  tets per tile, 64..512 (default 512);
  *   FEM_OPT_TILE_NODES distinct nodes per tile, 16..256 (default 256).
  * Errors: FEM_E_INVALID (unknown option, value out of range). */
-#define FEM_OPT_CG_CHUNK 0
+#define FEM_OPT_ROUND_STEPS 0
 #define FEM_OPT_TILE_TETS 1
 #define FEM_OPT_TILE_NODES 2
 int fem_batch_set_option(fem_batch *batch, int32_t option, int32_t value);

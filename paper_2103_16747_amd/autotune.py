@@ -31,7 +31,7 @@ def _short_jobs(mesh, count, seed0, steps):
 def _time_config(meshes, jobs, precision, tile, chunk):
     batch = fem.FemBatch(sum(len(j) for j in jobs), precision)
     batch.set_option(fem.FEM_OPT_TILE_TETS, tile)
-    batch.set_option(fem.FEM_OPT_CG_CHUNK, chunk)
+    batch.set_option(fem.FEM_OPT_ROUND_STEPS, chunk)
     mids = [batch.add_mesh(m.X, m.tets, m.fixed) for m in meshes]
     ids = [(batch.add_job(mid, ind), ind) for mid, js in zip(mids, jobs) for ind in js]
     batch.run()                       # warm-up: graphs captured, caches warm

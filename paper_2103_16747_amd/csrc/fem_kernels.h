@@ -39,15 +39,13 @@ constexpr int kTileNodes = 256;   // distinct nodes per tile (8-bit local ids)
 
 enum Phase : int {
     PH_IDLE = 0,
-    PH_GRAD = 1,      // element pass at u (start of a load step)
-    PH_INIT = 2,      // gather g and node blocks, Newton test, CG setup
+    PH_GRAD = 1,      // element pass at u, then Newton init (start of a load step)
+    PH_INIT = 2,      // Newton init after an accepted line-search trial
     PH_CG = 3,        // CG iterations
-    PH_DOT = 4,       // g . dx
-    PH_TRIAL = 5,     // line-search trial: element pass at u + alpha dx
-    PH_DONE = 6,      // all load steps taken
-    PH_EVAL_GRAD = 7, // diagnostics: gradient at u, then idle
-    PH_EVAL_INIT = 8,
-    PH_EVAL_HV = 9    // diagnostics: q = H z, then idle
+    PH_TRIAL = 4,     // line-search trial: element pass at u + alpha dx
+    PH_DONE = 5,      // all load steps taken
+    PH_EVAL_GRAD = 6, // diagnostics: gradient at u, then idle
+    PH_EVAL_HV = 7    // diagnostics: q = H z, then idle
 };
 
 // Status codes (same values as the C ABI).
@@ -55,9 +53,6 @@ enum : int { ST_OK = 0, ST_NOT_CONVERGED = -6, ST_INVERSION = -7 };
 
 // Partial-sum streams of an instance (each red_stride doubles).
 enum : int { RS_PQ = 0, RS_RZ, RS_RR, RS_GD, RS_E, RS_MAG, RS_MINJ, RS_GG, RS_IRZ, RS_COUNT };
-
-// Finalize stages.
-enum : int { FIN_CG = 0, FIN_ELEM = 1, FIN_INIT = 2 };
 
 struct Indenter {
     int kind;            // 0 sphere, 1 cylinder, 2 box, 3 ring
@@ -76,7 +71,7 @@ struct SolveParams {
 struct InstState {
     int phase, step, steps, step_started;
     int newton_it, cg_it, halvings, apply;
-    int status, last_status, last_cg, pad0;   // last_cg: length of the previous CG solve
+    int status, last_status, last_cg, need_gd;   // last_cg: length of the previous CG solve
     double rz, rr, pq, alpha, beta, tol2;
     double E, emag, minJ, gg, r0, gd, alpha_ls;
     double mu, lam, depth;
@@ -497,32 +492,33 @@ __device__ __forceinline__ void store_partials(double *red, int stride, const in
         for (int i = 0; i < NS; i++) red[streams[i] * stride + slot] = v[i];
 }
 
+// LDS of a tile block, shared by the two tile paths (doubles): the element
+// path keeps 9 FP64 accumulators and 3 state values per entry, the Hessian
+// path 3 accumulators and 6 state values.
+template <typename T>
+struct TileLds {
+    static constexpr int kElem = 9 * kTileNodes + (3 * kTileNodes * (int)sizeof(T) + 7) / 8;
+    static constexpr int kHv = 3 * kTileNodes + (6 * kTileNodes * (int)sizeof(T) + 7) / 8;
+    static constexpr int kDoubles = kElem > kHv ? kElem : kHv;
+};
+
 // ---------------------------------------------------------------------------
-// Element + contact pass (phases GRAD, EVAL_GRAD, DOT = first line-search
-// trial at alpha = 1, TRIAL). Tile blocks: energy, magnitude, min J, and per
-// entry partials of the gradient and of the 3x3 node diagonal blocks
+// Element + contact pass of one tile block (phases GRAD, EVAL_GRAD, TRIAL at
+// u + alpha dx). Tile blocks: energy, magnitude, min J, and per entry
+// partials of the gradient and of the 3x3 node diagonal blocks
 // V (mu |b|^2 I + (mu + lam - lam ln J) c c^T), c = F^-T b. Contact blocks:
 // penalty energy, gradient k phi n and block k n n^T (+ k phi Hess(phi) with
 // the exact contact Hessian) per eligible node.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_elem(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
-                                                 int nwork, const SolveParams *P) {
-    const int L = logical_block();
-    if (L >= nwork) return;
-    const int2 w = work[L];
-    const InstBufs<T> &B = bufs[w.x];
-    const InstState *s = B.s;
-    const int phase = s->phase;
-    if (phase != PH_GRAD && phase != PH_TRIAL && phase != PH_DOT && phase != PH_EVAL_GRAD) return;
-    const Topo<T> &tp = topos[B.topo];
-    const T alpha = phase == PH_TRIAL ? (T)s->alpha_ls : (phase == PH_DOT ? (T)1 : (T)0);
+__device__ __forceinline__ void tile_element(const Topo<T> &tp, const InstBufs<T> &B, const InstState *s, int blk,
+                                             T alpha, int contact_full, double *pool) {
     const T mu = (T)s->mu, lam = (T)s->lam;
     double acc[3] = {0.0, 0.0, INFINITY};   // energy, magnitude, min J
-    if (w.y < tp.ntile) {
-        __shared__ T su[3 * kTileNodes];
-        __shared__ double sa[9 * kTileNodes];   // FP64 accumulation in both precisions
-        const int t = w.y;
+    if (blk < tp.ntile) {
+        double *sa = pool;                          // 9 per entry, FP64 in both precisions
+        T *su = (T *)(pool + 9 * kTileNodes);       // 3 per entry
+        const int t = blk;
         const int e0 = tp.tile_ent[t], ne = tp.tile_ent[t + 1] - e0;
         const int k0 = tp.tile_tet[t], nk = tp.tile_tet[t + 1] - k0;
         for (int l = threadIdx.x; l < ne; l += kBlock) {
@@ -605,7 +601,7 @@ __global__ __launch_bounds__(kBlock) void k_elem(const Topo<T> *topos, const Ins
         __syncthreads();
         for (int i = threadIdx.x; i < 9 * ne; i += kBlock) B.pg[9 * e0 + i] = (T)sa[i];
     } else {
-        const int j = (w.y - tp.ntile) * kBlock + threadIdx.x;
+        const int j = (blk - tp.ntile) * kBlock + threadIdx.x;
         if (j < tp.nc) {
             const int i = tp.cnodes[j];
             double x[3];
@@ -615,9 +611,8 @@ __global__ __launch_bounds__(kBlock) void k_elem(const Topo<T> *topos, const Ins
                 if (alpha != (T)0) ui = fma_t(alpha, B.dx[3 * i + d], ui);
                 x[d] = tp.X[3 * i + d] + (double)ui;
             }
-            const int cf = P->contact_full;
             double phi, nv[3], Hs[6];
-            sdf_eval(s->ind, x, cf != 0, phi, nv, Hs);
+            sdf_eval(s->ind, x, contact_full != 0, phi, nv, Hs);
             T out[9];
 #pragma unroll
             for (int c = 0; c < 9; c++) out[c] = (T)0;
@@ -630,7 +625,7 @@ __global__ __launch_bounds__(kBlock) void k_elem(const Topo<T> *topos, const Ins
                 for (int d = 0; d < 3; d++) out[d] = (T)(kp * phi * nv[d]);
                 const double nn[6] = {nv[0] * nv[0], nv[1] * nv[1], nv[2] * nv[2], nv[0] * nv[1], nv[0] * nv[2], nv[1] * nv[2]};
 #pragma unroll
-                for (int c = 0; c < 6; c++) out[3 + c] = (T)(kp * (nn[c] + (cf ? phi * Hs[c] : 0.0)));
+                for (int c = 0; c < 6; c++) out[3 + c] = (T)(kp * (nn[c] + (contact_full ? phi * Hs[c] : 0.0)));
             }
 #pragma unroll
             for (int c = 0; c < 9; c++) B.cp[9 * j + c] = out[c];
@@ -641,122 +636,29 @@ __global__ __launch_bounds__(kBlock) void k_elem(const Topo<T> *topos, const Ins
     block_reduce<2, true>(sums, mn);
     double v[3] = {sums[0], sums[1], mn};
     const int streams[3] = {RS_E, RS_MAG, RS_MINJ};
-    store_partials<3>(B.red, B.red_stride, streams, w.y, v);
+    store_partials<3>(B.red, B.red_stride, streams, blk, v);
 }
 
 // ---------------------------------------------------------------------------
-// Newton init (phases INIT, EVAL_INIT), one thread per node: applies an
-// accepted line-search step u += alpha dx, gathers g and the node block from
-// the tile and contact partials, forms the block (or scalar) Jacobi inverse,
-// r = -g and z = M^-1 r on free nodes; partial sums of |g_free|^2 and r.z.
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_init(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
-                                                 int nwork, const SolveParams *P) {
-    const int L = logical_block();
-    if (L >= nwork) return;
-    const int2 w = work[L];
-    const InstBufs<T> &B = bufs[w.x];
-    const InstState *s = B.s;
-    const int phase = s->phase;
-    if (phase != PH_INIT && phase != PH_EVAL_INIT) return;
-    const Topo<T> &tp = topos[B.topo];
-    const bool apply = s->apply != 0;
-    const T alpha = (T)s->alpha_ls;
-    double acc[2] = {0.0, 0.0};
-    double unused = 0.0;
-    const int i = w.y * kBlock + threadIdx.x;
-    if (i < tp.n) {
-        if (apply)
-#pragma unroll
-            for (int d = 0; d < 3; d++) B.u[3 * i + d] = fma_t(alpha, B.dx[3 * i + d], B.u[3 * i + d]);
-        T gsum[9];
-#pragma unroll
-        for (int c = 0; c < 9; c++) gsum[c] = (T)0;
-        for (int q = tp.node_ent_off[i]; q < tp.node_ent_off[i + 1]; q++) {
-            const T *src = B.pg + 9 * tp.node_ent[q];
-#pragma unroll
-            for (int c = 0; c < 9; c++) gsum[c] += src[c];
-        }
-        const int j = tp.cidx[i];
-        if (j >= 0)
-#pragma unroll
-            for (int c = 0; c < 9; c++) gsum[c] += B.cp[9 * j + c];
-#pragma unroll
-        for (int d = 0; d < 3; d++) B.g[3 * i + d] = gsum[d];
-        T M[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
-        T rr[3] = {(T)0, (T)0, (T)0}, zz[3] = {(T)0, (T)0, (T)0};
-        if (!tp.fixed[i]) {
-            const T a = gsum[3], bb = gsum[4], c = gsum[5], d = gsum[6], e = gsum[7], f = gsum[8];
-            const T m2 = a * bb - d * d;
-            const T c00 = bb * c - f * f, c01 = e * f - d * c, c02 = d * f - bb * e;
-            const T det = a * c00 + d * c01 + e * c02;
-            if (P->block_jacobi && a > (T)0 && m2 > (T)0 && det > (T)0) {
-                const T id = (T)1 / det;
-                M[0] = c00 * id;
-                M[1] = (a * c - e * e) * id;
-                M[2] = m2 * id;
-                M[3] = c01 * id;
-                M[4] = c02 * id;
-                M[5] = (d * e - a * f) * id;
-            } else {
-                M[0] = safe_recip(a);
-                M[1] = safe_recip(bb);
-                M[2] = safe_recip(c);
-            }
-#pragma unroll
-            for (int d2 = 0; d2 < 3; d2++) rr[d2] = -gsum[d2];
-            zz[0] = M[0] * rr[0] + M[3] * rr[1] + M[4] * rr[2];
-            zz[1] = M[3] * rr[0] + M[1] * rr[1] + M[5] * rr[2];
-            zz[2] = M[4] * rr[0] + M[5] * rr[1] + M[2] * rr[2];
-#pragma unroll
-            for (int d2 = 0; d2 < 3; d2++) {
-                acc[0] += (double)rr[d2] * (double)rr[d2];
-                acc[1] += (double)rr[d2] * (double)zz[d2];
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < 6; c++) B.dinv[6 * i + c] = M[c];
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-            B.r[3 * i + d] = rr[d];
-            B.z[3 * i + d] = zz[d];
-            B.p[3 * i + d] = (T)0;
-            B.dx[3 * i + d] = (T)0;
-        }
-    }
-    block_reduce<2, false>(acc, unused);
-    const int streams[2] = {RS_GG, RS_IRZ};
-    store_partials<2>(B.red, B.red_stride, streams, w.y, acc);
-}
-
-// ---------------------------------------------------------------------------
-// CG, Hessian-vector half (phases CG, EVAL_HV): q = H p with p = z + beta
-// p_prev formed while staging (the update kernel forms the same value). Per
-// tet, with F recomputed from the staged u:
+// Hessian-vector product of one tile block (phases CG, EVAL_HV): q = H p with
+// p = z + beta p_prev formed while staging (the node pass forms the same
+// value). Per tet, with F recomputed from the staged u:
 //   dP = mu dG + (mu - lam ln J) (F^-1 dG F^-1)^T + lam tr(F^-1 dG) F^-T.
 // p.q is accumulated element by element (and over contact blocks), so alpha
-// is known to the update kernel without a pass over q.
+// is known to the node pass without a pass over q.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_hv(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
-                                               int nwork, const SolveParams *P) {
-    const int L = logical_block();
-    if (L >= nwork) return;
-    const int2 w = work[L];
-    const InstBufs<T> &B = bufs[w.x];
-    const InstState *s = B.s;
-    const int phase = s->phase;
-    if (phase != PH_CG && phase != PH_EVAL_HV) return;
-    const Topo<T> &tp = topos[B.topo];
+__device__ __forceinline__ void tile_hessvec(const Topo<T> &tp, const InstBufs<T> &B, const InstState *s, int blk,
+                                             double *pool) {
     const T beta = (T)s->beta;
     const T mu = (T)s->mu, lam = (T)s->lam;
     double acc[1] = {0.0};
     double unused = 0.0;
-    if (w.y < tp.ntile) {
-        __shared__ T su[3 * kTileNodes], sp[3 * kTileNodes];
-        __shared__ double sa[3 * kTileNodes];   // FP64 accumulation in both precisions
-        const int t = w.y;
+    if (blk < tp.ntile) {
+        double *sa = pool;                          // 3 per entry, FP64 in both precisions
+        T *su = (T *)(pool + 3 * kTileNodes);       // 3 per entry
+        T *sp = su + 3 * kTileNodes;                // 3 per entry
+        const int t = blk;
         const int e0 = tp.tile_ent[t], ne = tp.tile_ent[t + 1] - e0;
         const int k0 = tp.tile_tet[t], nk = tp.tile_tet[t + 1] - k0;
         for (int l = threadIdx.x; l < ne; l += kBlock) {
@@ -817,7 +719,7 @@ __global__ __launch_bounds__(kBlock) void k_hv(const Topo<T> *topos, const InstB
         __syncthreads();
         for (int i = threadIdx.x; i < 3 * ne; i += kBlock) B.pq[3 * e0 + i] = (T)sa[i];
     } else {
-        const int j = (w.y - tp.ntile) * kBlock + threadIdx.x;
+        const int j = (blk - tp.ntile) * kBlock + threadIdx.x;
         if (j < tp.nc) {
             const T *H = B.cp + 9 * j + 3;
             if (H[0] != (T)0 || H[1] != (T)0 || H[2] != (T)0 || H[3] != (T)0 || H[4] != (T)0 || H[5] != (T)0) {
@@ -834,41 +736,136 @@ __global__ __launch_bounds__(kBlock) void k_hv(const Topo<T> *topos, const InstB
     }
     block_reduce<1, false>(acc, unused);
     const int streams[1] = {RS_PQ};
-    store_partials<1>(B.red, B.red_stride, streams, w.y, acc);
+    store_partials<1>(B.red, B.red_stride, streams, blk, acc);
 }
 
 // ---------------------------------------------------------------------------
-// CG, update half (phases CG, EVAL_HV), one thread per node. Every block sums
-// the Hv kernel's p.q partials (fixed order, so all blocks agree) and forms
-// alpha = r.z / p.q; then it gathers q from the tile partials plus the contact
-// block times p and, on free nodes, sets p = z + beta p_prev, dx += alpha p,
-// r -= alpha q, z = M^-1 r, with partial sums of r.z and r.r. At p.q <= 0 CG
-// stops (on its first iteration the preconditioned residual becomes the
-// Newton direction).
+// Tile pass: one block per (instance, tile or contact block). Each instance's
+// blocks take the Hessian-vector path while it is in CG (or EVAL_HV), the
+// element path in GRAD, EVAL_GRAD and TRIAL, and return otherwise. The two
+// paths share one LDS pool (their register needs are alike, so the union
+// does not lower occupancy).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_update(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
-                                                   int nwork, const SolveParams *P) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 1 : 3))) void k_tile(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
+                                                 int nwork, const SolveParams *P) {
+    __shared__ double pool[TileLds<T>::kDoubles];
     const int L = logical_block();
     if (L >= nwork) return;
     const int2 w = work[L];
     const InstBufs<T> &B = bufs[w.x];
     const InstState *s = B.s;
     const int phase = s->phase;
-    if (phase != PH_CG && phase != PH_EVAL_HV) return;
-    const Topo<T> &tp = topos[B.topo];
+    if (phase == PH_CG || phase == PH_EVAL_HV) {
+        tile_hessvec(topos[B.topo], B, s, w.y, pool);
+    } else if (phase == PH_GRAD || phase == PH_EVAL_GRAD || phase == PH_TRIAL) {
+        const T alpha = phase == PH_TRIAL ? (T)s->alpha_ls : (T)0;
+        tile_element(topos[B.topo], B, s, w.y, alpha, P->contact_full, pool);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Newton init of one node block (phases GRAD, EVAL_GRAD after the element
+// path of the same pass; INIT after an accepted line-search trial). Applies
+// an accepted step u += alpha dx, gathers g and the node block from the tile
+// and contact partials, forms the block (or scalar) Jacobi inverse, r = -g and
+// z = M^-1 r on free nodes; partial sums of |g_free|^2 and r.z.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void node_init(const Topo<T> &tp, const InstBufs<T> &B, const InstState *s, int blk,
+                                          bool apply, int block_jacobi) {
+    const T alpha = (T)s->alpha_ls;
+    double acc[2] = {0.0, 0.0};
+    double unused = 0.0;
+    const int i = blk * kBlock + threadIdx.x;
+    if (i < tp.n) {
+        if (apply)
+#pragma unroll
+            for (int d = 0; d < 3; d++) B.u[3 * i + d] = fma_t(alpha, B.dx[3 * i + d], B.u[3 * i + d]);
+        T gsum[9];
+#pragma unroll
+        for (int c = 0; c < 9; c++) gsum[c] = (T)0;
+        for (int q = tp.node_ent_off[i]; q < tp.node_ent_off[i + 1]; q++) {
+            const T *src = B.pg + 9 * tp.node_ent[q];
+#pragma unroll
+            for (int c = 0; c < 9; c++) gsum[c] += src[c];
+        }
+        const int j = tp.cidx[i];
+        if (j >= 0)
+#pragma unroll
+            for (int c = 0; c < 9; c++) gsum[c] += B.cp[9 * j + c];
+#pragma unroll
+        for (int d = 0; d < 3; d++) B.g[3 * i + d] = gsum[d];
+        T M[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+        T rr[3] = {(T)0, (T)0, (T)0}, zz[3] = {(T)0, (T)0, (T)0};
+        if (!tp.fixed[i]) {
+            const T a = gsum[3], bb = gsum[4], c = gsum[5], d = gsum[6], e = gsum[7], f = gsum[8];
+            const T m2 = a * bb - d * d;
+            const T c00 = bb * c - f * f, c01 = e * f - d * c, c02 = d * f - bb * e;
+            const T det = a * c00 + d * c01 + e * c02;
+            if (block_jacobi && a > (T)0 && m2 > (T)0 && det > (T)0) {
+                const T id = (T)1 / det;
+                M[0] = c00 * id;
+                M[1] = (a * c - e * e) * id;
+                M[2] = m2 * id;
+                M[3] = c01 * id;
+                M[4] = c02 * id;
+                M[5] = (d * e - a * f) * id;
+            } else {
+                M[0] = safe_recip(a);
+                M[1] = safe_recip(bb);
+                M[2] = safe_recip(c);
+            }
+#pragma unroll
+            for (int d2 = 0; d2 < 3; d2++) rr[d2] = -gsum[d2];
+            zz[0] = M[0] * rr[0] + M[3] * rr[1] + M[4] * rr[2];
+            zz[1] = M[3] * rr[0] + M[1] * rr[1] + M[5] * rr[2];
+            zz[2] = M[4] * rr[0] + M[5] * rr[1] + M[2] * rr[2];
+#pragma unroll
+            for (int d2 = 0; d2 < 3; d2++) {
+                acc[0] += (double)rr[d2] * (double)rr[d2];
+                acc[1] += (double)rr[d2] * (double)zz[d2];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 6; c++) B.dinv[6 * i + c] = M[c];
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            B.r[3 * i + d] = rr[d];
+            B.z[3 * i + d] = zz[d];
+            B.p[3 * i + d] = (T)0;
+            B.dx[3 * i + d] = (T)0;
+        }
+    }
+    block_reduce<2, false>(acc, unused);
+    const int streams[2] = {RS_GG, RS_IRZ};
+    store_partials<2>(B.red, B.red_stride, streams, blk, acc);
+}
+
+// ---------------------------------------------------------------------------
+// CG update of one node block (phases CG, EVAL_HV). Every block sums the tile
+// pass's p.q partials (fixed order, so all blocks agree) and forms
+// alpha = r.z / p.q; then it gathers q from the tile partials plus the contact
+// block times p and, on free nodes, sets p = z + beta p_prev, dx += alpha p,
+// r -= alpha q, z = M^-1 r, with partial sums of r.z and r.r. At p.q <= 0 CG
+// stops (on its first iteration the preconditioned residual becomes the
+// Newton direction). EVAL_HV writes q instead.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void node_update(const Topo<T> &tp, const InstBufs<T> &B, const InstState *s, int blk,
+                                            bool eval) {
     const double pq = block_sum_partials(B.red + RS_PQ * B.red_stride, tp.ntile + tp.ncb);
     const bool negcurv = !(pq > 0.0);
     const T alpha = negcurv ? (T)0 : (T)(s->rz / pq);
     const T beta = (T)s->beta;
     double acc[2] = {0.0, 0.0};   // r.z, r.r
     double unused = 0.0;
-    const int i = w.y * kBlock + threadIdx.x;
+    const int i = blk * kBlock + threadIdx.x;
     if (i < tp.n) {
         T pv[3];
 #pragma unroll
         for (int d = 0; d < 3; d++) pv[d] = fma_t(beta, B.p[3 * i + d], B.z[3 * i + d]);
-        if (phase == PH_EVAL_HV || !negcurv) {
+        if (eval || !negcurv) {
             T qv[3] = {(T)0, (T)0, (T)0};
             for (int q = tp.node_ent_off[i]; q < tp.node_ent_off[i + 1]; q++) {
                 const T *src = B.pq + 3 * tp.node_ent[q];
@@ -883,7 +880,7 @@ __global__ __launch_bounds__(kBlock) void k_update(const Topo<T> *topos, const I
                 qv[1] += H[3] * pv[0] + H[1] * pv[1] + H[5] * pv[2];
                 qv[2] += H[4] * pv[0] + H[5] * pv[1] + H[2] * pv[2];
             }
-            if (phase == PH_EVAL_HV) {
+            if (eval) {
 #pragma unroll
                 for (int d = 0; d < 3; d++) B.qout[3 * i + d] = qv[d];
             } else if (!tp.fixed[i]) {
@@ -912,44 +909,103 @@ __global__ __launch_bounds__(kBlock) void k_update(const Topo<T> *topos, const I
     }
     block_reduce<2, false>(acc, unused);
     const int streams[2] = {RS_RZ, RS_RR};
-    store_partials<2>(B.red, B.red_stride, streams, w.y, acc);
+    store_partials<2>(B.red, B.red_stride, streams, blk, acc);
 }
 
-// Partial sums of g . dx (phase DOT).
+// Partial sums of g . dx of one node block (first line-search trial).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_dot(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
-                                                int nwork) {
-    const int L = logical_block();
-    if (L >= nwork) return;
-    const int2 w = work[L];
-    const InstBufs<T> &B = bufs[w.x];
-    if (B.s->phase != PH_DOT) return;
-    const Topo<T> &tp = topos[B.topo];
+__device__ __forceinline__ void node_dot(const Topo<T> &tp, const InstBufs<T> &B, int blk) {
     double acc[1] = {0.0};
     double unused = 0.0;
-    const int i = w.y * kBlock + threadIdx.x;
+    const int i = blk * kBlock + threadIdx.x;
     if (i < tp.n)
 #pragma unroll
         for (int d = 0; d < 3; d++) acc[0] += (double)B.g[3 * i + d] * (double)B.dx[3 * i + d];
     block_reduce<1, false>(acc, unused);
     const int streams[1] = {RS_GD};
-    store_partials<1>(B.red, B.red_stride, streams, w.y, acc);
+    store_partials<1>(B.red, B.red_stride, streams, blk, acc);
 }
 
 // ---------------------------------------------------------------------------
-// Finalize: one wavefront per live instance sums the partials of the stage's
-// work kernel in a fixed order and takes the state-machine transition.
-//   FIN_CG   after Hv + update: alpha, beta, r.z, CG stop or negative
-//            curvature -> DOT; EVAL_HV -> IDLE.
-//   FIN_ELEM after the element pass: GRAD/EVAL_GRAD record the energy;
-//            DOT (trial at alpha = 1) and TRIAL take the Armijo test with the
-//            rounding floor noise_eps * sum of energy-term magnitudes.
-//   FIN_INIT after init: Newton test on |g_free| against the step's first
-//            residual; CG set-up with the inexact-Newton tolerance.
+// Node pass: one block per (instance, 256 nodes), after the tile pass of the
+// same step. CG -> update; GRAD, EVAL_GRAD, INIT -> Newton init; TRIAL ->
+// g . dx on the first trial of a line search; other phases return.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_node(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
+                                                 int nwork, const SolveParams *P) {
+    const int L = logical_block();
+    if (L >= nwork) return;
+    const int2 w = work[L];
+    const InstBufs<T> &B = bufs[w.x];
+    const InstState *s = B.s;
+    const int phase = s->phase;
+    const Topo<T> &tp = topos[B.topo];
+    if (phase == PH_CG || phase == PH_EVAL_HV)
+        node_update(tp, B, s, w.y, phase == PH_EVAL_HV);
+    else if (phase == PH_GRAD || phase == PH_EVAL_GRAD || phase == PH_INIT)
+        node_init(tp, B, s, w.y, phase == PH_INIT && s->apply != 0, P->block_jacobi);
+    else if (phase == PH_TRIAL && s->need_gd)
+        node_dot(tp, B, w.y);
+}
+
+// Newton test on |g_free| against the load step's first residual, then CG
+// set-up with the inexact-Newton tolerance (finalising thread).
+__device__ inline void newton_test(InstState *s, const SolveParams *P, double gg, double rz) {
+    s->gg = gg;
+    const double gn = sqrt(gg);
+    if (s->apply) {
+        s->newton_it++;
+        s->st_newton++;
+        s->apply = 0;
+    }
+    if (s->step_started) {
+        s->r0 = gn;
+        s->st_g0 = gn;
+        s->step_started = 0;
+    }
+    if (gn <= fmax(P->newton_rtol * s->r0, P->newton_atol)) {
+        end_step(s, ST_OK);
+    } else if (s->newton_it >= P->max_newton) {
+        end_step(s, ST_NOT_CONVERGED);
+    } else {
+        const double eta = fmin(P->cg_eta_max, fmax(P->cg_rtol, gn / s->r0));
+        s->tol2 = eta * eta * gg;
+        s->rz = rz;
+        s->rr = gg;
+        s->beta = 0.0;
+        s->alpha = 0.0;
+        s->cg_it = 0;
+        s->phase = PH_CG;
+    }
+}
+
+// End of a CG solve: the first line-search trial at alpha = 1 follows, with
+// g . dx taken by its node pass.
+__device__ inline void start_line_search(InstState *s) {
+    s->last_cg = s->cg_it;
+    s->alpha_ls = 1.0;
+    s->halvings = 0;
+    s->need_gd = 1;
+    s->phase = PH_TRIAL;
+}
+
+// ---------------------------------------------------------------------------
+// Finalize: one wavefront per live instance sums, in a fixed order, the
+// partials its blocks wrote in this step's tile and node passes and takes the
+// state-machine transition.
+//   CG         alpha, beta, r.z; CG stop (tolerance, iteration cap, p.q <= 0)
+//              -> TRIAL at alpha = 1.
+//   GRAD       energy of the load step's start, then the Newton test.
+//   TRIAL      Armijo test with the rounding floor noise_eps * sum of
+//              energy-term magnitudes: accept -> INIT, else halve alpha or
+//              end the load step.
+//   INIT       Newton test.
+//   EVAL_GRAD, EVAL_HV -> IDLE.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(64) void k_finalize(const Topo<T> *topos, const InstBufs<T> *bufs, const int *live,
-                                                 int nlive, const SolveParams *P, int stage) {
+                                                 int nlive, const SolveParams *P) {
     if ((int)blockIdx.x >= nlive) return;
     const InstBufs<T> &B = bufs[live[blockIdx.x]];
     InstState *s = B.s;
@@ -957,8 +1013,7 @@ __global__ __launch_bounds__(64) void k_finalize(const Topo<T> *topos, const Ins
     const Topo<T> &tp = topos[B.topo];
     const int S = B.red_stride;
     const int nt = tp.ntile + tp.ncb, nn = (tp.n + kBlock - 1) / kBlock;
-    if (stage == FIN_CG) {
-        if (phase != PH_CG && phase != PH_EVAL_HV) return;
+    if (phase == PH_CG || phase == PH_EVAL_HV) {
         const double pq = wave_sum_partials(B.red + RS_PQ * S, nt);
         const double rz = wave_sum_partials(B.red + RS_RZ * S, nn);
         const double rr = wave_sum_partials(B.red + RS_RR * S, nn);
@@ -970,8 +1025,7 @@ __global__ __launch_bounds__(64) void k_finalize(const Topo<T> *topos, const Ins
         }
         s->st_hv++;
         if (!(pq > 0.0)) {
-            s->last_cg = s->cg_it;
-            s->phase = PH_DOT;
+            start_line_search(s);
             return;
         }
         s->alpha = s->rz / pq;
@@ -980,31 +1034,37 @@ __global__ __launch_bounds__(64) void k_finalize(const Topo<T> *topos, const Ins
         s->beta = rz / s->rz;
         s->rz = rz;
         s->rr = rr;
-        if (rr <= s->tol2 || s->cg_it >= P->max_cg) {
-            s->last_cg = s->cg_it;
-            s->phase = PH_DOT;
-        }
-    } else if (stage == FIN_ELEM) {
-        if (phase != PH_GRAD && phase != PH_TRIAL && phase != PH_DOT && phase != PH_EVAL_GRAD) return;
+        if (rr <= s->tol2 || s->cg_it >= P->max_cg) start_line_search(s);
+    } else if (phase == PH_GRAD || phase == PH_EVAL_GRAD || phase == PH_TRIAL) {
         const double E = wave_sum_partials(B.red + RS_E * S, nt);
         const double mag = wave_sum_partials(B.red + RS_MAG * S, nt);
         const double mn = wave_min_partials(B.red + RS_MINJ * S, nt);
-        const double gd = phase == PH_DOT ? wave_sum_partials(B.red + RS_GD * S, nn) : 0.0;
+        double gg = 0.0, rz = 0.0, gd = 0.0;
+        if (phase != PH_TRIAL) {
+            gg = wave_sum_partials(B.red + RS_GG * S, nn);
+            rz = wave_sum_partials(B.red + RS_IRZ * S, nn);
+        } else if (s->need_gd) {
+            gd = wave_sum_partials(B.red + RS_GD * S, nn);
+        }
         if (threadIdx.x != 0) return;
         const double Et = mn > 0.0 ? E : INFINITY;
         s->st_grad++;
-        if (phase == PH_GRAD || phase == PH_EVAL_GRAD) {
+        if (phase != PH_TRIAL) {
             s->E = Et;
             s->emag = mag;
             s->minJ = mn;
             s->apply = 0;
-            s->phase = phase == PH_GRAD ? PH_INIT : PH_EVAL_INIT;
+            if (phase == PH_EVAL_GRAD) {
+                s->gg = gg;
+                s->phase = PH_IDLE;
+            } else {
+                newton_test(s, P, gg, rz);
+            }
             return;
         }
-        if (phase == PH_DOT) {
+        if (s->need_gd) {
             s->gd = gd;
-            s->alpha_ls = 1.0;
-            s->halvings = 0;
+            s->need_gd = 0;
         }
         s->st_ls++;
         const double noise = P->noise_eps * s->emag;
@@ -1019,43 +1079,12 @@ __global__ __launch_bounds__(64) void k_finalize(const Topo<T> *topos, const Ins
         } else {
             s->halvings++;
             s->alpha_ls *= 0.5;
-            s->phase = PH_TRIAL;
         }
-    } else {
-        if (phase != PH_INIT && phase != PH_EVAL_INIT) return;
+    } else if (phase == PH_INIT) {
         const double gg = wave_sum_partials(B.red + RS_GG * S, nn);
         const double rz = wave_sum_partials(B.red + RS_IRZ * S, nn);
         if (threadIdx.x != 0) return;
-        s->gg = gg;
-        if (phase == PH_EVAL_INIT) {
-            s->phase = PH_IDLE;
-            return;
-        }
-        const double gn = sqrt(gg);
-        if (s->apply) {
-            s->newton_it++;
-            s->st_newton++;
-            s->apply = 0;
-        }
-        if (s->step_started) {
-            s->r0 = gn;
-            s->st_g0 = gn;
-            s->step_started = 0;
-        }
-        if (gn <= fmax(P->newton_rtol * s->r0, P->newton_atol)) {
-            end_step(s, ST_OK);
-        } else if (s->newton_it >= P->max_newton) {
-            end_step(s, ST_NOT_CONVERGED);
-        } else {
-            const double eta = fmin(P->cg_eta_max, fmax(P->cg_rtol, gn / s->r0));
-            s->tol2 = eta * eta * gg;
-            s->rz = rz;
-            s->rr = gg;
-            s->beta = 0.0;
-            s->alpha = 0.0;
-            s->cg_it = 0;
-            s->phase = PH_CG;
-        }
+        newton_test(s, P, gg, rz);
     }
 }
 

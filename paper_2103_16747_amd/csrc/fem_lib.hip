@@ -553,48 +553,40 @@ int write_state(fem_batch *B, int slot) {
 
 inline bool running_phase(int ph) { return ph != PH_IDLE && ph != PH_DONE; }
 
-// One round: (Hv, update, finalize) x C, dot, element pass, finalize, init,
-// finalize. With kernel timing on, sampled launches are bracketed by events.
+// One round: C solver steps, each a tile pass, a node pass and a finalize
+// over every live instance. With kernel timing on, sampled launches are
+// bracketed by events.
 template <typename T>
-int enqueue_round(fem_batch *B, int chunk, hipEvent_t (*ev)[2]) {
+int enqueue_round(fem_batch *B, int chunk) {
     const Topo<T> *tp = (const Topo<T> *)B->d_topos;
     const InstBufs<T> *bf = (const InstBufs<T> *)B->d_bufs;
     const int gt = pad8(B->nwork_tile), gn = pad8(B->nwork_node), nl = B->nlive;
     for (int c = 0; c < chunk; c++) {
-        int slot = ev ? -1 : timer_begin(B, FEM_KERNEL_HV);
-        if (ev && c == 0) HIP_TRY(hipEventRecord(ev[FEM_KERNEL_HV][0], B->stream));
-        k_hv<T><<<gt, kBlock, 0, B->stream>>>(tp, bf, B->d_work_tile, B->nwork_tile, B->d_params);
-        if (ev && c == 0) HIP_TRY(hipEventRecord(ev[FEM_KERNEL_HV][1], B->stream));
+        int slot = timer_begin(B, FEM_KERNEL_TILE);
+        k_tile<T><<<gt, kBlock, 0, B->stream>>>(tp, bf, B->d_work_tile, B->nwork_tile, B->d_params);
         timer_end(B, slot);
-        slot = ev ? -1 : timer_begin(B, FEM_KERNEL_CG_UPDATE);
-        if (ev && c == 0) HIP_TRY(hipEventRecord(ev[FEM_KERNEL_CG_UPDATE][0], B->stream));
-        k_update<T><<<gn, kBlock, 0, B->stream>>>(tp, bf, B->d_work_node, B->nwork_node, B->d_params);
-        if (ev && c == 0) HIP_TRY(hipEventRecord(ev[FEM_KERNEL_CG_UPDATE][1], B->stream));
+        slot = timer_begin(B, FEM_KERNEL_NODE);
+        k_node<T><<<gn, kBlock, 0, B->stream>>>(tp, bf, B->d_work_node, B->nwork_node, B->d_params);
         timer_end(B, slot);
-        k_finalize<T><<<nl, 64, 0, B->stream>>>(tp, bf, B->d_live, nl, B->d_params, FIN_CG);
+        slot = timer_begin(B, FEM_KERNEL_FINALIZE);
+        k_finalize<T><<<nl, 64, 0, B->stream>>>(tp, bf, B->d_live, nl, B->d_params);
+        timer_end(B, slot);
     }
-    k_dot<T><<<gn, kBlock, 0, B->stream>>>(tp, bf, B->d_work_node, B->nwork_node);
-    const int slot = ev ? -1 : timer_begin(B, FEM_KERNEL_ELEMENT);
-    if (ev) HIP_TRY(hipEventRecord(ev[FEM_KERNEL_ELEMENT][0], B->stream));
-    k_elem<T><<<gt, kBlock, 0, B->stream>>>(tp, bf, B->d_work_tile, B->nwork_tile, B->d_params);
-    if (ev) HIP_TRY(hipEventRecord(ev[FEM_KERNEL_ELEMENT][1], B->stream));
-    timer_end(B, slot);
-    k_finalize<T><<<nl, 64, 0, B->stream>>>(tp, bf, B->d_live, nl, B->d_params, FIN_ELEM);
-    k_init<T><<<gn, kBlock, 0, B->stream>>>(tp, bf, B->d_work_node, B->nwork_node, B->d_params);
-    k_finalize<T><<<nl, 64, 0, B->stream>>>(tp, bf, B->d_live, nl, B->d_params, FIN_INIT);
     return launch_check("round");
 }
 
-// Launches a round, replaying a captured graph for the chunk length when
-// graphs are on (chunks are powers of two from 4 to 64). With kernel timing
+// Launches a round, replaying a captured graph for its length when graphs are
+// on (lengths rounded up to a multiple of 4, of 8 above 32; at most 64 solver
+// steps). With kernel timing
 // on, rounds are launched kernel by kernel so events can bracket single
 // kernels (event records cannot be captured into the graph here).
 template <typename T>
 int launch_round(fem_batch *B, int chunk) {
     if (pad8(B->nwork_tile) == 0 || pad8(B->nwork_node) == 0 || B->nlive == 0) return FEM_OK;
-    if (!B->use_graphs || B->timer.every > 0) return enqueue_round<T>(B, chunk, nullptr);
-    int c = 4;
-    while (c < chunk && c < 64) c <<= 1;
+    if (!B->use_graphs || B->timer.every > 0) return enqueue_round<T>(B, std::max(1, std::min(64, chunk)));
+    // graph lengths: multiples of 4 up to 32, of 8 up to 64
+    int c = std::max(4, std::min(64, chunk));
+    c = c <= 32 ? (c + 3) / 4 * 4 : (c + 7) / 8 * 8;
     int gi = -1;
     for (int i = 0; i < (int)B->graphs.size(); i++)
         if (B->graphs[i].chunk == c) gi = i;
@@ -603,7 +595,7 @@ int launch_round(fem_batch *B, int chunk) {
         G.chunk = c;
         hipGraph_t graph = nullptr;
         HIP_TRY(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
-        const int rc = enqueue_round<T>(B, c, nullptr);
+        const int rc = enqueue_round<T>(B, c);
         const hipError_t ec = hipStreamEndCapture(B->stream, &graph);
         if (rc) return rc;
         if (ec != hipSuccess) return fail(FEM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
@@ -632,13 +624,14 @@ int run_impl(fem_batch *B, int max_rounds, int *n_running) {
             single = i;
         }
         if (running == 0 || (max_rounds > 0 && rounds >= max_rounds)) break;
-        // CG iterations per round: a fixed 16 for batches; for one job, what
-        // its current CG solve is expected to need from the previous one.
+        // Solver steps per round: a fixed 16 for batches; for one job, what
+        // its current Newton iteration is expected to need (CG iterations of
+        // the previous solve, plus the line-search trial and the init).
         int chunk = B->chunk > 0 ? B->chunk : 16;
         if (running == 1 && B->chunk <= 0) {
             const InstState &s = B->h_states[single];
             const int expect = s.last_cg > 0 ? s.last_cg : 16;
-            chunk = s.phase == PH_CG ? std::max(4, std::min(64, expect - s.cg_it)) : std::max(4, std::min(64, expect));
+            chunk = s.phase == PH_CG ? expect - s.cg_it + 2 : expect + 3;
         }
         TRY(launch_round<T>(B, chunk));
         TRY(read_states(B));
@@ -1317,6 +1310,13 @@ int fem_batch_get_kernel_timing(const fem_batch *B, int32_t kernel, int64_t *cou
     return FEM_OK;
 }
 
+int fem_batch_get_kernel_launches(const fem_batch *B, int32_t kernel, int64_t *launches) {
+    g_last_error.clear();
+    if (!B || !launches || kernel < 0 || kernel >= KernelTimer::kKinds) return fail(FEM_E_INVALID, "bad argument");
+    *launches = B->timer.seen[kernel];
+    return FEM_OK;
+}
+
 int fem_batch_set_graphs(fem_batch *B, int32_t enable) {
     g_last_error.clear();
     if (!B) return fail(FEM_E_INVALID, "null batch");
@@ -1333,7 +1333,7 @@ int fem_batch_set_option(fem_batch *B, int32_t option, int32_t value) {
     g_last_error.clear();
     if (!B) return fail(FEM_E_INVALID, "null batch");
     switch (option) {
-    case FEM_OPT_CG_CHUNK:
+    case FEM_OPT_ROUND_STEPS:
         if (value < 0 || value > 64) return fail(FEM_E_INVALID, "chunk must be 0..64");
         B->chunk = value;
         return FEM_OK;

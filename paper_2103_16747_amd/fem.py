@@ -29,11 +29,11 @@ EXPORTS = ("fem_create_mesh", "fem_destroy_mesh", "fem_set_material", "fem_set_i
            "fem_get_kernel_timing", "fem_batch_create", "fem_batch_destroy", "fem_batch_add_mesh",
            "fem_batch_mesh_info", "fem_batch_add_job", "fem_batch_restart_job", "fem_batch_remove_job", "fem_batch_run", "fem_batch_job_info",
            "fem_batch_get_displacements", "fem_batch_get_contact_patch", "fem_batch_set_kernel_timing",
-           "fem_batch_get_kernel_timing", "fem_set_graphs", "fem_batch_set_graphs", "fem_batch_set_option",
+           "fem_batch_get_kernel_timing", "fem_batch_get_kernel_launches", "fem_set_graphs", "fem_batch_set_graphs", "fem_batch_set_option",
            "fem_batch_job_footprint", "fem_status_string",
            "fem_last_error")
-FEM_KERNEL_HV, FEM_KERNEL_CG_UPDATE, FEM_KERNEL_ELEMENT = 0, 1, 2
-FEM_OPT_CG_CHUNK, FEM_OPT_TILE_TETS, FEM_OPT_TILE_NODES = 0, 1, 2
+FEM_KERNEL_TILE, FEM_KERNEL_NODE, FEM_KERNEL_FINALIZE = 0, 1, 2
+FEM_OPT_ROUND_STEPS, FEM_OPT_TILE_TETS, FEM_OPT_TILE_NODES = 0, 1, 2
 
 
 class FemError(RuntimeError):
@@ -126,6 +126,7 @@ def load(path: str = LIB_PATH):
     L.fem_batch_get_contact_patch.argtypes = [vp, C.c_int32, i32p, dp, dp, C.c_int32, i32p, dp]
     L.fem_batch_set_kernel_timing.argtypes = [vp, C.c_int32]
     L.fem_batch_get_kernel_timing.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+    L.fem_batch_get_kernel_launches.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64)]
     L.fem_set_graphs.argtypes = [vp, C.c_int32]
     L.fem_batch_set_graphs.argtypes = [vp, C.c_int32]
     L.fem_batch_set_option.argtypes = [vp, C.c_int32, C.c_int32]
@@ -447,6 +448,12 @@ def fem_batch_get_kernel_timing(h, kernel: int):
     return cnt.value, ms.value
 
 
+def fem_batch_get_kernel_launches(h, kernel: int):
+    n = C.c_int64()
+    _check(load().fem_batch_get_kernel_launches(h, int(kernel), C.byref(n)))
+    return n.value
+
+
 class FemBatch:
     """Owns one libfem batch handle: meshes plus concurrently solved jobs."""
 
@@ -518,3 +525,6 @@ class FemBatch:
 
     def kernel_timing(self, kernel):
         return fem_batch_get_kernel_timing(self.h, kernel)
+
+    def kernel_launches(self, kernel):
+        return fem_batch_get_kernel_launches(self.h, kernel)

@@ -143,20 +143,25 @@ def test_layout_covers_mesh():
 def test_graph_replay_matches_stream_launches(precision):
     """Rounds replayed from captured graphs (many replays, with host state
     writes and synchronisations between them) give the results of rounds
-    launched kernel by kernel; kernel timing (which launches kernel by kernel) records events."""
+    launched kernel by kernel; kernel timing (which launches kernel by
+    kernel) records events for each of the three kernels."""
     mesh = W.cube_block_mesh()
     jobs = cube_jobs()
     out = {}
     for graphs in (1, 0):
         batch = fem.FemBatch(len(jobs), precision)
         batch.set_graphs(graphs)
-        batch.set_kernel_timing(4)
+        if not graphs:
+            batch.set_kernel_timing(4)
         mid = batch.add_mesh(mesh.X, mesh.tets, mesh.fixed)
         ids = [batch.add_job(mid, j, E0, NU0) for j in jobs]
         assert batch.run(tight(batch, precision)) == 0
         out[graphs] = [batch.displacements(j) for j in ids]
-        cnt, ms = batch.kernel_timing(fem.FEM_KERNEL_HV)
-        assert cnt > 0 and ms > 0
+        if not graphs:
+            for k in (fem.FEM_KERNEL_TILE, fem.FEM_KERNEL_NODE, fem.FEM_KERNEL_FINALIZE):
+                cnt, ms = batch.kernel_timing(k)
+                launches = batch.kernel_launches(k)
+                assert cnt > 0 and ms > 0 and launches >= 4 * (cnt - 1) + 1
         batch.close()
     tol = 1e-9 if precision == "fp64" else 1e-5
     for a, b in zip(out[1], out[0]):
