@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <bitset>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -88,6 +89,40 @@ uint32_t spread_bits(uint32_t v) {   // 10 bits -> every third bit
 
 // Tets in Morton order of their centroids, cut greedily into tiles of at most
 // kTileTets tets and kTileNodes distinct nodes.
+// Order of a tile's tets for the device: the tile kernels hand 64
+// consecutive tets to one wavefront, which accumulates into LDS one local
+// node slot at a time, so lanes that share a node in the same slot collide
+// on one address. Tets are dealt greedily to groups of 64 (the last group
+// holds the remainder) so that, where possible, no two tets of a group share
+// a node in the same slot; among conflict-free groups the emptiest is taken.
+// placed[j] = index into words of the tet placed at position j.
+void spread_tile(const std::vector<uint32_t> &words, std::vector<int> &placed) {
+    const int nk = (int)words.size();
+    const int ng = (nk + 63) / 64;
+    std::vector<int> cap(ng, 64);
+    if (ng > 0) cap[ng - 1] = nk - 64 * (ng - 1);
+    std::vector<std::bitset<256>> used((size_t)ng * 4);
+    std::vector<std::vector<int>> members(ng);
+    for (int t = 0; t < nk; t++) {
+        int best = -1, best_conf = 5, best_room = -1;
+        for (int g = 0; g < ng; g++) {
+            const int room = cap[g] - (int)members[g].size();
+            if (room == 0) continue;
+            int conf = 0;
+            for (int a = 0; a < 4; a++) conf += used[4 * g + a][(words[t] >> (8 * a)) & 0xff] ? 1 : 0;
+            if (conf < best_conf || (conf == best_conf && room > best_room)) {
+                best = g;
+                best_conf = conf;
+                best_room = room;
+            }
+        }
+        members[best].push_back(t);
+        for (int a = 0; a < 4; a++) used[4 * best + a].set((words[t] >> (8 * a)) & 0xff);
+    }
+    placed.clear();
+    for (const std::vector<int> &g : members) placed.insert(placed.end(), g.begin(), g.end());
+}
+
 void build_layout(const double *X, int n, const int32_t *tets, int m, int max_tets, int max_nodes, HostLayout &L) {
     L.n = n;
     L.m = m;
@@ -120,17 +155,28 @@ void build_layout(const double *X, int n, const int32_t *tets, int m, int max_te
     L.ent_node.clear();
     L.tet_loc.assign(m, 0);
     L.order.resize(m);
-    for (int k = 0; k < m; k++) L.order[k] = key[k].second;
     int tile = 0, tile_tets = 0, tile_nodes = 0, pos = 0;
     std::vector<int> tile_list;
+    std::vector<uint32_t> words;
+    std::vector<int> elems, placed;
     auto close_tile = [&]() {
         std::sort(tile_list.begin(), tile_list.end());   // entries in ascending node order
         for (size_t k = 0; k < tile_list.size(); k++) local[tile_list[k]] = (int)k;
-        for (int k = L.tile_tet.back(); k < pos; k++) {
+        const int t0 = L.tile_tet.back();
+        words.clear();
+        elems.clear();
+        for (int k = t0; k < pos; k++) {
             const int e = key[k].second;
             uint32_t w = 0;
             for (int a = 0; a < 4; a++) w |= (uint32_t)local[tets[4 * e + a]] << (8 * a);
-            L.tet_loc[k] = w;
+            words.push_back(w);
+            elems.push_back(e);
+        }
+        spread_tile(words, placed);
+        for (int k = t0; k < pos; k++) {
+            const int src = placed[k - t0];
+            L.tet_loc[k] = words[src];
+            L.order[k] = elems[src];
         }
         for (int v : tile_list) L.ent_node.push_back(v);
         L.tile_tet.push_back(pos);
