@@ -87,15 +87,31 @@ struct InstState {
     int steps_ok, steps_failed, first_fail, pad2;
 };
 
+// Per-tet record in tile order: D_m^-1 (row a = shape gradient of local node
+// a+1), rest volume and the four 8-bit local node slots, padded to a multiple
+// of 16 bytes so a lane fetches its tet with 16-byte loads from one address.
+template <typename T> struct TetRec;
+template <> struct alignas(16) TetRec<float> {
+    float Bm[9];
+    float V;
+    uint32_t loc;
+    uint32_t pad;
+};
+template <> struct alignas(16) TetRec<double> {
+    double Bm[9];
+    double V;
+    uint32_t loc;
+    uint32_t pad[3];
+};
+static_assert(sizeof(TetRec<float>) == 48 && sizeof(TetRec<double>) == 96, "tet record layout");
+
 template <typename T>
 struct Topo {
     int n, m, ntile, nent, nc, ncb;     // ncb = contact blocks
     const int *tile_tet;                // ntile + 1
     const int *tile_ent;                // ntile + 1
     const int *ent_node;                // nent
-    const T *Bt;                        // 9 x m: D_m^-1 per tet in tile order (field-major)
-    const T *Vt;                        // m: rest volume per tet in tile order
-    const uint32_t *tet_loc;            // m packed local ids
+    const TetRec<T> *rec;               // m, tile order
     const int *node_ent_off;            // n + 1
     const int *node_ent;                // nent
     const uint8_t *fixed;               // n
@@ -228,13 +244,29 @@ struct ElemGeo {
     T V;
 };
 
-// Rest constants of tet k (tile order) from the per-mesh cache.
+__device__ __forceinline__ void unpack_loc(uint32_t w, int l[4]) {
+    l[0] = w & 0xff;
+    l[1] = (w >> 8) & 0xff;
+    l[2] = (w >> 16) & 0xff;
+    l[3] = w >> 24;
+}
+
+// Rest constants and local node slots of tet k (tile order) from the per-mesh
+// records, as whole 16-byte words.
 template <typename T>
-__device__ __forceinline__ ElemGeo<T> load_geometry(const Topo<T> &tp, int k) {
+__device__ __forceinline__ ElemGeo<T> load_tet(const Topo<T> &tp, int k, int l[4]) {
+    constexpr int kWords = (int)(sizeof(TetRec<T>) / 16);
+    const uint4 *src = reinterpret_cast<const uint4 *>(tp.rec + k);
+    uint4 w[kWords];
+#pragma unroll
+    for (int i = 0; i < kWords; i++) w[i] = src[i];
+    TetRec<T> r;
+    __builtin_memcpy(&r, w, sizeof r);
     ElemGeo<T> g;
 #pragma unroll
-    for (int c = 0; c < 9; c++) g.Bm[c] = tp.Bt[c * tp.m + k];
-    g.V = tp.Vt[k];
+    for (int c = 0; c < 9; c++) g.Bm[c] = r.Bm[c];
+    g.V = r.V;
+    unpack_loc(r.loc, l);
     return g;
 }
 
@@ -276,14 +308,31 @@ __device__ __forceinline__ T fast_log1p(T x) {
     return (T)2 * s * p;
 }
 
-// G = sum_a (w_{a+1} - w_0) (x) row_a(D_m^-1), w read from LDS (3 per entry).
+// Staged node vectors in LDS: kSw values per entry (x, y, z, unused), so a
+// node is one aligned 4-vector read.
+constexpr int kSw = 4;
+template <typename T> using vec4_t = T __attribute__((ext_vector_type(4)));
+
+// The four nodes' staged vectors of one tet, read once into registers.
 template <typename T>
-__device__ __forceinline__ void edge_gradient(const T *sw, const int l[4], const T Bm[9], T G[9]) {
+__device__ __forceinline__ void load_nodes(const T *sw, const int l[4], T w[4][3]) {
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+        const vec4_t<T> v = *reinterpret_cast<const vec4_t<T> *>(sw + kSw * l[a]);
+        w[a][0] = v.x;
+        w[a][1] = v.y;
+        w[a][2] = v.z;
+    }
+}
+
+// G = sum_a (w_{a+1} - w_0) (x) row_a(D_m^-1).
+template <typename T>
+__device__ __forceinline__ void edge_gradient(const T w[4][3], const T Bm[9], T G[9]) {
     T d[3][3];
 #pragma unroll
     for (int a = 0; a < 3; a++)
 #pragma unroll
-        for (int i = 0; i < 3; i++) d[a][i] = sw[3 * l[a + 1] + i] - sw[3 * l[0] + i];
+        for (int i = 0; i < 3; i++) d[a][i] = w[a + 1][i] - w[0][i];
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
@@ -329,13 +378,6 @@ __device__ __forceinline__ void element_nodal(const T S[9], const T Bm[9], T V, 
             f[a + 1][i] = V * (S[3 * i] * Bm[3 * a] + S[3 * i + 1] * Bm[3 * a + 1] + S[3 * i + 2] * Bm[3 * a + 2]);
 #pragma unroll
     for (int i = 0; i < 3; i++) f[0][i] = -(f[1][i] + f[2][i] + f[3][i]);
-}
-
-__device__ __forceinline__ void unpack_loc(uint32_t w, int l[4]) {
-    l[0] = w & 0xff;
-    l[1] = (w >> 8) & 0xff;
-    l[2] = (w >> 16) & 0xff;
-    l[3] = w >> 24;
 }
 
 // ---------------------------------------------------------------------------
@@ -496,12 +538,13 @@ __device__ __forceinline__ void store_partials(double *red, int stride, const in
 }
 
 // LDS of a tile block, shared by the two tile paths (doubles): the element
-// path keeps 9 FP64 accumulators and 3 state values per entry, the Hessian
-// path 3 accumulators and 6 state values.
+// path keeps 9 FP64 accumulators and one staged vector per entry, the
+// Hessian path 3 accumulators and two staged vectors.
 template <typename T>
 struct TileLds {
-    static constexpr int kElem = 9 * kTileNodes + (3 * kTileNodes * (int)sizeof(T) + 7) / 8;
-    static constexpr int kHv = 3 * kTileNodes + (6 * kTileNodes * (int)sizeof(T) + 7) / 8;
+    static constexpr int kVec = kSw * kTileNodes * (int)sizeof(T) / 8;
+    static constexpr int kElem = 9 * kTileNodes + kVec;
+    static constexpr int kHv = 3 * kTileNodes + 2 * kVec;
     static constexpr int kDoubles = kElem > kHv ? kElem : kHv;
 };
 
@@ -520,7 +563,7 @@ __device__ __forceinline__ void tile_element(const Topo<T> &tp, const InstBufs<T
     double acc[3] = {0.0, 0.0, INFINITY};   // energy, magnitude, min J
     if (blk < tp.ntile) {
         double *sa = pool;                          // 9 per entry, FP64 in both precisions
-        T *su = (T *)(pool + 9 * kTileNodes);       // 3 per entry
+        T *su = (T *)(pool + 9 * kTileNodes);       // kSw per entry
         const int t = blk;
         const int e0 = tp.tile_ent[t], ne = tp.tile_ent[t + 1] - e0;
         const int k0 = tp.tile_tet[t], nk = tp.tile_tet[t + 1] - k0;
@@ -530,18 +573,20 @@ __device__ __forceinline__ void tile_element(const Topo<T> &tp, const InstBufs<T
             for (int d = 0; d < 3; d++) {
                 T uu = B.u[3 * gid + d];
                 if (alpha != (T)0) uu = fma_t(alpha, B.dx[3 * gid + d], uu);
-                su[3 * l + d] = uu;
+                su[kSw * l + d] = uu;
             }
+            su[kSw * l + 3] = (T)0;
 #pragma unroll
             for (int c = 0; c < 9; c++) sa[9 * l + c] = 0.0;
         }
         __syncthreads();
         for (int k = threadIdx.x; k < nk; k += kBlock) {
             int l[4];
-            unpack_loc(tp.tet_loc[k0 + k], l);
-            const ElemGeo<T> geo = load_geometry(tp, k0 + k);
+            const ElemGeo<T> geo = load_tet(tp, k0 + k, l);
+            T wu[4][3];
+            load_nodes(su, l, wu);
             T G[9];
-            edge_gradient(su, l, geo.Bm, G);
+            edge_gradient(wu, geo.Bm, G);
             const T Jm1 = det_minus_one(G);
             const T J = (T)1 + Jm1;
             acc[2] = fmin(acc[2], (double)J);
@@ -659,8 +704,8 @@ __device__ __forceinline__ void tile_hessvec(const Topo<T> &tp, const InstBufs<T
     double unused = 0.0;
     if (blk < tp.ntile) {
         double *sa = pool;                          // 3 per entry, FP64 in both precisions
-        T *su = (T *)(pool + 3 * kTileNodes);       // 3 per entry
-        T *sp = su + 3 * kTileNodes;                // 3 per entry
+        T *su = (T *)(pool + 3 * kTileNodes);       // kSw per entry
+        T *sp = su + kSw * kTileNodes;              // kSw per entry
         const int t = blk;
         const int e0 = tp.tile_ent[t], ne = tp.tile_ent[t + 1] - e0;
         const int k0 = tp.tile_tet[t], nk = tp.tile_tet[t + 1] - k0;
@@ -668,19 +713,23 @@ __device__ __forceinline__ void tile_hessvec(const Topo<T> &tp, const InstBufs<T
             const int gid = tp.ent_node[e0 + l];
 #pragma unroll
             for (int d = 0; d < 3; d++) {
-                su[3 * l + d] = B.u[3 * gid + d];
-                sp[3 * l + d] = fma_t(beta, B.p[3 * gid + d], B.z[3 * gid + d]);
+                su[kSw * l + d] = B.u[3 * gid + d];
+                sp[kSw * l + d] = fma_t(beta, B.p[3 * gid + d], B.z[3 * gid + d]);
                 sa[3 * l + d] = 0.0;
             }
+            su[kSw * l + 3] = (T)0;
+            sp[kSw * l + 3] = (T)0;
         }
         __syncthreads();
         double pq = 0.0;
         for (int k = threadIdx.x; k < nk; k += kBlock) {
             int l[4];
-            unpack_loc(tp.tet_loc[k0 + k], l);
-            const ElemGeo<T> geo = load_geometry(tp, k0 + k);
+            const ElemGeo<T> geo = load_tet(tp, k0 + k, l);
+            T wu[4][3], wp[4][3];
+            load_nodes(su, l, wu);
+            load_nodes(sp, l, wp);
             T G[9];
-            edge_gradient(su, l, geo.Bm, G);
+            edge_gradient(wu, geo.Bm, G);
             const T Jm1 = det_minus_one(G);
             const T J = (T)1 + Jm1;
             if (!(J > (T)0)) continue;
@@ -688,7 +737,7 @@ __device__ __forceinline__ void tile_hessvec(const Topo<T> &tp, const InstBufs<T
             T FiT[9];
             inverse_transpose<T, true>(G, J, FiT);
             T dG[9];
-            edge_gradient(sp, l, geo.Bm, dG);
+            edge_gradient(wp, geo.Bm, dG);
             // A = F^-1 dG (F^-1 = FiT^T)
             T A[9];
 #pragma unroll
@@ -714,7 +763,7 @@ __device__ __forceinline__ void tile_hessvec(const Topo<T> &tp, const InstBufs<T
                 atomicAdd(dst + 0, (double)f[a][0]);
                 atomicAdd(dst + 1, (double)f[a][1]);
                 atomicAdd(dst + 2, (double)f[a][2]);
-                e_pq += sp[3 * l[a]] * f[a][0] + sp[3 * l[a] + 1] * f[a][1] + sp[3 * l[a] + 2] * f[a][2];
+                e_pq += wp[a][0] * f[a][0] + wp[a][1] * f[a][1] + wp[a][2] * f[a][2];
             }
             pq += (double)e_pq;
         }
@@ -752,7 +801,7 @@ __device__ __forceinline__ void tile_hessvec(const Topo<T> &tp, const InstBufs<T
 template <typename T>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 1 : 3))) void k_tile(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
                                                  int nwork, const SolveParams *P) {
-    __shared__ double pool[TileLds<T>::kDoubles];
+    __shared__ __attribute__((aligned(32))) double pool[TileLds<T>::kDoubles];
     const int L = logical_block();
     if (L >= nwork) return;
     const int2 w = work[L];
@@ -1203,10 +1252,11 @@ __global__ __launch_bounds__(kBlock) void k_check_volumes(const double *X, const
 }
 
 // Rest constants per tet in tile order (FP64, stored in the path precision):
-// D_m = [X1-X0, X2-X0, X3-X0], D_m^-1 by cofactors, V = det D_m / 6.
+// D_m = [X1-X0, X2-X0, X3-X0], D_m^-1 by cofactors, V = det D_m / 6; with the
+// tet's packed local node slots.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_rest_constants(const double *X, const int *tet, const int *order, int m,
-                                                           T *Bt, T *Vt) {
+__global__ __launch_bounds__(kBlock) void k_rest_constants(const double *X, const int *tet, const int *order,
+                                                           const uint32_t *loc, int m, TetRec<T> *rec) {
     const int k = blockIdx.x * kBlock + threadIdx.x;
     if (k >= m) return;
     const int e = order[k];
@@ -1224,9 +1274,12 @@ __global__ __launch_bounds__(kBlock) void k_rest_constants(const double *X, cons
     const double inv[9] = {c00 * id, (D[2] * D[7] - D[1] * D[8]) * id, (D[1] * D[5] - D[2] * D[4]) * id,
                            c01 * id, (D[0] * D[8] - D[2] * D[6]) * id, (D[2] * D[3] - D[0] * D[5]) * id,
                            c02 * id, (D[1] * D[6] - D[0] * D[7]) * id, (D[0] * D[4] - D[1] * D[3]) * id};
+    TetRec<T> r{};
 #pragma unroll
-    for (int c = 0; c < 9; c++) Bt[c * m + k] = (T)inv[c];
-    Vt[k] = (T)(det / 6.0);
+    for (int c = 0; c < 9; c++) r.Bm[c] = (T)inv[c];
+    r.V = (T)(det / 6.0);
+    r.loc = loc[k];
+    rec[k] = r;
 }
 
 // Boundary faces by hashing the sorted node triple (21 bits per id) of each

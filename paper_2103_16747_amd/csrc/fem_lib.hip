@@ -368,8 +368,8 @@ int add_topology(fem_batch *B, const double *X, int n, const int32_t *tets, int 
     R.nent = L.nent;
     Arena A;
     const size_t o_tile_tet = A.take<int>(L.ntile + 1), o_tile_ent = A.take<int>(L.ntile + 1);
-    const size_t o_ent_node = A.take<int>(L.nent), o_Bt = A.take<T>(9 * (size_t)m), o_Vt = A.take<T>(m);
-    const size_t o_loc = A.take<uint32_t>(m), o_neo = A.take<int>(n + 1), o_ne = A.take<int>(L.nent);
+    const size_t o_ent_node = A.take<int>(L.nent), o_rec = A.take<TetRec<T>>(m);
+    const size_t o_neo = A.take<int>(n + 1), o_ne = A.take<int>(L.nent);
     const size_t o_fixed = A.take<uint8_t>(n), o_cn = A.take<int>(n), o_cidx = A.take<int>(n);
     const size_t o_X = A.take<double>(3 * (size_t)n), o_elig = A.take<uint8_t>(n);
     HIP_TRY(hipMalloc(&R.arena, A.off));
@@ -382,7 +382,6 @@ int add_topology(fem_batch *B, const double *X, int n, const int32_t *tets, int 
     if (!rc) rc = up(o_tile_tet, L.tile_tet.data(), L.tile_tet.size() * sizeof(int));
     if (!rc) rc = up(o_tile_ent, L.tile_ent.data(), L.tile_ent.size() * sizeof(int));
     if (!rc) rc = up(o_ent_node, L.ent_node.data(), L.ent_node.size() * sizeof(int));
-    if (!rc) rc = up(o_loc, L.tet_loc.data(), L.tet_loc.size() * sizeof(uint32_t));
     if (!rc) rc = up(o_neo, L.node_ent_off.data(), L.node_ent_off.size() * sizeof(int));
     if (!rc) rc = up(o_ne, L.node_ent.data(), L.node_ent.size() * sizeof(int));
     if (!rc) rc = up(o_fixed, fixed, n);
@@ -391,17 +390,20 @@ int add_topology(fem_batch *B, const double *X, int n, const int32_t *tets, int 
     unsigned slots = 1;
     while (slots < 8u * (unsigned)m) slots <<= 1;
     int *d_tets = nullptr, *d_scalar = nullptr, *d_order = nullptr;
+    uint32_t *d_loc = nullptr;
     unsigned long long *keys = nullptr;
     unsigned *cnt = nullptr;
     uint8_t *surf = nullptr;
     const int big = 0x7fffffff;
     if (!rc && (hipMalloc(&d_tets, 4 * (size_t)m * sizeof(int)) != hipSuccess || hipMalloc(&d_scalar, 2 * sizeof(int)) != hipSuccess ||
                 hipMalloc(&d_order, (size_t)m * sizeof(int)) != hipSuccess ||
+                hipMalloc(&d_loc, (size_t)m * sizeof(uint32_t)) != hipSuccess ||
                 hipMalloc(&keys, slots * sizeof(unsigned long long)) != hipSuccess ||
                 hipMalloc(&cnt, slots * sizeof(unsigned)) != hipSuccess || hipMalloc(&surf, n) != hipSuccess))
         rc = fail(FEM_E_OOM, "set-up scratch allocation failed");
     if (!rc && (hipMemcpyAsync(d_tets, tets, 4 * (size_t)m * sizeof(int), hipMemcpyHostToDevice, B->stream) != hipSuccess ||
                 hipMemcpyAsync(d_order, L.order.data(), (size_t)m * sizeof(int), hipMemcpyHostToDevice, B->stream) != hipSuccess ||
+                hipMemcpyAsync(d_loc, L.tet_loc.data(), (size_t)m * sizeof(uint32_t), hipMemcpyHostToDevice, B->stream) != hipSuccess ||
                 hipMemcpyAsync(d_scalar, &big, sizeof(int), hipMemcpyHostToDevice, B->stream) != hipSuccess ||
                 hipMemsetAsync(keys, 0xff, slots * sizeof(unsigned long long), B->stream) != hipSuccess ||
                 hipMemsetAsync(cnt, 0, slots * sizeof(unsigned), B->stream) != hipSuccess ||
@@ -410,8 +412,8 @@ int add_topology(fem_batch *B, const double *X, int n, const int32_t *tets, int 
     int host[2] = {0, 0};
     if (!rc) {
         k_check_volumes<<<ceil_div(m, kBlock), kBlock, 0, B->stream>>>((const double *)(base + o_X), d_tets, m, d_scalar);
-        k_rest_constants<T><<<ceil_div(m, kBlock), kBlock, 0, B->stream>>>((const double *)(base + o_X), d_tets, d_order, m,
-                                                                           (T *)(base + o_Bt), (T *)(base + o_Vt));
+        k_rest_constants<T><<<ceil_div(m, kBlock), kBlock, 0, B->stream>>>((const double *)(base + o_X), d_tets, d_order,
+                                                                           d_loc, m, (TetRec<T> *)(base + o_rec));
         k_faces_insert<<<ceil_div(4LL * m, kBlock), kBlock, 0, B->stream>>>(d_tets, m, keys, cnt, slots - 1);
         k_faces_mark<<<ceil_div(4LL * m, kBlock), kBlock, 0, B->stream>>>(d_tets, m, keys, cnt, slots - 1, surf);
         k_compact_eligible<<<1, 1024, 0, B->stream>>>(surf, (const uint8_t *)(base + o_fixed), n,
@@ -425,6 +427,7 @@ int add_topology(fem_batch *B, const double *X, int n, const int32_t *tets, int 
     (void)hipStreamSynchronize(B->stream);
     if (d_tets) (void)hipFree(d_tets);
     if (d_order) (void)hipFree(d_order);
+    if (d_loc) (void)hipFree(d_loc);
     if (d_scalar) (void)hipFree(d_scalar);
     if (keys) (void)hipFree(keys);
     if (cnt) (void)hipFree(cnt);
@@ -447,9 +450,7 @@ int add_topology(fem_batch *B, const double *X, int n, const int32_t *tets, int 
     v.tile_tet = (const int *)(base + o_tile_tet);
     v.tile_ent = (const int *)(base + o_tile_ent);
     v.ent_node = (const int *)(base + o_ent_node);
-    v.Bt = (const T *)(base + o_Bt);
-    v.Vt = (const T *)(base + o_Vt);
-    v.tet_loc = (const uint32_t *)(base + o_loc);
+    v.rec = (const TetRec<T> *)(base + o_rec);
     v.node_ent_off = (const int *)(base + o_neo);
     v.node_ent = (const int *)(base + o_ne);
     v.fixed = (const uint8_t *)(base + o_fixed);
