@@ -1252,19 +1252,21 @@ __global__ __launch_bounds__(kBlock) void k_check_volumes(const double *X, const
 }
 
 // Rest constants per tet in tile order (FP64, stored in the path precision):
-// D_m = [X1-X0, X2-X0, X3-X0], D_m^-1 by cofactors, V = det D_m / 6; with the
-// tet's packed local node slots.
+// D_m = [X1-X0, X2-X0, X3-X0], D_m^-1 by cofactors, V = det D_m / 6, from the
+// tet's nodes in device vertex order (tnodes, 4 per tet in tile order; an
+// even reordering of the input, so det D_m keeps its sign); with the tet's
+// packed local node slots.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_rest_constants(const double *X, const int *tet, const int *order,
-                                                           const uint32_t *loc, int m, TetRec<T> *rec) {
+__global__ __launch_bounds__(kBlock) void k_rest_constants(const double *X, const int *tnodes, const uint32_t *loc,
+                                                           int m, TetRec<T> *rec) {
     const int k = blockIdx.x * kBlock + threadIdx.x;
     if (k >= m) return;
-    const int e = order[k];
-    const int v0 = tet[4 * e];
+    const int *tet = tnodes + 4 * (size_t)k;
+    const int v0 = tet[0];
     double D[9];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        const int va = tet[4 * e + a + 1];
+        const int va = tet[a + 1];
 #pragma unroll
         for (int i = 0; i < 3; i++) D[3 * i + a] = X[3 * va + i] - X[3 * v0 + i];
     }

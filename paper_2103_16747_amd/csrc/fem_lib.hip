@@ -74,8 +74,8 @@ struct Arena {
 struct HostLayout {
     int n = 0, m = 0, ntile = 0, nent = 0;
     std::vector<int> tile_tet, tile_ent, ent_node, node_ent_off, node_ent;
-    std::vector<int> order;      // tile order -> input tet index
     std::vector<uint32_t> tet_loc;
+    std::vector<int> tet_nodes;         // 4 x m: global node ids per tet in tile order and device vertex order
 };
 
 uint32_t spread_bits(uint32_t v) {   // 10 bits -> every third bit
@@ -89,38 +89,61 @@ uint32_t spread_bits(uint32_t v) {   // 10 bits -> every third bit
 
 // Tets in Morton order of their centroids, cut greedily into tiles of at most
 // kTileTets tets and kTileNodes distinct nodes.
-// Order of a tile's tets for the device: the tile kernels hand 64
-// consecutive tets to one wavefront, which accumulates into LDS one local
-// node slot at a time, so lanes that share a node in the same slot collide
-// on one address. Tets are dealt greedily to groups of 64 (the last group
-// holds the remainder) so that, where possible, no two tets of a group share
-// a node in the same slot; among conflict-free groups the emptiest is taken.
-// placed[j] = index into words of the tet placed at position j.
+// Order and vertex rotation of a tile's tets for the device. The tile
+// kernels hand 64 consecutive tets to one wavefront, which accumulates into
+// LDS one local node slot at a time with 64-bit atomics; lanes that share a
+// node in one slot serialise on one address, and the LDS serves such an
+// instruction 16 lanes at a time, where nodes whose local ids agree mod 16
+// fall on one bank. Tets are dealt greedily to quarters of 16 positions (the
+// last one holds the remainder), each also free to take one of the 12 even
+// vertex orders (orientation, hence the sign of det D_m, is kept): first
+// avoiding a node repeated in one slot within a group of 64, then a bank
+// repeated in one slot within a quarter; ties go to the emptiest quarter.
+// placed[j] = (index into words) * 16 + order, for position j.
+constexpr int kEvenPerm[12][4] = {{0, 1, 2, 3}, {0, 2, 3, 1}, {0, 3, 1, 2}, {1, 0, 3, 2}, {1, 2, 0, 3}, {1, 3, 2, 0},
+                                  {2, 0, 1, 3}, {2, 1, 3, 0}, {2, 3, 0, 1}, {3, 0, 2, 1}, {3, 1, 0, 2}, {3, 2, 1, 0}};
+
 void spread_tile(const std::vector<uint32_t> &words, std::vector<int> &placed) {
     const int nk = (int)words.size();
     const int ng = (nk + 63) / 64;
-    std::vector<int> cap(ng, 64);
-    if (ng > 0) cap[ng - 1] = nk - 64 * (ng - 1);
-    std::vector<std::bitset<256>> used((size_t)ng * 4);
-    std::vector<std::vector<int>> members(ng);
+    const int nq = (nk + 15) / 16;
+    std::vector<int> cap(nq, 16);
+    if (nq > 0) cap[nq - 1] = nk - 16 * (nq - 1);
+    std::vector<std::bitset<256>> used((size_t)ng * 4);   // nodes per group and slot
+    std::vector<uint32_t> bank((size_t)nq * 4, 0u);       // local id mod 16 per quarter and slot
+    std::vector<std::vector<int>> members(nq);
     for (int t = 0; t < nk; t++) {
-        int best = -1, best_conf = 5, best_room = -1;
-        for (int g = 0; g < ng; g++) {
-            const int room = cap[g] - (int)members[g].size();
+        int l[4];
+        for (int a = 0; a < 4; a++) l[a] = (words[t] >> (8 * a)) & 0xff;
+        int best = -1, best_perm = 0, best_cost = 1 << 30, best_room = -1;
+        for (int q = 0; q < nq; q++) {
+            const int room = cap[q] - (int)members[q].size();
             if (room == 0) continue;
-            int conf = 0;
-            for (int a = 0; a < 4; a++) conf += used[4 * g + a][(words[t] >> (8 * a)) & 0xff] ? 1 : 0;
-            if (conf < best_conf || (conf == best_conf && room > best_room)) {
-                best = g;
-                best_conf = conf;
-                best_room = room;
+            const int g = q / 4;
+            for (int r = 0; r < 12; r++) {
+                int cost = 0;
+                for (int a = 0; a < 4; a++) {
+                    const int v = l[kEvenPerm[r][a]];
+                    cost += used[4 * g + a][v] ? 64 : 0;
+                    cost += (bank[4 * q + a] >> (v & 15)) & 1u;
+                }
+                if (cost < best_cost || (cost == best_cost && room > best_room)) {
+                    best = q;
+                    best_perm = r;
+                    best_cost = cost;
+                    best_room = room;
+                }
             }
         }
-        members[best].push_back(t);
-        for (int a = 0; a < 4; a++) used[4 * best + a].set((words[t] >> (8 * a)) & 0xff);
+        members[best].push_back(t * 16 + best_perm);
+        for (int a = 0; a < 4; a++) {
+            const int v = l[kEvenPerm[best_perm][a]];
+            used[4 * (best / 4) + a].set(v);
+            bank[4 * best + a] |= 1u << (v & 15);
+        }
     }
     placed.clear();
-    for (const std::vector<int> &g : members) placed.insert(placed.end(), g.begin(), g.end());
+    for (const std::vector<int> &q : members) placed.insert(placed.end(), q.begin(), q.end());
 }
 
 void build_layout(const double *X, int n, const int32_t *tets, int m, int max_tets, int max_nodes, HostLayout &L) {
@@ -154,7 +177,7 @@ void build_layout(const double *X, int n, const int32_t *tets, int m, int max_te
     L.tile_ent.assign(1, 0);
     L.ent_node.clear();
     L.tet_loc.assign(m, 0);
-    L.order.resize(m);
+    L.tet_nodes.assign(4 * (size_t)m, 0);
     int tile = 0, tile_tets = 0, tile_nodes = 0, pos = 0;
     std::vector<int> tile_list;
     std::vector<uint32_t> words;
@@ -174,9 +197,15 @@ void build_layout(const double *X, int n, const int32_t *tets, int m, int max_te
         }
         spread_tile(words, placed);
         for (int k = t0; k < pos; k++) {
-            const int src = placed[k - t0];
-            L.tet_loc[k] = words[src];
-            L.order[k] = elems[src];
+            const int src = placed[k - t0] >> 4, r = placed[k - t0] & 15;
+            const int e = elems[src];
+            uint32_t w = 0;
+            for (int a = 0; a < 4; a++) {
+                const int from = kEvenPerm[r][a];
+                w |= ((words[src] >> (8 * from)) & 0xffu) << (8 * a);
+                L.tet_nodes[4 * (size_t)k + a] = tets[4 * (size_t)e + from];
+            }
+            L.tet_loc[k] = w;
         }
         for (int v : tile_list) L.ent_node.push_back(v);
         L.tile_tet.push_back(pos);
@@ -389,20 +418,20 @@ int add_topology(fem_batch *B, const double *X, int n, const int32_t *tets, int 
     // Rest volumes and boundary faces from the original connectivity.
     unsigned slots = 1;
     while (slots < 8u * (unsigned)m) slots <<= 1;
-    int *d_tets = nullptr, *d_scalar = nullptr, *d_order = nullptr;
+    int *d_tets = nullptr, *d_scalar = nullptr, *d_tnodes = nullptr;
     uint32_t *d_loc = nullptr;
     unsigned long long *keys = nullptr;
     unsigned *cnt = nullptr;
     uint8_t *surf = nullptr;
     const int big = 0x7fffffff;
     if (!rc && (hipMalloc(&d_tets, 4 * (size_t)m * sizeof(int)) != hipSuccess || hipMalloc(&d_scalar, 2 * sizeof(int)) != hipSuccess ||
-                hipMalloc(&d_order, (size_t)m * sizeof(int)) != hipSuccess ||
+                hipMalloc(&d_tnodes, 4 * (size_t)m * sizeof(int)) != hipSuccess ||
                 hipMalloc(&d_loc, (size_t)m * sizeof(uint32_t)) != hipSuccess ||
                 hipMalloc(&keys, slots * sizeof(unsigned long long)) != hipSuccess ||
                 hipMalloc(&cnt, slots * sizeof(unsigned)) != hipSuccess || hipMalloc(&surf, n) != hipSuccess))
         rc = fail(FEM_E_OOM, "set-up scratch allocation failed");
     if (!rc && (hipMemcpyAsync(d_tets, tets, 4 * (size_t)m * sizeof(int), hipMemcpyHostToDevice, B->stream) != hipSuccess ||
-                hipMemcpyAsync(d_order, L.order.data(), (size_t)m * sizeof(int), hipMemcpyHostToDevice, B->stream) != hipSuccess ||
+                hipMemcpyAsync(d_tnodes, L.tet_nodes.data(), 4 * (size_t)m * sizeof(int), hipMemcpyHostToDevice, B->stream) != hipSuccess ||
                 hipMemcpyAsync(d_loc, L.tet_loc.data(), (size_t)m * sizeof(uint32_t), hipMemcpyHostToDevice, B->stream) != hipSuccess ||
                 hipMemcpyAsync(d_scalar, &big, sizeof(int), hipMemcpyHostToDevice, B->stream) != hipSuccess ||
                 hipMemsetAsync(keys, 0xff, slots * sizeof(unsigned long long), B->stream) != hipSuccess ||
@@ -412,8 +441,8 @@ int add_topology(fem_batch *B, const double *X, int n, const int32_t *tets, int 
     int host[2] = {0, 0};
     if (!rc) {
         k_check_volumes<<<ceil_div(m, kBlock), kBlock, 0, B->stream>>>((const double *)(base + o_X), d_tets, m, d_scalar);
-        k_rest_constants<T><<<ceil_div(m, kBlock), kBlock, 0, B->stream>>>((const double *)(base + o_X), d_tets, d_order,
-                                                                           d_loc, m, (TetRec<T> *)(base + o_rec));
+        k_rest_constants<T><<<ceil_div(m, kBlock), kBlock, 0, B->stream>>>((const double *)(base + o_X), d_tnodes, d_loc,
+                                                                           m, (TetRec<T> *)(base + o_rec));
         k_faces_insert<<<ceil_div(4LL * m, kBlock), kBlock, 0, B->stream>>>(d_tets, m, keys, cnt, slots - 1);
         k_faces_mark<<<ceil_div(4LL * m, kBlock), kBlock, 0, B->stream>>>(d_tets, m, keys, cnt, slots - 1, surf);
         k_compact_eligible<<<1, 1024, 0, B->stream>>>(surf, (const uint8_t *)(base + o_fixed), n,
@@ -426,7 +455,7 @@ int add_topology(fem_batch *B, const double *X, int n, const int32_t *tets, int 
     if (!rc && hipStreamSynchronize(B->stream) != hipSuccess) rc = fail(FEM_E_DEVICE, "mesh set-up failed");
     (void)hipStreamSynchronize(B->stream);
     if (d_tets) (void)hipFree(d_tets);
-    if (d_order) (void)hipFree(d_order);
+    if (d_tnodes) (void)hipFree(d_tnodes);
     if (d_loc) (void)hipFree(d_loc);
     if (d_scalar) (void)hipFree(d_scalar);
     if (keys) (void)hipFree(keys);
