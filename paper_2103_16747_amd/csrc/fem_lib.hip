@@ -278,6 +278,7 @@ struct TopoRec {
 
 struct InstRec {
     bool live = false;
+    bool in_tables = false;   // has blocks in the current work tables
     int topo = -1;
     void *arena = nullptr;
     InstBufs<float> b32{};
@@ -540,29 +541,37 @@ void free_instance(fem_batch *B, int slot) {
     B->tables_dirty = true;
 }
 
-// Work tables: tile (+ contact) blocks and node blocks of every live
-// instance, ordered tile-major so one tile of consecutive instances is
-// processed back to back (on one XCD, see logical_block()).
+inline bool running_phase(int ph) { return ph != PH_IDLE && ph != PH_DONE; }
+
+// Work tables: tile (+ contact) blocks and node blocks of every running
+// instance (as of the host's last view of the states), ordered tile-major so
+// one tile of consecutive instances is processed back to back (on one XCD,
+// see logical_block()). Finished instances are left out, so their blocks
+// cost nothing; one made to run again (restart) is put back by the next run.
+// Mesh and buffer descriptors are uploaded again only after a structural
+// change (mesh or job added or removed).
 template <typename T>
 int rebuild_tables(fem_batch *B) {
     std::vector<int2> wt, wn;
+    std::vector<int> live;
     int max_t = 0, max_nb = 0;
-    for (const InstRec &R : B->insts)
-        if (R.live) {
-            const TopoRec &tp = B->topos[R.topo];
-            max_t = std::max(max_t, tp.ntile + tp.ncb);
-            max_nb = std::max(max_nb, ceil_div(tp.n, kBlock));
-        }
+    for (int i = 0; i < B->capacity; i++) {
+        InstRec &R = B->insts[i];
+        R.in_tables = R.live && running_phase(B->h_states[i].phase);
+        if (!R.in_tables) continue;
+        const TopoRec &tp = B->topos[R.topo];
+        max_t = std::max(max_t, tp.ntile + tp.ncb);
+        max_nb = std::max(max_nb, ceil_div(tp.n, kBlock));
+        live.push_back(i);
+    }
     for (int t = 0; t < max_t; t++)
-        for (int i = 0; i < B->capacity; i++) {
-            const InstRec &R = B->insts[i];
-            if (R.live && t < B->topos[R.topo].ntile + B->topos[R.topo].ncb) wt.push_back(make_int2(i, t));
+        for (int i : live) {
+            const TopoRec &tp = B->topos[B->insts[i].topo];
+            if (t < tp.ntile + tp.ncb) wt.push_back(make_int2(i, t));
         }
     for (int t = 0; t < max_nb; t++)
-        for (int i = 0; i < B->capacity; i++) {
-            const InstRec &R = B->insts[i];
-            if (R.live && t < ceil_div(B->topos[R.topo].n, kBlock)) wn.push_back(make_int2(i, t));
-        }
+        for (int i : live)
+            if (t < ceil_div(B->topos[B->insts[i].topo].n, kBlock)) wn.push_back(make_int2(i, t));
     auto upload = [&](const std::vector<int2> &v, int2 *&d, int &cap, int &count) -> int {
         if ((int)v.size() > cap) {
             if (d) (void)hipFree(d);
@@ -577,24 +586,25 @@ int rebuild_tables(fem_batch *B) {
     drop_graphs(B);
     TRY(upload(wt, B->d_work_tile, B->cap_work_tile, B->nwork_tile));
     TRY(upload(wn, B->d_work_node, B->cap_work_node, B->nwork_node));
-    std::vector<int> live;
-    for (int i = 0; i < B->capacity; i++)
-        if (B->insts[i].live) live.push_back(i);
     B->nlive = (int)live.size();
     if (!live.empty())
         HIP_TRY(hipMemcpyAsync(B->d_live, live.data(), live.size() * sizeof(int), hipMemcpyHostToDevice, B->stream));
-    std::vector<Topo<T>> tv;
-    for (TopoRec &R : B->topos) tv.push_back(topo_view<T>(R));
-    TRY(sync(B));
-    if (B->d_topos) (void)hipFree(B->d_topos);
-    B->d_topos = nullptr;
-    HIP_TRY(hipMalloc(&B->d_topos, std::max<size_t>(tv.size(), 1) * sizeof(Topo<T>)));
-    if (!tv.empty())
-        HIP_TRY(hipMemcpyAsync(B->d_topos, tv.data(), tv.size() * sizeof(Topo<T>), hipMemcpyHostToDevice, B->stream));
-    std::vector<InstBufs<T>> bv(B->capacity);
-    for (int i = 0; i < B->capacity; i++) bv[i] = inst_view<T>(B->insts[i]);
-    HIP_TRY(hipMemcpyAsync(B->d_bufs, bv.data(), bv.size() * sizeof(InstBufs<T>), hipMemcpyHostToDevice, B->stream));
-    TRY(sync(B));
+    if (B->tables_dirty) {
+        std::vector<Topo<T>> tv;
+        for (TopoRec &R : B->topos) tv.push_back(topo_view<T>(R));
+        TRY(sync(B));
+        if (B->d_topos) (void)hipFree(B->d_topos);
+        B->d_topos = nullptr;
+        HIP_TRY(hipMalloc(&B->d_topos, std::max<size_t>(tv.size(), 1) * sizeof(Topo<T>)));
+        if (!tv.empty())
+            HIP_TRY(hipMemcpyAsync(B->d_topos, tv.data(), tv.size() * sizeof(Topo<T>), hipMemcpyHostToDevice, B->stream));
+        std::vector<InstBufs<T>> bv(B->capacity);
+        for (int i = 0; i < B->capacity; i++) bv[i] = inst_view<T>(B->insts[i]);
+        HIP_TRY(hipMemcpyAsync(B->d_bufs, bv.data(), bv.size() * sizeof(InstBufs<T>), hipMemcpyHostToDevice, B->stream));
+        TRY(sync(B));
+    } else {
+        TRY(sync(B));
+    }
     B->tables_dirty = false;
     return FEM_OK;
 }
@@ -627,8 +637,6 @@ int write_state(fem_batch *B, int slot) {
     HIP_TRY(hipMemcpyAsync(B->d_states + slot, B->h_states + slot, sizeof(InstState), hipMemcpyHostToDevice, B->stream));
     return sync(B);
 }
-
-inline bool running_phase(int ph) { return ph != PH_IDLE && ph != PH_DONE; }
 
 // One round: C solver steps, each a tile pass, a node pass and a finalize
 // over every live instance. With kernel timing on, sampled launches are
@@ -689,18 +697,27 @@ int launch_round(fem_batch *B, int chunk) {
 // Advances every running job until all are done or max_rounds rounds ran.
 template <typename T>
 int run_impl(fem_batch *B, int max_rounds, int *n_running) {
-    if (B->tables_dirty) TRY(rebuild_tables<T>(B));
     int rounds = 0, running = 0;
     TRY(read_states(B));
     for (;;) {
         running = 0;
-        int single = -1;
+        int single = -1, dead = 0;
+        bool missing = false;
         for (int i = 0; i < B->capacity; i++) {
-            if (!B->insts[i].live || !running_phase(B->h_states[i].phase)) continue;
-            running++;
-            single = i;
+            const InstRec &R = B->insts[i];
+            if (!R.live) continue;
+            if (running_phase(B->h_states[i].phase)) {
+                running++;
+                single = i;
+                missing = missing || !R.in_tables;
+            } else if (R.in_tables) {
+                dead += B->topos[R.topo].ntile + B->topos[R.topo].ncb;
+            }
         }
         if (running == 0 || (max_rounds > 0 && rounds >= max_rounds)) break;
+        // Finished jobs leave the tables once they hold a quarter of the tile
+        // blocks (a geometric number of rebuilds over a batch's tail).
+        if (B->tables_dirty || missing || 4 * dead > B->nwork_tile) TRY(rebuild_tables<T>(B));
         // Solver steps per round: a fixed 16 for batches; for one job, what
         // its current Newton iteration is expected to need (CG iterations of
         // the previous solve, plus the line-search trial and the init).
