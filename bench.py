@@ -166,6 +166,24 @@ def cpu_baseline(mesh, ind, seconds):
                       f"on the {mesh.m}-tet fingertip ({el:.1f} s); solves/s = ({steps}/{ind.steps}) / time"}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tile_fingertip50k_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per tile-kernel launch from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs (copy-calibrated), or None when they are
+    missing or were taken on a different kernel source."""
+    from paper_2103_16747_amd.profiling import kernel_source_hash
+
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return t["traffic_bytes_per_dispatch"]
+
+
 def roofline(r, word):
     """Roofline of the tile kernel (the dominant one) over the timed region:
     algorithmic flops per launch (the passes the jobs made, times the tets per
@@ -191,7 +209,7 @@ def roofline(r, word):
     byts = tile_bytes(r["layout"], word, r["hv_passes"], r["grad_passes"], t["launches"])
     kname = "k_tile<float>" if word == 4 else "k_tile<double>"
     return ({"bound": "alu", "kernel": kname, "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
-             "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+             "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(),
              "frac_of_non_packed_peak": achieved / FP32_NONPACKED_PEAK_TFLOPS,
              "avg_launch_us": t["avg_us"], "sampled_launches": t["sampled"], "launches": t["launches"],
              "flops_per_launch": per_launch,

@@ -63,27 +63,40 @@ def counters(d):
 
 
 def traffic(fetch_dir, write_dir, copy_bytes, pattern, copy_pattern=r"copy|elementwise|Copy"):
+    """Per-dispatch HBM bytes of the kernels matching `pattern`: the mean of
+    FETCH_SIZE and of WRITE_SIZE over all their dispatches, each scaled by
+    copy_bytes over what the same counter read for the largest copy dispatch
+    (the calibration copy)."""
     fc, wc = counters(fetch_dir), counters(write_dir)
 
     def pick(cs, name, pat):
-        vals = [v for k, m in cs.items() if re.search(pat, k) for v in m.get(name, [])]
-        return vals
+        return [v for k, m in cs.items() if re.search(pat, k) for v in m.get(name, [])]
 
     cf = pick(fc, "FETCH_SIZE", copy_pattern)
     cw = pick(wc, "WRITE_SIZE", copy_pattern)
     if not cf or not cw:
         raise RuntimeError("no copy-kernel counters found")
-    # the largest copy dispatch is the calibration copy
     f_scale = copy_bytes / (max(cf) * 1024.0)
     w_scale = copy_bytes / (max(cw) * 1024.0)
     kf = pick(fc, "FETCH_SIZE", pattern)
     kw = pick(wc, "WRITE_SIZE", pattern)
-    kf_busy = [v for v in kf if v > 0.05 * max(kf)] if kf else []
-    kw_busy = [v for v in kw if v > 0.05 * max(kw)] if kw else []
+    if not kf or not kw:
+        raise RuntimeError("no counters for " + pattern)
+    fetch = statistics.mean(kf) * 1024.0 * f_scale
+    write = statistics.mean(kw) * 1024.0 * w_scale
     return {"copy_fetch_KiB": max(cf), "copy_write_KiB": max(cw), "fetch_scale": f_scale, "write_scale": w_scale,
-            "dispatches": len(kf_busy),
-            "fetch_bytes_per_dispatch": statistics.mean(kf_busy) * 1024.0 * f_scale if kf_busy else None,
-            "write_bytes_per_dispatch": statistics.mean(kw_busy) * 1024.0 * w_scale if kw_busy else None}
+            "dispatches_fetch": len(kf), "dispatches_write": len(kw),
+            "fetch_bytes_per_dispatch": fetch, "write_bytes_per_dispatch": write,
+            "traffic_bytes_per_dispatch": fetch + write}
+
+
+def kernel_source_hash():
+    """SHA-256 of the device source; traffic figures are valid only for the
+    kernels they were taken on."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(here, "csrc", "fem_kernels.h"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
 
 
 def main(argv=None):
@@ -98,6 +111,7 @@ def main(argv=None):
     b.add_argument("write_dir")
     b.add_argument("--copy-bytes", type=float, required=True)
     b.add_argument("--kernel", required=True)
+    b.add_argument("--json", default=None, help="also write the result here, with the kernel source hash")
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         for r in kernel_stats(args.dir, args.kernel):
@@ -109,6 +123,12 @@ def main(argv=None):
         t = traffic(args.fetch_dir, args.write_dir, args.copy_bytes, args.kernel)
         for k, v in t.items():
             print(f"{k}: {v}")
+        if args.json:
+            import json
+            t["kernel"] = args.kernel
+            t["kernel_source_sha256"] = kernel_source_hash()
+            with open(args.json, "w") as f:
+                json.dump(t, f, indent=1)
 
 
 if __name__ == "__main__":
