@@ -146,9 +146,9 @@ void spread_tile(const std::vector<uint32_t> &words, std::vector<int> &placed) {
     for (const std::vector<int> &q : members) placed.insert(placed.end(), q.begin(), q.end());
 }
 
-void build_layout(const double *X, int n, const int32_t *tets, int m, int max_tets, int max_nodes, HostLayout &L) {
-    L.n = n;
-    L.m = m;
+// Tets sorted along a Morton curve of their centroids (10 bits per axis over
+// the mesh's bounding cube); ties keep input order.
+std::vector<int> morton_order(const double *X, int n, const int32_t *tets, int m) {
     double lo[3] = {X[0], X[1], X[2]}, hi[3] = {X[0], X[1], X[2]};
     for (int i = 0; i < n; i++)
         for (int d = 0; d < 3; d++) {
@@ -172,6 +172,36 @@ void build_layout(const double *X, int n, const int32_t *tets, int m, int max_te
         key[e] = {code, e};
     }
     std::sort(key.begin(), key.end());
+    std::vector<int> order(m);
+    for (int k = 0; k < m; k++) order[k] = key[k].second;
+    return order;
+}
+
+// Device node numbering: nodes numbered by first touch along the tets'
+// Morton order, so the nodes a tile touches are mostly consecutive and its
+// gathers of node vectors read whole cache lines. perm[new] = input id.
+std::vector<int> node_order(const double *X, int n, const int32_t *tets, int m) {
+    const std::vector<int> order = morton_order(X, n, tets, m);
+    std::vector<int> perm;
+    std::vector<char> seen(n, 0);
+    perm.reserve(n);
+    for (int e : order)
+        for (int a = 0; a < 4; a++) {
+            const int v = tets[4 * e + a];
+            if (!seen[v]) {
+                seen[v] = 1;
+                perm.push_back(v);
+            }
+        }
+    for (int v = 0; v < n; v++)
+        if (!seen[v]) perm.push_back(v);
+    return perm;
+}
+
+void build_layout(const double *X, int n, const int32_t *tets, int m, int max_tets, int max_nodes, HostLayout &L) {
+    L.n = n;
+    L.m = m;
+    const std::vector<int> order = morton_order(X, n, tets, m);
     std::vector<int> stamp(n, -1), local(n, 0);
     L.tile_tet.assign(1, 0);
     L.tile_ent.assign(1, 0);
@@ -189,7 +219,7 @@ void build_layout(const double *X, int n, const int32_t *tets, int m, int max_te
         words.clear();
         elems.clear();
         for (int k = t0; k < pos; k++) {
-            const int e = key[k].second;
+            const int e = order[k];
             uint32_t w = 0;
             for (int a = 0; a < 4; a++) w |= (uint32_t)local[tets[4 * e + a]] << (8 * a);
             words.push_back(w);
@@ -216,7 +246,7 @@ void build_layout(const double *X, int n, const int32_t *tets, int m, int max_te
         tile_list.clear();
     };
     for (int k = 0; k < m; k++) {
-        const int e = key[k].second;
+        const int e = order[k];
         int fresh = 0;
         for (int a = 0; a < 4; a++) {
             const int v = tets[4 * e + a];
@@ -270,6 +300,7 @@ struct RoundGraph {
 
 struct TopoRec {
     int n = 0, m = 0, ntile = 0, nent = 0, nc = 0, ncb = 0;
+    std::vector<int> perm;     // device node id -> caller's node id (node_order())
     void *arena = nullptr;
     uint8_t *elig = nullptr;   // device, n
     Topo<float> v32{};
@@ -388,10 +419,26 @@ template <> Topo<float> &topo_view<float>(TopoRec &R) { return R.v32; }
 template <> Topo<double> &topo_view<double>(TopoRec &R) { return R.v64; }
 
 template <typename T>
-int add_topology(fem_batch *B, const double *X, int n, const int32_t *tets, int m, const uint8_t *fixed, int *id) {
+int add_topology(fem_batch *B, const double *X_in, int n, const int32_t *tets_in, int m, const uint8_t *fixed_in,
+                 int *id) {
+    // Everything on the device uses the node numbering of node_order().
+    TopoRec R;
+    R.perm = node_order(X_in, n, tets_in, m);
+    std::vector<int> inv(n);
+    for (int i = 0; i < n; i++) inv[R.perm[i]] = i;
+    std::vector<double> Xv(3 * (size_t)n);
+    std::vector<uint8_t> fv(n);
+    std::vector<int32_t> tv(4 * (size_t)m);
+    for (int i = 0; i < n; i++) {
+        for (int d = 0; d < 3; d++) Xv[3 * (size_t)i + d] = X_in[3 * (size_t)R.perm[i] + d];
+        fv[i] = fixed_in[R.perm[i]];
+    }
+    for (size_t q = 0; q < 4 * (size_t)m; q++) tv[q] = inv[tets_in[q]];
+    const double *X = Xv.data();
+    const int32_t *tets = tv.data();
+    const uint8_t *fixed = fv.data();
     HostLayout L;
     build_layout(X, n, tets, m, B->tile_tets, B->tile_nodes, L);
-    TopoRec R;
     R.n = n;
     R.m = m;
     R.ntile = L.ntile;
@@ -743,27 +790,37 @@ int run(fem_batch *B, int max_rounds, int *n_running) {
 // ---------------------------------------------------------------------------
 // Host <-> device node vectors in the batch precision
 // ---------------------------------------------------------------------------
-int upload_real(fem_batch *B, void *dst, const double *src, size_t len) {
-    TRY(stage(B, std::max<size_t>(len * 8, 64)));
+// Node vectors (n x 3) between the caller's numbering and the device's
+// (perm[device id] = caller id), converted to the batch precision.
+int upload_nodes(fem_batch *B, const std::vector<int> &perm, void *dst, const double *src) {
+    const size_t n = perm.size();
+    TRY(stage(B, std::max<size_t>(3 * n * 8, 64)));
     if (B->precision == FEM_PREC_FP32) {
         float *h = (float *)B->h_stage;
-        for (size_t i = 0; i < len; i++) h[i] = (float)src[i];
+        for (size_t i = 0; i < n; i++)
+            for (int d = 0; d < 3; d++) h[3 * i + d] = (float)src[3 * (size_t)perm[i] + d];
     } else {
-        std::memcpy(B->h_stage, src, len * sizeof(double));
+        double *h = (double *)B->h_stage;
+        for (size_t i = 0; i < n; i++)
+            for (int d = 0; d < 3; d++) h[3 * i + d] = src[3 * (size_t)perm[i] + d];
     }
-    HIP_TRY(hipMemcpyAsync(dst, B->h_stage, len * B->elem(), hipMemcpyHostToDevice, B->stream));
+    HIP_TRY(hipMemcpyAsync(dst, B->h_stage, 3 * n * B->elem(), hipMemcpyHostToDevice, B->stream));
     return sync(B);
 }
 
-int download_real(fem_batch *B, double *dst, const void *src, size_t len) {
-    TRY(stage(B, std::max<size_t>(len * 8, 64)));
-    HIP_TRY(hipMemcpyAsync(B->h_stage, src, len * B->elem(), hipMemcpyDeviceToHost, B->stream));
+int download_nodes(fem_batch *B, const std::vector<int> &perm, double *dst, const void *src) {
+    const size_t n = perm.size();
+    TRY(stage(B, std::max<size_t>(3 * n * 8, 64)));
+    HIP_TRY(hipMemcpyAsync(B->h_stage, src, 3 * n * B->elem(), hipMemcpyDeviceToHost, B->stream));
     TRY(sync(B));
     if (B->precision == FEM_PREC_FP32) {
         const float *h = (const float *)B->h_stage;
-        for (size_t i = 0; i < len; i++) dst[i] = (double)h[i];
+        for (size_t i = 0; i < n; i++)
+            for (int d = 0; d < 3; d++) dst[3 * (size_t)perm[i] + d] = (double)h[3 * i + d];
     } else {
-        std::memcpy(dst, B->h_stage, len * sizeof(double));
+        const double *h = (const double *)B->h_stage;
+        for (size_t i = 0; i < n; i++)
+            for (int d = 0; d < 3; d++) dst[3 * (size_t)perm[i] + d] = h[3 * i + d];
     }
     return FEM_OK;
 }
@@ -989,11 +1046,25 @@ int contact_patch_impl(fem_batch *B, int slot, int32_t *ids, double *f, double *
     *n_contact = count;
     if (F_total) std::memcpy(F_total, Ft, sizeof Ft);
     if (capacity < count) return fail(FEM_E_BUFFER, "capacity below the contact count");
-    if (count > 0) {
-        if (ids) HIP_TRY(hipMemcpyAsync(ids, d_ids, count * sizeof(int), hipMemcpyDeviceToHost, B->stream));
-        if (f) HIP_TRY(hipMemcpyAsync(f, d_f, 3 * (size_t)count * sizeof(double), hipMemcpyDeviceToHost, B->stream));
-        if (phi) HIP_TRY(hipMemcpyAsync(phi, d_phi, count * sizeof(double), hipMemcpyDeviceToHost, B->stream));
+    if (count > 0 && (ids || f || phi)) {
+        // Device node ids -> caller ids, listed in ascending caller order.
+        std::vector<int> hid(count);
+        std::vector<double> hf(3 * (size_t)count), hphi(count);
+        HIP_TRY(hipMemcpyAsync(hid.data(), d_ids, count * sizeof(int), hipMemcpyDeviceToHost, B->stream));
+        HIP_TRY(hipMemcpyAsync(hf.data(), d_f, 3 * (size_t)count * sizeof(double), hipMemcpyDeviceToHost, B->stream));
+        HIP_TRY(hipMemcpyAsync(hphi.data(), d_phi, count * sizeof(double), hipMemcpyDeviceToHost, B->stream));
         TRY(sync(B));
+        const std::vector<int> &perm = B->topos[B->insts[slot].topo].perm;
+        std::vector<int> idx(count);
+        for (int k = 0; k < count; k++) idx[k] = k;
+        std::sort(idx.begin(), idx.end(), [&](int a, int b) { return perm[hid[a]] < perm[hid[b]]; });
+        for (int k = 0; k < count; k++) {
+            const int src = idx[k];
+            if (ids) ids[k] = perm[hid[src]];
+            if (f)
+                for (int d = 0; d < 3; d++) f[3 * (size_t)k + d] = hf[3 * (size_t)src + d];
+            if (phi) phi[k] = hphi[src];
+        }
     }
     return FEM_OK;
 }
@@ -1131,7 +1202,7 @@ int fem_get_displacements(const fem_mesh *M, double *u, int64_t capacity) {
     if (!M || !u) return fail(FEM_E_INVALID, "null argument");
     if (capacity < 3LL * M->n) return fail(FEM_E_BUFFER, "capacity below 3 n");
     TRY(set_device(M->batch));
-    return download_real(M->batch, u, inst_ptr(M->batch, 0, V_U), 3 * (size_t)M->n);
+    return download_nodes(M->batch, M->batch->topos[0].perm, u, inst_ptr(M->batch, 0, V_U));
 }
 
 int fem_set_displacements(fem_mesh *M, const double *u, int64_t count) {
@@ -1141,7 +1212,7 @@ int fem_set_displacements(fem_mesh *M, const double *u, int64_t count) {
     for (int64_t i = 0; i < count; i++)
         if (!is_finite(u[i])) return fail(FEM_E_INVALID, "non-finite displacement");
     TRY(set_device(M->batch));
-    return upload_real(M->batch, inst_ptr(M->batch, 0, V_U), u, (size_t)count);
+    return upload_nodes(M->batch, M->batch->topos[0].perm, inst_ptr(M->batch, 0, V_U), u);
 }
 
 int fem_get_contact_patch(const fem_mesh *Mc, int32_t *ids, double *f, double *phi, int32_t capacity,
@@ -1170,8 +1241,10 @@ int fem_get_mesh_info(const fem_mesh *M, int32_t *n_nodes, int32_t *n_tets, int3
     if (eligible) {
         if (capacity < M->n) return fail(FEM_E_BUFFER, "capacity below n");
         TRY(set_device(M->batch));
-        HIP_TRY(hipMemcpyAsync(eligible, tp.elig, M->n, hipMemcpyDeviceToHost, M->batch->stream));
+        std::vector<uint8_t> dev(M->n);
+        HIP_TRY(hipMemcpyAsync(dev.data(), tp.elig, M->n, hipMemcpyDeviceToHost, M->batch->stream));
         TRY(sync(M->batch));
+        for (int i = 0; i < M->n; i++) eligible[tp.perm[i]] = dev[i];
     }
     return FEM_OK;
 }
@@ -1193,7 +1266,7 @@ int fem_eval_gradient(fem_mesh *M, double *g, int64_t capacity, double *energy, 
     TRY(run(B, 2, nullptr));
     if (energy) *energy = B->h_states[0].E;
     if (min_J) *min_J = B->h_states[0].minJ;
-    if (g) return download_real(B, g, inst_ptr(B, 0, V_G), 3 * (size_t)M->n);
+    if (g) return download_nodes(B, B->topos[0].perm, g, inst_ptr(B, 0, V_G));
     return FEM_OK;
 }
 
@@ -1218,14 +1291,14 @@ int fem_eval_hessvec(fem_mesh *M, const fem_solve_params *params, const double *
     TRY(run(B, 2, nullptr));
     // q = H v through the CG kernels with z = v, p_prev = 0, beta = 0.
     std::vector<double> zeros(3 * (size_t)M->n, 0.0);
-    TRY(upload_real(B, inst_ptr(B, 0, V_Z), v, 3 * (size_t)M->n));
-    TRY(upload_real(B, inst_ptr(B, 0, V_P), zeros.data(), 3 * (size_t)M->n));
+    TRY(upload_nodes(B, B->topos[0].perm, inst_ptr(B, 0, V_Z), v));
+    TRY(upload_nodes(B, B->topos[0].perm, inst_ptr(B, 0, V_P), zeros.data()));
     TRY(read_states(B));
     B->h_states[0].beta = 0.0;
     B->h_states[0].phase = PH_EVAL_HV;
     TRY(write_state(B, 0));
     TRY(run(B, 2, nullptr));
-    return download_real(B, q, inst_ptr(B, 0, V_Q), 3 * (size_t)M->n);
+    return download_nodes(B, B->topos[0].perm, q, inst_ptr(B, 0, V_Q));
 }
 
 int fem_set_kernel_timing(fem_mesh *M, int32_t every) {
@@ -1366,7 +1439,7 @@ int fem_batch_get_displacements(fem_batch *B, int32_t job, double *u, int64_t ca
     const int n = B->topos[B->insts[job].topo].n;
     if (capacity < 3LL * n) return fail(FEM_E_BUFFER, "capacity below 3 n");
     TRY(set_device(B));
-    return download_real(B, u, inst_ptr(B, job, V_U), 3 * (size_t)n);
+    return download_nodes(B, B->topos[B->insts[job].topo].perm, u, inst_ptr(B, job, V_U));
 }
 
 int fem_batch_get_contact_patch(fem_batch *B, int32_t job, int32_t *ids, double *f, double *phi, int32_t capacity,
