@@ -1,30 +1,32 @@
 // Device kernels of the indentation solve for gfx950 (CDNA4, wave64).
 //
 // Data layout in HBM.
-//   Topology (shared by every instance of one mesh): tets are ordered along a
-//   Morton curve and cut into tiles of at most kTileTets tets that touch at
-//   most kTileNodes distinct nodes. Per tile: its node list ("entries", global
-//   ids); per tet one 32-bit word of four 8-bit local node indices and the
-//   rest-shape constants D_m^-1 and V (computed once in FP64). Node -> entry
-//   CSR lists for the deterministic gather of tile partial sums.
+//   Topology (shared by every instance of one mesh): nodes numbered by first
+//   touch along the tets' Morton order; tets in Morton order, cut into tiles
+//   of at most kTileTets tets that touch at most kTileNodes distinct nodes.
+//   Per tile: its node list ("entries", global ids). Per tet, in tile order,
+//   one record of D_m^-1, V (computed once in FP64) and four 8-bit local node
+//   slots. Node -> entry CSR lists for the deterministic gather of tile
+//   partial sums.
 //   Instance state: node vectors packed xyz (n x 3), tile partial sums per
 //   entry, contact blocks per contact-eligible node, FP64 solver scalars.
 //
 // Per pass a tile block stages its entries' state vectors in LDS, reads each
-// tet's packed indices and rest constants (shared by every job on the mesh, so
-// a tile's constants are fetched once per XCD and reused from L2 by the other
-// jobs), recomputes F from u, accumulates nodal contributions with FP64 LDS
-// atomics and writes one partial per entry; node kernels gather those
-// partials. Global memory sees no atomics in the solve kernels.
+// tet's record (shared by every job on the mesh, so a tile's records are
+// fetched once per XCD and reused from L2 by the other jobs), recomputes F
+// from u, accumulates nodal contributions with FP64 LDS atomics and writes
+// one partial per entry; node kernels gather those partials. Global memory
+// sees no atomics in the solve kernels.
 //
 // Control: each instance runs a Newton / PCG / line-search state machine on
 // the device. Work kernels write one FP64 partial per block and per reduced
 // quantity; a finalize kernel (one wavefront per instance) sums them in a
 // fixed order and takes the transition, so no kernel needs cross-block
 // synchronisation (an agent-scope fence per block costs an L2 write-back on
-// this part). A round (Hv, update, finalize) x C, dot, element, finalize,
-// init, finalize serves every instance whatever phase it is in; blocks of
-// instances in another phase return at once.
+// this part). A solver step is a tile pass, a node pass and a finalize over
+// every running instance; each instance advances by one phase per step
+// (a CG iteration, a line-search trial, a Newton init), whatever phase the
+// others are in.
 #pragma once
 
 #include <hip/hip_runtime.h>
