@@ -90,13 +90,20 @@ def traffic(fetch_dir, write_dir, copy_bytes, pattern, copy_pattern=r"copy|eleme
             "traffic_bytes_per_dispatch": fetch + write}
 
 
-def kernel_source_hash():
-    """SHA-256 of the device source; traffic figures are valid only for the
-    kernels they were taken on."""
+def kernel_source_hash(text=None):
+    """SHA-256 of the device source with comments and blank lines removed;
+    traffic figures are valid only for the kernels they were taken on."""
     import hashlib
-    here = os.path.dirname(os.path.abspath(__file__))
-    with open(os.path.join(here, "csrc", "fem_kernels.h"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    if text is None:
+        here = os.path.dirname(os.path.abspath(__file__))
+        with open(os.path.join(here, "csrc", "fem_kernels.h")) as f:
+            text = f.read()
+    code = []
+    for line in text.splitlines():
+        line = line.split("//", 1)[0].rstrip()
+        if line.strip():
+            code.append(line)
+    return hashlib.sha256("\n".join(code).encode()).hexdigest()
 
 
 def main(argv=None):
