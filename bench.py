@@ -333,8 +333,8 @@ def main():
     ap.add_argument("--config", choices=("batched", "uneven", "serving"), default="batched",
                     help="batched: 256 jobs on the 50k fingertip (default); uneven: 64 jobs at 5k-120k tets with "
                          "autotuned shapes; serving: Poisson request streams through the serving loop")
-    ap.add_argument("--rates", default="10,50,200", help="serving: arrival rates (req/s)")
-    ap.add_argument("--requests", type=int, default=48, help="serving: requests per rate")
+    ap.add_argument("--rates", default="10,50,200,500", help="serving: arrival rates (req/s)")
+    ap.add_argument("--requests", type=int, default=160, help="serving: requests per rate")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="before the solves, one device copy of this many MiB (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
