@@ -44,7 +44,8 @@ class Problem(C.Structure):
     _fields_ = [("n", C.c_int), ("m", C.c_int), ("X", C.POINTER(C.c_double)), ("T", C.POINTER(C.c_int)),
                 ("fixed", C.POINTER(C.c_ubyte)), ("eligible", C.POINTER(C.c_ubyte)),
                 ("B", C.POINTER(C.c_double)), ("V", C.POINTER(C.c_double)),
-                ("mu", C.c_double), ("lam", C.c_double), ("ind", Indenter)]
+                ("mu", C.c_double), ("lam", C.c_double), ("ind", Indenter), ("dt", C.c_double),
+                ("mass", C.POINTER(C.c_double)), ("utilde", C.POINTER(C.c_double))]
 
 
 class Params(C.Structure):
@@ -82,6 +83,8 @@ def lib():
         L.orc_sdf.restype = C.c_double
         L.orc_precompute.argtypes = [C.c_int, dp, C.c_int, ip, dp, dp]
         L.orc_surface_nodes.argtypes = [C.c_int, C.c_int, ip, up]
+        L.orc_lumped_mass.argtypes = [C.c_int, C.c_int, ip, dp, C.c_double, dp]
+        L.orc_lumped_mass.restype = None
         L.orc_deformation_gradient.argtypes = [C.POINTER(Problem), dp, C.c_int, dp]
         L.orc_energy.argtypes = [C.POINTER(Problem), dp, dp]
         L.orc_energy.restype = C.c_double
@@ -167,6 +170,14 @@ def surface_nodes(n, tets):
     return s, nb
 
 
+def lumped_mass(n, tets, V, rho):
+    m = np.zeros(n)
+    T = np.ascontiguousarray(tets, dtype=np.int32)
+    lib().orc_lumped_mass(int(n), int(T.shape[0]), T.ctypes.data_as(C.POINTER(C.c_int)), _dp(_f64(V)),
+                          float(rho), _dp(m))
+    return m
+
+
 def default_params(**kw) -> Params:
     """Oracle solve settings: Newton to 1e-8 relative residual, CG forcing
     between 1e-8 and 0.1, block Jacobi, Armijo c1 = 1e-4, 40 halvings."""
@@ -201,6 +212,42 @@ class Solver:
         self.p.V = _dp(self.V)
         self.set_material(E, nu)
         self.p.ind = make_indenter(SPHERE, [0.0], c=(1e9, 1e9, 1e9), k=0.0)
+        self.dt = 0.0
+        self.mass = None
+        self.utilde = np.zeros((self.n, 3))
+
+    def set_dynamics(self, dt, rho):
+        """Backward-Euler time stepping with lumped masses (dt = 0: quasi-static)."""
+        self.dt = float(dt)
+        self.mass = lumped_mass(self.n, self.T, self.V, rho)
+        self.p.dt = self.dt
+        self.p.mass = _dp(self.mass) if dt > 0 else None
+        self.p.utilde = _dp(self.utilde) if dt > 0 else None
+
+    def dyn_step(self, u, v, params=None):
+        """One backward-Euler step from (u, v) (not modified) at the current
+        indenter pose: ut = u + dt v, Newton on the incremental potential from
+        u, then v_new = (u_new - u) / dt. Returns (u_new, v_new, info)."""
+        if not self.dt > 0:
+            raise ValueError("set_dynamics(dt > 0, rho) first")
+        u = self._u(u)
+        self.utilde[...] = u + self.dt * self._u(v)
+        un, info = self.step(u, params)
+        return un, (un - u) / self.dt, info
+
+    def solve_dynamic(self, ind, dt, rho, params=None, steps=None, u0=None, v0=None):
+        """Time steps of a workload Indentation with the indenter at
+        ind.center(k) at step k; returns the list of (u, v, info)."""
+        self.set_dynamics(dt, rho)
+        u = np.zeros((self.n, 3)) if u0 is None else self._u(u0).copy()
+        v = np.zeros((self.n, 3)) if v0 is None else self._u(v0).copy()
+        out = []
+        S = ind.steps if steps is None else steps
+        for k in range(1, S + 1):
+            self.set_indenter(ind.kind, ind.shape, ind.R, ind.center(k), ind.k_penalty)
+            u, v, info = self.dyn_step(u, v, params)
+            out.append((u, v, info))
+        return out
 
     def set_material(self, E, nu):
         self.mu, self.lam = lame(E, nu)

@@ -331,6 +331,15 @@ static void shape_grads(const double *B, double b[4][3]) {
     for (int j = 0; j < 3; j++) b[0][j] = -(b[1][j] + b[2][j] + b[3][j]);
 }
 
+/* Backward Euler's inertial term is present (dt > 0 with masses and predictor). */
+static int dynamic(const orc_problem *p) { return p->dt > 0.0 && p->mass && p->utilde; }
+
+void orc_lumped_mass(int n, int m, const int *T, const double *V, double rho, double *mass) {
+    memset(mass, 0, sizeof(double) * (size_t)n);
+    for (int e = 0; e < m; e++)
+        for (int a = 0; a < 4; a++) mass[T[4 * e + a]] += rho * V[e] / 4.0;
+}
+
 static double contact_phi(const orc_problem *p, const double *u, int i, double nrm[3]) {
     double x[3] = {p->X[3 * i] + u[3 * i], p->X[3 * i + 1] + u[3 * i + 1], p->X[3 * i + 2] + u[3 * i + 2]};
     return orc_sdf(&p->ind, x, nrm);
@@ -354,7 +363,10 @@ static double energy_terms(const orc_problem *p, const double *u, double *mag, d
         double lnJ = log(J);
         double t1 = 0.5 * p->mu * (I1 - 3.0), t2 = -p->mu * lnJ, t3 = 0.5 * p->lam * lnJ * lnJ;
         E += p->V[e] * (t1 + t2 + t3);
-        M += p->V[e] * (fabs(t1) + fabs(t2) + fabs(t3));
+        /* Rounding scale of the three terms: I1 - 3 and ln J are formed by
+         * cancellation, so their error follows the operands (I1 + 3, and 1
+         * for ln J near J = 1), not the terms' own size. */
+        M += p->V[e] * (0.5 * p->mu * (I1 + 3.0) + (p->mu + p->lam * fabs(lnJ)) * (1.0 + fabs(lnJ)));
     }
     for (int i = 0; i < p->n; i++) {
         if (!p->eligible[i]) continue;
@@ -362,6 +374,19 @@ static double energy_terms(const orc_problem *p, const double *u, double *mag, d
         double phi = contact_phi(p, u, i, nrm);
         if (phi < 0.0) {
             double c = 0.5 * p->ind.k * phi * phi;
+            E += c;
+            M += c;
+        }
+    }
+    if (dynamic(p)) {
+        for (int i = 0; i < p->n; i++) {
+            if (p->fixed[i]) continue;
+            double d2 = 0.0;
+            for (int d = 0; d < 3; d++) {
+                double w = u[3 * i + d] - p->utilde[3 * i + d];
+                d2 += w * w;
+            }
+            double c = 0.5 * p->mass[i] / (p->dt * p->dt) * d2;
             E += c;
             M += c;
         }
@@ -398,6 +423,11 @@ void orc_gradient(const orc_problem *p, const double *u, double *g) {
         if (phi < 0.0)
             for (int d = 0; d < 3; d++) g[3 * i + d] += p->ind.k * phi * nrm[d];
     }
+    if (dynamic(p))
+        for (int i = 0; i < p->n; i++) {
+            if (p->fixed[i]) continue;
+            for (int d = 0; d < 3; d++) g[3 * i + d] += p->mass[i] / (p->dt * p->dt) * (u[3 * i + d] - p->utilde[3 * i + d]);
+        }
 }
 
 /* Element stiffness K_e[(a,i),(c,k)] = V sum_{j,l} b_a,j A[(i,j),(k,l)] b_c,l. */
@@ -521,6 +551,12 @@ static void bsr_assemble(const orc_problem *p, const double *u, bsr *H, int cont
                 for (int b = 0; b < 3; b++) blk[3 * a + b] += p->ind.k * (nrm[a] * nrm[b] + phi * Hs[3 * a + b]);
         }
     }
+    if (dynamic(p))
+        for (int i = 0; i < p->n; i++) {
+            if (p->fixed[i]) continue;
+            double *blk = bsr_block(H, i, i);
+            for (int a = 0; a < 3; a++) blk[4 * a] += p->mass[i] / (p->dt * p->dt);
+        }
 }
 
 static void bsr_mul(const bsr *H, const double *v, double *q) {

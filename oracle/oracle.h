@@ -15,6 +15,12 @@
  *   Pi(u) = sum_e V_e Psi(F_e(u)) + sum_{i eligible} k/2 min(0, phi(X_i+u_i))^2
  * with the displacement of fixed nodes held at its current value.
  *
+ * Implicit dynamics (the paper's simulator integrates the skin in time,
+ * Sec. III-A): with a time step dt > 0 and lumped nodal masses m_i, a step
+ * of backward Euler minimises the incremental potential
+ *   Phi(u) = Pi(u) + sum_{i free} m_i / (2 dt^2) |u_i - ut_i|^2,
+ * ut = u^n + dt v^n, and then v^{n+1} = (u^{n+1} - u^n) / dt.
+ *
  * All arrays are row-major, caller-owned, double precision unless stated.
  */
 #ifndef FEM_ORACLE_H
@@ -53,6 +59,9 @@ typedef struct {
     const double *V;              /* m: rest volumes */
     double mu, lam;               /* Lame parameters */
     orc_indenter ind;
+    double dt;                    /* time step (s); 0 = quasi-static */
+    const double *mass;           /* n lumped nodal masses (kg), or NULL */
+    const double *utilde;         /* n x 3 inertial predictor u^n + dt v^n, or NULL */
 } orc_problem;
 
 typedef struct {
@@ -94,6 +103,9 @@ double orc_sdf(const orc_indenter *ind, const double x[3], double grad[3]);
 /* Mesh precompute: B and V per tet. Returns 0, or -(1+e) for the first tet e
  * with V <= 0. */
 int orc_precompute(int n, const double *X, int m, const int *T, double *B, double *V);
+
+/* Lumped nodal masses: each tet gives rho V_e / 4 to each of its nodes. */
+void orc_lumped_mass(int n, int m, const int *T, const double *V, double rho, double *mass);
 
 /* Marks nodes on boundary faces (faces of exactly one tet); returns the number
  * of boundary faces. */
