@@ -318,6 +318,81 @@ def bench_serving(args):
     return out
 
 
+def bench_dynamic(args):
+    """The batched workload as implicit time steps: 256 fingertip jobs, each
+    step a backward-Euler step of dt = 1e-4 s (the paper's time step) with
+    lumped masses at 1100 kg/m^3, the indenter moving depth/100 per step.
+    The first jobs' first steps are checked against stored FP64 oracle
+    results (tests/golden/fingertip50k_dynamic_oracle.npz)."""
+    from paper_2103_16747_amd import fem, workload as W
+
+    mesh = W.fingertip_mesh(50000)
+    dt, rho = 1e-4, 1100.0
+    inds = []
+    for i in range(args.jobs):
+        ind = W.seat_on_mesh(W.random_indentation(3000 + i), mesh)
+        ind.dt, ind.density = dt, rho
+        inds.append(ind)
+    batch = fem.FemBatch(len(inds), "fp32")
+    mid = batch.add_mesh(mesh.X, mesh.tets, mesh.fixed)
+    info = batch.mesh_info(mid)
+    jobs = [batch.add_job(mid, ind) for ind in inds]
+    batch.run()
+    progress("warm-up dynamic batch done")
+    walls, tu, failed, lat = [], 0, 0, []
+    for _ in range(args.steps):
+        for j, ind in zip(jobs, inds):
+            batch.restart_job(j, ind)
+        t0 = time.perf_counter()
+        done_at, running = {}, len(jobs)
+        while running:
+            running = batch.run(max_rounds=8)
+            now = time.perf_counter() - t0
+            for j in jobs:
+                if j not in done_at and batch.job_info(j)["done"]:
+                    done_at[j] = now
+        walls.append(time.perf_counter() - t0)
+        progress(f"dynamic batch: {len(jobs)} jobs in {walls[-1]:.2f} s")
+        infos = [batch.job_info(j) for j in jobs]
+        tu += sum(i["tet_updates"] for i in infos)
+        failed += sum(i["steps_failed"] for i in infos)
+        lat += list(done_at.values())
+    stats = [batch.job_info(j) for j in jobs]
+    batch.close()
+    # the first jobs' first time steps against stored FP64 oracle results
+    errs = {}
+    gold_path = os.path.join(ROOT, "tests", "golden", "fingertip50k_dynamic_oracle.npz")
+    if os.path.exists(gold_path):
+        gold = np.load(gold_path)
+        k_check = int(gold["steps"])
+        for seed in (int(x) for x in gold["seeds"]):
+            ind = inds[seed - 3000]
+            short = W.Indentation(ind.kind, ind.shape, ind.R, ind.c0, ind.direction, ind.depth * k_check / ind.steps,
+                                  k_check, ind.k_penalty, dt=dt, density=rho)
+            b1 = fem.FemBatch(1, "fp32")
+            j1 = b1.add_job(b1.add_mesh(mesh.X, mesh.tets, mesh.fixed), short)
+            b1.run()
+            u_ref, v_ref = gold[f"u_{seed}"], gold[f"v_{seed}"]
+            errs[str(seed)] = {"steps": k_check,
+                               "u": float(np.abs(b1.displacements(j1) - u_ref).max() / np.abs(u_ref).max()),
+                               "v": float(np.abs(b1.velocities(j1) - v_ref).max() / np.abs(v_ref).max())}
+            b1.close()
+    wall = sum(walls)
+    lat_ms = np.array(lat) * 1e3
+    K, J = args.steps, len(jobs)
+    return {"metric": METRIC, "value": K * J / wall, "unit": "solves/s", "n_gpus": 1, "steps": K, "warmup": 1,
+            "ms_per_step": wall / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"implicit dynamics: {J} jobs on the synthetic 50k-tet fingertip, seeded indenters, "
+                                   "100 backward-Euler steps of 1e-4 s each (lumped mass, 1100 kg/m^3)",
+                       "mesh_tets": mesh.m, "tiles": info["n_tiles"]},
+            "tet_updates_per_s": tu / wall, "failed_load_steps": failed,
+            "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+            "cg_iters_per_job": float(np.mean([s["cg_iters"] for s in stats])),
+            "newton_iters_per_job": float(np.mean([s["newton_iters"] for s in stats])),
+            "e_inf_vs_fp64_oracle_first_steps": errs}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -330,9 +405,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--timing-every", type=int, default=8)
-    ap.add_argument("--config", choices=("batched", "uneven", "serving"), default="batched",
+    ap.add_argument("--config", choices=("batched", "uneven", "serving", "dynamic"), default="batched",
                     help="batched: 256 jobs on the 50k fingertip (default); uneven: 64 jobs at 5k-120k tets with "
-                         "autotuned shapes; serving: Poisson request streams through the serving loop")
+                         "autotuned shapes; serving: Poisson request streams through the serving loop; dynamic: "
+                         "the batched workload as implicit time steps of 1e-4 s")
     ap.add_argument("--rates", default="10,50,200,500", help="serving: arrival rates (req/s)")
     ap.add_argument("--requests", type=int, default=160, help="serving: requests per rate")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -360,6 +436,9 @@ def main():
         return
     if args.config == "serving":
         print(json.dumps(bench_serving(args)), flush=True)
+        return
+    if args.config == "dynamic":
+        print(json.dumps(bench_dynamic(args)), flush=True)
         return
     mesh = W.fingertip_mesh(50000)
     inds = [W.seat_on_mesh(W.random_indentation(3000 + i), mesh) for i in range(args.jobs)]

@@ -160,8 +160,26 @@ int fem_step(fem_mesh *mesh, const fem_solve_params *params, fem_step_info *info
 int fem_get_displacements(const fem_mesh *mesh, double *u, int64_t capacity);
 
 /* Replaces the nodal displacements (warm start, resume, or prescribed
- * displacements on fixed nodes); count must equal 3 n. Errors: FEM_E_INVALID. */
+ * displacements on fixed nodes); count must equal 3 n. Velocities are kept.
+ * Errors: FEM_E_INVALID. */
 int fem_set_displacements(fem_mesh *mesh, const double *u, int64_t count);
+
+/* Implicit time stepping (paper Sec. III-A: the simulator integrates the
+ * skin in time). With dt > 0 every fem_step is one backward-Euler step of
+ * length dt: Newton on the incremental potential
+ *   Pi(u) + sum_{i free} m_i / (2 dt^2) |u_i - ut_i|^2,  ut = u^n + dt v^n,
+ * with lumped masses m_i = density * sum_{tets at i} V_e / 4 (density from
+ * fem_set_material), then v^{n+1} = (u^{n+1} - u^n) / dt. dt = 0 returns to
+ * quasi-static load steps. Velocities start at zero.
+ * Errors: FEM_E_INVALID (dt < 0 or non-finite), FEM_E_STATE (dt > 0 without
+ * a material of positive density). */
+int fem_set_dynamics(fem_mesh *mesh, double dt);
+
+/* Nodal velocities after the last step (n x 3, capacity >= 3 n; zero for
+ * quasi-static steps), and their replacement (count = 3 n, e.g. an initial
+ * velocity field). Errors: FEM_E_INVALID, FEM_E_BUFFER. */
+int fem_get_velocities(const fem_mesh *mesh, double *v, int64_t capacity);
+int fem_set_velocities(fem_mesh *mesh, const double *v, int64_t count);
 
 /* Contact patch at the current state (paper Sec. III-A: nodal contact forces,
  * summed into resultant forces): ids of the eligible nodes with phi < 0 in
@@ -227,6 +245,9 @@ typedef struct {
     double depth;        /* total indentation depth (m) */
     int32_t steps;       /* quasi-static load steps */
     double k_penalty;    /* N/m per node */
+    double dt;           /* > 0: each step is a backward-Euler time step of
+                            this length (see fem_set_dynamics); 0: quasi-static */
+    double density;      /* kg/m^3, for the lumped masses when dt > 0 */
 } fem_indentation;
 
 typedef struct {
@@ -276,6 +297,9 @@ int fem_batch_run(fem_batch *batch, const fem_solve_params *params, int32_t max_
 
 /* Progress and counters of a job (as of the end of the last run). */
 int fem_batch_job_info(const fem_batch *batch, int32_t job_id, fem_job_info *info);
+
+/* A job's velocities (n x 3, zero for quasi-static jobs), as fem_get_velocities. */
+int fem_batch_get_velocities(fem_batch *batch, int32_t job_id, double *v, int64_t capacity);
 
 /* A job's displacements (n x 3) and contact patch, as the single-mesh calls. */
 int fem_batch_get_displacements(fem_batch *batch, int32_t job_id, double *u, int64_t capacity);

@@ -54,7 +54,8 @@ enum Phase : int {
 enum : int { ST_OK = 0, ST_FLOOR = 1, ST_NOT_CONVERGED = -6, ST_INVERSION = -7 };
 
 // Partial-sum streams of an instance (each red_stride doubles).
-enum : int { RS_PQ = 0, RS_RZ, RS_RR, RS_GD, RS_E, RS_MAG, RS_MINJ, RS_GG, RS_IRZ, RS_COUNT };
+// RS_EN: inertial energy of implicit time steps (node blocks).
+enum : int { RS_PQ = 0, RS_RZ, RS_RR, RS_GD, RS_E, RS_MAG, RS_MINJ, RS_GG, RS_IRZ, RS_EN, RS_COUNT };
 
 struct Indenter {
     int kind;            // 0 sphere, 1 cylinder, 2 box, 3 ring
@@ -77,6 +78,7 @@ struct InstState {
     double rz, rr, pq, alpha, beta, tol2;
     double E, emag, minJ, gg, r0, gd, alpha_ls;
     double mu, lam, depth;
+    double dt, rho;                           // implicit time step (0: quasi-static), density
     double gbest;                             // smallest |g_free| of the load step so far
     int stall, steps_floor;                   // accepted iterations without halving gbest
     double c0[3], dir[3];
@@ -120,6 +122,8 @@ struct Topo {
     const int *cnodes;                  // nc
     const int *cidx;                    // n: contact slot or -1
     const double *X;                    // n x 3
+    const T *nvol;                      // n: lumped volume share sum_e V_e / 4
+    const uint8_t *owner;               // nent: 1 on each node's first entry
 };
 
 template <typename T>
@@ -131,6 +135,7 @@ struct InstBufs {
     T *pq;                              // nent x 3: Hv partials
     T *cp;                              // nc x 9: contact gradient (3) + block (6)
     T *qout;                            // n x 3 (diagnostics)
+    T *v, *ut;                          // n x 3: velocity of the last completed step, inertial predictor
     double *red;                        // RS_COUNT x red_stride
     InstState *s;
 };
@@ -711,19 +716,27 @@ __device__ __forceinline__ void tile_hessvec(const Topo<T> &tp, const InstBufs<T
         const int t = blk;
         const int e0 = tp.tile_ent[t], ne = tp.tile_ent[t + 1] - e0;
         const int k0 = tp.tile_tet[t], nk = tp.tile_tet[t + 1] - k0;
+        // Implicit steps add (m_i / dt^2) |p_i|^2 to p.q, taken once per node
+        // (on its first entry).
+        const double cm = s->dt > 0.0 ? s->rho / (s->dt * s->dt) : 0.0;
+        double pq = 0.0;
         for (int l = threadIdx.x; l < ne; l += kBlock) {
             const int gid = tp.ent_node[e0 + l];
+            T pv[3];
 #pragma unroll
             for (int d = 0; d < 3; d++) {
                 su[kSw * l + d] = B.u[3 * gid + d];
-                sp[kSw * l + d] = fma_t(beta, B.p[3 * gid + d], B.z[3 * gid + d]);
+                pv[d] = fma_t(beta, B.p[3 * gid + d], B.z[3 * gid + d]);
+                sp[kSw * l + d] = pv[d];
                 sa[3 * l + d] = 0.0;
             }
             su[kSw * l + 3] = (T)0;
             sp[kSw * l + 3] = (T)0;
+            if (cm > 0.0 && tp.owner[e0 + l])
+                pq += cm * (double)tp.nvol[gid] *
+                      ((double)pv[0] * (double)pv[0] + (double)pv[1] * (double)pv[1] + (double)pv[2] * (double)pv[2]);
         }
         __syncthreads();
-        double pq = 0.0;
         for (int k = threadIdx.x; k < nk; k += kBlock) {
             int l[4];
             const ElemGeo<T> geo = load_tet(tp, k0 + k, l);
@@ -824,12 +837,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T
 // an accepted step u += alpha dx, gathers g and the node block from the tile
 // and contact partials, forms the block (or scalar) Jacobi inverse, r = -g and
 // z = M^-1 r on free nodes; partial sums of |g_free|^2 and r.z.
+// Implicit steps (dt > 0): at the start of a time step (step_start) the
+// velocity of the step just completed, v += (u - ut) / dt, and the new
+// predictor ut = u + dt v are formed first; every init then adds the inertial
+// gradient (m/dt^2)(u - ut), (m/dt^2) I to the node block, and the inertial
+// energy (m/2dt^2)|u - ut|^2 to its own partial sum.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void node_init(const Topo<T> &tp, const InstBufs<T> &B, const InstState *s, int blk,
-                                          bool apply, int block_jacobi) {
+                                          bool apply, bool step_start, int block_jacobi) {
     const T alpha = (T)s->alpha_ls;
-    double acc[2] = {0.0, 0.0};
+    const bool dyn = s->dt > 0.0;
+    double acc[3] = {0.0, 0.0, 0.0};   // |g_free|^2, r.z, inertial energy
     double unused = 0.0;
     const int i = blk * kBlock + threadIdx.x;
     if (i < tp.n) {
@@ -848,6 +867,29 @@ __device__ __forceinline__ void node_init(const Topo<T> &tp, const InstBufs<T> &
         if (j >= 0)
 #pragma unroll
             for (int c = 0; c < 9; c++) gsum[c] += B.cp[9 * j + c];
+        if (dyn && !tp.fixed[i]) {
+            const T h = (T)s->dt;
+            const T cm = (T)(s->rho / (s->dt * s->dt)) * tp.nvol[i];
+            double en = 0.0;
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                const T ui = B.u[3 * i + d];
+                T ti = B.ut[3 * i + d];
+                if (step_start) {
+                    const T vv = B.v[3 * i + d] + (ui - ti) / h;
+                    B.v[3 * i + d] = vv;
+                    ti = fma_t(h, vv, ui);
+                    B.ut[3 * i + d] = ti;
+                }
+                const T w = ui - ti;
+                gsum[d] = fma_t(cm, w, gsum[d]);
+                en += (double)w * (double)w;
+            }
+            acc[2] = 0.5 * (double)cm * en;
+            gsum[3] += cm;
+            gsum[4] += cm;
+            gsum[5] += cm;
+        }
 #pragma unroll
         for (int d = 0; d < 3; d++) B.g[3 * i + d] = gsum[d];
         T M[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
@@ -891,9 +933,9 @@ __device__ __forceinline__ void node_init(const Topo<T> &tp, const InstBufs<T> &
             B.dx[3 * i + d] = (T)0;
         }
     }
-    block_reduce<2, false>(acc, unused);
-    const int streams[2] = {RS_GG, RS_IRZ};
-    store_partials<2>(B.red, B.red_stride, streams, blk, acc);
+    block_reduce<3, false>(acc, unused);
+    const int streams[3] = {RS_GG, RS_IRZ, RS_EN};
+    store_partials<3>(B.red, B.red_stride, streams, blk, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -934,6 +976,11 @@ __device__ __forceinline__ void node_update(const Topo<T> &tp, const InstBufs<T>
                 qv[1] += H[3] * pv[0] + H[1] * pv[1] + H[5] * pv[2];
                 qv[2] += H[4] * pv[0] + H[5] * pv[1] + H[2] * pv[2];
             }
+            if (s->dt > 0.0 && !tp.fixed[i]) {
+                const T cm = (T)(s->rho / (s->dt * s->dt)) * tp.nvol[i];
+#pragma unroll
+                for (int d = 0; d < 3; d++) qv[d] = fma_t(cm, pv[d], qv[d]);
+            }
             if (eval) {
 #pragma unroll
                 for (int d = 0; d < 3; d++) B.qout[3 * i + d] = qv[d];
@@ -966,24 +1013,39 @@ __device__ __forceinline__ void node_update(const Topo<T> &tp, const InstBufs<T>
     store_partials<2>(B.red, B.red_stride, streams, blk, acc);
 }
 
-// Partial sums of g . dx of one node block (first line-search trial).
+// Line-search trial, node part: partial sums of g . dx (first trial of a
+// line search) and, for implicit steps, of the inertial energy
+// (m/2dt^2)|u + alpha dx - ut|^2 at the trial point.
 template <typename T>
-__device__ __forceinline__ void node_dot(const Topo<T> &tp, const InstBufs<T> &B, int blk) {
-    double acc[1] = {0.0};
+__device__ __forceinline__ void node_trial(const Topo<T> &tp, const InstBufs<T> &B, const InstState *s, int blk) {
+    double acc[2] = {0.0, 0.0};
     double unused = 0.0;
     const int i = blk * kBlock + threadIdx.x;
-    if (i < tp.n)
+    if (i < tp.n) {
+        if (s->need_gd)
 #pragma unroll
-        for (int d = 0; d < 3; d++) acc[0] += (double)B.g[3 * i + d] * (double)B.dx[3 * i + d];
-    block_reduce<1, false>(acc, unused);
-    const int streams[1] = {RS_GD};
-    store_partials<1>(B.red, B.red_stride, streams, blk, acc);
+            for (int d = 0; d < 3; d++) acc[0] += (double)B.g[3 * i + d] * (double)B.dx[3 * i + d];
+        if (s->dt > 0.0 && !tp.fixed[i]) {
+            const T alpha = (T)s->alpha_ls;
+            double en = 0.0;
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                const T w = fma_t(alpha, B.dx[3 * i + d], B.u[3 * i + d]) - B.ut[3 * i + d];
+                en += (double)w * (double)w;
+            }
+            acc[1] = 0.5 * (s->rho / (s->dt * s->dt)) * (double)tp.nvol[i] * en;
+        }
+    }
+    block_reduce<2, false>(acc, unused);
+    const int streams[2] = {RS_GD, RS_EN};
+    store_partials<2>(B.red, B.red_stride, streams, blk, acc);
 }
 
 // ---------------------------------------------------------------------------
 // Node pass: one block per (instance, 256 nodes), after the tile pass of the
 // same step. CG -> update; GRAD, EVAL_GRAD, INIT -> Newton init; TRIAL ->
-// g . dx on the first trial of a line search; other phases return.
+// g . dx on the first trial of a line search and the inertial energy of
+// implicit steps; other phases return.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_node(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
@@ -998,9 +1060,9 @@ __global__ __launch_bounds__(kBlock) void k_node(const Topo<T> *topos, const Ins
     if (phase == PH_CG || phase == PH_EVAL_HV)
         node_update(tp, B, s, w.y, phase == PH_EVAL_HV);
     else if (phase == PH_GRAD || phase == PH_EVAL_GRAD || phase == PH_INIT)
-        node_init(tp, B, s, w.y, phase == PH_INIT && s->apply != 0, P->block_jacobi);
-    else if (phase == PH_TRIAL && s->need_gd)
-        node_dot(tp, B, w.y);
+        node_init(tp, B, s, w.y, phase == PH_INIT && s->apply != 0, phase == PH_GRAD, P->block_jacobi);
+    else if (phase == PH_TRIAL && (s->need_gd || s->dt > 0.0))
+        node_trial(tp, B, s, w.y);
 }
 
 // Newton test on |g_free| against the load step's first residual, then CG
@@ -1104,8 +1166,10 @@ __global__ __launch_bounds__(64) void k_finalize(const Topo<T> *topos, const Ins
         s->rr = rr;
         if (rr <= s->tol2 || s->cg_it >= P->max_cg) start_line_search(s);
     } else if (phase == PH_GRAD || phase == PH_EVAL_GRAD || phase == PH_TRIAL) {
-        const double E = wave_sum_partials(B.red + RS_E * S, nt);
-        const double mag = wave_sum_partials(B.red + RS_MAG * S, nt);
+        // tile partials, plus the nodes' inertial energy of implicit steps
+        const double en = s->dt > 0.0 ? wave_sum_partials(B.red + RS_EN * S, nn) : 0.0;
+        const double E = wave_sum_partials(B.red + RS_E * S, nt) + en;
+        const double mag = wave_sum_partials(B.red + RS_MAG * S, nt) + en;
         const double mn = wave_min_partials(B.red + RS_MINJ * S, nt);
         double gg = 0.0, rz = 0.0, gd = 0.0;
         if (phase != PH_TRIAL) {

@@ -353,6 +353,7 @@ struct fem_mesh {
     int n = 0, m = 0;
     bool have_material = false, have_indenter = false;
     double E = 0, nu = 0, density = 0;
+    double dt = 0;                  // implicit time step; 0 = quasi-static
     Indenter ind{};
 };
 
@@ -449,6 +450,26 @@ int add_topology(fem_batch *B, const double *X_in, int n, const int32_t *tets_in
     const size_t o_neo = A.take<int>(n + 1), o_ne = A.take<int>(L.nent);
     const size_t o_fixed = A.take<uint8_t>(n), o_cn = A.take<int>(n), o_cidx = A.take<int>(n);
     const size_t o_X = A.take<double>(3 * (size_t)n), o_elig = A.take<uint8_t>(n);
+    const size_t o_nvol = A.take<T>(n), o_owner = A.take<uint8_t>(L.nent);
+    // Lumped volume share per node (sum over its tets of V_e / 4, FP64 on the
+    // host) and each node's first tile entry.
+    std::vector<T> nvol(n, (T)0);
+    {
+        std::vector<double> acc(n, 0.0);
+        for (int e = 0; e < m; e++) {
+            const int32_t *t = tets + 4 * (size_t)e;
+            double D[9];
+            for (int a = 0; a < 3; a++)
+                for (int i = 0; i < 3; i++) D[3 * i + a] = X[3 * (size_t)t[a + 1] + i] - X[3 * (size_t)t[0] + i];
+            const double det = D[0] * (D[4] * D[8] - D[5] * D[7]) - D[1] * (D[3] * D[8] - D[5] * D[6]) +
+                               D[2] * (D[3] * D[7] - D[4] * D[6]);
+            for (int a = 0; a < 4; a++) acc[t[a]] += std::fabs(det) / 24.0;
+        }
+        for (int i = 0; i < n; i++) nvol[i] = (T)acc[i];
+    }
+    std::vector<uint8_t> owner(std::max(L.nent, 1), 0);
+    for (int i = 0; i < n; i++)
+        if (L.node_ent_off[i + 1] > L.node_ent_off[i]) owner[L.node_ent[L.node_ent_off[i]]] = 1;
     HIP_TRY(hipMalloc(&R.arena, A.off));
     char *base = (char *)R.arena;
     auto up = [&](size_t off, const void *src, size_t bytes) -> int {
@@ -463,6 +484,8 @@ int add_topology(fem_batch *B, const double *X_in, int n, const int32_t *tets_in
     if (!rc) rc = up(o_ne, L.node_ent.data(), L.node_ent.size() * sizeof(int));
     if (!rc) rc = up(o_fixed, fixed, n);
     if (!rc) rc = up(o_X, X, 3 * (size_t)n * sizeof(double));
+    if (!rc) rc = up(o_nvol, nvol.data(), (size_t)n * sizeof(T));
+    if (!rc) rc = up(o_owner, owner.data(), (size_t)L.nent);
     // Rest volumes and boundary faces from the original connectivity.
     unsigned slots = 1;
     while (slots < 8u * (unsigned)m) slots <<= 1;
@@ -534,6 +557,8 @@ int add_topology(fem_batch *B, const double *X_in, int n, const int32_t *tets_in
     v.cnodes = (const int *)(base + o_cn);
     v.cidx = (const int *)(base + o_cidx);
     v.X = (const double *)(base + o_X);
+    v.nvol = (const T *)(base + o_nvol);
+    v.owner = (const uint8_t *)(base + o_owner);
     B->topos.push_back(R);
     B->tables_dirty = true;
     *id = (int)B->topos.size() - 1;
@@ -559,6 +584,7 @@ int alloc_instance(fem_batch *B, int slot, int topo) {
     const size_t o_pg = A.take<T>(9 * (size_t)tp.nent), o_pq = A.take<T>(3 * (size_t)tp.nent);
     const size_t o_cp = A.take<T>(9 * (size_t)std::max(tp.nc, 1)), o_q = A.take<T>(3 * (size_t)n);
     const size_t o_red = A.take<double>(RS_COUNT * (size_t)stride);
+    const size_t o_v = A.take<T>(3 * (size_t)n), o_ut = A.take<T>(3 * (size_t)n);
     InstRec &R = B->insts[slot];
     HIP_TRY(hipMalloc(&R.arena, A.off));
     HIP_TRY(hipMemsetAsync(R.arena, 0, A.off, B->stream));
@@ -574,6 +600,8 @@ int alloc_instance(fem_batch *B, int slot, int topo) {
     b.cp = (T *)(base + o_cp);
     b.qout = (T *)(base + o_q);
     b.red = (double *)(base + o_red);
+    b.v = (T *)(base + o_v);
+    b.ut = (T *)(base + o_ut);
     b.s = B->d_states + slot;
     R.topo = topo;
     R.live = true;
@@ -825,18 +853,37 @@ int download_nodes(fem_batch *B, const std::vector<int> &perm, double *dst, cons
     return FEM_OK;
 }
 
-enum { V_U = 0, V_G, V_Z, V_P, V_Q };
+enum { V_U = 0, V_G, V_Z, V_P, V_Q, V_V, V_UT };
 
 void *inst_ptr(fem_batch *B, int slot, int which) {
     InstRec &R = B->insts[slot];
     if (B->precision == FEM_PREC_FP32) {
         InstBufs<float> &b = R.b32;
-        float *p[] = {b.u, b.g, b.z, b.p, b.qout};
+        float *p[] = {b.u, b.g, b.z, b.p, b.qout, b.v, b.ut};
         return p[which];
     }
     InstBufs<double> &b = R.b64;
-    double *p[] = {b.u, b.g, b.z, b.p, b.qout};
+    double *p[] = {b.u, b.g, b.z, b.p, b.qout, b.v, b.ut};
     return p[which];
+}
+
+// Velocity of a job at the end of its last completed step, in the caller's
+// numbering: the stored velocity plus the update the next step would make,
+// v + (u - ut) / dt (zero for quasi-static jobs).
+int download_velocity(fem_batch *B, int slot, double *v) {
+    const std::vector<int> &perm = B->topos[B->insts[slot].topo].perm;
+    const size_t n = perm.size();
+    const double dt = B->h_states[slot].dt;
+    if (!(dt > 0.0)) {
+        std::fill(v, v + 3 * n, 0.0);
+        return FEM_OK;
+    }
+    std::vector<double> u(3 * n), ut(3 * n);
+    TRY(download_nodes(B, perm, v, inst_ptr(B, slot, V_V)));
+    TRY(download_nodes(B, perm, u.data(), inst_ptr(B, slot, V_U)));
+    TRY(download_nodes(B, perm, ut.data(), inst_ptr(B, slot, V_UT)));
+    for (size_t q = 0; q < 3 * n; q++) v[q] += (u[q] - ut[q]) / dt;
+    return FEM_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -979,8 +1026,10 @@ int check_params(const fem_solve_params &P) {
 
 // A job's initial state: material, pose schedule, counters, phase GRAD.
 void init_job_state(InstState &s, double E, double nu, const Indenter &ind, const double c0[3], const double dir[3],
-                    double depth, int steps) {
+                    double depth, int steps, double dt, double rho) {
     std::memset(&s, 0, sizeof s);
+    s.dt = dt;
+    s.rho = rho;
     s.mu = E / (2.0 * (1.0 + nu));
     s.lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
     s.ind = ind;
@@ -1185,7 +1234,7 @@ int fem_step(fem_mesh *M, const fem_solve_params *params, fem_step_info *info) {
     TRY(params_to_device(B, P));
     const double zero[3] = {0.0, 0.0, 0.0};
     const int hint = B->h_states[0].last_cg;
-    init_job_state(B->h_states[0], M->E, M->nu, M->ind, M->ind.c, zero, 0.0, 1);
+    init_job_state(B->h_states[0], M->E, M->nu, M->ind, M->ind.c, zero, 0.0, 1, M->dt, M->density);
     B->h_states[0].last_cg = hint;
     TRY(write_state(B, 0));
     TRY(run(B, 0, nullptr));
@@ -1212,7 +1261,43 @@ int fem_set_displacements(fem_mesh *M, const double *u, int64_t count) {
     for (int64_t i = 0; i < count; i++)
         if (!is_finite(u[i])) return fail(FEM_E_INVALID, "non-finite displacement");
     TRY(set_device(M->batch));
-    return upload_nodes(M->batch, M->batch->topos[0].perm, inst_ptr(M->batch, 0, V_U), u);
+    TRY(upload_nodes(M->batch, M->batch->topos[0].perm, inst_ptr(M->batch, 0, V_U), u));
+    // The predictor follows, so the stored velocity is kept as it is.
+    HIP_TRY(hipMemcpyAsync(inst_ptr(M->batch, 0, V_UT), inst_ptr(M->batch, 0, V_U), 3 * (size_t)M->n * M->batch->elem(),
+                           hipMemcpyDeviceToDevice, M->batch->stream));
+    return sync(M->batch);
+}
+
+int fem_set_dynamics(fem_mesh *M, double dt) {
+    g_last_error.clear();
+    if (!M) return fail(FEM_E_INVALID, "null mesh");
+    if (!is_finite(dt) || dt < 0) return fail(FEM_E_INVALID, "dt must be >= 0");
+    if (dt > 0 && !(M->have_material && M->density > 0)) return fail(FEM_E_STATE, "set a material with density > 0 first");
+    M->dt = dt;
+    return FEM_OK;
+}
+
+int fem_get_velocities(const fem_mesh *Mc, double *v, int64_t capacity) {
+    g_last_error.clear();
+    if (!Mc || !v) return fail(FEM_E_INVALID, "null argument");
+    if (capacity < 3LL * Mc->n) return fail(FEM_E_BUFFER, "capacity below 3 n");
+    fem_mesh *M = const_cast<fem_mesh *>(Mc);
+    TRY(set_device(M->batch));
+    M->batch->h_states[0].dt = M->dt;
+    return download_velocity(M->batch, 0, v);
+}
+
+int fem_set_velocities(fem_mesh *M, const double *v, int64_t count) {
+    g_last_error.clear();
+    if (!M || !v) return fail(FEM_E_INVALID, "null argument");
+    if (count != 3LL * M->n) return fail(FEM_E_INVALID, "count must be 3 n");
+    for (int64_t i = 0; i < count; i++)
+        if (!is_finite(v[i])) return fail(FEM_E_INVALID, "non-finite velocity");
+    TRY(set_device(M->batch));
+    TRY(upload_nodes(M->batch, M->batch->topos[0].perm, inst_ptr(M->batch, 0, V_V), v));
+    HIP_TRY(hipMemcpyAsync(inst_ptr(M->batch, 0, V_UT), inst_ptr(M->batch, 0, V_U), 3 * (size_t)M->n * M->batch->elem(),
+                           hipMemcpyDeviceToDevice, M->batch->stream));
+    return sync(M->batch);
 }
 
 int fem_get_contact_patch(const fem_mesh *Mc, int32_t *ids, double *f, double *phi, int32_t capacity,
@@ -1260,7 +1345,7 @@ int fem_eval_gradient(fem_mesh *M, double *g, int64_t capacity, double *energy, 
     fem_default_params(&P, B->precision);
     TRY(params_to_device(B, P));
     const double zero[3] = {0.0, 0.0, 0.0};
-    init_job_state(B->h_states[0], M->E, M->nu, M->ind, M->ind.c, zero, 0.0, 1);
+    init_job_state(B->h_states[0], M->E, M->nu, M->ind, M->ind.c, zero, 0.0, 1, M->dt, M->density);
     B->h_states[0].phase = PH_EVAL_GRAD;
     TRY(write_state(B, 0));
     TRY(run(B, 2, nullptr));
@@ -1285,7 +1370,7 @@ int fem_eval_hessvec(fem_mesh *M, const fem_solve_params *params, const double *
     TRY(set_device(B));
     TRY(params_to_device(B, P));
     const double zero[3] = {0.0, 0.0, 0.0};
-    init_job_state(B->h_states[0], M->E, M->nu, M->ind, M->ind.c, zero, 0.0, 1);
+    init_job_state(B->h_states[0], M->E, M->nu, M->ind, M->ind.c, zero, 0.0, 1, M->dt, M->density);
     B->h_states[0].phase = PH_EVAL_GRAD;
     TRY(write_state(B, 0));
     TRY(run(B, 2, nullptr));
@@ -1342,6 +1427,8 @@ int fem_batch_add_job(fem_batch *B, int32_t mesh_id, double E, double nu, const 
     if (job->steps < 1 || !is_finite(job->depth) || job->depth < 0) return fail(FEM_E_INVALID, "bad schedule");
     for (int d = 0; d < 3; d++)
         if (!is_finite(job->direction[d])) return fail(FEM_E_INVALID, "bad direction");
+    if (!is_finite(job->dt) || job->dt < 0 || (job->dt > 0 && !(job->density > 0 && is_finite(job->density))))
+        return fail(FEM_E_INVALID, "implicit steps need dt >= 0 and density > 0");
     int slot = -1;
     for (int i = 0; i < B->capacity; i++)
         if (!B->insts[i].live) {
@@ -1352,7 +1439,8 @@ int fem_batch_add_job(fem_batch *B, int32_t mesh_id, double E, double nu, const 
     TRY(set_device(B));
     TRY(B->precision == FEM_PREC_FP32 ? alloc_instance<float>(B, slot, mesh_id)
                                      : alloc_instance<double>(B, slot, mesh_id));
-    init_job_state(B->h_states[slot], E, nu, ind, job->c0, job->direction, job->depth, job->steps);
+    init_job_state(B->h_states[slot], E, nu, ind, job->c0, job->direction, job->depth, job->steps, job->dt,
+                   job->density);
     TRY(write_state(B, slot));
     *job_id = slot;
     return FEM_OK;
@@ -1367,11 +1455,15 @@ int fem_batch_restart_job(fem_batch *B, int32_t job_id, double E, double nu, con
     if (job->steps < 1 || !is_finite(job->depth) || job->depth < 0) return fail(FEM_E_INVALID, "bad schedule");
     for (int d = 0; d < 3; d++)
         if (!is_finite(job->direction[d])) return fail(FEM_E_INVALID, "bad direction");
+    if (!is_finite(job->dt) || job->dt < 0 || (job->dt > 0 && !(job->density > 0 && is_finite(job->density))))
+        return fail(FEM_E_INVALID, "implicit steps need dt >= 0 and density > 0");
     TRY(set_device(B));
     const int n = B->topos[B->insts[job_id].topo].n;
-    HIP_TRY(hipMemsetAsync(inst_ptr(B, job_id, V_U), 0, 3 * (size_t)n * B->elem(), B->stream));
+    for (int which : {V_U, V_V, V_UT})
+        HIP_TRY(hipMemsetAsync(inst_ptr(B, job_id, which), 0, 3 * (size_t)n * B->elem(), B->stream));
     const int hint = B->h_states[job_id].last_cg;
-    init_job_state(B->h_states[job_id], E, nu, ind, job->c0, job->direction, job->depth, job->steps);
+    init_job_state(B->h_states[job_id], E, nu, ind, job->c0, job->direction, job->depth, job->steps, job->dt,
+                   job->density);
     B->h_states[job_id].last_cg = hint;
     // Stream-ordered before any later kernel or state read; the pinned source
     // slot is not written again until the host has synchronised.
@@ -1431,6 +1523,15 @@ int fem_batch_job_info(const fem_batch *B, int32_t job, fem_job_info *info) {
     J.g_norm = s.st_g;
     *info = J;
     return FEM_OK;
+}
+
+int fem_batch_get_velocities(fem_batch *B, int32_t job, double *v, int64_t capacity) {
+    g_last_error.clear();
+    if (!v || !job_ok(B, job)) return fail(FEM_E_INVALID, "unknown job");
+    const int n = B->topos[B->insts[job].topo].n;
+    if (capacity < 3LL * n) return fail(FEM_E_BUFFER, "capacity below 3 n");
+    TRY(set_device(B));
+    return download_velocity(B, job, v);
 }
 
 int fem_batch_get_displacements(fem_batch *B, int32_t job, double *u, int64_t capacity) {
@@ -1536,6 +1637,8 @@ int fem_batch_job_footprint(const fem_batch *B, int32_t mesh_id, int64_t *bytes)
     add(3 * (size_t)tp.nent * w);
     add(9 * (size_t)std::max(tp.nc, 1) * w);
     add(RS_COUNT * stride * sizeof(double));
+    add(3 * (size_t)tp.n * w);
+    add(3 * (size_t)tp.n * w);
     *bytes = (int64_t)total;
     return FEM_OK;
 }

@@ -26,10 +26,10 @@ PRECISIONS = {"fp64": FEM_PREC_FP64, "fp32": FEM_PREC_FP32}
 # Entry points declared in include/fem.h.
 EXPORTS = ("fem_create_mesh", "fem_destroy_mesh", "fem_set_material", "fem_set_indenter", "fem_default_params",
            "fem_step", "fem_get_displacements", "fem_set_displacements", "fem_get_contact_patch",
-           "fem_get_mesh_info", "fem_eval_gradient", "fem_eval_hessvec", "fem_set_kernel_timing",
+           "fem_get_mesh_info", "fem_set_dynamics", "fem_get_velocities", "fem_set_velocities", "fem_eval_gradient", "fem_eval_hessvec", "fem_set_kernel_timing",
            "fem_get_kernel_timing", "fem_batch_create", "fem_batch_destroy", "fem_batch_add_mesh",
            "fem_batch_mesh_info", "fem_batch_add_job", "fem_batch_restart_job", "fem_batch_remove_job", "fem_batch_run", "fem_batch_job_info",
-           "fem_batch_get_displacements", "fem_batch_get_contact_patch", "fem_batch_set_kernel_timing",
+           "fem_batch_get_displacements", "fem_batch_get_velocities", "fem_batch_get_contact_patch", "fem_batch_set_kernel_timing",
            "fem_batch_get_kernel_timing", "fem_batch_get_kernel_launches", "fem_set_graphs", "fem_batch_set_graphs", "fem_batch_set_option",
            "fem_batch_job_footprint", "fem_status_string",
            "fem_last_error")
@@ -66,7 +66,8 @@ class fem_step_info(C.Structure):
 
 class fem_indentation(C.Structure):
     _fields_ = [("kind", C.c_int32), ("shape", C.c_double * 4), ("R", C.c_double * 9), ("c0", C.c_double * 3),
-                ("direction", C.c_double * 3), ("depth", C.c_double), ("steps", C.c_int32), ("k_penalty", C.c_double)]
+                ("direction", C.c_double * 3), ("depth", C.c_double), ("steps", C.c_int32), ("k_penalty", C.c_double),
+                ("dt", C.c_double), ("density", C.c_double)]
 
 
 class fem_job_info(C.Structure):
@@ -107,6 +108,10 @@ def load(path: str = LIB_PATH):
     L.fem_step.argtypes = [vp, C.POINTER(fem_solve_params), C.POINTER(fem_step_info)]
     L.fem_get_displacements.argtypes = [vp, dp, C.c_int64]
     L.fem_set_displacements.argtypes = [vp, dp, C.c_int64]
+    L.fem_set_dynamics.argtypes = [vp, C.c_double]
+    L.fem_get_velocities.argtypes = [vp, dp, C.c_int64]
+    L.fem_set_velocities.argtypes = [vp, dp, C.c_int64]
+    L.fem_batch_get_velocities.argtypes = [vp, C.c_int32, dp, C.c_int64]
     L.fem_get_contact_patch.argtypes = [vp, i32p, dp, dp, C.c_int32, i32p, dp]
     L.fem_get_mesh_info.argtypes = [vp, i32p, i32p, i32p, u8p, C.c_int32]
     L.fem_eval_gradient.argtypes = [vp, dp, C.c_int64, dp, dp]
@@ -217,6 +222,21 @@ def fem_set_displacements(h, u):
     _check(load().fem_set_displacements(h, _dp(uu), uu.size))
 
 
+def fem_set_dynamics(h, dt: float):
+    _check(load().fem_set_dynamics(h, float(dt)))
+
+
+def fem_get_velocities(h, n: int) -> np.ndarray:
+    v = np.zeros((n, 3))
+    _check(load().fem_get_velocities(h, _dp(v), v.size))
+    return v
+
+
+def fem_set_velocities(h, v):
+    vv = np.ascontiguousarray(v, dtype=np.float64)
+    _check(load().fem_set_velocities(h, _dp(vv), vv.size))
+
+
 def fem_get_contact_patch(h):
     cnt = C.c_int32()
     Ft = np.zeros(3)
@@ -306,6 +326,15 @@ class FemMesh:
     def set_displacements(self, u):
         fem_set_displacements(self.h, u)
 
+    def set_dynamics(self, dt):
+        fem_set_dynamics(self.h, dt)
+
+    def velocities(self):
+        return fem_get_velocities(self.h, self.n)
+
+    def set_velocities(self, v):
+        fem_set_velocities(self.h, v)
+
     def contact_patch(self):
         return fem_get_contact_patch(self.h)
 
@@ -386,6 +415,8 @@ def make_indentation(ind) -> fem_indentation:
     j.depth = float(ind.depth)
     j.steps = int(ind.steps)
     j.k_penalty = float(ind.k_penalty)
+    j.dt = float(getattr(ind, "dt", 0.0))
+    j.density = float(getattr(ind, "density", 1100.0))
     return j
 
 
@@ -422,6 +453,12 @@ def fem_batch_get_displacements(h, job: int, n: int) -> np.ndarray:
     u = np.zeros((n, 3))
     _check(load().fem_batch_get_displacements(h, int(job), _dp(u), u.size))
     return u
+
+
+def fem_batch_get_velocities(h, job: int, n: int) -> np.ndarray:
+    v = np.zeros((n, 3))
+    _check(load().fem_batch_get_velocities(h, int(job), _dp(v), v.size))
+    return v
 
 
 def fem_batch_get_contact_patch(h, job: int):
@@ -506,6 +543,9 @@ class FemBatch:
 
     def displacements(self, job):
         return fem_batch_get_displacements(self.h, job, self.mesh_nodes[self.job_mesh[job]])
+
+    def velocities(self, job):
+        return fem_batch_get_velocities(self.h, job, self.mesh_nodes[self.job_mesh[job]])
 
     def contact_patch(self, job):
         return fem_batch_get_contact_patch(self.h, job)

@@ -252,6 +252,8 @@ class Indentation:
     k_penalty: float = 1.0e4
     contact_point: np.ndarray | None = None
     seed: int | None = None
+    dt: float = 0.0           # > 0: implicit time steps of this length (s)
+    density: float = 1100.0   # kg/m^3, lumped masses of implicit steps
 
     def center(self, step: int) -> np.ndarray:
         """Indenter centre at load step `step` (0 = initial contact pose)."""

@@ -72,3 +72,37 @@ def test_fingertip_jobs_match_oracle(gold, precision):
         assert err <= bound, (seed, step, err)
     batch.close()
     full.close()
+
+
+DYN_GOLD = os.path.join(os.path.dirname(__file__), "golden", "fingertip50k_dynamic_oracle.npz")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fingertip_time_steps_match_oracle(precision):
+    """Backward-Euler time steps (dt = 1e-4 s) of the benchmark's first jobs
+    on the 50k fingertip, batched, against stored oracle results
+    (tests/golden/make_fingertip_dynamic_reference.py); velocities within 10x
+    the displacement bound."""
+    if not os.path.exists(DYN_GOLD):
+        pytest.skip("oracle reference file not generated")
+    gold = np.load(DYN_GOLD)
+    mesh = W.fingertip_mesh(50000)
+    steps, dt, rho = int(gold["steps"]), float(gold["dt"]), float(gold["rho"])
+    seeds = [int(s) for s in gold["seeds"]]
+    batch = fem.FemBatch(len(seeds), precision)
+    mid = batch.add_mesh(mesh.X, mesh.tets, mesh.fixed)
+    ids = {}
+    for s in seeds:
+        ind = W.seat_on_mesh(W.random_indentation(s), mesh)
+        short = W.Indentation(ind.kind, ind.shape, ind.R, ind.c0, ind.direction, ind.depth * steps / ind.steps, steps,
+                              ind.k_penalty, dt=dt, density=rho)
+        ids[s] = batch.add_job(mid, short)
+    P = batch.default_params(newton_rtol=2e-9, cg_rtol=1e-10) if precision == "fp64" else batch.default_params()
+    assert batch.run(P) == 0
+    bound = 1e-6 if precision == "fp64" else 1e-4
+    for s in seeds:
+        eu = e_inf(batch.displacements(ids[s]), gold[f"u_{s}"])
+        ev = e_inf(batch.velocities(ids[s]), gold[f"v_{s}"])
+        print(f"{precision} dynamic seed {s} step {steps}: e_inf u {eu:.3e} v {ev:.3e}", flush=True)
+        assert eu <= bound and ev <= 10 * bound, (s, eu, ev)
+    batch.close()
