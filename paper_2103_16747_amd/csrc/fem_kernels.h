@@ -79,6 +79,7 @@ struct InstState {
     double E, emag, minJ, gg, r0, gd, alpha_ls;
     double mu, lam, depth;
     double dt, rho;                           // implicit time step (0: quasi-static), density
+    double mdt2;                              // rho / dt^2 (0: quasi-static)
     double gbest;                             // smallest |g_free| of the load step so far
     int stall, steps_floor;                   // accepted iterations without halving gbest
     double c0[3], dir[3];
@@ -259,16 +260,23 @@ __device__ __forceinline__ void unpack_loc(uint32_t w, int l[4]) {
 }
 
 // Rest constants and local node slots of tet k (tile order) from the per-mesh
-// records, as whole 16-byte words.
+// records, fetched as whole 16-byte words (fetch_tet) and unpacked once they
+// are needed (unpack_tet), so a fetch can be issued ahead of its use.
+template <typename T> struct TetWords {
+    uint4 w[sizeof(TetRec<T>) / 16];
+};
+
 template <typename T>
-__device__ __forceinline__ ElemGeo<T> load_tet(const Topo<T> &tp, int k, int l[4]) {
-    constexpr int kWords = (int)(sizeof(TetRec<T>) / 16);
+__device__ __forceinline__ void fetch_tet(const Topo<T> &tp, int k, TetWords<T> &tw) {
     const uint4 *src = reinterpret_cast<const uint4 *>(tp.rec + k);
-    uint4 w[kWords];
 #pragma unroll
-    for (int i = 0; i < kWords; i++) w[i] = src[i];
+    for (int i = 0; i < (int)(sizeof(TetRec<T>) / 16); i++) tw.w[i] = src[i];
+}
+
+template <typename T>
+__device__ __forceinline__ ElemGeo<T> unpack_tet(const TetWords<T> &tw, int l[4]) {
     TetRec<T> r;
-    __builtin_memcpy(&r, w, sizeof r);
+    __builtin_memcpy(&r, tw.w, sizeof r);
     ElemGeo<T> g;
 #pragma unroll
     for (int c = 0; c < 9; c++) g.Bm[c] = r.Bm[c];
@@ -574,6 +582,10 @@ __device__ __forceinline__ void tile_element(const Topo<T> &tp, const InstBufs<T
         const int t = blk;
         const int e0 = tp.tile_ent[t], ne = tp.tile_ent[t + 1] - e0;
         const int k0 = tp.tile_tet[t], nk = tp.tile_tet[t + 1] - k0;
+        // This thread's first tet record is fetched before the staging
+        // barrier, so its latency overlaps the staging loads.
+        TetWords<T> tw;
+        if ((int)threadIdx.x < nk) fetch_tet(tp, k0 + (int)threadIdx.x, tw);
         for (int l = threadIdx.x; l < ne; l += kBlock) {
             const int gid = tp.ent_node[e0 + l];
 #pragma unroll
@@ -589,7 +601,8 @@ __device__ __forceinline__ void tile_element(const Topo<T> &tp, const InstBufs<T
         __syncthreads();
         for (int k = threadIdx.x; k < nk; k += kBlock) {
             int l[4];
-            const ElemGeo<T> geo = load_tet(tp, k0 + k, l);
+            if (k != (int)threadIdx.x) fetch_tet(tp, k0 + k, tw);
+            const ElemGeo<T> geo = unpack_tet(tw, l);
             T wu[4][3];
             load_nodes(su, l, wu);
             T G[9];
@@ -718,8 +731,12 @@ __device__ __forceinline__ void tile_hessvec(const Topo<T> &tp, const InstBufs<T
         const int k0 = tp.tile_tet[t], nk = tp.tile_tet[t + 1] - k0;
         // Implicit steps add (m_i / dt^2) |p_i|^2 to p.q, taken once per node
         // (on its first entry).
-        const double cm = s->dt > 0.0 ? s->rho / (s->dt * s->dt) : 0.0;
+        const double cm = s->mdt2;
         double pq = 0.0;
+        // This thread's first tet record is fetched before the staging
+        // barrier, so its latency overlaps the staging loads.
+        TetWords<T> tw;
+        if ((int)threadIdx.x < nk) fetch_tet(tp, k0 + (int)threadIdx.x, tw);
         for (int l = threadIdx.x; l < ne; l += kBlock) {
             const int gid = tp.ent_node[e0 + l];
             T pv[3];
@@ -739,7 +756,8 @@ __device__ __forceinline__ void tile_hessvec(const Topo<T> &tp, const InstBufs<T
         __syncthreads();
         for (int k = threadIdx.x; k < nk; k += kBlock) {
             int l[4];
-            const ElemGeo<T> geo = load_tet(tp, k0 + k, l);
+            if (k != (int)threadIdx.x) fetch_tet(tp, k0 + k, tw);
+            const ElemGeo<T> geo = unpack_tet(tw, l);
             T wu[4][3], wp[4][3];
             load_nodes(su, l, wu);
             load_nodes(sp, l, wp);
@@ -820,14 +838,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T
     const int L = logical_block();
     if (L >= nwork) return;
     const int2 w = work[L];
-    const InstBufs<T> &B = bufs[w.x];
+    // Descriptors copied up front, before any store of the kernel, so they
+    // are fetched once as uniform (scalar) loads.
+    const InstBufs<T> B = bufs[w.x];
+    const Topo<T> tp = topos[B.topo];
+    const int contact_full = P->contact_full;
     const InstState *s = B.s;
     const int phase = s->phase;
     if (phase == PH_CG || phase == PH_EVAL_HV) {
-        tile_hessvec(topos[B.topo], B, s, w.y, pool);
+        tile_hessvec(tp, B, s, w.y, pool);
     } else if (phase == PH_GRAD || phase == PH_EVAL_GRAD || phase == PH_TRIAL) {
         const T alpha = phase == PH_TRIAL ? (T)s->alpha_ls : (T)0;
-        tile_element(topos[B.topo], B, s, w.y, alpha, P->contact_full, pool);
+        tile_element(tp, B, s, w.y, alpha, contact_full, pool);
     }
 }
 
@@ -847,7 +869,8 @@ template <typename T>
 __device__ __forceinline__ void node_init(const Topo<T> &tp, const InstBufs<T> &B, const InstState *s, int blk,
                                           bool apply, bool step_start, int block_jacobi) {
     const T alpha = (T)s->alpha_ls;
-    const bool dyn = s->dt > 0.0;
+    const double dt = s->dt, mdt2 = s->mdt2;
+    const bool dyn = dt > 0.0;
     double acc[3] = {0.0, 0.0, 0.0};   // |g_free|^2, r.z, inertial energy
     double unused = 0.0;
     const int i = blk * kBlock + threadIdx.x;
@@ -868,8 +891,8 @@ __device__ __forceinline__ void node_init(const Topo<T> &tp, const InstBufs<T> &
 #pragma unroll
             for (int c = 0; c < 9; c++) gsum[c] += B.cp[9 * j + c];
         if (dyn && !tp.fixed[i]) {
-            const T h = (T)s->dt;
-            const T cm = (T)(s->rho / (s->dt * s->dt)) * tp.nvol[i];
+            const T h = (T)dt;
+            const T cm = (T)mdt2 * tp.nvol[i];
             double en = 0.0;
 #pragma unroll
             for (int d = 0; d < 3; d++) {
@@ -947,13 +970,16 @@ __device__ __forceinline__ void node_init(const Topo<T> &tp, const InstBufs<T> &
 // stops (on its first iteration the preconditioned residual becomes the
 // Newton direction). EVAL_HV writes q instead.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool DYN>
 __device__ __forceinline__ void node_update(const Topo<T> &tp, const InstBufs<T> &B, const InstState *s, int blk,
                                             bool eval) {
+    // solver scalars first, so their loads overlap the partial sums
+    const double rz = s->rz;
+    const T beta = (T)s->beta;
+    const int cg_first = s->cg_it == 0;
     const double pq = block_sum_partials(B.red + RS_PQ * B.red_stride, tp.ntile + tp.ncb);
     const bool negcurv = !(pq > 0.0);
-    const T alpha = negcurv ? (T)0 : (T)(s->rz / pq);
-    const T beta = (T)s->beta;
+    const T alpha = negcurv ? (T)0 : (T)(rz / pq);
     double acc[2] = {0.0, 0.0};   // r.z, r.r
     double unused = 0.0;
     const int i = blk * kBlock + threadIdx.x;
@@ -976,8 +1002,8 @@ __device__ __forceinline__ void node_update(const Topo<T> &tp, const InstBufs<T>
                 qv[1] += H[3] * pv[0] + H[1] * pv[1] + H[5] * pv[2];
                 qv[2] += H[4] * pv[0] + H[5] * pv[1] + H[2] * pv[2];
             }
-            if (s->dt > 0.0 && !tp.fixed[i]) {
-                const T cm = (T)(s->rho / (s->dt * s->dt)) * tp.nvol[i];
+            if (DYN && !tp.fixed[i]) {
+                const T cm = (T)s->mdt2 * tp.nvol[i];
 #pragma unroll
                 for (int d = 0; d < 3; d++) qv[d] = fma_t(cm, pv[d], qv[d]);
             }
@@ -1003,7 +1029,7 @@ __device__ __forceinline__ void node_update(const Topo<T> &tp, const InstBufs<T>
                 acc[0] = (double)rv[0] * (double)z0 + (double)rv[1] * (double)z1 + (double)rv[2] * (double)z2;
                 acc[1] = (double)rv[0] * (double)rv[0] + (double)rv[1] * (double)rv[1] + (double)rv[2] * (double)rv[2];
             }
-        } else if (s->cg_it == 0) {
+        } else if (cg_first) {
 #pragma unroll
             for (int d = 0; d < 3; d++) B.dx[3 * i + d] = pv[d];
         }
@@ -1033,7 +1059,7 @@ __device__ __forceinline__ void node_trial(const Topo<T> &tp, const InstBufs<T> 
                 const T w = fma_t(alpha, B.dx[3 * i + d], B.u[3 * i + d]) - B.ut[3 * i + d];
                 en += (double)w * (double)w;
             }
-            acc[1] = 0.5 * (s->rho / (s->dt * s->dt)) * (double)tp.nvol[i] * en;
+            acc[1] = 0.5 * s->mdt2 * (double)tp.nvol[i] * en;
         }
     }
     block_reduce<2, false>(acc, unused);
@@ -1053,12 +1079,20 @@ __global__ __launch_bounds__(kBlock) void k_node(const Topo<T> *topos, const Ins
     const int L = logical_block();
     if (L >= nwork) return;
     const int2 w = work[L];
-    const InstBufs<T> &B = bufs[w.x];
+    // Descriptors copied up front, before any store of the kernel, so they
+    // are fetched once as uniform (scalar) loads.
+    const InstBufs<T> B = bufs[w.x];
+    const Topo<T> tp = topos[B.topo];
     const InstState *s = B.s;
     const int phase = s->phase;
-    const Topo<T> &tp = topos[B.topo];
-    if (phase == PH_CG || phase == PH_EVAL_HV)
-        node_update(tp, B, s, w.y, phase == PH_EVAL_HV);
+    if (phase == PH_CG || phase == PH_EVAL_HV) {
+        // the inertial term as a separate instance keeps it out of the
+        // quasi-static CG update
+        if (s->mdt2 > 0.0)
+            node_update<T, true>(tp, B, s, w.y, phase == PH_EVAL_HV);
+        else
+            node_update<T, false>(tp, B, s, w.y, phase == PH_EVAL_HV);
+    }
     else if (phase == PH_GRAD || phase == PH_EVAL_GRAD || phase == PH_INIT)
         node_init(tp, B, s, w.y, phase == PH_INIT && s->apply != 0, phase == PH_GRAD, P->block_jacobi);
     else if (phase == PH_TRIAL && (s->need_gd || s->dt > 0.0))
@@ -1137,10 +1171,10 @@ template <typename T>
 __global__ __launch_bounds__(64) void k_finalize(const Topo<T> *topos, const InstBufs<T> *bufs, const int *live,
                                                  int nlive, const SolveParams *P) {
     if ((int)blockIdx.x >= nlive) return;
-    const InstBufs<T> &B = bufs[live[blockIdx.x]];
+    const InstBufs<T> B = bufs[live[blockIdx.x]];
+    const Topo<T> tp = topos[B.topo];
     InstState *s = B.s;
     const int phase = s->phase;
-    const Topo<T> &tp = topos[B.topo];
     const int S = B.red_stride;
     const int nt = tp.ntile + tp.ncb, nn = (tp.n + kBlock - 1) / kBlock;
     if (phase == PH_CG || phase == PH_EVAL_HV) {

@@ -1030,6 +1030,7 @@ void init_job_state(InstState &s, double E, double nu, const Indenter &ind, cons
     std::memset(&s, 0, sizeof s);
     s.dt = dt;
     s.rho = rho;
+    s.mdt2 = dt > 0.0 ? rho / (dt * dt) : 0.0;
     s.mu = E / (2.0 * (1.0 + nu));
     s.lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
     s.ind = ind;
