@@ -85,6 +85,12 @@ def lib():
         L.orc_surface_nodes.argtypes = [C.c_int, C.c_int, ip, up]
         L.orc_lumped_mass.argtypes = [C.c_int, C.c_int, ip, dp, C.c_double, dp]
         L.orc_lumped_mass.restype = None
+        L.orc_cauchy.argtypes = [dp, C.c_double, C.c_double, dp, dp]
+        L.orc_cauchy.restype = None
+        L.orc_tet_stress.argtypes = [C.POINTER(Problem), dp, dp, dp]
+        L.orc_tet_stress.restype = None
+        L.orc_displacement_stats.argtypes = [C.c_int, dp, dp, dp]
+        L.orc_displacement_stats.restype = None
         L.orc_deformation_gradient.argtypes = [C.POINTER(Problem), dp, C.c_int, dp]
         L.orc_energy.argtypes = [C.POINTER(Problem), dp, dp]
         L.orc_energy.restype = C.c_double
@@ -168,6 +174,21 @@ def surface_nodes(n, tets):
     nb = lib().orc_surface_nodes(n, T.shape[0], T.ctypes.data_as(C.POINTER(C.c_int)),
                                  s.ctypes.data_as(C.POINTER(C.c_ubyte)))
     return s, nb
+
+
+def cauchy(F, mu, lam):
+    """(sigma as xx yy zz xy xz yz, von Mises) of one deformation gradient."""
+    s = np.zeros(6)
+    vm = C.c_double()
+    lib().orc_cauchy(_dp(_f64(F, (3, 3))), mu, lam, _dp(s), C.byref(vm))
+    return s, vm.value
+
+
+def displacement_stats(u):
+    u = _f64(u).reshape(-1, 3)
+    mx, mean = C.c_double(), C.c_double()
+    lib().orc_displacement_stats(int(u.shape[0]), _dp(u), C.byref(mx), C.byref(mean))
+    return mx.value, mean.value
 
 
 def lumped_mass(n, tets, V, rho):
@@ -298,6 +319,13 @@ class Solver:
         info = Info()
         lib().orc_step(C.byref(self.p), C.byref(prm), _dp(un), C.byref(info))
         return un, info.as_dict()
+
+    def tet_stress(self, u):
+        """Per-tet Cauchy stress (m x 6: xx yy zz xy xz yz) and von Mises (m)."""
+        sig = np.zeros((self.m, 6))
+        vm = np.zeros(self.m)
+        lib().orc_tet_stress(C.byref(self.p), _dp(self._u(u)), _dp(sig), _dp(vm))
+        return sig, vm
 
     def contact_patch(self, u):
         uu = self._u(u)

@@ -826,3 +826,51 @@ int orc_contact_patch(const orc_problem *p, const double *u, int *ids, double *f
     if (F_total) memcpy(F_total, Ft, sizeof Ft);
     return count;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Outputs for data generation: per-tet Cauchy stress and von Mises stress,
+ * and the displacement-norm statistics the paper reports per indentation. */
+void orc_cauchy(const double F[9], double mu, double lam, double sigma[6], double *vm) {
+    double P[9], S[9];
+    orc_pk1(F, mu, lam, P);
+    double J = det3(F);
+    /* sigma = P F^T / J */
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double s = 0.0;
+            for (int k = 0; k < 3; k++) s += P[3 * i + k] * F[3 * j + k];
+            S[3 * i + j] = s / J;
+        }
+    sigma[0] = S[0];
+    sigma[1] = S[4];
+    sigma[2] = S[8];
+    sigma[3] = 0.5 * (S[1] + S[3]);
+    sigma[4] = 0.5 * (S[2] + S[6]);
+    sigma[5] = 0.5 * (S[5] + S[7]);
+    if (vm) {
+        double a = sigma[0] - sigma[1], b = sigma[1] - sigma[2], c = sigma[2] - sigma[0];
+        *vm = sqrt(0.5 * (a * a + b * b + c * c) + 3.0 * (sigma[3] * sigma[3] + sigma[4] * sigma[4] + sigma[5] * sigma[5]));
+    }
+}
+
+void orc_tet_stress(const orc_problem *p, const double *u, double *sigma, double *vm) {
+    for (int e = 0; e < p->m; e++) {
+        double F[9], s[6], v;
+        orc_deformation_gradient(p, u, e, F);
+        orc_cauchy(F, p->mu, p->lam, s, &v);
+        if (sigma)
+            for (int c = 0; c < 6; c++) sigma[6 * (size_t)e + c] = s[c];
+        if (vm) vm[e] = v;
+    }
+}
+
+void orc_displacement_stats(int n, const double *u, double *max_norm, double *mean_norm) {
+    double mx = 0.0, sum = 0.0;
+    for (int i = 0; i < n; i++) {
+        double a = sqrt(u[3 * i] * u[3 * i] + u[3 * i + 1] * u[3 * i + 1] + u[3 * i + 2] * u[3 * i + 2]);
+        if (a > mx) mx = a;
+        sum += a;
+    }
+    *max_norm = mx;
+    *mean_norm = n > 0 ? sum / n : 0.0;
+}

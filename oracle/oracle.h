@@ -142,6 +142,18 @@ int orc_step(const orc_problem *p, const orc_params *prm, double *u, orc_info *i
 int orc_contact_patch(const orc_problem *p, const double *u, int *ids, double *f, double *phi,
                       double F_total[3]);
 
+/* Cauchy stress sigma = P F^T / J of one deformation gradient, as
+ * (xx, yy, zz, xy, xz, yz), and its von Mises value (vm may be NULL). */
+void orc_cauchy(const double F[9], double mu, double lam, double sigma[6], double *vm);
+
+/* Per-tet Cauchy stress (m x 6) and von Mises stress (m) at u (either output
+ * may be NULL). */
+void orc_tet_stress(const orc_problem *p, const double *u, double *sigma, double *vm);
+
+/* max_i |u_i| and mean_i |u_i| over all n nodes (paper Sec. IV's per-
+ * indentation displacement statistics). */
+void orc_displacement_stats(int n, const double *u, double *max_norm, double *mean_norm);
+
 #ifdef __cplusplus
 }
 #endif
