@@ -115,8 +115,18 @@ def run_batched(mesh, inds, precision, timed_steps, warm_steps, timing_every=0, 
         batch.set_kernel_timing(0)
     finals = [batch.displacements(j) for j in jobs[:4]]
     stats = [batch.job_info(j) for j in jobs]
+    # data-generation outputs of the finished jobs: per-tet stress and
+    # displacement statistics (device kernels; the stress copy to the host
+    # is included)
+    t0 = time.perf_counter()
+    nout = min(len(jobs), 32)
+    for j in jobs[:nout]:
+        batch.tet_stress(j)
+        batch.displacement_stats(j)
+    out_ms = (time.perf_counter() - t0) / nout * 1e3
     batch.close()
     return {"walls": walls, "lat": lat, "tet_updates": tu, "failed_steps": failed, "floor_steps": floor,
+            "outputs_ms_per_job": out_ms,
             "timing": timing, "hv_passes": hv, "grad_passes": gp, "layout": info, "finals": finals, "stats": stats}
 
 
@@ -477,6 +487,7 @@ def main():
         "failed_load_steps": r32["failed_steps"],
         "floor_load_steps": r32["floor_steps"],
         "cg_iters_per_job": float(np.mean([s["cg_iters"] for s in r32["stats"]])),
+        "outputs_ms_per_job": r32["outputs_ms_per_job"],
         "newton_iters_per_job": float(np.mean([s["newton_iters"] for s in r32["stats"]])),
     }
     gold_path = os.path.join(ROOT, "tests", "golden", "fingertip50k_oracle.npz")

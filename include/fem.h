@@ -190,6 +190,21 @@ int fem_set_velocities(fem_mesh *mesh, const double *v, int64_t count);
 int fem_get_contact_patch(const fem_mesh *mesh, int32_t *ids, double *f, double *phi, int32_t capacity,
                           int32_t *n_contact, double F_total[3]);
 
+/* Per-tet stress at the current displacement (paper Sec. III-A: the
+ * simulator's deformation field, here reduced to the stress a data-generation
+ * pipeline records): Cauchy stress sigma = P F^T / J of the Neo-Hookean law,
+ * 6 values per tet (xx, yy, zz, xy, xz, yz, Pa) in the caller's tet order,
+ * and its von Mises value sqrt(3/2 s:s) with s the deviator. Computed in the
+ * handle's precision, returned as double; a tet with det F <= 0 gives NaN.
+ * Either output may be NULL; capacity is in tets (>= n_tets).
+ * Errors: FEM_E_INVALID, FEM_E_STATE (no material), FEM_E_BUFFER. */
+int fem_get_tet_stress(const fem_mesh *mesh, double *sigma, double *von_mises, int64_t capacity);
+
+/* max_i |u_i| and mean_i |u_i| over all nodes at the current displacement
+ * (the per-indentation displacement statistics of paper Sec. IV). Either
+ * output may be NULL. Errors: FEM_E_INVALID. */
+int fem_get_displacement_stats(const fem_mesh *mesh, double *max_norm, double *mean_norm);
+
 /* Mesh facts computed at creation: node and tet counts, number of
  * contact-eligible nodes, and (if eligible != NULL, capacity >= n) the
  * per-node eligibility flags. */
@@ -297,6 +312,10 @@ int fem_batch_run(fem_batch *batch, const fem_solve_params *params, int32_t max_
 
 /* Progress and counters of a job (as of the end of the last run). */
 int fem_batch_job_info(const fem_batch *batch, int32_t job_id, fem_job_info *info);
+
+/* A job's per-tet stress and displacement statistics, as the single-mesh calls. */
+int fem_batch_get_tet_stress(fem_batch *batch, int32_t job_id, double *sigma, double *von_mises, int64_t capacity);
+int fem_batch_get_displacement_stats(fem_batch *batch, int32_t job_id, double *max_norm, double *mean_norm);
 
 /* A job's velocities (n x 3, zero for quasi-static jobs), as fem_get_velocities. */
 int fem_batch_get_velocities(fem_batch *batch, int32_t job_id, double *v, int64_t capacity);

@@ -125,6 +125,7 @@ struct Topo {
     const double *X;                    // n x 3
     const T *nvol;                      // n: lumped volume share sum_e V_e / 4
     const uint8_t *owner;               // nent: 1 on each node's first entry
+    const int *tet_id;                  // m: input index of the tet at each tile position
 };
 
 template <typename T>
@@ -1328,6 +1329,119 @@ __global__ __launch_bounds__(1024) void k_contact_patch(const Topo<T> *topos, co
         *count = base_s;
 #pragma unroll
         for (int d = 0; d < 3; d++) Ftot[d] = F_s[d];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Outputs for data generation (one instance at its current state).
+// k_tet_stress: one block per tile stages the tile's displacements in LDS;
+// per tet F = I + G, the first Piola-Kirchhoff stress as in the element
+// pass, the Cauchy stress sigma = P F^T / J (symmetrised; xx yy zz xy xz yz)
+// and its von Mises value, written in FP64 at the tet's input index.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_tet_stress(const Topo<T> *topos, const InstBufs<T> *bufs, int inst,
+                                                       double *sigma, double *vm) {
+    __shared__ __attribute__((aligned(32))) T su[kSw * kTileNodes];
+    const InstBufs<T> B = bufs[inst];
+    const Topo<T> tp = topos[B.topo];
+    const int t = blockIdx.x;
+    if (t >= tp.ntile) return;
+    const T mu = (T)B.s->mu, lam = (T)B.s->lam;
+    const int e0 = tp.tile_ent[t], ne = tp.tile_ent[t + 1] - e0;
+    const int k0 = tp.tile_tet[t], nk = tp.tile_tet[t + 1] - k0;
+    for (int l = threadIdx.x; l < ne; l += kBlock) {
+        const int gid = tp.ent_node[e0 + l];
+#pragma unroll
+        for (int d = 0; d < 3; d++) su[kSw * l + d] = B.u[3 * gid + d];
+        su[kSw * l + 3] = (T)0;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nk; k += kBlock) {
+        int l[4];
+        TetWords<T> tw;
+        fetch_tet(tp, k0 + k, tw);
+        const ElemGeo<T> geo = unpack_tet(tw, l);
+        T wu[4][3];
+        load_nodes(su, l, wu);
+        T G[9];
+        edge_gradient(wu, geo.Bm, G);
+        const T Jm1 = det_minus_one(G);
+        const T J = (T)1 + Jm1;
+        const int id = tp.tet_id[k0 + k];
+        double out[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        double v = 0.0;
+        if (J > (T)0) {
+            const T lnJ = log1p_t(Jm1);
+            T FiT[9];
+            inverse_transpose(G, J, FiT);
+            T Pk[9], F[9];
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int j = 0; j < 3; j++) {
+                    const T FG = FiT[3 * i] * G[3 * j] + FiT[3 * i + 1] * G[3 * j + 1] + FiT[3 * i + 2] * G[3 * j + 2];
+                    Pk[3 * i + j] = mu * (G[3 * i + j] + FG) + lam * lnJ * FiT[3 * i + j];
+                    F[3 * i + j] = G[3 * i + j] + (i == j ? (T)1 : (T)0);
+                }
+            double S[9];
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int j = 0; j < 3; j++)
+                    S[3 * i + j] = ((double)Pk[3 * i] * F[3 * j] + (double)Pk[3 * i + 1] * F[3 * j + 1] +
+                                    (double)Pk[3 * i + 2] * F[3 * j + 2]) / (double)J;
+            out[0] = S[0];
+            out[1] = S[4];
+            out[2] = S[8];
+            out[3] = 0.5 * (S[1] + S[3]);
+            out[4] = 0.5 * (S[2] + S[6]);
+            out[5] = 0.5 * (S[5] + S[7]);
+            const double a = out[0] - out[1], b = out[1] - out[2], c = out[2] - out[0];
+            v = sqrt(0.5 * (a * a + b * b + c * c) + 3.0 * (out[3] * out[3] + out[4] * out[4] + out[5] * out[5]));
+        } else {
+            v = NAN;
+#pragma unroll
+            for (int c = 0; c < 6; c++) out[c] = NAN;
+        }
+        if (sigma)
+#pragma unroll
+            for (int c = 0; c < 6; c++) sigma[6 * (size_t)id + c] = out[c];
+        if (vm) vm[id] = v;
+    }
+}
+
+// max_i |u_i| and mean_i |u_i| of one instance (one block, FP64 sums).
+template <typename T>
+__global__ __launch_bounds__(1024) void k_disp_stats(const Topo<T> *topos, const InstBufs<T> *bufs, int inst,
+                                                     double *out) {
+    __shared__ double smax[16], ssum[16];
+    const InstBufs<T> B = bufs[inst];
+    const int n = topos[B.topo].n;
+    double mx = 0.0, sum = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double x = B.u[3 * i], y = B.u[3 * i + 1], z = B.u[3 * i + 2];
+        const double a = sqrt(x * x + y * y + z * z);
+        mx = fmax(mx, a);
+        sum += a;
+    }
+    sum = wave_sum(sum);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_down(mx, o, 64));
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        smax[wv] = mx;
+        ssum[wv] = sum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m2 = 0.0, s2 = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); k++) {
+            m2 = fmax(m2, smax[k]);
+            s2 += ssum[k];
+        }
+        out[0] = m2;
+        out[1] = n > 0 ? s2 / n : 0.0;
     }
 }
 

@@ -75,6 +75,7 @@ struct HostLayout {
     int n = 0, m = 0, ntile = 0, nent = 0;
     std::vector<int> tile_tet, tile_ent, ent_node, node_ent_off, node_ent;
     std::vector<uint32_t> tet_loc;
+    std::vector<int> order;             // tile position -> input tet index
     std::vector<int> tet_nodes;         // 4 x m: global node ids per tet in tile order and device vertex order
 };
 
@@ -207,6 +208,7 @@ void build_layout(const double *X, int n, const int32_t *tets, int m, int max_te
     L.tile_ent.assign(1, 0);
     L.ent_node.clear();
     L.tet_loc.assign(m, 0);
+    L.order.assign(m, 0);
     L.tet_nodes.assign(4 * (size_t)m, 0);
     int tile = 0, tile_tets = 0, tile_nodes = 0, pos = 0;
     std::vector<int> tile_list;
@@ -236,6 +238,7 @@ void build_layout(const double *X, int n, const int32_t *tets, int m, int max_te
                 L.tet_nodes[4 * (size_t)k + a] = tets[4 * (size_t)e + from];
             }
             L.tet_loc[k] = w;
+            L.order[k] = e;
         }
         for (int v : tile_list) L.ent_node.push_back(v);
         L.tile_tet.push_back(pos);
@@ -338,6 +341,8 @@ struct fem_batch {
     bool tables_dirty = true;
     void *patch = nullptr;
     size_t patch_bytes = 0;
+    void *outbuf = nullptr;                 // stress / statistics outputs
+    size_t outbuf_bytes = 0;
     void *h_stage = nullptr;
     size_t h_stage_bytes = 0;
     KernelTimer timer;
@@ -450,7 +455,7 @@ int add_topology(fem_batch *B, const double *X_in, int n, const int32_t *tets_in
     const size_t o_neo = A.take<int>(n + 1), o_ne = A.take<int>(L.nent);
     const size_t o_fixed = A.take<uint8_t>(n), o_cn = A.take<int>(n), o_cidx = A.take<int>(n);
     const size_t o_X = A.take<double>(3 * (size_t)n), o_elig = A.take<uint8_t>(n);
-    const size_t o_nvol = A.take<T>(n), o_owner = A.take<uint8_t>(L.nent);
+    const size_t o_nvol = A.take<T>(n), o_owner = A.take<uint8_t>(L.nent), o_tid = A.take<int>(m);
     // Lumped volume share per node (sum over its tets of V_e / 4, FP64 on the
     // host) and each node's first tile entry.
     std::vector<T> nvol(n, (T)0);
@@ -486,6 +491,7 @@ int add_topology(fem_batch *B, const double *X_in, int n, const int32_t *tets_in
     if (!rc) rc = up(o_X, X, 3 * (size_t)n * sizeof(double));
     if (!rc) rc = up(o_nvol, nvol.data(), (size_t)n * sizeof(T));
     if (!rc) rc = up(o_owner, owner.data(), (size_t)L.nent);
+    if (!rc) rc = up(o_tid, L.order.data(), (size_t)m * sizeof(int));
     // Rest volumes and boundary faces from the original connectivity.
     unsigned slots = 1;
     while (slots < 8u * (unsigned)m) slots <<= 1;
@@ -559,6 +565,7 @@ int add_topology(fem_batch *B, const double *X_in, int n, const int32_t *tets_in
     v.X = (const double *)(base + o_X);
     v.nvol = (const T *)(base + o_nvol);
     v.owner = (const uint8_t *)(base + o_owner);
+    v.tet_id = (const int *)(base + o_tid);
     B->topos.push_back(R);
     B->tables_dirty = true;
     *id = (int)B->topos.size() - 1;
@@ -903,7 +910,7 @@ void batch_release(fem_batch *B) {
             (void)hipEventDestroy(B->timer.ev[i][1]);
         }
     void *dev[] = {B->d_states, B->d_topos, B->d_bufs, B->d_work_tile, B->d_work_node, B->d_live, B->d_params,
-                   B->patch};
+                   B->patch, B->outbuf};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (B->h_states) (void)hipHostFree(B->h_states);
@@ -1120,6 +1127,54 @@ int contact_patch_impl(fem_batch *B, int slot, int32_t *ids, double *f, double *
 }
 
 bool job_ok(const fem_batch *B, int job) { return B && job >= 0 && job < B->capacity && B->insts[job].live; }
+
+int outbuf(fem_batch *B, size_t bytes) {
+    if (B->outbuf_bytes >= bytes) return FEM_OK;
+    if (B->outbuf) (void)hipFree(B->outbuf);
+    B->outbuf = nullptr;
+    B->outbuf_bytes = 0;
+    HIP_TRY(hipMalloc(&B->outbuf, bytes));
+    B->outbuf_bytes = bytes;
+    return FEM_OK;
+}
+
+// Per-tet Cauchy and von Mises stress of one instance at its current state.
+int tet_stress_impl(fem_batch *B, int slot, double *sigma, double *vm, int64_t capacity) {
+    const TopoRec &tp = B->topos[B->insts[slot].topo];
+    if (capacity < tp.m) return fail(FEM_E_BUFFER, "capacity below the tet count");
+    if (!sigma && !vm) return FEM_OK;
+    if (B->tables_dirty) TRY(B->precision == FEM_PREC_FP32 ? rebuild_tables<float>(B) : rebuild_tables<double>(B));
+    TRY(outbuf(B, 7 * (size_t)tp.m * sizeof(double)));
+    double *d_sig = (double *)B->outbuf, *d_vm = d_sig + 6 * (size_t)tp.m;
+    if (B->precision == FEM_PREC_FP32)
+        k_tet_stress<float><<<tp.ntile, kBlock, 0, B->stream>>>((const Topo<float> *)B->d_topos,
+                                                                (const InstBufs<float> *)B->d_bufs, slot, d_sig, d_vm);
+    else
+        k_tet_stress<double><<<tp.ntile, kBlock, 0, B->stream>>>((const Topo<double> *)B->d_topos,
+                                                                 (const InstBufs<double> *)B->d_bufs, slot, d_sig, d_vm);
+    TRY(launch_check("k_tet_stress"));
+    if (sigma) HIP_TRY(hipMemcpyAsync(sigma, d_sig, 6 * (size_t)tp.m * sizeof(double), hipMemcpyDeviceToHost, B->stream));
+    if (vm) HIP_TRY(hipMemcpyAsync(vm, d_vm, (size_t)tp.m * sizeof(double), hipMemcpyDeviceToHost, B->stream));
+    return sync(B);
+}
+
+int disp_stats_impl(fem_batch *B, int slot, double *max_norm, double *mean_norm) {
+    if (B->tables_dirty) TRY(B->precision == FEM_PREC_FP32 ? rebuild_tables<float>(B) : rebuild_tables<double>(B));
+    TRY(outbuf(B, 2 * sizeof(double)));
+    double *d = (double *)B->outbuf, h[2];
+    if (B->precision == FEM_PREC_FP32)
+        k_disp_stats<float><<<1, 1024, 0, B->stream>>>((const Topo<float> *)B->d_topos,
+                                                       (const InstBufs<float> *)B->d_bufs, slot, d);
+    else
+        k_disp_stats<double><<<1, 1024, 0, B->stream>>>((const Topo<double> *)B->d_topos,
+                                                        (const InstBufs<double> *)B->d_bufs, slot, d);
+    TRY(launch_check("k_disp_stats"));
+    HIP_TRY(hipMemcpyAsync(h, d, sizeof h, hipMemcpyDeviceToHost, B->stream));
+    TRY(sync(B));
+    if (max_norm) *max_norm = h[0];
+    if (mean_norm) *mean_norm = h[1];
+    return FEM_OK;
+}
 
 }  // namespace
 
@@ -1524,6 +1579,41 @@ int fem_batch_job_info(const fem_batch *B, int32_t job, fem_job_info *info) {
     J.g_norm = s.st_g;
     *info = J;
     return FEM_OK;
+}
+
+int fem_get_tet_stress(const fem_mesh *M, double *sigma, double *von_mises, int64_t capacity) {
+    g_last_error.clear();
+    if (!M) return fail(FEM_E_INVALID, "null mesh");
+    if (!M->have_material) return fail(FEM_E_STATE, "set the material first");
+    TRY(set_device(M->batch));
+    // the material of the handle, as the next step would use it
+    TRY(read_states(M->batch));
+    InstState &s = M->batch->h_states[0];
+    s.mu = M->E / (2.0 * (1.0 + M->nu));
+    s.lam = M->E * M->nu / ((1.0 + M->nu) * (1.0 - 2.0 * M->nu));
+    TRY(write_state(M->batch, 0));
+    return tet_stress_impl(M->batch, 0, sigma, von_mises, capacity);
+}
+
+int fem_get_displacement_stats(const fem_mesh *M, double *max_norm, double *mean_norm) {
+    g_last_error.clear();
+    if (!M) return fail(FEM_E_INVALID, "null mesh");
+    TRY(set_device(M->batch));
+    return disp_stats_impl(M->batch, 0, max_norm, mean_norm);
+}
+
+int fem_batch_get_tet_stress(fem_batch *B, int32_t job, double *sigma, double *von_mises, int64_t capacity) {
+    g_last_error.clear();
+    if (!job_ok(B, job)) return fail(FEM_E_INVALID, "unknown job");
+    TRY(set_device(B));
+    return tet_stress_impl(B, job, sigma, von_mises, capacity);
+}
+
+int fem_batch_get_displacement_stats(fem_batch *B, int32_t job, double *max_norm, double *mean_norm) {
+    g_last_error.clear();
+    if (!job_ok(B, job)) return fail(FEM_E_INVALID, "unknown job");
+    TRY(set_device(B));
+    return disp_stats_impl(B, job, max_norm, mean_norm);
 }
 
 int fem_batch_get_velocities(fem_batch *B, int32_t job, double *v, int64_t capacity) {

@@ -26,10 +26,11 @@ PRECISIONS = {"fp64": FEM_PREC_FP64, "fp32": FEM_PREC_FP32}
 # Entry points declared in include/fem.h.
 EXPORTS = ("fem_create_mesh", "fem_destroy_mesh", "fem_set_material", "fem_set_indenter", "fem_default_params",
            "fem_step", "fem_get_displacements", "fem_set_displacements", "fem_get_contact_patch",
-           "fem_get_mesh_info", "fem_set_dynamics", "fem_get_velocities", "fem_set_velocities", "fem_eval_gradient", "fem_eval_hessvec", "fem_set_kernel_timing",
+           "fem_get_mesh_info", "fem_get_tet_stress", "fem_get_displacement_stats", "fem_set_dynamics", "fem_get_velocities", "fem_set_velocities", "fem_eval_gradient", "fem_eval_hessvec", "fem_set_kernel_timing",
            "fem_get_kernel_timing", "fem_batch_create", "fem_batch_destroy", "fem_batch_add_mesh",
            "fem_batch_mesh_info", "fem_batch_add_job", "fem_batch_restart_job", "fem_batch_remove_job", "fem_batch_run", "fem_batch_job_info",
-           "fem_batch_get_displacements", "fem_batch_get_velocities", "fem_batch_get_contact_patch", "fem_batch_set_kernel_timing",
+           "fem_batch_get_displacements", "fem_batch_get_velocities", "fem_batch_get_tet_stress",
+           "fem_batch_get_displacement_stats", "fem_batch_get_contact_patch", "fem_batch_set_kernel_timing",
            "fem_batch_get_kernel_timing", "fem_batch_get_kernel_launches", "fem_set_graphs", "fem_batch_set_graphs", "fem_batch_set_option",
            "fem_batch_job_footprint", "fem_status_string",
            "fem_last_error")
@@ -109,6 +110,10 @@ def load(path: str = LIB_PATH):
     L.fem_get_displacements.argtypes = [vp, dp, C.c_int64]
     L.fem_set_displacements.argtypes = [vp, dp, C.c_int64]
     L.fem_set_dynamics.argtypes = [vp, C.c_double]
+    L.fem_get_tet_stress.argtypes = [vp, dp, dp, C.c_int64]
+    L.fem_get_displacement_stats.argtypes = [vp, dp, dp]
+    L.fem_batch_get_tet_stress.argtypes = [vp, C.c_int32, dp, dp, C.c_int64]
+    L.fem_batch_get_displacement_stats.argtypes = [vp, C.c_int32, dp, dp]
     L.fem_get_velocities.argtypes = [vp, dp, C.c_int64]
     L.fem_set_velocities.argtypes = [vp, dp, C.c_int64]
     L.fem_batch_get_velocities.argtypes = [vp, C.c_int32, dp, C.c_int64]
@@ -222,6 +227,32 @@ def fem_set_displacements(h, u):
     _check(load().fem_set_displacements(h, _dp(uu), uu.size))
 
 
+def fem_get_tet_stress(h, m: int):
+    sig = np.zeros((m, 6))
+    vm = np.zeros(m)
+    _check(load().fem_get_tet_stress(h, _dp(sig), _dp(vm), m))
+    return sig, vm
+
+
+def fem_get_displacement_stats(h):
+    mx, mean = C.c_double(), C.c_double()
+    _check(load().fem_get_displacement_stats(h, C.byref(mx), C.byref(mean)))
+    return mx.value, mean.value
+
+
+def fem_batch_get_tet_stress(h, job: int, m: int):
+    sig = np.zeros((m, 6))
+    vm = np.zeros(m)
+    _check(load().fem_batch_get_tet_stress(h, int(job), _dp(sig), _dp(vm), m))
+    return sig, vm
+
+
+def fem_batch_get_displacement_stats(h, job: int):
+    mx, mean = C.c_double(), C.c_double()
+    _check(load().fem_batch_get_displacement_stats(h, int(job), C.byref(mx), C.byref(mean)))
+    return mx.value, mean.value
+
+
 def fem_set_dynamics(h, dt: float):
     _check(load().fem_set_dynamics(h, float(dt)))
 
@@ -328,6 +359,12 @@ class FemMesh:
 
     def set_dynamics(self, dt):
         fem_set_dynamics(self.h, dt)
+
+    def tet_stress(self):
+        return fem_get_tet_stress(self.h, self.m)
+
+    def displacement_stats(self):
+        return fem_get_displacement_stats(self.h)
 
     def velocities(self):
         return fem_get_velocities(self.h, self.n)
@@ -499,6 +536,7 @@ class FemBatch:
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.h = fem_batch_create(max_jobs, self.precision, device, stream)
         self.mesh_nodes = {}
+        self.mesh_tets = {}
         self.job_mesh = {}
 
     def close(self):
@@ -518,6 +556,7 @@ class FemBatch:
     def add_mesh(self, X, tets, fixed):
         mid = fem_batch_add_mesh(self.h, X, tets, fixed)
         self.mesh_nodes[mid] = int(np.asarray(X).shape[0])
+        self.mesh_tets[mid] = int(np.asarray(tets).shape[0])
         return mid
 
     def mesh_info(self, mesh_id):
@@ -546,6 +585,12 @@ class FemBatch:
 
     def velocities(self, job):
         return fem_batch_get_velocities(self.h, job, self.mesh_nodes[self.job_mesh[job]])
+
+    def tet_stress(self, job):
+        return fem_batch_get_tet_stress(self.h, job, self.mesh_tets[self.job_mesh[job]])
+
+    def displacement_stats(self, job):
+        return fem_batch_get_displacement_stats(self.h, job)
 
     def contact_patch(self, job):
         return fem_batch_get_contact_patch(self.h, job)
