@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "oracle.c")
 
 SPHERE, CYLINDER, BOX, RING = 0, 1, 2, 3
+NEOHOOKEAN, COROTATIONAL = 0, 1
 OK, NOT_CONVERGED, INVERSION, NOT_SPD = 0, -6, -7, -9
 
 
@@ -45,7 +46,7 @@ class Problem(C.Structure):
                 ("fixed", C.POINTER(C.c_ubyte)), ("eligible", C.POINTER(C.c_ubyte)),
                 ("B", C.POINTER(C.c_double)), ("V", C.POINTER(C.c_double)),
                 ("mu", C.c_double), ("lam", C.c_double), ("ind", Indenter), ("dt", C.c_double),
-                ("mass", C.POINTER(C.c_double)), ("utilde", C.POINTER(C.c_double))]
+                ("mass", C.POINTER(C.c_double)), ("utilde", C.POINTER(C.c_double)), ("model", C.c_int)]
 
 
 class Params(C.Structure):
@@ -85,6 +86,11 @@ def lib():
         L.orc_surface_nodes.argtypes = [C.c_int, C.c_int, ip, up]
         L.orc_lumped_mass.argtypes = [C.c_int, C.c_int, ip, dp, C.c_double, dp]
         L.orc_lumped_mass.restype = None
+        L.orc_polar.argtypes = [dp, dp, dp]
+        L.orc_psi_cr.argtypes = [dp, C.c_double, C.c_double]
+        L.orc_psi_cr.restype = C.c_double
+        L.orc_pk1_cr.argtypes = [dp, C.c_double, C.c_double, dp]
+        L.orc_dpk1_cr.argtypes = [dp, dp, C.c_double, C.c_double, dp]
         L.orc_cauchy.argtypes = [dp, C.c_double, C.c_double, dp, dp]
         L.orc_cauchy.restype = None
         L.orc_tet_stress.argtypes = [C.POINTER(Problem), dp, dp, dp]
@@ -176,6 +182,28 @@ def surface_nodes(n, tets):
     return s, nb
 
 
+def polar(F):
+    R, S = np.zeros((3, 3)), np.zeros((3, 3))
+    rc = lib().orc_polar(_dp(_f64(F, (3, 3))), _dp(R), _dp(S))
+    return rc, R, S
+
+
+def psi_cr(F, mu, lam):
+    return lib().orc_psi_cr(_dp(_f64(F, (3, 3))), mu, lam)
+
+
+def pk1_cr(F, mu, lam):
+    P = np.zeros((3, 3))
+    lib().orc_pk1_cr(_dp(_f64(F, (3, 3))), mu, lam, _dp(P))
+    return P
+
+
+def dpk1_cr(F, dF, mu, lam):
+    dP = np.zeros((3, 3))
+    lib().orc_dpk1_cr(_dp(_f64(F, (3, 3))), _dp(_f64(dF, (3, 3))), mu, lam, _dp(dP))
+    return dP
+
+
 def cauchy(F, mu, lam):
     """(sigma as xx yy zz xy xz yz, von Mises) of one deformation gradient."""
     s = np.zeros(6)
@@ -236,6 +264,10 @@ class Solver:
         self.dt = 0.0
         self.mass = None
         self.utilde = np.zeros((self.n, 3))
+
+    def set_model(self, model):
+        """Constitutive law: NEOHOOKEAN (default) or COROTATIONAL."""
+        self.p.model = int(model)
 
     def set_dynamics(self, dt, rho):
         """Backward-Euler time stepping with lumped masses (dt = 0: quasi-static)."""

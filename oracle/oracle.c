@@ -120,12 +120,124 @@ void orc_dpk1(const double F[9], const double dF[9], double mu, double lam, doub
         dP[i] = mu * dF[i] + (mu - lam * lnJ) * t2[i] + lam * tr * FiT[i];
 }
 
-/* 9x9 tangent A[(i,j),(k,l)] = dP_ij / dF_kl, column by column from dP. */
-static void dpdf(const double F[9], double mu, double lam, double A[81]) {
+/* ------------------------------------------------------------------------ */
+/* Co-rotational linear elasticity (the constitutive model of the paper's    */
+/* own simulator, Sec. III-A): with the polar decomposition F = R S,          */
+/*   Psi = mu |F - R|^2 + lam/2 (tr S - 3)^2,                                 */
+/*   P = 2 mu (F - R) + lam (tr S - 3) R.                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Eigen-decomposition of a symmetric 3x3 matrix by cyclic Jacobi rotations:
+ * A = V diag(w) V^T, V's columns the eigenvectors. */
+static void sym_eig3(const double A[9], double w[3], double V[9]) {
+    double a[9];
+    memcpy(a, A, sizeof a);
+    for (int i = 0; i < 9; i++) V[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 60; sweep++) {
+        double off = a[1] * a[1] + a[2] * a[2] + a[5] * a[5];
+        double dia = a[0] * a[0] + a[4] * a[4] + a[8] * a[8];
+        if (off <= 1e-34 * dia) break;
+        static const int PQ[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+        for (int r = 0; r < 3; r++) {
+            int p = PQ[r][0], q = PQ[r][1];
+            double apq = a[3 * p + q];
+            if (apq == 0.0) continue;
+            double theta = (a[3 * q + q] - a[3 * p + p]) / (2.0 * apq);
+            double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+            /* a <- J^T a J with J the rotation in the (p, q) plane */
+            for (int k = 0; k < 3; k++) {
+                double akp = a[3 * k + p], akq = a[3 * k + q];
+                a[3 * k + p] = c * akp - sn * akq;
+                a[3 * k + q] = sn * akp + c * akq;
+            }
+            for (int k = 0; k < 3; k++) {
+                double apk = a[3 * p + k], aqk = a[3 * q + k];
+                a[3 * p + k] = c * apk - sn * aqk;
+                a[3 * q + k] = sn * apk + c * aqk;
+            }
+            for (int k = 0; k < 3; k++) {
+                double vkp = V[3 * k + p], vkq = V[3 * k + q];
+                V[3 * k + p] = c * vkp - sn * vkq;
+                V[3 * k + q] = sn * vkp + c * vkq;
+            }
+        }
+    }
+    w[0] = a[0];
+    w[1] = a[4];
+    w[2] = a[8];
+}
+
+int orc_polar(const double F[9], double R[9], double S[9]) {
+    double C[9], w[3], V[9], Si[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) C[3 * i + j] = F[i] * F[j] + F[3 + i] * F[3 + j] + F[6 + i] * F[6 + j];
+    sym_eig3(C, w, V);
+    if (!(w[0] > 0.0 && w[1] > 0.0 && w[2] > 0.0)) return -1;
+    double sq[3] = {sqrt(w[0]), sqrt(w[1]), sqrt(w[2])};
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double s = 0.0, si = 0.0;
+            for (int k = 0; k < 3; k++) {
+                s += V[3 * i + k] * sq[k] * V[3 * j + k];
+                si += V[3 * i + k] / sq[k] * V[3 * j + k];
+            }
+            S[3 * i + j] = s;
+            Si[3 * i + j] = si;
+        }
+    matmul3(F, Si, R);
+    return det3(F) > 0.0 ? 0 : -1;
+}
+
+double orc_psi_cr(const double F[9], double mu, double lam) {
+    double R[9], S[9];
+    if (orc_polar(F, R, S) != 0) return INFINITY;
+    double d2 = 0.0;
+    for (int i = 0; i < 9; i++) d2 += (F[i] - R[i]) * (F[i] - R[i]);
+    double e = S[0] + S[4] + S[8] - 3.0;
+    return mu * d2 + 0.5 * lam * e * e;
+}
+
+void orc_pk1_cr(const double F[9], double mu, double lam, double P[9]) {
+    double R[9], S[9];
+    orc_polar(F, R, S);
+    double e = S[0] + S[4] + S[8] - 3.0;
+    for (int i = 0; i < 9; i++) P[i] = 2.0 * mu * (F[i] - R[i]) + lam * e * R[i];
+}
+
+/* dR = R W with W = [w]x skew: symmetry of d(R^T F) gives
+ * (tr S I - S) w = axial(R^T dF - dF^T R), axial(K) = (K_21, K_02, K_10). */
+void orc_dpk1_cr(const double F[9], const double dF[9], double mu, double lam, double dP[9]) {
+    double R[9], S[9], RT[9], M[9], K[9], Ki[9], dR[9];
+    orc_polar(F, R, S);
+    transpose3(R, RT);
+    matmul3(RT, dF, M);
+    double a[3] = {M[7] - M[5], M[2] - M[6], M[3] - M[1]};
+    double trS = S[0] + S[4] + S[8];
+    for (int i = 0; i < 9; i++) K[i] = -S[i];
+    K[0] += trS;
+    K[4] += trS;
+    K[8] += trS;
+    inv3(K, Ki);
+    double w[3];
+    for (int i = 0; i < 3; i++) w[i] = Ki[3 * i] * a[0] + Ki[3 * i + 1] * a[1] + Ki[3 * i + 2] * a[2];
+    double W[9] = {0.0, -w[2], w[1], w[2], 0.0, -w[0], -w[1], w[0], 0.0};
+    matmul3(R, W, dR);
+    double trM = M[0] + M[4] + M[8];
+    for (int i = 0; i < 9; i++)
+        dP[i] = 2.0 * mu * (dF[i] - dR[i]) + lam * trM * R[i] + lam * (trS - 3.0) * dR[i];
+}
+
+/* 9x9 tangent A[(i,j),(k,l)] = dP_ij / dF_kl, column by column from dP, for
+ * the problem's law. */
+static void dpdf_law(int model, const double F[9], double mu, double lam, double A[81]) {
     for (int kl = 0; kl < 9; kl++) {
         double dF[9] = {0}, dP[9];
         dF[kl] = 1.0;
-        orc_dpk1(F, dF, mu, lam, dP);
+        if (model == ORC_COROTATIONAL)
+            orc_dpk1_cr(F, dF, mu, lam, dP);
+        else
+            orc_dpk1(F, dF, mu, lam, dP);
         for (int ij = 0; ij < 9; ij++) A[ij * 9 + kl] = dP[ij];
     }
 }
@@ -360,6 +472,17 @@ static double energy_terms(const orc_problem *p, const double *u, double *mag, d
         }
         double I1 = 0.0;
         for (int i = 0; i < 9; i++) I1 += F[i] * F[i];
+        if (p->model == ORC_COROTATIONAL) {
+            double R[9], S[9];
+            orc_polar(F, R, S);
+            double d2 = 0.0;
+            for (int i = 0; i < 9; i++) d2 += (F[i] - R[i]) * (F[i] - R[i]);
+            double trS = S[0] + S[4] + S[8];
+            E += p->V[e] * (p->mu * d2 + 0.5 * p->lam * (trS - 3.0) * (trS - 3.0));
+            /* rounding scale: the operands of F - R and tr S - 3 */
+            M += p->V[e] * (p->mu * (I1 + 3.0) + 0.5 * p->lam * (trS + 3.0) * (trS + 3.0));
+            continue;
+        }
         double lnJ = log(J);
         double t1 = 0.5 * p->mu * (I1 - 3.0), t2 = -p->mu * lnJ, t3 = 0.5 * p->lam * lnJ * lnJ;
         E += p->V[e] * (t1 + t2 + t3);
@@ -405,7 +528,10 @@ void orc_gradient(const orc_problem *p, const double *u, double *g) {
     for (int e = 0; e < p->m; e++) {
         double F[9], P[9], b[4][3];
         orc_deformation_gradient(p, u, e, F);
-        orc_pk1(F, p->mu, p->lam, P);
+        if (p->model == ORC_COROTATIONAL)
+            orc_pk1_cr(F, p->mu, p->lam, P);
+        else
+            orc_pk1(F, p->mu, p->lam, P);
         shape_grads(p->B + 9 * e, b);
         const int *t = p->T + 4 * e;
         /* dE/dx_a = V P b_a */
@@ -434,7 +560,7 @@ void orc_gradient(const orc_problem *p, const double *u, double *g) {
 static void element_hessian(const orc_problem *p, const double *u, int e, double K[144]) {
     double F[9], A[81], b[4][3];
     orc_deformation_gradient(p, u, e, F);
-    dpdf(F, p->mu, p->lam, A);
+    dpdf_law(p->model, F, p->mu, p->lam, A);
     shape_grads(p->B + 9 * e, b);
     for (int a = 0; a < 4; a++)
         for (int i = 0; i < 3; i++)
@@ -830,9 +956,8 @@ int orc_contact_patch(const orc_problem *p, const double *u, int *ids, double *f
 /* ------------------------------------------------------------------------ */
 /* Outputs for data generation: per-tet Cauchy stress and von Mises stress,
  * and the displacement-norm statistics the paper reports per indentation. */
-void orc_cauchy(const double F[9], double mu, double lam, double sigma[6], double *vm) {
-    double P[9], S[9];
-    orc_pk1(F, mu, lam, P);
+static void cauchy_from_pk1(const double F[9], const double P[9], double sigma[6], double *vm) {
+    double S[9];
     double J = det3(F);
     /* sigma = P F^T / J */
     for (int i = 0; i < 3; i++)
@@ -853,11 +978,23 @@ void orc_cauchy(const double F[9], double mu, double lam, double sigma[6], doubl
     }
 }
 
+void orc_cauchy(const double F[9], double mu, double lam, double sigma[6], double *vm) {
+    double P[9];
+    orc_pk1(F, mu, lam, P);
+    cauchy_from_pk1(F, P, sigma, vm);
+}
+
 void orc_tet_stress(const orc_problem *p, const double *u, double *sigma, double *vm) {
     for (int e = 0; e < p->m; e++) {
         double F[9], s[6], v;
         orc_deformation_gradient(p, u, e, F);
-        orc_cauchy(F, p->mu, p->lam, s, &v);
+        if (p->model == ORC_COROTATIONAL) {
+            double P[9];
+            orc_pk1_cr(F, p->mu, p->lam, P);
+            cauchy_from_pk1(F, P, s, &v);
+        } else {
+            orc_cauchy(F, p->mu, p->lam, s, &v);
+        }
         if (sigma)
             for (int c = 0; c < 6; c++) sigma[6 * (size_t)e + c] = s[c];
         if (vm) vm[e] = v;

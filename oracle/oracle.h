@@ -32,6 +32,10 @@ extern "C" {
 
 enum { ORC_SPHERE = 0, ORC_CYLINDER = 1, ORC_BOX = 2, ORC_RING = 3 };
 
+/* Constitutive law: compressible Neo-Hookean (the paper's validated skin
+ * model) or co-rotational linear elasticity (its simulator's model). */
+enum { ORC_NEOHOOKEAN = 0, ORC_COROTATIONAL = 1 };
+
 enum {
     ORC_OK = 0,
     ORC_NOT_CONVERGED = -6,
@@ -62,6 +66,7 @@ typedef struct {
     double dt;                    /* time step (s); 0 = quasi-static */
     const double *mass;           /* n lumped nodal masses (kg), or NULL */
     const double *utilde;         /* n x 3 inertial predictor u^n + dt v^n, or NULL */
+    int model;                    /* ORC_NEOHOOKEAN or ORC_COROTATIONAL */
 } orc_problem;
 
 typedef struct {
@@ -96,6 +101,15 @@ void orc_lame(double E, double nu, double *mu, double *lam);
 double orc_psi(const double F[9], double mu, double lam);
 void orc_pk1(const double F[9], double mu, double lam, double P[9]);
 void orc_dpk1(const double F[9], const double dF[9], double mu, double lam, double dP[9]);
+
+/* Co-rotational law: polar decomposition F = R S (R proper rotation, S
+ * symmetric positive definite; returns 0, or -1 when det F <= 0), energy
+ * Psi = mu |F - R|^2 + lam/2 (tr S - 3)^2, P = 2 mu (F - R) + lam (tr S - 3) R
+ * and its exact directional derivative (with dR). */
+int orc_polar(const double F[9], double R[9], double S[9]);
+double orc_psi_cr(const double F[9], double mu, double lam);
+void orc_pk1_cr(const double F[9], double mu, double lam, double P[9]);
+void orc_dpk1_cr(const double F[9], const double dF[9], double mu, double lam, double dP[9]);
 
 /* Signed distance of world point x to the indenter and its world gradient. */
 double orc_sdf(const orc_indenter *ind, const double x[3], double grad[3]);
