@@ -40,6 +40,18 @@ METRIC = "FEM indentation solves/s + tet-updates/s, FP32 vs FP64 path; p50/p99 l
 #   element: G (54), J - 1 (30), ln J (1), energy and magnitude (36),
 #   F^-T (40), P (82), nodal forces (60), node diagonal blocks (161) -> 464
 FLOPS_PER_TET = {"hv": 417, "element": 464}
+# The co-rotational law (same counting): both passes share G, J - 1, dG or
+# the node blocks, nodal forces and p.q with the Neo-Hookean ones (223 for
+# the Hessian-vector pass, 305 for the element pass). Per tet the law adds
+# the polar rotation, 3 + 83 per Newton iteration, and E = (C - I)(S + I)^-1
+# (243); then the Hessian-vector pass R^T dG, the rotation rate w and dP
+# (184), the element pass tr E, |E|^2, the energy and P = R (2 mu E +
+# lam tr E I) (81). The iteration count is data-dependent: 2.2 per tet on
+# average over the co-rotational fingertip states at 20-100 % of the
+# indentation depth, which gives 836 and 815.
+POLAR_ITERS = 2.2
+FLOPS_PER_TET_CR = {"hv": round(223 + 3 + 83 * POLAR_ITERS + 243 + 184),
+                    "element": round(305 + 3 + 83 * POLAR_ITERS + 243 + 81)}
 FP32_VECTOR_PEAK_TFLOPS = 157.3      # 256 CU x 64 lanes x 2 x 2.4 GHz x 2 (packed FP32)
 FP32_NONPACKED_PEAK_TFLOPS = 78.6    # the same without packed FP32, which this build does not emit
 
@@ -70,17 +82,18 @@ def progress(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_batched(mesh, inds, precision, timed_steps, warm_steps, timing_every=0, track_latency=True):
+def run_batched(mesh, inds, precision, timed_steps, warm_steps, timing_every=0, track_latency=True,
+                material=(0.3e6, 0.45)):
     from paper_2103_16747_amd import fem
 
     batch = fem.FemBatch(len(inds), precision)
     mid = batch.add_mesh(mesh.X, mesh.tets, mesh.fixed)
     info = batch.mesh_info(mid)
-    jobs = [batch.add_job(mid, ind) for ind in inds]
+    jobs = [batch.add_job(mid, ind, *material) for ind in inds]
     P = batch.default_params()
     for _ in range(warm_steps):
         for j, ind in zip(jobs, inds):
-            batch.restart_job(j, ind)
+            batch.restart_job(j, ind, *material)
         batch.run(P)
         progress(f"warm-up batch {precision} done")
     if timing_every:
@@ -88,7 +101,7 @@ def run_batched(mesh, inds, precision, timed_steps, warm_steps, timing_every=0, 
     walls, lat, tu, failed, floor, hv, gp = [], [], 0, 0, 0, 0, 0
     for _ in range(timed_steps):
         for j, ind in zip(jobs, inds):
-            batch.restart_job(j, ind)
+            batch.restart_job(j, ind, *material)
         t0 = time.perf_counter()
         done_at = {}
         running = len(jobs)
@@ -194,7 +207,7 @@ def measured_traffic():
     return t["traffic_bytes_per_dispatch"]
 
 
-def roofline(r, word):
+def roofline(r, word, flops_per_tet=FLOPS_PER_TET, kname=None):
     """Roofline of the tile kernel (the dominant one) over the timed region:
     algorithmic flops per launch (the passes the jobs made, times the tets per
     pass and FLOPS_PER_TET, over the number of launches) divided by the mean
@@ -212,12 +225,13 @@ def roofline(r, word):
     if not t["sampled"]:
         return None, None
     m = r["layout"]["n_tets"]
-    flops = m * (r["hv_passes"] * FLOPS_PER_TET["hv"] + r["grad_passes"] * FLOPS_PER_TET["element"])
+    flops = m * (r["hv_passes"] * flops_per_tet["hv"] + r["grad_passes"] * flops_per_tet["element"])
     per_launch = flops / t["launches"]
     avg_s = t["avg_us"] * 1e-6
     achieved = per_launch / avg_s / 1e12
     byts = tile_bytes(r["layout"], word, r["hv_passes"], r["grad_passes"], t["launches"])
-    kname = "k_tile<float>" if word == 4 else "k_tile<double>"
+    if kname is None:
+        kname = "k_tile<float, LAW_NH>" if word == 4 else "k_tile<double, LAW_NH>"
     return ({"bound": "alu", "kernel": kname, "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
              "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(),
              "frac_of_non_packed_peak": achieved / FP32_NONPACKED_PEAK_TFLOPS,
@@ -403,6 +417,48 @@ def bench_dynamic(args):
             "e_inf_vs_fp64_oracle_first_steps": errs}
 
 
+def bench_corotational(args):
+    """The batched workload under the co-rotational law of the paper's own
+    simulator (E = 1.55 MPa, nu = 0.316, Sec. III-A): 256 jobs on the 50k
+    fingertip, FP32 path, with the roofline of k_tile<float, LAW_CR>. The
+    indentation depths are halved (up to 1.5 mm): the co-rotational law has
+    no barrier against inversion, and boxes and rings pressed through most
+    of the 3 mm skin invert elements (the oracle fails the same load
+    steps)."""
+    from paper_2103_16747_amd import workload as W
+
+    mesh = W.fingertip_mesh(50000)
+    inds = []
+    for i in range(args.jobs):
+        ind = W.seat_on_mesh(W.random_indentation(3000 + i), mesh)
+        ind.model = 1
+        ind.depth *= 0.5
+        inds.append(ind)
+    r = run_batched(mesh, inds, "fp32", args.steps, args.warmup, args.timing_every, material=(1.55e6, 0.316))
+    K, J = args.steps, args.jobs
+    wall = sum(r["walls"])
+    lat_ms = np.array(r["lat"]) * 1e3
+    out = {"metric": METRIC, "value": K * J / wall, "unit": "solves/s", "n_gpus": 1, "steps": K,
+           "warmup": args.warmup, "ms_per_step": wall / K * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"co-rotational batched indentation: {J} jobs on the synthetic 50k-tet fingertip, "
+                                  "E = 1.55 MPa, nu = 0.316, seeded indenters at half depth (up to 1.5 mm), "
+                                  "100 quasi-static load steps each",
+                      "jobs_per_step": J, "mesh_tets": mesh.m},
+           "tet_updates_per_s": r["tet_updates"] / wall,
+           "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+           "failed_load_steps": r["failed_steps"], "floor_load_steps": r["floor_steps"],
+           "cg_iters_per_job": float(np.mean([s["cg_iters"] for s in r["stats"]])),
+           "newton_iters_per_job": float(np.mean([s["newton_iters"] for s in r["stats"]])),
+           "flops_per_tet": FLOPS_PER_TET_CR, "polar_iterations_assumed": POLAR_ITERS}
+    rl, kav = roofline(r, 4, FLOPS_PER_TET_CR, "k_tile<float, LAW_CR>")
+    if rl:
+        rl["traffic"] = None
+        out["roofline"] = rl
+        out["kernel_avg_us"] = kav
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -415,10 +471,12 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--timing-every", type=int, default=8)
-    ap.add_argument("--config", choices=("batched", "uneven", "serving", "dynamic"), default="batched",
+    ap.add_argument("--config", choices=("batched", "uneven", "serving", "dynamic", "corotational"),
+                    default="batched",
                     help="batched: 256 jobs on the 50k fingertip (default); uneven: 64 jobs at 5k-120k tets with "
                          "autotuned shapes; serving: Poisson request streams through the serving loop; dynamic: "
-                         "the batched workload as implicit time steps of 1e-4 s")
+                         "the batched workload as implicit time steps of 1e-4 s; corotational: the batched workload under the "
+                         "co-rotational law")
     ap.add_argument("--rates", default="10,50,200,500", help="serving: arrival rates (req/s)")
     ap.add_argument("--requests", type=int, default=160, help="serving: requests per rate")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -449,6 +507,9 @@ def main():
         return
     if args.config == "dynamic":
         print(json.dumps(bench_dynamic(args)), flush=True)
+        return
+    if args.config == "corotational":
+        print(json.dumps(bench_corotational(args)), flush=True)
         return
     mesh = W.fingertip_mesh(50000)
     inds = [W.seat_on_mesh(W.random_indentation(3000 + i), mesh) for i in range(args.jobs)]

@@ -62,6 +62,15 @@ extern "C" {
 #define FEM_BOX 2                 /* shape = {hx, hy, hz} half extents */
 #define FEM_RING 3                /* shape = {major radius, minor radius}; torus about local z */
 
+/* Constitutive laws (paper Sec. III-A): the compressible Neo-Hookean law of
+ * the validated skin model, Psi = mu/2 (tr F^T F - 3) - mu ln J + lam/2 ln^2 J,
+ * and the co-rotational linear elasticity of the paper's own simulator,
+ * Psi = mu |F - R|^2 + lam/2 (tr S - 3)^2 with the polar decomposition
+ * F = R S (Newton's method uses its exact tangent, rotation derivative
+ * included). mu and lam follow from (E, nu) for both. */
+#define FEM_MODEL_NEOHOOKEAN 0
+#define FEM_MODEL_COROTATIONAL 1
+
 #define FEM_PRECOND_JACOBI 0      /* scalar Jacobi */
 #define FEM_PRECOND_BLOCK 1       /* 3x3 node-block Jacobi */
 
@@ -140,6 +149,10 @@ int fem_set_material(fem_mesh *mesh, double E, double nu, double density);
  * R not a rotation, non-finite values). */
 int fem_set_indenter(fem_mesh *mesh, int32_t kind, const double *shape, int32_t n_shape, const double R[9],
                      const double c[3], double k_penalty);
+
+/* Selects the constitutive law for the following steps (default
+ * FEM_MODEL_NEOHOOKEAN). Errors: FEM_E_INVALID (unknown model). */
+int fem_set_model(fem_mesh *mesh, int32_t model);
 
 /* Fills the default solve parameters for a precision mode. */
 void fem_default_params(fem_solve_params *params, int32_t precision);
@@ -263,6 +276,7 @@ typedef struct {
     double dt;           /* > 0: each step is a backward-Euler time step of
                             this length (see fem_set_dynamics); 0: quasi-static */
     double density;      /* kg/m^3, for the lumped masses when dt > 0 */
+    int32_t model;       /* FEM_MODEL_NEOHOOKEAN or FEM_MODEL_COROTATIONAL */
 } fem_indentation;
 
 typedef struct {

@@ -82,6 +82,7 @@ struct InstState {
     double mdt2;                              // rho / dt^2 (0: quasi-static)
     double gbest;                             // smallest |g_free| of the load step so far
     int stall, steps_floor;                   // accepted iterations without halving gbest
+    int model, pad3;                          // constitutive law (LAW_NH, LAW_CR)
     double c0[3], dir[3];
     Indenter ind;
     // current load step
@@ -384,6 +385,210 @@ __device__ __forceinline__ void inverse_transpose(const T G[9], T J, T FiT[9]) {
     FiT[8] = (F[0] * F[4] - F[1] * F[3]) * iJ;
 }
 
+// ---------------------------------------------------------------------------
+// Constitutive laws, per tet from G = F - I (J - 1 and J given).
+//   element(): energy density (sum and rounding magnitude of its terms), the
+//     first Piola-Kirchhoff stress P, and the node diagonal block of the
+//     element's Hessian (or its fixed-rotation part) in the form
+//     V (alpha |b|^2 I + beta c c^T), c = Mb b.
+//   hessvec(): dP for the perturbation dG.
+// LAW_NH, compressible Neo-Hookean: Psi = mu/2 (tr F^T F - 3) - mu ln J +
+//   lam/2 ln^2 J. LAW_CR, co-rotational linear elasticity (F = R S):
+//   Psi = mu |F - R|^2 + lam/2 (tr S - 3)^2, P = 2 mu (F - R) + lam (tr S - 3) R.
+// ---------------------------------------------------------------------------
+enum : int { LAW_NH = 0, LAW_CR = 1 };
+
+template <typename T, int LAW> struct Law;
+
+template <typename T> struct Law<T, LAW_NH> {
+    __device__ static __forceinline__ void element(const T G[9], T Jm1, T J, T mu, T lam, T &psi, T &mag, T P[9],
+                                                   T Mb[9], T &alpha, T &beta) {
+        const T lnJ = log1p_t(Jm1);
+        const T trG = G[0] + G[4] + G[8];
+        T G2 = (T)0;
+#pragma unroll
+        for (int c = 0; c < 9; c++) G2 += G[c] * G[c];
+        const T t1 = (T)0.5 * mu * ((T)2 * trG + G2), t2 = -mu * lnJ, t3 = (T)0.5 * lam * lnJ * lnJ;
+        psi = t1 + t2 + t3;
+        mag = abs_t(t1) + abs_t(t2) + abs_t(t3);
+        inverse_transpose(G, J, Mb);
+        // P = mu (F - F^-T) + lam ln J F^-T with F - F^-T = G + F^-T G^T, which
+        // keeps full relative precision at small strain.
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                const T FG = Mb[3 * i] * G[3 * j] + Mb[3 * i + 1] * G[3 * j + 1] + Mb[3 * i + 2] * G[3 * j + 2];
+                P[3 * i + j] = mu * (G[3 * i + j] + FG) + lam * lnJ * Mb[3 * i + j];
+            }
+        alpha = mu;
+        beta = mu + lam - lam * lnJ;
+    }
+
+    // dP = mu dG + (mu - lam ln J) (F^-1 dG F^-1)^T + lam tr(F^-1 dG) F^-T
+    __device__ static __forceinline__ void hessvec(const T G[9], T Jm1, T J, const T dG[9], T mu, T lam, T dP[9]) {
+        const T cc = mu - lam * fast_log1p(Jm1);
+        T FiT[9];
+        inverse_transpose<T, true>(G, J, FiT);
+        // A = F^-1 dG (F^-1 = FiT^T)
+        T A[9];
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) A[3 * i + j] = FiT[i] * dG[j] + FiT[3 + i] * dG[3 + j] + FiT[6 + i] * dG[6 + j];
+        const T tr = A[0] + A[4] + A[8];
+        // (A F^-1)^T_ij = sum_k A_jk FiT_ik
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                const T Mt = A[3 * j] * FiT[3 * i] + A[3 * j + 1] * FiT[3 * i + 1] + A[3 * j + 2] * FiT[3 * i + 2];
+                dP[3 * i + j] = mu * dG[3 * i + j] + cc * Mt + lam * tr * FiT[3 * i + j];
+            }
+    }
+};
+
+// Rotation factor of F = I + G (det F > 0) by Newton's iteration for the
+// polar decomposition with determinant scaling, X <- (g X + X^-T / g) / 2,
+// g = |det X|^(-1/3), to convergence at the working precision.
+template <typename T>
+__device__ __forceinline__ void polar_rotation(const T G[9], T R[9]) {
+#pragma unroll
+    for (int c = 0; c < 9; c++) R[c] = G[c];
+    R[0] += (T)1;
+    R[4] += (T)1;
+    R[8] += (T)1;
+    const T tol = sizeof(T) == 4 ? (T)8e-7 : (T)4e-15;
+    for (int it = 0; it < 12; it++) {
+        T C[9];   // cofactors: X^-T = C / det
+        C[0] = R[4] * R[8] - R[5] * R[7];
+        C[1] = R[5] * R[6] - R[3] * R[8];
+        C[2] = R[3] * R[7] - R[4] * R[6];
+        C[3] = R[2] * R[7] - R[1] * R[8];
+        C[4] = R[0] * R[8] - R[2] * R[6];
+        C[5] = R[1] * R[6] - R[0] * R[7];
+        C[6] = R[1] * R[5] - R[2] * R[4];
+        C[7] = R[2] * R[3] - R[0] * R[5];
+        C[8] = R[0] * R[4] - R[1] * R[3];
+        const T det = R[0] * C[0] + R[1] * C[1] + R[2] * C[2];
+        const float g = exp2f(-log2f((float)abs_t(det)) * (1.0f / 3.0f));
+        const T a = (T)0.5 * (T)g, b = (T)0.5 / ((T)g * det);
+        T diff = (T)0;
+#pragma unroll
+        for (int c = 0; c < 9; c++) {
+            const T x = a * R[c] + b * C[c];
+            diff = fmax(diff, abs_t(x - R[c]));
+            R[c] = x;
+        }
+        if (diff <= tol) break;
+    }
+}
+
+template <typename T> struct Law<T, LAW_CR> {
+    // R, and E = S - I formed without cancellation as (C - I)(S + I)^-1 with
+    // C - I = G + G^T + G^T G (C = F^T F, S = R^T F, S + I near 2 I).
+    __device__ static __forceinline__ void rotation_strain(const T G[9], T R[9], T E[9]) {
+        polar_rotation(G, R);
+        T S[9], E2[9];
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                // S = R^T (I + G)
+                S[3 * i + j] = R[3 * 0 + i] * G[3 * 0 + j] + R[3 * 1 + i] * G[3 * 1 + j] + R[3 * 2 + i] * G[3 * 2 + j] +
+                               R[3 * j + i];
+                E2[3 * i + j] = G[3 * i + j] + G[3 * j + i] +
+                                (G[3 * 0 + i] * G[3 * 0 + j] + G[3 * 1 + i] * G[3 * 1 + j] + G[3 * 2 + i] * G[3 * 2 + j]);
+            }
+        // (S + I)^-1, S symmetrised
+        T A[9];
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) A[3 * i + j] = (T)0.5 * (S[3 * i + j] + S[3 * j + i]) + (i == j ? (T)1 : (T)0);
+        T Ai[9];
+        Ai[0] = A[4] * A[8] - A[5] * A[7];
+        Ai[1] = A[2] * A[7] - A[1] * A[8];
+        Ai[2] = A[1] * A[5] - A[2] * A[4];
+        Ai[3] = A[5] * A[6] - A[3] * A[8];
+        Ai[4] = A[0] * A[8] - A[2] * A[6];
+        Ai[5] = A[2] * A[3] - A[0] * A[5];
+        Ai[6] = A[3] * A[7] - A[4] * A[6];
+        Ai[7] = A[1] * A[6] - A[0] * A[7];
+        Ai[8] = A[0] * A[4] - A[1] * A[3];
+        const T id = (T)1 / (A[0] * Ai[0] + A[1] * Ai[3] + A[2] * Ai[6]);
+        T Q[9];
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++)
+                Q[3 * i + j] = (E2[3 * i] * Ai[j] + E2[3 * i + 1] * Ai[3 + j] + E2[3 * i + 2] * Ai[6 + j]) * id;
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) E[3 * i + j] = (T)0.5 * (Q[3 * i + j] + Q[3 * j + i]);
+    }
+
+    __device__ static __forceinline__ void element(const T G[9], T Jm1, T J, T mu, T lam, T &psi, T &mag, T P[9],
+                                                   T Mb[9], T &alpha, T &beta) {
+        T E[9];
+        rotation_strain(G, Mb, E);
+        const T trE = E[0] + E[4] + E[8];
+        T E2 = (T)0;
+#pragma unroll
+        for (int c = 0; c < 9; c++) E2 += E[c] * E[c];
+        psi = mu * E2 + (T)0.5 * lam * trE * trE;   // |F - R| = |R (S - I)| = |E|
+        mag = psi;
+        // P = R (2 mu E + lam tr E I)
+        T X[9];
+#pragma unroll
+        for (int c = 0; c < 9; c++) X[c] = (T)2 * mu * E[c];
+        X[0] += lam * trE;
+        X[4] += lam * trE;
+        X[8] += lam * trE;
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++)
+                P[3 * i + j] = Mb[3 * i] * X[j] + Mb[3 * i + 1] * X[3 + j] + Mb[3 * i + 2] * X[6 + j];
+        alpha = (T)2 * mu;
+        beta = lam;
+    }
+
+    // dP = 2 mu (dG - dR) + lam tr(R^T dG) R + lam tr E dR, dR = R [w]x with
+    // (tr S I - S) w = axial(R^T dG - dG^T R).
+    __device__ static __forceinline__ void hessvec(const T G[9], T Jm1, T J, const T dG[9], T mu, T lam, T dP[9]) {
+        T R[9], E[9];
+        rotation_strain(G, R, E);
+        T M[9];   // R^T dG
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) M[3 * i + j] = R[i] * dG[j] + R[3 + i] * dG[3 + j] + R[6 + i] * dG[6 + j];
+        const T ax[3] = {M[7] - M[5], M[2] - M[6], M[3] - M[1]};
+        const T trE = E[0] + E[4] + E[8];
+        // K = tr S I - S = (2 + tr E) I - E (symmetric)
+        const T k00 = (T)2 + trE - E[0], k11 = (T)2 + trE - E[4], k22 = (T)2 + trE - E[8];
+        const T k01 = -E[1], k02 = -E[2], k12 = -E[5];
+        const T c00 = k11 * k22 - k12 * k12, c01 = k02 * k12 - k01 * k22, c02 = k01 * k12 - k02 * k11;
+        const T c11 = k00 * k22 - k02 * k02, c12 = k01 * k02 - k00 * k12, c22 = k00 * k11 - k01 * k01;
+        const T kid = (T)1 / (k00 * c00 + k01 * c01 + k02 * c02);
+        const T w0 = (c00 * ax[0] + c01 * ax[1] + c02 * ax[2]) * kid;
+        const T w1 = (c01 * ax[0] + c11 * ax[1] + c12 * ax[2]) * kid;
+        const T w2 = (c02 * ax[0] + c12 * ax[1] + c22 * ax[2]) * kid;
+        const T trM = M[0] + M[4] + M[8];
+        // dR = R W, W = [[0, -w2, w1], [w2, 0, -w0], [-w1, w0, 0]]
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            const T r0 = R[3 * i], r1 = R[3 * i + 1], r2 = R[3 * i + 2];
+            const T dR0 = r1 * w2 - r2 * w1, dR1 = r2 * w0 - r0 * w2, dR2 = r0 * w1 - r1 * w0;
+            dP[3 * i + 0] = (T)2 * mu * (dG[3 * i + 0] - dR0) + lam * trM * r0 + lam * trE * dR0;
+            dP[3 * i + 1] = (T)2 * mu * (dG[3 * i + 1] - dR1) + lam * trM * r1 + lam * trE * dR1;
+            dP[3 * i + 2] = (T)2 * mu * (dG[3 * i + 2] - dR2) + lam * trM * r2 + lam * trE * dR2;
+        }
+    }
+};
+
 // Nodal vectors V S row_a(D_m^-1)^T for nodes a+1; node 0 gets minus the sum.
 template <typename T>
 __device__ __forceinline__ void element_nodal(const T S[9], const T Bm[9], T V, T f[4][3]) {
@@ -572,7 +777,7 @@ struct TileLds {
 // penalty energy, gradient k phi n and block k n n^T (+ k phi Hess(phi) with
 // the exact contact Hessian) per eligible node.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int LAW>
 __device__ __forceinline__ void tile_element(const Topo<T> &tp, const InstBufs<T> &B, const InstState *s, int blk,
                                              T alpha, int contact_full, double *pool) {
     const T mu = (T)s->mu, lam = (T)s->lam;
@@ -615,29 +820,12 @@ __device__ __forceinline__ void tile_element(const Topo<T> &tp, const InstBufs<T
                 acc[0] = INFINITY;
                 continue;
             }
-            const T lnJ = log1p_t(Jm1);
-            const T trG = G[0] + G[4] + G[8];
-            T G2 = (T)0;
-#pragma unroll
-            for (int c = 0; c < 9; c++) G2 += G[c] * G[c];
-            const T t1 = (T)0.5 * mu * ((T)2 * trG + G2), t2 = -mu * lnJ, t3 = (T)0.5 * lam * lnJ * lnJ;
-            acc[0] += (double)(geo.V * (t1 + t2 + t3));
-            acc[1] += (double)(geo.V * (abs_t(t1) + abs_t(t2) + abs_t(t3)));
-            T FiT[9];
-            inverse_transpose(G, J, FiT);
-            // P = mu (F - F^-T) + lam ln J F^-T with F - F^-T = G + F^-T G^T, which
-            // keeps full relative precision at small strain.
-            T Pk[9];
-#pragma unroll
-            for (int i = 0; i < 3; i++)
-#pragma unroll
-                for (int j = 0; j < 3; j++) {
-                    const T FG = FiT[3 * i] * G[3 * j] + FiT[3 * i + 1] * G[3 * j + 1] + FiT[3 * i + 2] * G[3 * j + 2];
-                    Pk[3 * i + j] = mu * (G[3 * i + j] + FG) + lam * lnJ * FiT[3 * i + j];
-                }
+            T psi, mag, Pk[9], FiT[9], kI, kc;   // FiT: the block's c = Mb b
+            Law<T, LAW>::element(G, Jm1, J, mu, lam, psi, mag, Pk, FiT, kI, kc);
+            acc[0] += (double)(geo.V * psi);
+            acc[1] += (double)(geo.V * mag);
             T f[4][3];
             element_nodal(Pk, geo.Bm, geo.V, f);
-            const T kc = mu + lam - lam * lnJ;
 #pragma unroll
             for (int a = 0; a < 4; a++) {
                 double *dst = sa + 9 * l[a];
@@ -657,7 +845,7 @@ __device__ __forceinline__ void tile_element(const Topo<T> &tp, const InstBufs<T
                 const T cx = FiT[0] * bb[0] + FiT[1] * bb[1] + FiT[2] * bb[2];
                 const T cy = FiT[3] * bb[0] + FiT[4] * bb[1] + FiT[5] * bb[2];
                 const T cz = FiT[6] * bb[0] + FiT[7] * bb[1] + FiT[8] * bb[2];
-                const T sI = geo.V * mu * (bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2]);
+                const T sI = geo.V * kI * (bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2]);
                 const T Vk = geo.V * kc;
                 atomicAdd(dst + 3, (double)(sI + Vk * cx * cx));
                 atomicAdd(dst + 4, (double)(sI + Vk * cy * cy));
@@ -716,7 +904,7 @@ __device__ __forceinline__ void tile_element(const Topo<T> &tp, const InstBufs<T
 // p.q is accumulated element by element (and over contact blocks), so alpha
 // is known to the node pass without a pass over q.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int LAW>
 __device__ __forceinline__ void tile_hessvec(const Topo<T> &tp, const InstBufs<T> &B, const InstState *s, int blk,
                                              double *pool) {
     const T beta = (T)s->beta;
@@ -767,27 +955,10 @@ __device__ __forceinline__ void tile_hessvec(const Topo<T> &tp, const InstBufs<T
             const T Jm1 = det_minus_one(G);
             const T J = (T)1 + Jm1;
             if (!(J > (T)0)) continue;
-            const T cc = mu - lam * fast_log1p(Jm1);
-            T FiT[9];
-            inverse_transpose<T, true>(G, J, FiT);
             T dG[9];
             edge_gradient(wp, geo.Bm, dG);
-            // A = F^-1 dG (F^-1 = FiT^T)
-            T A[9];
-#pragma unroll
-            for (int i = 0; i < 3; i++)
-#pragma unroll
-                for (int j = 0; j < 3; j++) A[3 * i + j] = FiT[i] * dG[j] + FiT[3 + i] * dG[3 + j] + FiT[6 + i] * dG[6 + j];
-            const T tr = A[0] + A[4] + A[8];
-            // (A F^-1)^T_ij = sum_k A_jk FiT_ik
             T dP[9];
-#pragma unroll
-            for (int i = 0; i < 3; i++)
-#pragma unroll
-                for (int j = 0; j < 3; j++) {
-                    const T Mt = A[3 * j] * FiT[3 * i] + A[3 * j + 1] * FiT[3 * i + 1] + A[3 * j + 2] * FiT[3 * i + 2];
-                    dP[3 * i + j] = mu * dG[3 * i + j] + cc * Mt + lam * tr * FiT[3 * i + j];
-                }
+            Law<T, LAW>::hessvec(G, Jm1, J, dG, mu, lam, dP);
             T f[4][3];
             element_nodal(dP, geo.Bm, geo.V, f);
             T e_pq = (T)0;
@@ -832,7 +1003,7 @@ __device__ __forceinline__ void tile_hessvec(const Topo<T> &tp, const InstBufs<T
 // paths share one LDS pool (their register needs are alike, so the union
 // does not lower occupancy).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int LAW>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 1 : 3))) void k_tile(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
                                                  int nwork, const SolveParams *P) {
     __shared__ __attribute__((aligned(32))) double pool[TileLds<T>::kDoubles];
@@ -846,11 +1017,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T
     const int contact_full = P->contact_full;
     const InstState *s = B.s;
     const int phase = s->phase;
+    if (s->model != LAW) return;   // served by the other law's launch
     if (phase == PH_CG || phase == PH_EVAL_HV) {
-        tile_hessvec(tp, B, s, w.y, pool);
+        tile_hessvec<T, LAW>(tp, B, s, w.y, pool);
     } else if (phase == PH_GRAD || phase == PH_EVAL_GRAD || phase == PH_TRIAL) {
         const T alpha = phase == PH_TRIAL ? (T)s->alpha_ls : (T)0;
-        tile_element(tp, B, s, w.y, alpha, contact_full, pool);
+        tile_element<T, LAW>(tp, B, s, w.y, alpha, contact_full, pool);
     }
 }
 
@@ -1348,6 +1520,7 @@ __global__ __launch_bounds__(kBlock) void k_tet_stress(const Topo<T> *topos, con
     const int t = blockIdx.x;
     if (t >= tp.ntile) return;
     const T mu = (T)B.s->mu, lam = (T)B.s->lam;
+    const int model = B.s->model;
     const int e0 = tp.tile_ent[t], ne = tp.tile_ent[t + 1] - e0;
     const int k0 = tp.tile_tet[t], nk = tp.tile_tet[t + 1] - k0;
     for (int l = threadIdx.x; l < ne; l += kBlock) {
@@ -1372,18 +1545,13 @@ __global__ __launch_bounds__(kBlock) void k_tet_stress(const Topo<T> *topos, con
         double out[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         double v = 0.0;
         if (J > (T)0) {
-            const T lnJ = log1p_t(Jm1);
-            T FiT[9];
-            inverse_transpose(G, J, FiT);
-            T Pk[9], F[9];
+            T psi, mag, Pk[9], Mb[9], ka, kb, F[9];
+            if (model == LAW_CR)
+                Law<T, LAW_CR>::element(G, Jm1, J, mu, lam, psi, mag, Pk, Mb, ka, kb);
+            else
+                Law<T, LAW_NH>::element(G, Jm1, J, mu, lam, psi, mag, Pk, Mb, ka, kb);
 #pragma unroll
-            for (int i = 0; i < 3; i++)
-#pragma unroll
-                for (int j = 0; j < 3; j++) {
-                    const T FG = FiT[3 * i] * G[3 * j] + FiT[3 * i + 1] * G[3 * j + 1] + FiT[3 * i + 2] * G[3 * j + 2];
-                    Pk[3 * i + j] = mu * (G[3 * i + j] + FG) + lam * lnJ * FiT[3 * i + j];
-                    F[3 * i + j] = G[3 * i + j] + (i == j ? (T)1 : (T)0);
-                }
+            for (int c = 0; c < 9; c++) F[c] = G[c] + (c % 4 == 0 ? (T)1 : (T)0);
             double S[9];
 #pragma unroll
             for (int i = 0; i < 3; i++)

@@ -336,6 +336,7 @@ struct fem_batch {
     int nwork_tile = 0, nwork_node = 0, cap_work_tile = 0, cap_work_node = 0;
     int *d_live = nullptr;
     int nlive = 0;
+    int n_law[2] = {0, 0};                  // jobs in the tables per constitutive law
     SolveParams *d_params = nullptr;
     SolveParams *h_params = nullptr;
     bool tables_dirty = true;
@@ -359,6 +360,7 @@ struct fem_mesh {
     bool have_material = false, have_indenter = false;
     double E = 0, nu = 0, density = 0;
     double dt = 0;                  // implicit time step; 0 = quasi-static
+    int model = FEM_MODEL_NEOHOOKEAN;
     Indenter ind{};
 };
 
@@ -637,10 +639,12 @@ int rebuild_tables(fem_batch *B) {
     std::vector<int2> wt, wn;
     std::vector<int> live;
     int max_t = 0, max_nb = 0;
+    B->n_law[0] = B->n_law[1] = 0;
     for (int i = 0; i < B->capacity; i++) {
         InstRec &R = B->insts[i];
         R.in_tables = R.live && running_phase(B->h_states[i].phase);
         if (!R.in_tables) continue;
+        B->n_law[B->h_states[i].model == LAW_CR ? 1 : 0]++;
         const TopoRec &tp = B->topos[R.topo];
         max_t = std::max(max_t, tp.ntile + tp.ncb);
         max_nb = std::max(max_nb, ceil_div(tp.n, kBlock));
@@ -729,8 +733,13 @@ int enqueue_round(fem_batch *B, int chunk) {
     const InstBufs<T> *bf = (const InstBufs<T> *)B->d_bufs;
     const int gt = pad8(B->nwork_tile), gn = pad8(B->nwork_node), nl = B->nlive;
     for (int c = 0; c < chunk; c++) {
+        // one tile launch per constitutive law present (blocks of jobs on the
+        // other law return at once)
         int slot = timer_begin(B, FEM_KERNEL_TILE);
-        k_tile<T><<<gt, kBlock, 0, B->stream>>>(tp, bf, B->d_work_tile, B->nwork_tile, B->d_params);
+        if (B->n_law[0] > 0)
+            k_tile<T, LAW_NH><<<gt, kBlock, 0, B->stream>>>(tp, bf, B->d_work_tile, B->nwork_tile, B->d_params);
+        if (B->n_law[1] > 0)
+            k_tile<T, LAW_CR><<<gt, kBlock, 0, B->stream>>>(tp, bf, B->d_work_tile, B->nwork_tile, B->d_params);
         timer_end(B, slot);
         slot = timer_begin(B, FEM_KERNEL_NODE);
         k_node<T><<<gn, kBlock, 0, B->stream>>>(tp, bf, B->d_work_node, B->nwork_node, B->d_params);
@@ -1033,8 +1042,9 @@ int check_params(const fem_solve_params &P) {
 
 // A job's initial state: material, pose schedule, counters, phase GRAD.
 void init_job_state(InstState &s, double E, double nu, const Indenter &ind, const double c0[3], const double dir[3],
-                    double depth, int steps, double dt, double rho) {
+                    double depth, int steps, double dt, double rho, int model) {
     std::memset(&s, 0, sizeof s);
+    s.model = model;
     s.dt = dt;
     s.rho = rho;
     s.mdt2 = dt > 0.0 ? rho / (dt * dt) : 0.0;
@@ -1290,7 +1300,7 @@ int fem_step(fem_mesh *M, const fem_solve_params *params, fem_step_info *info) {
     TRY(params_to_device(B, P));
     const double zero[3] = {0.0, 0.0, 0.0};
     const int hint = B->h_states[0].last_cg;
-    init_job_state(B->h_states[0], M->E, M->nu, M->ind, M->ind.c, zero, 0.0, 1, M->dt, M->density);
+    init_job_state(B->h_states[0], M->E, M->nu, M->ind, M->ind.c, zero, 0.0, 1, M->dt, M->density, M->model);
     B->h_states[0].last_cg = hint;
     TRY(write_state(B, 0));
     TRY(run(B, 0, nullptr));
@@ -1322,6 +1332,14 @@ int fem_set_displacements(fem_mesh *M, const double *u, int64_t count) {
     HIP_TRY(hipMemcpyAsync(inst_ptr(M->batch, 0, V_UT), inst_ptr(M->batch, 0, V_U), 3 * (size_t)M->n * M->batch->elem(),
                            hipMemcpyDeviceToDevice, M->batch->stream));
     return sync(M->batch);
+}
+
+int fem_set_model(fem_mesh *M, int32_t model) {
+    g_last_error.clear();
+    if (!M) return fail(FEM_E_INVALID, "null mesh");
+    if (model != FEM_MODEL_NEOHOOKEAN && model != FEM_MODEL_COROTATIONAL) return fail(FEM_E_INVALID, "unknown model");
+    M->model = model;
+    return FEM_OK;
 }
 
 int fem_set_dynamics(fem_mesh *M, double dt) {
@@ -1401,7 +1419,7 @@ int fem_eval_gradient(fem_mesh *M, double *g, int64_t capacity, double *energy, 
     fem_default_params(&P, B->precision);
     TRY(params_to_device(B, P));
     const double zero[3] = {0.0, 0.0, 0.0};
-    init_job_state(B->h_states[0], M->E, M->nu, M->ind, M->ind.c, zero, 0.0, 1, M->dt, M->density);
+    init_job_state(B->h_states[0], M->E, M->nu, M->ind, M->ind.c, zero, 0.0, 1, M->dt, M->density, M->model);
     B->h_states[0].phase = PH_EVAL_GRAD;
     TRY(write_state(B, 0));
     TRY(run(B, 2, nullptr));
@@ -1426,7 +1444,7 @@ int fem_eval_hessvec(fem_mesh *M, const fem_solve_params *params, const double *
     TRY(set_device(B));
     TRY(params_to_device(B, P));
     const double zero[3] = {0.0, 0.0, 0.0};
-    init_job_state(B->h_states[0], M->E, M->nu, M->ind, M->ind.c, zero, 0.0, 1, M->dt, M->density);
+    init_job_state(B->h_states[0], M->E, M->nu, M->ind, M->ind.c, zero, 0.0, 1, M->dt, M->density, M->model);
     B->h_states[0].phase = PH_EVAL_GRAD;
     TRY(write_state(B, 0));
     TRY(run(B, 2, nullptr));
@@ -1485,6 +1503,8 @@ int fem_batch_add_job(fem_batch *B, int32_t mesh_id, double E, double nu, const 
         if (!is_finite(job->direction[d])) return fail(FEM_E_INVALID, "bad direction");
     if (!is_finite(job->dt) || job->dt < 0 || (job->dt > 0 && !(job->density > 0 && is_finite(job->density))))
         return fail(FEM_E_INVALID, "implicit steps need dt >= 0 and density > 0");
+    if (job->model != FEM_MODEL_NEOHOOKEAN && job->model != FEM_MODEL_COROTATIONAL)
+        return fail(FEM_E_INVALID, "unknown constitutive model");
     int slot = -1;
     for (int i = 0; i < B->capacity; i++)
         if (!B->insts[i].live) {
@@ -1496,7 +1516,7 @@ int fem_batch_add_job(fem_batch *B, int32_t mesh_id, double E, double nu, const 
     TRY(B->precision == FEM_PREC_FP32 ? alloc_instance<float>(B, slot, mesh_id)
                                      : alloc_instance<double>(B, slot, mesh_id));
     init_job_state(B->h_states[slot], E, nu, ind, job->c0, job->direction, job->depth, job->steps, job->dt,
-                   job->density);
+                   job->density, job->model);
     TRY(write_state(B, slot));
     *job_id = slot;
     return FEM_OK;
@@ -1513,13 +1533,15 @@ int fem_batch_restart_job(fem_batch *B, int32_t job_id, double E, double nu, con
         if (!is_finite(job->direction[d])) return fail(FEM_E_INVALID, "bad direction");
     if (!is_finite(job->dt) || job->dt < 0 || (job->dt > 0 && !(job->density > 0 && is_finite(job->density))))
         return fail(FEM_E_INVALID, "implicit steps need dt >= 0 and density > 0");
+    if (job->model != FEM_MODEL_NEOHOOKEAN && job->model != FEM_MODEL_COROTATIONAL)
+        return fail(FEM_E_INVALID, "unknown constitutive model");
     TRY(set_device(B));
     const int n = B->topos[B->insts[job_id].topo].n;
     for (int which : {V_U, V_V, V_UT})
         HIP_TRY(hipMemsetAsync(inst_ptr(B, job_id, which), 0, 3 * (size_t)n * B->elem(), B->stream));
     const int hint = B->h_states[job_id].last_cg;
     init_job_state(B->h_states[job_id], E, nu, ind, job->c0, job->direction, job->depth, job->steps, job->dt,
-                   job->density);
+                   job->density, job->model);
     B->h_states[job_id].last_cg = hint;
     // Stream-ordered before any later kernel or state read; the pinned source
     // slot is not written again until the host has synchronised.
@@ -1586,11 +1608,12 @@ int fem_get_tet_stress(const fem_mesh *M, double *sigma, double *von_mises, int6
     if (!M) return fail(FEM_E_INVALID, "null mesh");
     if (!M->have_material) return fail(FEM_E_STATE, "set the material first");
     TRY(set_device(M->batch));
-    // the material of the handle, as the next step would use it
+    // the material and law of the handle, as the next step would use them
     TRY(read_states(M->batch));
     InstState &s = M->batch->h_states[0];
     s.mu = M->E / (2.0 * (1.0 + M->nu));
     s.lam = M->E * M->nu / ((1.0 + M->nu) * (1.0 - 2.0 * M->nu));
+    s.model = M->model;
     TRY(write_state(M->batch, 0));
     return tet_stress_impl(M->batch, 0, sigma, von_mises, capacity);
 }
