@@ -7,6 +7,7 @@
 // step) is taken on the device by the kernels in fem_kernels.h. A single mesh
 // handle is a batch holding one job.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <bitset>
@@ -381,18 +382,29 @@ int stage(fem_batch *B, size_t bytes) {
     return FEM_OK;
 }
 
-int timer_begin(fem_batch *B, int kind) {
+// Sampling: every `every`-th launch of a kernel kind gets a timer slot; the
+// launch then goes through hipExtLaunchKernel with the slot's events, which
+// take the dispatch's own start and end timestamps (no marker packets or
+// cache maintenance of separate event records inside the measured span).
+int timer_slot(fem_batch *B, int kind) {
     KernelTimer &t = B->timer;
     if (t.every <= 0) return -1;
     if ((t.seen[kind]++ % t.every) != 0 || t.used >= KernelTimer::kPool) return -1;
     const int slot = t.used++;
     t.kind_of[slot] = kind;
-    if (hipEventRecord(t.ev[slot][0], B->stream) != hipSuccess) return -1;
     return slot;
 }
 
-void timer_end(fem_batch *B, int slot) {
-    if (slot >= 0) (void)hipEventRecord(B->timer.ev[slot][1], B->stream);
+// Launches `kernel` plainly, or with the timer slot's start (first) and stop
+// (last) events when sampled.
+template <typename K, typename... Args>
+void launch_timed(fem_batch *B, int slot, bool first, bool last, K kernel, dim3 grid, dim3 block, Args... args) {
+    if (slot < 0) {
+        hipLaunchKernelGGL(kernel, grid, block, 0, B->stream, args...);
+        return;
+    }
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, B->stream, first ? B->timer.ev[slot][0] : nullptr,
+                          last ? B->timer.ev[slot][1] : nullptr, 0, args...);
 }
 
 void timer_harvest(fem_batch *B) {
@@ -725,28 +737,31 @@ int write_state(fem_batch *B, int slot) {
 }
 
 // One round: C solver steps, each a tile pass, a node pass and a finalize
-// over every live instance. With kernel timing on, sampled launches are
-// bracketed by events.
+// over every live instance. With kernel timing on, sampled launches carry
+// events (a sampled tile pass with both laws present is timed from the start
+// of the first launch to the end of the second).
 template <typename T>
 int enqueue_round(fem_batch *B, int chunk) {
     const Topo<T> *tp = (const Topo<T> *)B->d_topos;
     const InstBufs<T> *bf = (const InstBufs<T> *)B->d_bufs;
     const int gt = pad8(B->nwork_tile), gn = pad8(B->nwork_node), nl = B->nlive;
+    const bool nh = B->n_law[0] > 0, cr = B->n_law[1] > 0;
     for (int c = 0; c < chunk; c++) {
         // one tile launch per constitutive law present (blocks of jobs on the
         // other law return at once)
-        int slot = timer_begin(B, FEM_KERNEL_TILE);
-        if (B->n_law[0] > 0)
-            k_tile<T, LAW_NH><<<gt, kBlock, 0, B->stream>>>(tp, bf, B->d_work_tile, B->nwork_tile, B->d_params);
-        if (B->n_law[1] > 0)
-            k_tile<T, LAW_CR><<<gt, kBlock, 0, B->stream>>>(tp, bf, B->d_work_tile, B->nwork_tile, B->d_params);
-        timer_end(B, slot);
-        slot = timer_begin(B, FEM_KERNEL_NODE);
-        k_node<T><<<gn, kBlock, 0, B->stream>>>(tp, bf, B->d_work_node, B->nwork_node, B->d_params);
-        timer_end(B, slot);
-        slot = timer_begin(B, FEM_KERNEL_FINALIZE);
-        k_finalize<T><<<nl, 64, 0, B->stream>>>(tp, bf, B->d_live, nl, B->d_params);
-        timer_end(B, slot);
+        int slot = timer_slot(B, FEM_KERNEL_TILE);
+        if (nh)
+            launch_timed(B, slot, true, !cr, k_tile<T, LAW_NH>, dim3(gt), dim3(kBlock), tp, bf,
+                         (const int2 *)B->d_work_tile, B->nwork_tile, (const SolveParams *)B->d_params);
+        if (cr)
+            launch_timed(B, slot, !nh, true, k_tile<T, LAW_CR>, dim3(gt), dim3(kBlock), tp, bf,
+                         (const int2 *)B->d_work_tile, B->nwork_tile, (const SolveParams *)B->d_params);
+        slot = timer_slot(B, FEM_KERNEL_NODE);
+        launch_timed(B, slot, true, true, k_node<T>, dim3(gn), dim3(kBlock), tp, bf, (const int2 *)B->d_work_node,
+                     B->nwork_node, (const SolveParams *)B->d_params);
+        slot = timer_slot(B, FEM_KERNEL_FINALIZE);
+        launch_timed(B, slot, true, true, k_finalize<T>, dim3(nl), dim3(64), tp, bf, (const int *)B->d_live, nl,
+                     (const SolveParams *)B->d_params);
     }
     return launch_check("round");
 }
