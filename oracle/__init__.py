@@ -46,7 +46,9 @@ class Problem(C.Structure):
                 ("fixed", C.POINTER(C.c_ubyte)), ("eligible", C.POINTER(C.c_ubyte)),
                 ("B", C.POINTER(C.c_double)), ("V", C.POINTER(C.c_double)),
                 ("mu", C.c_double), ("lam", C.c_double), ("ind", Indenter), ("dt", C.c_double),
-                ("mass", C.POINTER(C.c_double)), ("utilde", C.POINTER(C.c_double)), ("model", C.c_int)]
+                ("mass", C.POINTER(C.c_double)), ("utilde", C.POINTER(C.c_double)), ("model", C.c_int),
+                ("mu_f", C.c_double), ("eps_f", C.c_double), ("u_lag", C.POINTER(C.c_double)),
+                ("c_lag", C.c_double * 3)]
 
 
 class Params(C.Structure):
@@ -87,6 +89,8 @@ def lib():
         L.orc_lumped_mass.argtypes = [C.c_int, C.c_int, ip, dp, C.c_double, dp]
         L.orc_lumped_mass.restype = None
         L.orc_polar.argtypes = [dp, dp, dp]
+        L.orc_friction_f0.argtypes = [C.c_double, C.c_double, dp, dp, dp]
+        L.orc_friction_f0.restype = None
         L.orc_psi_cr.argtypes = [dp, C.c_double, C.c_double]
         L.orc_psi_cr.restype = C.c_double
         L.orc_pk1_cr.argtypes = [dp, C.c_double, C.c_double, dp]
@@ -227,6 +231,13 @@ def lumped_mass(n, tets, V, rho):
     return m
 
 
+def friction_f0(y, eps):
+    """Friction smoothing f0(y), f1(y) = f0'(y), f1'(y) at slip y."""
+    f0, f1, df1 = C.c_double(), C.c_double(), C.c_double()
+    lib().orc_friction_f0(float(y), float(eps), C.byref(f0), C.byref(f1), C.byref(df1))
+    return f0.value, f1.value, df1.value
+
+
 def default_params(**kw) -> Params:
     """Oracle solve settings: Newton to 1e-8 relative residual, CG forcing
     between 1e-8 and 0.1, block Jacobi, Armijo c1 = 1e-4, 40 halvings."""
@@ -264,10 +275,29 @@ class Solver:
         self.dt = 0.0
         self.mass = None
         self.utilde = np.zeros((self.n, 3))
+        self.mu_f, self.eps_f, self.u_lag = 0.0, 1e-6, None
 
     def set_model(self, model):
         """Constitutive law: NEOHOOKEAN (default) or COROTATIONAL."""
         self.p.model = int(model)
+
+    def set_friction(self, mu_f, eps=1e-6):
+        """Lagged, smoothed Coulomb friction (mu_f = 0: frictionless)."""
+        self.mu_f, self.eps_f = float(mu_f), float(eps)
+        self.p.mu_f, self.p.eps_f = self.mu_f, self.eps_f
+
+    def set_friction_lag(self, u_lag, c_lag):
+        """The lag state friction takes its normal forces and normals from:
+        displacement u_lag with the indenter centred at c_lag (same shape,
+        orientation and stiffness as the current indenter). None clears it."""
+        if u_lag is None:
+            self.u_lag = None
+            self.p.u_lag = None
+            return
+        self.u_lag = self._u(u_lag).copy()
+        self.p.u_lag = _dp(self.u_lag)
+        for d in range(3):
+            self.p.c_lag[d] = float(c_lag[d])
 
     def set_dynamics(self, dt, rho):
         """Backward-Euler time stepping with lumped masses (dt = 0: quasi-static)."""
@@ -298,6 +328,8 @@ class Solver:
         S = ind.steps if steps is None else steps
         for k in range(1, S + 1):
             self.set_indenter(ind.kind, ind.shape, ind.R, ind.center(k), ind.k_penalty)
+            if self.mu_f > 0.0:
+                self.set_friction_lag(u, ind.center(k - 1))
             u, v, info = self.dyn_step(u, v, params)
             out.append((u, v, info))
         return out
@@ -380,6 +412,9 @@ class Solver:
         S = ind.steps if steps is None else steps
         for k in range(1, S + 1):
             self.set_indenter(ind.kind, ind.shape, ind.R, ind.center(k), ind.k_penalty)
+            if self.mu_f > 0.0:
+                # friction lagged from the previous load step's result
+                self.set_friction_lag(u, ind.center(k - 1))
             u, info = self.step(u, params)
             out.append((u, info))
             if callback:

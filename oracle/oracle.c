@@ -13,8 +13,9 @@
  *   - Neo-Hookean: the compressible form
  *       Psi(F) = mu/2 (tr F^T F - 3) - mu ln J + lam/2 (ln J)^2,  J = det F,
  *     whose linearisation at F = I is isotropic Hooke with Lame (mu, lam);
- *   - contact: frictionless per-node penalty k/2 min(0, phi)^2 against the
- *     indenter's signed distance phi, on surface nodes that are not fixed;
+ *   - contact: per-node penalty k/2 min(0, phi)^2 against the indenter's
+ *     signed distance phi, on surface nodes that are not fixed; optionally
+ *     with lagged, smoothed Coulomb friction (see oracle.h);
  *   - quasi-static load steps solved by Newton, with the linear systems solved
  *     by Jacobi-preconditioned CG (truncated at non-positive curvature) and an
  *     Armijo backtracking line search that also rejects inverted tets;
@@ -457,6 +458,67 @@ static double contact_phi(const orc_problem *p, const double *u, int i, double n
     return orc_sdf(&p->ind, x, nrm);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Lagged, smoothed Coulomb friction                                         */
+/* ------------------------------------------------------------------------ */
+void orc_friction_f0(double y, double eps, double *f0, double *f1, double *df1) {
+    if (y < eps) {
+        *f0 = y * y / eps - y * y * y / (3.0 * eps * eps) + eps / 3.0;
+        *f1 = 2.0 * y / eps - y * y / (eps * eps);
+        *df1 = 2.0 / eps - 2.0 * y / (eps * eps);
+    } else {
+        *f0 = y;
+        *f1 = 1.0;
+        *df1 = 0.0;
+    }
+}
+
+/* Friction data of node i at u: returns 1 when the node carries friction
+ * (eligible, lag state present, in contact at the lag state), with its
+ * weight w = mu_f k (-phi_lag), lag normal and tangential slip s. */
+static int friction_at(const orc_problem *p, const double *u, int i, double *w, double nrm[3], double s[3]) {
+    if (!(p->mu_f > 0.0) || !p->u_lag || !p->eligible[i]) return 0;
+    orc_indenter lag = p->ind;
+    for (int d = 0; d < 3; d++) lag.c[d] = p->c_lag[d];
+    double xl[3];
+    for (int d = 0; d < 3; d++) xl[d] = p->X[3 * i + d] + p->u_lag[3 * i + d];
+    double phl = orc_sdf(&lag, xl, nrm);
+    if (!(phl < 0.0)) return 0;
+    *w = p->mu_f * p->ind.k * (-phl);
+    double dd[3];
+    for (int d = 0; d < 3; d++) dd[d] = u[3 * i + d] - p->u_lag[3 * i + d] - (p->ind.c[d] - p->c_lag[d]);
+    double dn = dd[0] * nrm[0] + dd[1] * nrm[1] + dd[2] * nrm[2];
+    for (int d = 0; d < 3; d++) s[d] = dd[d] - dn * nrm[d];
+    return 1;
+}
+
+/* Friction energy of node i and its gradient (either may be NULL). */
+static double friction_energy_grad(const orc_problem *p, const double *u, int i, double g[3]) {
+    double w, nrm[3], s[3];
+    if (g) g[0] = g[1] = g[2] = 0.0;
+    if (!friction_at(p, u, i, &w, nrm, s)) return 0.0;
+    double y = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]), f0, f1, df1;
+    orc_friction_f0(y, p->eps_f, &f0, &f1, &df1);
+    if (g && y > 0.0)
+        for (int d = 0; d < 3; d++) g[d] = w * f1 / y * s[d];
+    return w * f0;
+}
+
+/* Friction block of node i: w [ (f1/y) P + (f1' - f1/y) s s^T / y^2 ] with
+ * P = I - n n^T (the limit 2w/eps P at y = 0). */
+static void friction_block(const orc_problem *p, const double *u, int i, double Hb[9]) {
+    double w, nrm[3], s[3];
+    for (int c = 0; c < 9; c++) Hb[c] = 0.0;
+    if (!friction_at(p, u, i, &w, nrm, s)) return;
+    double y = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]), f0, f1, df1;
+    orc_friction_f0(y, p->eps_f, &f0, &f1, &df1);
+    double a = y > 0.0 ? f1 / y : 2.0 / p->eps_f;
+    double b = y > 0.0 ? (df1 - f1 / y) / (y * y) : 0.0;
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++)
+            Hb[3 * r + c] = w * (a * ((r == c ? 1.0 : 0.0) - nrm[r] * nrm[c]) + b * s[r] * s[c]);
+}
+
 /* Energy, with the sum of the magnitudes of its terms (for the line search's
  * rounding floor) and the smallest J. */
 static double energy_terms(const orc_problem *p, const double *u, double *mag, double *min_J) {
@@ -500,6 +562,11 @@ static double energy_terms(const orc_problem *p, const double *u, double *mag, d
             E += c;
             M += c;
         }
+    }
+    for (int i = 0; i < p->n; i++) {
+        double c = friction_energy_grad(p, u, i, NULL);
+        E += c;
+        M += c;
     }
     if (dynamic(p)) {
         for (int i = 0; i < p->n; i++) {
@@ -548,6 +615,9 @@ void orc_gradient(const orc_problem *p, const double *u, double *g) {
         double phi = contact_phi(p, u, i, nrm);
         if (phi < 0.0)
             for (int d = 0; d < 3; d++) g[3 * i + d] += p->ind.k * phi * nrm[d];
+        double gf[3];
+        friction_energy_grad(p, u, i, gf);
+        for (int d = 0; d < 3; d++) g[3 * i + d] += gf[d];
     }
     if (dynamic(p))
         for (int i = 0; i < p->n; i++) {
@@ -676,6 +746,10 @@ static void bsr_assemble(const orc_problem *p, const double *u, bsr *H, int cont
             for (int a = 0; a < 3; a++)
                 for (int b = 0; b < 3; b++) blk[3 * a + b] += p->ind.k * (nrm[a] * nrm[b] + phi * Hs[3 * a + b]);
         }
+        double Hf[9];
+        friction_block(p, u, i, Hf);
+        double *blk = bsr_block(H, i, i);
+        for (int c = 0; c < 9; c++) blk[c] += Hf[c];
     }
     if (dynamic(p))
         for (int i = 0; i < p->n; i++) {
@@ -939,11 +1013,16 @@ int orc_contact_patch(const orc_problem *p, const double *u, int *ids, double *f
     double Ft[3] = {0.0, 0.0, 0.0};
     for (int i = 0; i < p->n; i++) {
         if (!p->eligible[i]) continue;
-        double nrm[3];
+        double nrm[3], wf, nf[3], sf[3], gf[3];
         double ph = contact_phi(p, u, i, nrm);
-        if (!(ph < 0.0)) continue;
+        int fr = friction_at(p, u, i, &wf, nf, sf);
+        if (!(ph < 0.0) && !fr) continue;
+        friction_energy_grad(p, u, i, gf);
         double fi[3];
-        for (int d = 0; d < 3; d++) { fi[d] = -p->ind.k * ph * nrm[d]; Ft[d] += fi[d]; }
+        for (int d = 0; d < 3; d++) {
+            fi[d] = (ph < 0.0 ? -p->ind.k * ph * nrm[d] : 0.0) - gf[d];
+            Ft[d] += fi[d];
+        }
         if (ids) ids[count] = i;
         if (f) memcpy(f + 3 * (size_t)count, fi, sizeof fi);
         if (phi) phi[count] = ph;

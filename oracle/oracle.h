@@ -21,6 +21,20 @@
  *   Phi(u) = Pi(u) + sum_{i free} m_i / (2 dt^2) |u_i - ut_i|^2,
  * ut = u^n + dt v^n, and then v^{n+1} = (u^{n+1} - u^n) / dt.
  *
+ * Coulomb friction (the paper's simulator uses friction coefficient 0.783,
+ * Sec. III-A), lagged and smoothed so that each step stays a minimisation:
+ * the normal force and normal of every contact node are taken from a lag
+ * state (u_lag at indenter centre c_lag, normally the previous step's
+ * result), w_i = mu_f k max(0, -phi_lag_i); the node's slip relative to the
+ * indenter's translation since the lag state is s_i = (I - n_i n_i^T)
+ * (u_i - u_lag_i - (c - c_lag)), and the step adds
+ *   D(u) = sum_i w_i f0(|s_i|),
+ * f0(y) = y^2/eps - y^3/(3 eps^2) + eps/3 for y < eps and y beyond: a C1
+ * smoothing of |s| whose derivative rises from 0 to 1 over a slip of eps
+ * (the smoothing of Li et al., "Incremental Potential Contact", 2020). The
+ * friction force on a node is then at most w_i, and exactly w_i against the
+ * slip once |s_i| >= eps.
+ *
  * All arrays are row-major, caller-owned, double precision unless stated.
  */
 #ifndef FEM_ORACLE_H
@@ -67,6 +81,10 @@ typedef struct {
     const double *mass;           /* n lumped nodal masses (kg), or NULL */
     const double *utilde;         /* n x 3 inertial predictor u^n + dt v^n, or NULL */
     int model;                    /* ORC_NEOHOOKEAN or ORC_COROTATIONAL */
+    double mu_f;                  /* Coulomb friction coefficient; 0 = frictionless */
+    double eps_f;                 /* slip smoothing length (m), > 0 when mu_f > 0 */
+    const double *u_lag;          /* n x 3 displacement of the lag state, or NULL (no friction) */
+    double c_lag[3];              /* indenter centre of the lag state */
 } orc_problem;
 
 typedef struct {
@@ -111,6 +129,9 @@ double orc_psi_cr(const double F[9], double mu, double lam);
 void orc_pk1_cr(const double F[9], double mu, double lam, double P[9]);
 void orc_dpk1_cr(const double F[9], const double dF[9], double mu, double lam, double dP[9]);
 
+/* Friction smoothing: f0(y), f1(y) = f0'(y) and f1'(y) for slip y >= 0. */
+void orc_friction_f0(double y, double eps, double *f0, double *f1, double *df1);
+
 /* Signed distance of world point x to the indenter and its world gradient. */
 double orc_sdf(const orc_indenter *ind, const double x[3], double grad[3]);
 
@@ -150,9 +171,10 @@ int orc_linear_solve(const orc_problem *p, const double *u, const double *b, dou
 /* One load step: Newton from u (in/out) at the problem's indenter pose. */
 int orc_step(const orc_problem *p, const orc_params *prm, double *u, orc_info *info);
 
-/* Contact patch at u: ascending ids of nodes with phi < 0, forces on the skin
- * -k phi n, penetrations and the resultant. Returns the count (arrays may be
- * NULL to query it). */
+/* Contact patch at u: ascending ids of nodes that carry a contact force
+ * (phi < 0, or a lagged friction weight w > 0), forces on the skin
+ * -k min(0, phi) n - dD/du_i, phi and the resultant. Returns the count
+ * (arrays may be NULL to query it). */
 int orc_contact_patch(const orc_problem *p, const double *u, int *ids, double *f, double *phi,
                       double F_total[3]);
 
