@@ -417,43 +417,62 @@ def bench_dynamic(args):
             "e_inf_vs_fp64_oracle_first_steps": errs}
 
 
-def bench_corotational(args):
-    """The batched workload under the co-rotational law of the paper's own
-    simulator (E = 1.55 MPa, nu = 0.316, Sec. III-A): 256 jobs on the 50k
-    fingertip, FP32 path, with the roofline of k_tile<float, LAW_CR>. The
-    indentation depths are halved (up to 1.5 mm): the co-rotational law has
-    no barrier against inversion, and boxes and rings pressed through most
-    of the 3 mm skin invert elements (the oracle fails the same load
-    steps)."""
+VARIANTS = {
+    # name: (law, E, nu, depth factor, friction, dt, description)
+    "corotational": (1, 1.55e6, 0.316, 0.5, 0.0, 0.0,
+                     "co-rotational batched indentation: {J} jobs on the synthetic 50k-tet fingertip, E = 1.55 MPa, "
+                     "nu = 0.316, seeded indenters at half depth (up to 1.5 mm), 100 quasi-static load steps each"),
+    "friction": (0, 0.3e6, 0.45, 1.0, 0.783, 0.0,
+                 "batched indentation with Coulomb friction 0.783 (lagged, smoothed over 1 um): {J} jobs on the "
+                 "synthetic 50k-tet fingertip, seeded indenters, 100 quasi-static load steps each"),
+    "simulator": (1, 1.55e6, 0.316, 0.5, 0.783, 1e-4,
+                  "the paper's simulator model: co-rotational skin (E = 1.55 MPa, nu = 0.316), Coulomb friction "
+                  "0.783, backward-Euler steps of 1e-4 s (1100 kg/m^3); {J} jobs on the synthetic 50k-tet "
+                  "fingertip, seeded indenters at half depth, 100 steps each"),
+}
+
+
+def bench_variant(args, name):
+    """The batched workload (256 jobs on the 50k fingertip, FP32 path) with
+    the co-rotational law of the paper's own simulator (E = 1.55 MPa,
+    nu = 0.316, Sec. III-A), with Coulomb friction (coefficient 0.783), or
+    with both and implicit time steps of 1e-4 s, and the roofline of the
+    tile kernel instance that runs. Co-rotational variants halve the
+    indentation depths (up to 1.5 mm): the law has no barrier against
+    inversion, and boxes and rings pressed through most of the 3 mm skin
+    invert elements (the oracle fails the same load steps)."""
     from paper_2103_16747_amd import workload as W
 
+    law, E, nu, depth_f, mu_f, dt, desc = VARIANTS[name]
     mesh = W.fingertip_mesh(50000)
     inds = []
     for i in range(args.jobs):
         ind = W.seat_on_mesh(W.random_indentation(3000 + i), mesh)
-        ind.model = 1
-        ind.depth *= 0.5
+        ind.model = law
+        ind.depth *= depth_f
+        ind.friction, ind.friction_eps = mu_f, 1e-6
+        ind.dt, ind.density = dt, 1100.0
         inds.append(ind)
-    r = run_batched(mesh, inds, "fp32", args.steps, args.warmup, args.timing_every, material=(1.55e6, 0.316))
+    r = run_batched(mesh, inds, "fp32", args.steps, args.warmup, args.timing_every, material=(E, nu))
     K, J = args.steps, args.jobs
     wall = sum(r["walls"])
     lat_ms = np.array(r["lat"]) * 1e3
     out = {"metric": METRIC, "value": K * J / wall, "unit": "solves/s", "n_gpus": 1, "steps": K,
            "warmup": args.warmup, "ms_per_step": wall / K * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"co-rotational batched indentation: {J} jobs on the synthetic 50k-tet fingertip, "
-                                  "E = 1.55 MPa, nu = 0.316, seeded indenters at half depth (up to 1.5 mm), "
-                                  "100 quasi-static load steps each",
-                      "jobs_per_step": J, "mesh_tets": mesh.m},
+           "config": {"workload": desc.format(J=J), "jobs_per_step": J, "mesh_tets": mesh.m},
            "tet_updates_per_s": r["tet_updates"] / wall,
            "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
            "failed_load_steps": r["failed_steps"], "floor_load_steps": r["floor_steps"],
            "cg_iters_per_job": float(np.mean([s["cg_iters"] for s in r["stats"]])),
-           "newton_iters_per_job": float(np.mean([s["newton_iters"] for s in r["stats"]])),
-           "flops_per_tet": FLOPS_PER_TET_CR, "polar_iterations_assumed": POLAR_ITERS}
-    rl, kav = roofline(r, 4, FLOPS_PER_TET_CR, "k_tile<float, LAW_CR>")
+           "newton_iters_per_job": float(np.mean([s["newton_iters"] for s in r["stats"]]))}
+    fpt = FLOPS_PER_TET_CR if law == 1 else FLOPS_PER_TET
+    out["flops_per_tet"] = fpt
+    if law == 1:
+        out["polar_iterations_assumed"] = POLAR_ITERS
+    rl, kav = roofline(r, 4, fpt, "k_tile<float, LAW_CR>" if law == 1 else "k_tile<float, LAW_NH>")
     if rl:
-        rl["traffic"] = None
+        rl["traffic"] = None      # counters are taken on the default workload only
         out["roofline"] = rl
         out["kernel_avg_us"] = kav
     return out
@@ -471,12 +490,14 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--timing-every", type=int, default=8)
-    ap.add_argument("--config", choices=("batched", "uneven", "serving", "dynamic", "corotational"),
+    ap.add_argument("--config", choices=("batched", "uneven", "serving", "dynamic", "corotational", "friction",
+                                         "simulator"),
                     default="batched",
                     help="batched: 256 jobs on the 50k fingertip (default); uneven: 64 jobs at 5k-120k tets with "
                          "autotuned shapes; serving: Poisson request streams through the serving loop; dynamic: "
                          "the batched workload as implicit time steps of 1e-4 s; corotational: the batched workload under the "
-                         "co-rotational law")
+                         "co-rotational law; friction: with Coulomb friction 0.783; simulator: co-rotational, "
+                         "friction and implicit steps together")
     ap.add_argument("--rates", default="10,50,200,500", help="serving: arrival rates (req/s)")
     ap.add_argument("--requests", type=int, default=160, help="serving: requests per rate")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -508,8 +529,8 @@ def main():
     if args.config == "dynamic":
         print(json.dumps(bench_dynamic(args)), flush=True)
         return
-    if args.config == "corotational":
-        print(json.dumps(bench_corotational(args)), flush=True)
+    if args.config in VARIANTS:
+        print(json.dumps(bench_variant(args, args.config)), flush=True)
         return
     mesh = W.fingertip_mesh(50000)
     inds = [W.seat_on_mesh(W.random_indentation(3000 + i), mesh) for i in range(args.jobs)]

@@ -154,6 +154,23 @@ int fem_set_indenter(fem_mesh *mesh, int32_t kind, const double *shape, int32_t 
  * FEM_MODEL_NEOHOOKEAN). Errors: FEM_E_INVALID (unknown model). */
 int fem_set_model(fem_mesh *mesh, int32_t model);
 
+/* Coulomb friction between skin and indenter (paper Sec. III-A: the
+ * simulator's contact is frictional, coefficient 0.783), lagged and smoothed
+ * so that every step stays a minimisation with a symmetric Newton matrix.
+ * The normal force and normal of each contact node come from the lag state
+ * (the displacement at the start of the step, with the indenter where it was
+ * when that state was reached): w = mu_f k max(0, -phi_lag). Its slip is the
+ * tangential part of its displacement relative to the indenter's translation
+ * since, s = (I - n n^T)(u - u_lag - (c - c_lag)), and the step adds
+ * w f0(|s|) to the potential, f0 a C1 smoothing of |s| that is exact beyond
+ * a slip of eps: the friction force is at most w, and exactly w against the
+ * slip once |s| >= eps. The lag state is the result of the previous fem_step
+ * at its indenter pose, or the displacements of fem_set_displacements at the
+ * indenter pose set then; before either there is none and the step carries no
+ * friction. mu_f = 0 turns friction off (the default).
+ * Errors: FEM_E_INVALID (mu_f < 0, or eps <= 0 with mu_f > 0, non-finite). */
+int fem_set_friction(fem_mesh *mesh, double mu_f, double eps);
+
 /* Fills the default solve parameters for a precision mode. */
 void fem_default_params(fem_solve_params *params, int32_t precision);
 
@@ -174,7 +191,8 @@ int fem_get_displacements(const fem_mesh *mesh, double *u, int64_t capacity);
 
 /* Replaces the nodal displacements (warm start, resume, or prescribed
  * displacements on fixed nodes); count must equal 3 n. Velocities are kept.
- * Errors: FEM_E_INVALID. */
+ * With an indenter set, u at its current pose becomes the friction lag state
+ * of the next step. Errors: FEM_E_INVALID. */
 int fem_set_displacements(fem_mesh *mesh, const double *u, int64_t count);
 
 /* Implicit time stepping (paper Sec. III-A: the simulator integrates the
@@ -195,9 +213,10 @@ int fem_get_velocities(const fem_mesh *mesh, double *v, int64_t capacity);
 int fem_set_velocities(fem_mesh *mesh, const double *v, int64_t count);
 
 /* Contact patch at the current state (paper Sec. III-A: nodal contact forces,
- * summed into resultant forces): ids of the eligible nodes with phi < 0 in
- * ascending order, the force each exerts on the skin f = -k phi grad(phi)
- * (n_contact x 3), the penetrations phi, and F_total = sum f. Any output
+ * summed into resultant forces): ids of the eligible nodes that carry a
+ * contact force (phi < 0, or friction from the lag state) in ascending order,
+ * the force each exerts on the skin f = -k min(0, phi) grad(phi) plus the
+ * friction force (n_contact x 3), the penetrations phi, and F_total = sum f. Any output
  * pointer may be NULL except n_contact. If capacity < count, returns
  * FEM_E_BUFFER with *n_contact = the count needed (F_total still filled). */
 int fem_get_contact_patch(const fem_mesh *mesh, int32_t *ids, double *f, double *phi, int32_t capacity,
@@ -239,10 +258,11 @@ int fem_eval_hessvec(fem_mesh *mesh, const fem_solve_params *params, const doubl
  * three kernels over every live job: the tile pass (per job the matrix-free
  * Hessian-vector product during CG, the element + contact pass of a gradient
  * or line-search trial otherwise), the node pass (CG update, Newton init,
- * line-search directional derivative) and the finalize. With every > 0, HIP
- * events on the handle's stream bracket every every-th launch of each, and
- * rounds are launched kernel by kernel rather than from a captured graph;
- * every = 0 turns timing off. Counters are cleared on each call. */
+ * line-search directional derivative) and the finalize. With every > 0,
+ * every every-th launch of each is made with a start and a stop HIP event
+ * (hipExtLaunchKernel on the handle's stream: the dispatch's own start and
+ * end), and rounds are launched kernel by kernel rather than from a captured
+ * graph; every = 0 turns timing off. Counters are cleared on each call. */
 #define FEM_KERNEL_TILE 0
 #define FEM_KERNEL_NODE 1
 #define FEM_KERNEL_FINALIZE 2
@@ -277,6 +297,9 @@ typedef struct {
                             this length (see fem_set_dynamics); 0: quasi-static */
     double density;      /* kg/m^3, for the lumped masses when dt > 0 */
     int32_t model;       /* FEM_MODEL_NEOHOOKEAN or FEM_MODEL_COROTATIONAL */
+    double friction;     /* Coulomb coefficient, 0 = frictionless (see fem_set_friction);
+                            the lag state of the first step is u = 0 at c0 */
+    double friction_eps; /* slip smoothing length (m), > 0 when friction > 0 */
 } fem_indentation;
 
 typedef struct {

@@ -47,7 +47,8 @@ enum Phase : int {
     PH_TRIAL = 4,     // line-search trial: element pass at u + alpha dx
     PH_DONE = 5,      // all load steps taken
     PH_EVAL_GRAD = 6, // diagnostics: gradient at u, then idle
-    PH_EVAL_HV = 7    // diagnostics: q = H z, then idle
+    PH_EVAL_HV = 7,   // diagnostics: q = H z, then idle
+    PH_LAG = 8        // node pass forms the friction lag data, then after_lag
 };
 
 // Status codes (same values as the C ABI).
@@ -83,6 +84,10 @@ struct InstState {
     double gbest;                             // smallest |g_free| of the load step so far
     int stall, steps_floor;                   // accepted iterations without halving gbest
     int model, pad3;                          // constitutive law (LAW_NH, LAW_CR)
+    double mu_f, eps_f;                       // Coulomb friction coefficient (0: none), slip smoothing length
+    double c_lag[3];                          // indenter centre of the friction lag state
+    int lag_ok, after_lag;                    // 1: a lag state exists (u at the step start, c_lag);
+                                              // the phase that follows PH_LAG
     double c0[3], dir[3];
     Indenter ind;
     // current load step
@@ -139,6 +144,8 @@ struct InstBufs {
     T *cp;                              // nc x 9: contact gradient (3) + block (6)
     T *qout;                            // n x 3 (diagnostics)
     T *v, *ut;                          // n x 3: velocity of the last completed step, inertial predictor
+    double *fr;                         // nc x 8: friction lag data (w, normal, displacement relative to
+                                        // the indenter since the lag state, pad)
     double *red;                        // RS_COUNT x red_stride
     InstState *s;
 };
@@ -736,6 +743,9 @@ __device__ inline void end_step(InstState *s, int status) {
         s->steps_failed++;
         if (s->first_fail == 0) s->first_fail = status;
     }
+    // the state just reached is the next step's friction lag state
+    for (int d = 0; d < 3; d++) s->c_lag[d] = s->ind.c[d];
+    s->lag_ok = 1;
     if (s->step >= s->steps) {
         s->phase = PH_DONE;
         return;
@@ -743,7 +753,8 @@ __device__ inline void end_step(InstState *s, int status) {
     s->step++;
     const double f = s->depth * (double)s->step / (double)s->steps;
     for (int d = 0; d < 3; d++) s->ind.c[d] = s->c0[d] + f * s->dir[d];
-    s->phase = PH_GRAD;
+    s->phase = s->mu_f > 0.0 ? PH_LAG : PH_GRAD;
+    s->after_lag = PH_GRAD;
     s->step_started = 1;
     s->newton_it = 0;
     s->st_newton = s->st_cg = s->st_hv = s->st_grad = s->st_ls = 0;
@@ -768,6 +779,80 @@ struct TileLds {
     static constexpr int kHv = 3 * kTileNodes + 2 * kVec;
     static constexpr int kDoubles = kElem > kHv ? kElem : kHv;
 };
+
+// ---------------------------------------------------------------------------
+// Lagged, smoothed Coulomb friction at one contact node, in FP64. The lag
+// data fr: w = mu_f k (-phi) and the unit normal n at the lag state, then the
+// node's displacement relative to the indenter since the lag state, dd: it
+// starts at minus the indenter's translation and accumulates the applied
+// Newton increments in FP64 (so the slip keeps full precision on the FP32
+// path, where it would otherwise be a difference of two rounded positions).
+// With the tangential slip s = (I - n n^T) dd and y = |s|: energy
+// w f0(y), f0 = y^2/eps - y^3/(3 eps^2) + eps/3 below y = eps and y above
+// (C1), gradient w (f1/y) s, and the node block
+// w [(f1/y)(I - n n^T) + (f1' - f1/y)/y^2 s s^T] (xx yy zz xy xz yz), which
+// is positive semidefinite; f1 = f0'.
+// ---------------------------------------------------------------------------
+__device__ inline double friction_eval(const double fr[8], const double dd[3], double eps, double g[3], double H[6]) {
+    const double w = fr[0];
+    const double nl[3] = {fr[1], fr[2], fr[3]};
+    const double dn = dd[0] * nl[0] + dd[1] * nl[1] + dd[2] * nl[2];
+    double sv[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) sv[d] = dd[d] - dn * nl[d];
+    const double y = sqrt(sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2]);
+    double f0, a, b;
+    if (y < eps) {
+        const double ie = 1.0 / eps;
+        f0 = y * y * ie - y * y * y * ie * ie * (1.0 / 3.0) + eps * (1.0 / 3.0);
+        a = 2.0 * ie - y * ie * ie;              // f1 / y
+        b = y > 0.0 ? -ie * ie / y : 0.0;         // (f1' - f1 / y) / y^2
+    } else {
+        f0 = y;
+        a = 1.0 / y;
+        b = -a * a * a;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; d++) g[d] = w * a * sv[d];
+    H[0] = w * (a * (1.0 - nl[0] * nl[0]) + b * sv[0] * sv[0]);
+    H[1] = w * (a * (1.0 - nl[1] * nl[1]) + b * sv[1] * sv[1]);
+    H[2] = w * (a * (1.0 - nl[2] * nl[2]) + b * sv[2] * sv[2]);
+    H[3] = w * (-a * nl[0] * nl[1] + b * sv[0] * sv[1]);
+    H[4] = w * (-a * nl[0] * nl[2] + b * sv[0] * sv[2]);
+    H[5] = w * (-a * nl[1] * nl[2] + b * sv[1] * sv[2]);
+    return w * f0;
+}
+
+// Friction lag data of one contact node at the start of a load step (node
+// pass, phase PH_LAG): the penetration and normal at the current
+// displacement u (the previous step's result) against the indenter at its
+// previous centre c_lag; the relative displacement starts at minus the
+// indenter's translation since, c_lag - c.
+__device__ inline void friction_lag(const InstState *s, const double x[3], double fr[8]) {
+#pragma unroll
+    for (int c = 0; c < 8; c++) fr[c] = 0.0;
+    if (s->lag_ok) {
+        Indenter il = s->ind;
+#pragma unroll
+        for (int d = 0; d < 3; d++) il.c[d] = s->c_lag[d];
+        double phl, nl[3], Hn[6];
+        sdf_eval(il, x, false, phl, nl, Hn);
+        if (phl < 0.0) {
+            fr[0] = s->mu_f * s->ind.k * (-phl);
+#pragma unroll
+            for (int d = 0; d < 3; d++) fr[1 + d] = nl[d];
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; d++) fr[4 + d] = s->c_lag[d] - s->ind.c[d];
+}
+
+// Relative displacement of a contact node for friction, with a trial
+// increment.
+__device__ inline void friction_rel(const double fr[8], const double inc[3], double dd[3]) {
+#pragma unroll
+    for (int d = 0; d < 3; d++) dd[d] = fr[4 + d] + inc[d];
+}
 
 // ---------------------------------------------------------------------------
 // Element + contact pass of one tile block (phases GRAD, EVAL_GRAD, TRIAL at
@@ -870,22 +955,41 @@ __device__ __forceinline__ void tile_element(const Topo<T> &tp, const InstBufs<T
             }
             double phi, nv[3], Hs[6];
             sdf_eval(s->ind, x, contact_full != 0, phi, nv, Hs);
-            T out[9];
+            double od[9];
 #pragma unroll
-            for (int c = 0; c < 9; c++) out[c] = (T)0;
+            for (int c = 0; c < 9; c++) od[c] = 0.0;
             if (phi < 0.0) {
                 const double kp = s->ind.k;
                 const double ec = 0.5 * kp * phi * phi;
-                acc[0] = ec;
-                acc[1] = ec;
+                acc[0] += ec;
+                acc[1] += ec;
 #pragma unroll
-                for (int d = 0; d < 3; d++) out[d] = (T)(kp * phi * nv[d]);
+                for (int d = 0; d < 3; d++) od[d] = kp * phi * nv[d];
                 const double nn[6] = {nv[0] * nv[0], nv[1] * nv[1], nv[2] * nv[2], nv[0] * nv[1], nv[0] * nv[2], nv[1] * nv[2]};
 #pragma unroll
-                for (int c = 0; c < 6; c++) out[3 + c] = (T)(kp * (nn[c] + (contact_full ? phi * Hs[c] : 0.0)));
+                for (int c = 0; c < 6; c++) od[3 + c] = kp * (nn[c] + (contact_full ? phi * Hs[c] : 0.0));
+            }
+            if (s->mu_f > 0.0) {
+                double fl[8];
+#pragma unroll
+                for (int c = 0; c < 8; c++) fl[c] = B.fr[8 * j + c];
+                if (fl[0] > 0.0) {
+                    double inc[3], dd[3], gf[3], Hf[6];
+#pragma unroll
+                    for (int d = 0; d < 3; d++)
+                        inc[d] = alpha != (T)0 ? (double)alpha * (double)B.dx[3 * i + d] : 0.0;
+                    friction_rel(fl, inc, dd);
+                    const double ef = friction_eval(fl, dd, s->eps_f, gf, Hf);
+                    acc[0] += ef;
+                    acc[1] += ef;
+#pragma unroll
+                    for (int d = 0; d < 3; d++) od[d] += gf[d];
+#pragma unroll
+                    for (int c = 0; c < 6; c++) od[3 + c] += Hf[c];
+                }
             }
 #pragma unroll
-            for (int c = 0; c < 9; c++) B.cp[9 * j + c] = out[c];
+            for (int c = 0; c < 9; c++) B.cp[9 * j + c] = (T)od[c];
         }
     }
     double sums[2] = {acc[0], acc[1]};
@@ -1048,9 +1152,15 @@ __device__ __forceinline__ void node_init(const Topo<T> &tp, const InstBufs<T> &
     double unused = 0.0;
     const int i = blk * kBlock + threadIdx.x;
     if (i < tp.n) {
-        if (apply)
+        if (apply) {
 #pragma unroll
             for (int d = 0; d < 3; d++) B.u[3 * i + d] = fma_t(alpha, B.dx[3 * i + d], B.u[3 * i + d]);
+            // contact nodes with friction also accumulate the increment in FP64
+            const int jc = tp.cidx[i];
+            if (s->mu_f > 0.0 && jc >= 0)
+#pragma unroll
+                for (int d = 0; d < 3; d++) B.fr[8 * jc + 4 + d] += (double)alpha * (double)B.dx[3 * i + d];
+        }
         T gsum[9];
 #pragma unroll
         for (int c = 0; c < 9; c++) gsum[c] = (T)0;
@@ -1246,6 +1356,21 @@ __device__ __forceinline__ void node_trial(const Topo<T> &tp, const InstBufs<T> 
 // g . dx on the first trial of a line search and the inertial energy of
 // implicit steps; other phases return.
 // ---------------------------------------------------------------------------
+// Friction lag data of the contact-eligible nodes of one node block.
+template <typename T>
+__device__ __forceinline__ void node_lag(const Topo<T> &tp, const InstBufs<T> &B, const InstState *s, int blk) {
+    const int i = blk * kBlock + threadIdx.x;
+    if (i >= tp.n) return;
+    const int j = tp.cidx[i];
+    if (j < 0) return;
+    double x[3], fl[8];
+#pragma unroll
+    for (int d = 0; d < 3; d++) x[d] = tp.X[3 * i + d] + (double)B.u[3 * i + d];
+    friction_lag(s, x, fl);
+#pragma unroll
+    for (int c = 0; c < 8; c++) B.fr[8 * j + c] = fl[c];
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_node(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
                                                  int nwork, const SolveParams *P) {
@@ -1270,13 +1395,16 @@ __global__ __launch_bounds__(kBlock) void k_node(const Topo<T> *topos, const Ins
         node_init(tp, B, s, w.y, phase == PH_INIT && s->apply != 0, phase == PH_GRAD, P->block_jacobi);
     else if (phase == PH_TRIAL && (s->need_gd || s->dt > 0.0))
         node_trial(tp, B, s, w.y);
+    else if (phase == PH_LAG)
+        node_lag(tp, B, s, w.y);
 }
 
 // Newton test on |g_free| against the load step's first residual, then CG
 // set-up with the inexact-Newton tolerance (finalising thread). Rounding
-// floor: once the residual sits below floor_rtol * r0 and two accepted
-// iterations in a row have not halved the smallest residual of the step, the
-// working precision cannot take it lower and the step ends with ST_FLOOR.
+// floor: once the residual sits below floor_rtol * r0 and two accepted steps
+// in a row whose predicted energy change lies within rounding have not halved
+// the smallest residual of the step, the working precision cannot take it
+// lower and the step ends with ST_FLOOR.
 __device__ inline void newton_test(InstState *s, const SolveParams *P, double gg, double rz) {
     s->gg = gg;
     const double gn = sqrt(gg);
@@ -1287,7 +1415,14 @@ __device__ inline void newton_test(InstState *s, const SolveParams *P, double gg
         s->gbest = gn;
         s->stall = 0;
     } else if (s->apply) {
-        if (gn <= 0.5 * s->gbest) {
+        // At the rounding floor the search direction is noise: accepted steps
+        // do not reduce the residual, and the energy change they predict,
+        // g.dx, lies within the energy's rounding noise. A step that predicts
+        // a resolvable decrease means the iteration is still limited by
+        // nonlinearity (stick-slip transitions of friction, large
+        // rotations), so it does not count.
+        const bool at_noise = fabs(s->gd) <= P->noise_eps * s->emag;
+        if (gn <= 0.5 * s->gbest || !at_noise) {
             s->stall = 0;
         } else {
             s->stall++;
@@ -1350,6 +1485,10 @@ __global__ __launch_bounds__(64) void k_finalize(const Topo<T> *topos, const Ins
     const int phase = s->phase;
     const int S = B.red_stride;
     const int nt = tp.ntile + tp.ncb, nn = (tp.n + kBlock - 1) / kBlock;
+    if (phase == PH_LAG) {
+        if (threadIdx.x == 0) s->phase = s->after_lag;
+        return;
+    }
     if (phase == PH_CG || phase == PH_EVAL_HV) {
         const double pq = wave_sum_partials(B.red + RS_PQ * S, nt);
         const double rz = wave_sum_partials(B.red + RS_RZ * S, nn);
@@ -1429,8 +1568,10 @@ __global__ __launch_bounds__(64) void k_finalize(const Topo<T> *topos, const Ins
 
 // ---------------------------------------------------------------------------
 // Contact patch of one instance at its current state: one block walks the
-// eligible nodes in ascending order and compacts those with phi < 0 (ordered
-// scan): ids, forces on the skin -k phi n, phi, count and FP64 resultant.
+// eligible nodes in ascending order and compacts those that carry a contact
+// force, phi < 0 or friction from the lag state (ordered scan): ids, forces
+// on the skin -k min(0, phi) n minus the friction gradient, phi, count and
+// FP64 resultant.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(1024) void k_contact_patch(const Topo<T> *topos, const InstBufs<T> *bufs, int inst,
@@ -1443,6 +1584,8 @@ __global__ __launch_bounds__(1024) void k_contact_patch(const Topo<T> *topos, co
     const InstBufs<T> &B = bufs[inst];
     const Topo<T> &tp = topos[B.topo];
     const Indenter ind = B.s->ind;
+    const bool fric = B.s->mu_f > 0.0;
+    const double eps_f = B.s->eps_f;
     if (threadIdx.x == 0) {
         base_s = 0;
         F_s[0] = F_s[1] = F_s[2] = 0.0;
@@ -1451,7 +1594,7 @@ __global__ __launch_bounds__(1024) void k_contact_patch(const Topo<T> *topos, co
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int start = 0; start < tp.nc; start += 1024) {
         const int j = start + threadIdx.x;
-        double phi = 0.0, nv[3] = {0.0, 0.0, 0.0}, Hs[6];
+        double phi = 0.0, nv[3] = {0.0, 0.0, 0.0}, Hs[6], gf[3] = {0.0, 0.0, 0.0};
         int i = -1;
         bool act = false;
         if (j < tp.nc) {
@@ -1461,10 +1604,21 @@ __global__ __launch_bounds__(1024) void k_contact_patch(const Topo<T> *topos, co
             for (int d = 0; d < 3; d++) x[d] = tp.X[3 * i + d] + (double)B.u[3 * i + d];
             sdf_eval(ind, x, false, phi, nv, Hs);
             act = phi < 0.0;
+            if (fric) {
+                double fl[8], Hf[6], dd[3];
+                const double zero[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int c = 0; c < 8; c++) fl[c] = B.fr[8 * j + c];
+                if (fl[0] > 0.0) {
+                    friction_rel(fl, zero, dd);
+                    friction_eval(fl, dd, eps_f, gf, Hf);
+                    act = true;
+                }
+            }
         }
         double fv[3];
 #pragma unroll
-        for (int d = 0; d < 3; d++) fv[d] = act ? -ind.k * phi * nv[d] : 0.0;
+        for (int d = 0; d < 3; d++) fv[d] = act ? (phi < 0.0 ? -ind.k * phi * nv[d] : 0.0) - gf[d] : 0.0;
         const unsigned long long mask = __ballot(act);
         const int before = __popcll(mask & ((1ull << lane) - 1ull));
         double sf[3];

@@ -355,6 +355,14 @@ struct fem_batch {
     size_t elem() const { return precision == FEM_PREC_FP32 ? sizeof(float) : sizeof(double); }
 };
 
+// Friction settings of a job: coefficient, smoothing length and its lag state
+// (lag_ok = 0: none, so the first step has no friction).
+struct FrictionInit {
+    double mu_f = 0.0, eps_f = 1e-6;
+    int lag_ok = 0;
+    double c_lag[3] = {0.0, 0.0, 0.0};
+};
+
 struct fem_mesh {
     fem_batch *batch = nullptr;
     int n = 0, m = 0;
@@ -362,6 +370,7 @@ struct fem_mesh {
     double E = 0, nu = 0, density = 0;
     double dt = 0;                  // implicit time step; 0 = quasi-static
     int model = FEM_MODEL_NEOHOOKEAN;
+    FrictionInit friction;          // coefficient, slip length and lag state of the next step
     Indenter ind{};
 };
 
@@ -606,6 +615,7 @@ int alloc_instance(fem_batch *B, int slot, int topo) {
     const size_t o_cp = A.take<T>(9 * (size_t)std::max(tp.nc, 1)), o_q = A.take<T>(3 * (size_t)n);
     const size_t o_red = A.take<double>(RS_COUNT * (size_t)stride);
     const size_t o_v = A.take<T>(3 * (size_t)n), o_ut = A.take<T>(3 * (size_t)n);
+    const size_t o_fr = A.take<double>(8 * (size_t)std::max(tp.nc, 1));
     InstRec &R = B->insts[slot];
     HIP_TRY(hipMalloc(&R.arena, A.off));
     HIP_TRY(hipMemsetAsync(R.arena, 0, A.off, B->stream));
@@ -623,6 +633,7 @@ int alloc_instance(fem_batch *B, int slot, int topo) {
     b.red = (double *)(base + o_red);
     b.v = (T *)(base + o_v);
     b.ut = (T *)(base + o_ut);
+    b.fr = (double *)(base + o_fr);
     b.s = B->d_states + slot;
     R.topo = topo;
     R.live = true;
@@ -1039,6 +1050,12 @@ int check_indenter(int32_t kind, const double *shape, int32_t n_shape, const dou
     return FEM_OK;
 }
 
+int check_friction(double mu_f, double eps) {
+    if (!is_finite(mu_f) || mu_f < 0.0) return fail(FEM_E_INVALID, "friction coefficient must be finite and >= 0");
+    if (mu_f > 0.0 && !(is_finite(eps) && eps > 0.0)) return fail(FEM_E_INVALID, "friction needs a slip length > 0");
+    return FEM_OK;
+}
+
 int check_material(double E, double nu, double density) {
     if (!is_finite(E) || !is_finite(nu) || !is_finite(density) || !(E > 0) || !(nu > -1.0) || !(nu < 0.5) ||
         density < 0)
@@ -1056,10 +1073,25 @@ int check_params(const fem_solve_params &P) {
 }
 
 // A job's initial state: material, pose schedule, counters, phase GRAD.
+// A batch job's friction: its lag state at the start is u = 0 with the
+// indenter at c0.
+FrictionInit job_friction(const fem_indentation *job) {
+    FrictionInit f;
+    f.mu_f = job->friction;
+    f.eps_f = job->friction > 0.0 ? job->friction_eps : 1e-6;
+    f.lag_ok = 1;
+    for (int d = 0; d < 3; d++) f.c_lag[d] = job->c0[d];
+    return f;
+}
+
 void init_job_state(InstState &s, double E, double nu, const Indenter &ind, const double c0[3], const double dir[3],
-                    double depth, int steps, double dt, double rho, int model) {
+                    double depth, int steps, double dt, double rho, int model, const FrictionInit &fr) {
     std::memset(&s, 0, sizeof s);
     s.model = model;
+    s.mu_f = fr.mu_f;
+    s.eps_f = fr.eps_f;
+    s.lag_ok = fr.lag_ok;
+    for (int d = 0; d < 3; d++) s.c_lag[d] = fr.c_lag[d];
     s.dt = dt;
     s.rho = rho;
     s.mdt2 = dt > 0.0 ? rho / (dt * dt) : 0.0;
@@ -1076,7 +1108,8 @@ void init_job_state(InstState &s, double E, double nu, const Indenter &ind, cons
     const double f = depth / (double)steps;
     for (int d = 0; d < 3; d++) s.ind.c[d] = c0[d] + f * dir[d];
     s.step_started = 1;
-    s.phase = PH_GRAD;
+    s.after_lag = PH_GRAD;
+    s.phase = s.mu_f > 0.0 ? PH_LAG : PH_GRAD;
 }
 
 void fill_step_info(const InstState &s, int m, fem_step_info *info) {
@@ -1315,10 +1348,14 @@ int fem_step(fem_mesh *M, const fem_solve_params *params, fem_step_info *info) {
     TRY(params_to_device(B, P));
     const double zero[3] = {0.0, 0.0, 0.0};
     const int hint = B->h_states[0].last_cg;
-    init_job_state(B->h_states[0], M->E, M->nu, M->ind, M->ind.c, zero, 0.0, 1, M->dt, M->density, M->model);
+    init_job_state(B->h_states[0], M->E, M->nu, M->ind, M->ind.c, zero, 0.0, 1, M->dt, M->density, M->model,
+                   M->friction);
     B->h_states[0].last_cg = hint;
     TRY(write_state(B, 0));
     TRY(run(B, 0, nullptr));
+    // the state reached is the next step's friction lag state
+    M->friction.lag_ok = 1;
+    for (int d = 0; d < 3; d++) M->friction.c_lag[d] = M->ind.c[d];
     fem_step_info local{};
     fill_step_info(B->h_states[0], M->m, &local);
     if (info) *info = local;
@@ -1346,7 +1383,19 @@ int fem_set_displacements(fem_mesh *M, const double *u, int64_t count) {
     // The predictor follows, so the stored velocity is kept as it is.
     HIP_TRY(hipMemcpyAsync(inst_ptr(M->batch, 0, V_UT), inst_ptr(M->batch, 0, V_U), 3 * (size_t)M->n * M->batch->elem(),
                            hipMemcpyDeviceToDevice, M->batch->stream));
+    // u at the current indenter pose becomes the friction lag state
+    M->friction.lag_ok = M->have_indenter ? 1 : 0;
+    for (int d = 0; d < 3; d++) M->friction.c_lag[d] = M->ind.c[d];
     return sync(M->batch);
+}
+
+int fem_set_friction(fem_mesh *M, double mu_f, double eps) {
+    g_last_error.clear();
+    if (!M) return fail(FEM_E_INVALID, "null mesh");
+    TRY(check_friction(mu_f, eps));
+    M->friction.mu_f = mu_f;
+    M->friction.eps_f = mu_f > 0.0 ? eps : 1e-6;
+    return FEM_OK;
 }
 
 int fem_set_model(fem_mesh *M, int32_t model) {
@@ -1434,8 +1483,11 @@ int fem_eval_gradient(fem_mesh *M, double *g, int64_t capacity, double *energy, 
     fem_default_params(&P, B->precision);
     TRY(params_to_device(B, P));
     const double zero[3] = {0.0, 0.0, 0.0};
-    init_job_state(B->h_states[0], M->E, M->nu, M->ind, M->ind.c, zero, 0.0, 1, M->dt, M->density, M->model);
-    B->h_states[0].phase = PH_EVAL_GRAD;
+    init_job_state(B->h_states[0], M->E, M->nu, M->ind, M->ind.c, zero, 0.0, 1, M->dt, M->density, M->model,
+                   M->friction);
+    // with friction, the node pass forms the lag data first
+    B->h_states[0].after_lag = PH_EVAL_GRAD;
+    B->h_states[0].phase = M->friction.mu_f > 0.0 ? PH_LAG : PH_EVAL_GRAD;
     TRY(write_state(B, 0));
     TRY(run(B, 2, nullptr));
     if (energy) *energy = B->h_states[0].E;
@@ -1459,8 +1511,11 @@ int fem_eval_hessvec(fem_mesh *M, const fem_solve_params *params, const double *
     TRY(set_device(B));
     TRY(params_to_device(B, P));
     const double zero[3] = {0.0, 0.0, 0.0};
-    init_job_state(B->h_states[0], M->E, M->nu, M->ind, M->ind.c, zero, 0.0, 1, M->dt, M->density, M->model);
-    B->h_states[0].phase = PH_EVAL_GRAD;
+    init_job_state(B->h_states[0], M->E, M->nu, M->ind, M->ind.c, zero, 0.0, 1, M->dt, M->density, M->model,
+                   M->friction);
+    // with friction, the node pass forms the lag data first
+    B->h_states[0].after_lag = PH_EVAL_GRAD;
+    B->h_states[0].phase = M->friction.mu_f > 0.0 ? PH_LAG : PH_EVAL_GRAD;
     TRY(write_state(B, 0));
     TRY(run(B, 2, nullptr));
     // q = H v through the CG kernels with z = v, p_prev = 0, beta = 0.
@@ -1520,6 +1575,7 @@ int fem_batch_add_job(fem_batch *B, int32_t mesh_id, double E, double nu, const 
         return fail(FEM_E_INVALID, "implicit steps need dt >= 0 and density > 0");
     if (job->model != FEM_MODEL_NEOHOOKEAN && job->model != FEM_MODEL_COROTATIONAL)
         return fail(FEM_E_INVALID, "unknown constitutive model");
+    TRY(check_friction(job->friction, job->friction_eps));
     int slot = -1;
     for (int i = 0; i < B->capacity; i++)
         if (!B->insts[i].live) {
@@ -1531,7 +1587,7 @@ int fem_batch_add_job(fem_batch *B, int32_t mesh_id, double E, double nu, const 
     TRY(B->precision == FEM_PREC_FP32 ? alloc_instance<float>(B, slot, mesh_id)
                                      : alloc_instance<double>(B, slot, mesh_id));
     init_job_state(B->h_states[slot], E, nu, ind, job->c0, job->direction, job->depth, job->steps, job->dt,
-                   job->density, job->model);
+                   job->density, job->model, job_friction(job));
     TRY(write_state(B, slot));
     *job_id = slot;
     return FEM_OK;
@@ -1550,13 +1606,14 @@ int fem_batch_restart_job(fem_batch *B, int32_t job_id, double E, double nu, con
         return fail(FEM_E_INVALID, "implicit steps need dt >= 0 and density > 0");
     if (job->model != FEM_MODEL_NEOHOOKEAN && job->model != FEM_MODEL_COROTATIONAL)
         return fail(FEM_E_INVALID, "unknown constitutive model");
+    TRY(check_friction(job->friction, job->friction_eps));
     TRY(set_device(B));
     const int n = B->topos[B->insts[job_id].topo].n;
     for (int which : {V_U, V_V, V_UT})
         HIP_TRY(hipMemsetAsync(inst_ptr(B, job_id, which), 0, 3 * (size_t)n * B->elem(), B->stream));
     const int hint = B->h_states[job_id].last_cg;
     init_job_state(B->h_states[job_id], E, nu, ind, job->c0, job->direction, job->depth, job->steps, job->dt,
-                   job->density, job->model);
+                   job->density, job->model, job_friction(job));
     B->h_states[job_id].last_cg = hint;
     // Stream-ordered before any later kernel or state read; the pinned source
     // slot is not written again until the host has synchronised.
@@ -1768,6 +1825,7 @@ int fem_batch_job_footprint(const fem_batch *B, int32_t mesh_id, int64_t *bytes)
     add(RS_COUNT * stride * sizeof(double));
     add(3 * (size_t)tp.n * w);
     add(3 * (size_t)tp.n * w);
+    add(8 * (size_t)std::max(tp.nc, 1) * sizeof(double));
     *bytes = (int64_t)total;
     return FEM_OK;
 }

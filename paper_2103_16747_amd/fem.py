@@ -27,7 +27,7 @@ PRECISIONS = {"fp64": FEM_PREC_FP64, "fp32": FEM_PREC_FP32}
 # Entry points declared in include/fem.h.
 EXPORTS = ("fem_create_mesh", "fem_destroy_mesh", "fem_set_material", "fem_set_indenter", "fem_default_params",
            "fem_step", "fem_get_displacements", "fem_set_displacements", "fem_get_contact_patch",
-           "fem_get_mesh_info", "fem_get_tet_stress", "fem_get_displacement_stats", "fem_set_model", "fem_set_dynamics", "fem_get_velocities", "fem_set_velocities", "fem_eval_gradient", "fem_eval_hessvec", "fem_set_kernel_timing",
+           "fem_get_mesh_info", "fem_get_tet_stress", "fem_get_displacement_stats", "fem_set_model", "fem_set_friction", "fem_set_dynamics", "fem_get_velocities", "fem_set_velocities", "fem_eval_gradient", "fem_eval_hessvec", "fem_set_kernel_timing",
            "fem_get_kernel_timing", "fem_batch_create", "fem_batch_destroy", "fem_batch_add_mesh",
            "fem_batch_mesh_info", "fem_batch_add_job", "fem_batch_restart_job", "fem_batch_remove_job", "fem_batch_run", "fem_batch_job_info",
            "fem_batch_get_displacements", "fem_batch_get_velocities", "fem_batch_get_tet_stress",
@@ -69,7 +69,8 @@ class fem_step_info(C.Structure):
 class fem_indentation(C.Structure):
     _fields_ = [("kind", C.c_int32), ("shape", C.c_double * 4), ("R", C.c_double * 9), ("c0", C.c_double * 3),
                 ("direction", C.c_double * 3), ("depth", C.c_double), ("steps", C.c_int32), ("k_penalty", C.c_double),
-                ("dt", C.c_double), ("density", C.c_double), ("model", C.c_int32)]
+                ("dt", C.c_double), ("density", C.c_double), ("model", C.c_int32),
+                ("friction", C.c_double), ("friction_eps", C.c_double)]
 
 
 class fem_job_info(C.Structure):
@@ -112,6 +113,7 @@ def load(path: str = LIB_PATH):
     L.fem_set_displacements.argtypes = [vp, dp, C.c_int64]
     L.fem_set_dynamics.argtypes = [vp, C.c_double]
     L.fem_set_model.argtypes = [vp, C.c_int32]
+    L.fem_set_friction.argtypes = [vp, C.c_double, C.c_double]
     L.fem_get_tet_stress.argtypes = [vp, dp, dp, C.c_int64]
     L.fem_get_displacement_stats.argtypes = [vp, dp, dp]
     L.fem_batch_get_tet_stress.argtypes = [vp, C.c_int32, dp, dp, C.c_int64]
@@ -365,6 +367,9 @@ class FemMesh:
     def set_model(self, model):
         _check(load().fem_set_model(self.h, int(model)))
 
+    def set_friction(self, mu_f, eps=1e-6):
+        _check(load().fem_set_friction(self.h, float(mu_f), float(eps)))
+
     def tet_stress(self):
         return fem_get_tet_stress(self.h, self.m)
 
@@ -460,6 +465,8 @@ def make_indentation(ind) -> fem_indentation:
     j.dt = float(getattr(ind, "dt", 0.0))
     j.density = float(getattr(ind, "density", 1100.0))
     j.model = int(getattr(ind, "model", FEM_MODEL_NEOHOOKEAN))
+    j.friction = float(getattr(ind, "friction", 0.0))
+    j.friction_eps = float(getattr(ind, "friction_eps", 1e-6))
     return j
 
 
