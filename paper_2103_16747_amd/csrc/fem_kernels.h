@@ -1142,7 +1142,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T
 // gradient (m/dt^2)(u - ut), (m/dt^2) I to the node block, and the inertial
 // energy (m/2dt^2)|u - ut|^2 to its own partial sum.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool FRIC>
 __device__ __forceinline__ void node_init(const Topo<T> &tp, const InstBufs<T> &B, const InstState *s, int blk,
                                           bool apply, bool step_start, int block_jacobi) {
     const T alpha = (T)s->alpha_ls;
@@ -1156,10 +1156,12 @@ __device__ __forceinline__ void node_init(const Topo<T> &tp, const InstBufs<T> &
 #pragma unroll
             for (int d = 0; d < 3; d++) B.u[3 * i + d] = fma_t(alpha, B.dx[3 * i + d], B.u[3 * i + d]);
             // contact nodes with friction also accumulate the increment in FP64
-            const int jc = tp.cidx[i];
-            if (s->mu_f > 0.0 && jc >= 0)
+            if (FRIC && s->mu_f > 0.0) {
+                const int jc = tp.cidx[i];
+                if (jc >= 0)
 #pragma unroll
-                for (int d = 0; d < 3; d++) B.fr[8 * jc + 4 + d] += (double)alpha * (double)B.dx[3 * i + d];
+                    for (int d = 0; d < 3; d++) B.fr[8 * jc + 4 + d] += (double)alpha * (double)B.dx[3 * i + d];
+            }
         }
         T gsum[9];
 #pragma unroll
@@ -1371,7 +1373,7 @@ __device__ __forceinline__ void node_lag(const Topo<T> &tp, const InstBufs<T> &B
     for (int c = 0; c < 8; c++) B.fr[8 * j + c] = fl[c];
 }
 
-template <typename T>
+template <typename T, bool FRIC>
 __global__ __launch_bounds__(kBlock) void k_node(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
                                                  int nwork, const SolveParams *P) {
     const int L = logical_block();
@@ -1392,10 +1394,10 @@ __global__ __launch_bounds__(kBlock) void k_node(const Topo<T> *topos, const Ins
             node_update<T, false>(tp, B, s, w.y, phase == PH_EVAL_HV);
     }
     else if (phase == PH_GRAD || phase == PH_EVAL_GRAD || phase == PH_INIT)
-        node_init(tp, B, s, w.y, phase == PH_INIT && s->apply != 0, phase == PH_GRAD, P->block_jacobi);
+        node_init<T, FRIC>(tp, B, s, w.y, phase == PH_INIT && s->apply != 0, phase == PH_GRAD, P->block_jacobi);
     else if (phase == PH_TRIAL && (s->need_gd || s->dt > 0.0))
         node_trial(tp, B, s, w.y);
-    else if (phase == PH_LAG)
+    else if (FRIC && phase == PH_LAG)
         node_lag(tp, B, s, w.y);
 }
 

@@ -299,6 +299,7 @@ struct KernelTimer {
 // A captured round of kernels for one CG chunk length.
 struct RoundGraph {
     int chunk = 0;
+    int variant = 0;        // kernel instances captured (see kernel_variant)
     hipGraphExec_t exec = nullptr;
 };
 
@@ -337,7 +338,8 @@ struct fem_batch {
     int nwork_tile = 0, nwork_node = 0, cap_work_tile = 0, cap_work_node = 0;
     int *d_live = nullptr;
     int nlive = 0;
-    int n_law[2] = {0, 0};                  // jobs in the tables per constitutive law
+    int n_law[2] = {0, 0};                  // running jobs per constitutive law
+    int n_fric = 0;                         // running jobs with friction
     SolveParams *d_params = nullptr;
     SolveParams *h_params = nullptr;
     bool tables_dirty = true;
@@ -662,12 +664,10 @@ int rebuild_tables(fem_batch *B) {
     std::vector<int2> wt, wn;
     std::vector<int> live;
     int max_t = 0, max_nb = 0;
-    B->n_law[0] = B->n_law[1] = 0;
     for (int i = 0; i < B->capacity; i++) {
         InstRec &R = B->insts[i];
         R.in_tables = R.live && running_phase(B->h_states[i].phase);
         if (!R.in_tables) continue;
-        B->n_law[B->h_states[i].model == LAW_CR ? 1 : 0]++;
         const TopoRec &tp = B->topos[R.topo];
         max_t = std::max(max_t, tp.ntile + tp.ncb);
         max_nb = std::max(max_nb, ceil_div(tp.n, kBlock));
@@ -756,7 +756,7 @@ int enqueue_round(fem_batch *B, int chunk) {
     const Topo<T> *tp = (const Topo<T> *)B->d_topos;
     const InstBufs<T> *bf = (const InstBufs<T> *)B->d_bufs;
     const int gt = pad8(B->nwork_tile), gn = pad8(B->nwork_node), nl = B->nlive;
-    const bool nh = B->n_law[0] > 0, cr = B->n_law[1] > 0;
+    const bool nh = B->n_law[0] > 0, cr = B->n_law[1] > 0, fric = B->n_fric > 0;
     for (int c = 0; c < chunk; c++) {
         // one tile launch per constitutive law present (blocks of jobs on the
         // other law return at once)
@@ -767,9 +767,14 @@ int enqueue_round(fem_batch *B, int chunk) {
         if (cr)
             launch_timed(B, slot, !nh, true, k_tile<T, LAW_CR>, dim3(gt), dim3(kBlock), tp, bf,
                          (const int2 *)B->d_work_tile, B->nwork_tile, (const SolveParams *)B->d_params);
+        // the node pass with the friction phases only when a job needs them
         slot = timer_slot(B, FEM_KERNEL_NODE);
-        launch_timed(B, slot, true, true, k_node<T>, dim3(gn), dim3(kBlock), tp, bf, (const int2 *)B->d_work_node,
-                     B->nwork_node, (const SolveParams *)B->d_params);
+        if (fric)
+            launch_timed(B, slot, true, true, k_node<T, true>, dim3(gn), dim3(kBlock), tp, bf,
+                         (const int2 *)B->d_work_node, B->nwork_node, (const SolveParams *)B->d_params);
+        else
+            launch_timed(B, slot, true, true, k_node<T, false>, dim3(gn), dim3(kBlock), tp, bf,
+                         (const int2 *)B->d_work_node, B->nwork_node, (const SolveParams *)B->d_params);
         slot = timer_slot(B, FEM_KERNEL_FINALIZE);
         launch_timed(B, slot, true, true, k_finalize<T>, dim3(nl), dim3(64), tp, bf, (const int *)B->d_live, nl,
                      (const SolveParams *)B->d_params);
@@ -782,19 +787,36 @@ int enqueue_round(fem_batch *B, int chunk) {
 // steps). With kernel timing
 // on, rounds are launched kernel by kernel so events can bracket single
 // kernels (event records cannot be captured into the graph here).
+// Kernel instances a round needs, from the host's view of the running jobs
+// (laws present, friction present), as bits 1 (Neo-Hookean), 2
+// (co-rotational), 4 (friction). A job's law and friction are set with its
+// state by the host, so this view is current at every round.
+int kernel_variant(fem_batch *B) {
+    B->n_law[0] = B->n_law[1] = 0;
+    B->n_fric = 0;
+    for (int i = 0; i < B->capacity; i++) {
+        if (!B->insts[i].live || !B->insts[i].in_tables || !running_phase(B->h_states[i].phase)) continue;
+        B->n_law[B->h_states[i].model == LAW_CR ? 1 : 0]++;
+        if (B->h_states[i].mu_f > 0.0) B->n_fric++;
+    }
+    return (B->n_law[0] > 0 ? 1 : 0) | (B->n_law[1] > 0 ? 2 : 0) | (B->n_fric > 0 ? 4 : 0);
+}
+
 template <typename T>
 int launch_round(fem_batch *B, int chunk) {
     if (pad8(B->nwork_tile) == 0 || pad8(B->nwork_node) == 0 || B->nlive == 0) return FEM_OK;
+    const int variant = kernel_variant(B);
     if (!B->use_graphs || B->timer.every > 0) return enqueue_round<T>(B, std::max(1, std::min(64, chunk)));
     // graph lengths: multiples of 4 up to 32, of 8 up to 64
     int c = std::max(4, std::min(64, chunk));
     c = c <= 32 ? (c + 3) / 4 * 4 : (c + 7) / 8 * 8;
     int gi = -1;
     for (int i = 0; i < (int)B->graphs.size(); i++)
-        if (B->graphs[i].chunk == c) gi = i;
+        if (B->graphs[i].chunk == c && B->graphs[i].variant == variant) gi = i;
     if (gi < 0) {
         RoundGraph G;
         G.chunk = c;
+        G.variant = variant;
         hipGraph_t graph = nullptr;
         HIP_TRY(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
         const int rc = enqueue_round<T>(B, c);

@@ -213,3 +213,38 @@ def test_friction_arguments_are_validated():
     with pytest.raises(fem.FemError):
         batch.add_job(mid, ind, E0, NU0)
     batch.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_switching_law_and_friction_between_steps(oracle_lib, meshes, precision):
+    """One single-mesh handle: a frictionless Neo-Hookean step, then the
+    co-rotational law with friction for the next step (the kernels a round
+    launches follow the jobs' current settings)."""
+    say("case switch law and friction", precision)
+    mesh = meshes["cube8"]
+    c1, c2 = punch_path()[2], punch_path()[5]
+    dev = fem.FemMesh(mesh.X, mesh.tets, mesh.fixed, precision=precision)
+    dev.set_material(E0, NU0, 1100.0)
+    place(dev, c1)
+    P = dev.default_params(newton_rtol=1e-10, cg_rtol=1e-10) if precision == "fp64" else dev.default_params()
+    assert dev.step(P)["status"] >= 0
+    u1 = dev.displacements()
+    dev.set_model(fem.FEM_MODEL_COROTATIONAL)
+    dev.set_friction(MU_F, EPS)
+    place(dev, c2)
+    assert dev.step(P)["status"] >= 0
+    u2 = dev.displacements()
+    orc = oracle_lib.Solver(mesh.X, mesh.tets, mesh.fixed, E=E0, nu=NU0)
+    Po = oracle_lib.default_params(newton_rtol=1e-11, cg_rtol=1e-11)
+    place(orc, c1)
+    r1, i1 = orc.step(np.zeros((mesh.n, 3)), Po)
+    orc.set_model(oracle_lib.COROTATIONAL)
+    orc.set_friction(MU_F, EPS)
+    orc.set_friction_lag(r1, c1)
+    place(orc, c2)
+    r2, i2 = orc.step(r1, Po)
+    assert i1["status"] == 0 and i2["status"] == 0
+    e1, e2 = e_inf(u1, r1), e_inf(u2, r2)
+    say("e_inf %.3e %.3e" % (e1, e2))
+    assert e1 <= SOLVE[precision] and e2 <= SOLVE[precision]
+    dev.close()
