@@ -86,7 +86,8 @@ typedef struct {
     double newton_rtol;  /* converged when |g_free| <= max(newton_rtol * |g_free(start)|, newton_atol) */
     double newton_atol;  /* newtons */
     int32_t max_newton;
-    double cg_rtol;      /* floor of the CG forcing term eta = clamp(|g|/|g_start|, cg_rtol, cg_eta_max) */
+    double cg_rtol;      /* floor of the CG forcing term
+                            eta = clamp((|g|/|g_start|)^cg_eta_power, cg_rtol, cg_eta_max) */
     double cg_eta_max;
     int32_t max_cg;      /* per Newton iteration */
     int32_t precond;     /* FEM_PRECOND_* */
@@ -98,6 +99,11 @@ typedef struct {
                                  step's smallest |g_free|, the step ends with
                                  FEM_W_FLOOR if |g_free| <= newton_floor_rtol *
                                  |g_free(start)|; 0 disables the exit */
+    double cg_eta_power; /* exponent p of the forcing term, in (0, 1]: 1 keeps
+                            Newton's quadratic convergence with tight late
+                            solves; p < 1 gives order 1 + p with fewer CG
+                            iterations per Newton iteration (default 0.75 on
+                            the FP32 path, 1 on FP64) */
 } fem_solve_params;
 
 typedef struct {

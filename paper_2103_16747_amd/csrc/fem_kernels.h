@@ -67,7 +67,7 @@ struct Indenter {
 };
 
 struct SolveParams {
-    double newton_rtol, newton_atol, cg_rtol, cg_eta_max, c1, noise_eps, floor_rtol;
+    double newton_rtol, newton_atol, cg_rtol, cg_eta_max, c1, noise_eps, floor_rtol, eta_power;
     int max_newton, max_cg, block_jacobi, contact_full, max_halvings, pad;
 };
 
@@ -1443,7 +1443,10 @@ __device__ inline void newton_test(InstState *s, const SolveParams *P, double gg
     } else if (s->newton_it >= P->max_newton) {
         end_step(s, ST_NOT_CONVERGED);
     } else {
-        const double eta = fmin(P->cg_eta_max, fmax(P->cg_rtol, gn / s->r0));
+        // inexact Newton: forcing term (|g| / |g_start|)^p, p = 1/2 by default
+        // (superlinear of order 1 + p, without tight solves late in a step)
+        const double rel = gn / s->r0;
+        const double eta = fmin(P->cg_eta_max, fmax(P->cg_rtol, P->eta_power == 1.0 ? rel : pow(rel, P->eta_power)));
         s->tol2 = eta * eta * gg;
         s->rz = rz;
         s->rr = gg;

@@ -724,6 +724,7 @@ int params_to_device(fem_batch *B, const fem_solve_params &P) {
     d.newton_atol = P.newton_atol;
     d.cg_rtol = P.cg_rtol;
     d.cg_eta_max = P.cg_eta_max;
+    d.eta_power = P.cg_eta_power;
     d.c1 = P.c1;
     d.floor_rtol = P.newton_floor_rtol;
     d.noise_eps = 16.0 * (B->precision == FEM_PREC_FP32 ? (double)std::numeric_limits<float>::epsilon()
@@ -1087,7 +1088,7 @@ int check_material(double E, double nu, double density) {
 
 int check_params(const fem_solve_params &P) {
     if (!(P.newton_rtol >= 0) || !(P.newton_atol >= 0) || P.max_newton < 0 || !(P.cg_rtol > 0) ||
-        !(P.cg_eta_max >= P.cg_rtol) || P.max_cg < 1 || (P.precond != 0 && P.precond != 1) || !(P.c1 >= 0) ||
+        !(P.cg_eta_max >= P.cg_rtol) || !(P.cg_eta_power > 0.0 && P.cg_eta_power <= 1.0) || P.max_cg < 1 || (P.precond != 0 && P.precond != 1) || !(P.c1 >= 0) ||
         !(P.c1 < 1) || P.max_halvings < 0 || P.max_halvings > 200 || !(P.newton_floor_rtol >= 0) ||
         !(P.newton_floor_rtol < 1))
         return fail(FEM_E_INVALID, "invalid solve parameters");
@@ -1283,11 +1284,12 @@ const char *fem_last_error(void) { return g_last_error.c_str(); }
 
 void fem_default_params(fem_solve_params *P, int32_t precision) {
     if (!P) return;
-    P->newton_rtol = precision == FEM_PREC_FP32 ? 1e-5 : 1e-8;
+    P->newton_rtol = precision == FEM_PREC_FP32 ? 3e-6 : 1e-8;
     P->newton_atol = precision == FEM_PREC_FP32 ? 1e-9 : 1e-14;
     P->max_newton = 50;
     P->cg_rtol = precision == FEM_PREC_FP32 ? 1e-5 : 1e-8;
     P->cg_eta_max = 0.1;
+    P->cg_eta_power = precision == FEM_PREC_FP32 ? 0.75 : 1.0;
     P->max_cg = 100000;
     P->precond = FEM_PRECOND_BLOCK;
     P->contact_hessian = 1;

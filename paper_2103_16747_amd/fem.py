@@ -53,7 +53,7 @@ class fem_solve_params(C.Structure):
     _fields_ = [("newton_rtol", C.c_double), ("newton_atol", C.c_double), ("max_newton", C.c_int32),
                 ("cg_rtol", C.c_double), ("cg_eta_max", C.c_double), ("max_cg", C.c_int32),
                 ("precond", C.c_int32), ("contact_hessian", C.c_int32), ("c1", C.c_double),
-                ("max_halvings", C.c_int32), ("newton_floor_rtol", C.c_double)]
+                ("max_halvings", C.c_int32), ("newton_floor_rtol", C.c_double), ("cg_eta_power", C.c_double)]
 
 
 class fem_step_info(C.Structure):

@@ -52,6 +52,7 @@ def test_default_params(lib):
     assert p64.newton_rtol == 1e-8 and p64.precond == 1 and p64.contact_hessian == 1
     assert p32.newton_rtol > p64.newton_rtol
     assert p64.newton_floor_rtol > p64.newton_rtol and p32.newton_floor_rtol > p32.newton_rtol
+    assert p64.cg_eta_power == 1.0 and p32.cg_eta_power == 0.75
 
 
 def _create(lib, X, T, F):
