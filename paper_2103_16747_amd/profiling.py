@@ -2,6 +2,7 @@
 
     python -m paper_2103_16747_amd.profiling stats  <rocprof dir> [--kernel REGEX]
     python -m paper_2103_16747_amd.profiling traffic <fetch dir> <write dir> --copy-bytes N [--kernel REGEX]
+    python -m paper_2103_16747_amd.profiling counters <pmc dir> --kernel REGEX
 
 `stats` reads a --kernel-trace --stats run (kernel_stats.csv / kernel_trace.csv)
 and prints per-kernel calls and durations. `traffic` reads two --pmc runs, one
@@ -90,6 +91,24 @@ def traffic(fetch_dir, write_dir, copy_bytes, pattern, copy_pattern=r"copy|eleme
             "traffic_bytes_per_dispatch": fetch + write}
 
 
+def counter_means(d, pattern):
+    """Per-dispatch means of every counter of a --pmc run for the kernels
+    matching `pattern`, with the number of dispatches and their mean
+    duration (us, from the dispatch timestamps)."""
+    tot, cnt, dur = {}, {}, {}
+    for r in csv.DictReader(open(_find(d, "counter_collection.csv"))):
+        if not re.search(pattern, r["Kernel_Name"]):
+            continue
+        name = r["Counter_Name"]
+        tot[name] = tot.get(name, 0.0) + float(r["Counter_Value"])
+        cnt[name] = cnt.get(name, 0) + 1
+        dur[r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+    if not dur:
+        raise RuntimeError("no counters for " + pattern)
+    return {"dispatches": len(dur), "mean_duration_us": statistics.mean(dur.values()),
+            "per_dispatch": {k: tot[k] / cnt[k] for k in sorted(tot)}}
+
+
 def kernel_source_hash(text=None):
     """SHA-256 of the device source with comments and blank lines removed;
     traffic figures are valid only for the kernels they were taken on."""
@@ -119,6 +138,9 @@ def main(argv=None):
     b.add_argument("--copy-bytes", type=float, required=True)
     b.add_argument("--kernel", required=True)
     b.add_argument("--json", default=None, help="also write the result here, with the kernel source hash")
+    c = sub.add_parser("counters")
+    c.add_argument("dir")
+    c.add_argument("--kernel", required=True)
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         for r in kernel_stats(args.dir, args.kernel):
@@ -126,6 +148,11 @@ def main(argv=None):
                   f"max={r['max_us']:9.2f}us total={r['total_ms']:9.2f}ms {r['pct']:5.1f}%")
         if args.kernel and args.busy_floor_us > 0:
             print("busy dispatches:", busy_kernel_stats(args.dir, args.kernel, args.busy_floor_us))
+    elif args.cmd == "counters":
+        r = counter_means(args.dir, args.kernel)
+        print(f"dispatches {r['dispatches']}  mean duration {r['mean_duration_us']:.2f} us")
+        for k, v in r["per_dispatch"].items():
+            print(f"  {k:28s} {v:.4e} per dispatch")
     else:
         t = traffic(args.fetch_dir, args.write_dir, args.copy_bytes, args.kernel)
         for k, v in t.items():
