@@ -33,7 +33,7 @@ METRIC = "FEM indentation solves/s + tet-updates/s, FP32 vs FP64 path; p50/p99 l
 
 # Algorithmic arithmetic per tet of the two tile-kernel paths (an FMA counts
 # two; one transcendental counts one; FP64 LDS accumulation and conversions
-# are not counted; the derivation is in the design notes):
+# are not counted):
 #   Hessian-vector: G from u (54), J - 1 (30), ln J series and c (16),
 #   F^-T (40), dG from p (54), A = F^-1 dG and its trace (47), dP (91),
 #   nodal forces (60), p.q (25)                                  -> 417
@@ -53,7 +53,7 @@ POLAR_ITERS = 2.2
 FLOPS_PER_TET_CR = {"hv": round(223 + 3 + 83 * POLAR_ITERS + 243 + 184),
                     "element": round(305 + 3 + 83 * POLAR_ITERS + 243 + 81)}
 FP32_VECTOR_PEAK_TFLOPS = 157.3      # 256 CU x 64 lanes x 2 x 2.4 GHz x 2 (packed FP32)
-FP32_NONPACKED_PEAK_TFLOPS = 78.6    # the same without packed FP32, which this build does not emit
+FP32_NONPACKED_PEAK_TFLOPS = 78.6    # the same without packed FP32, which the library is compiled without
 
 
 def tile_bytes(info, word, hv_passes, el_passes, launches):
@@ -504,8 +504,8 @@ def main():
                     help="before the solves, one device copy of this many MiB (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: each batch of indentation jobs runs on a single MI355X and this build "
-              "has no multi-GPU path; run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: each batch of indentation jobs runs on a single MI355X and the "
+              "library has no multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

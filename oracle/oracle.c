@@ -9,7 +9,7 @@
  * skin, Neo-Hookean material as in the validated model, fixed boundary nodes,
  * rigid indenters driven into the skin, outputs = nodal positions and nodal
  * contact forces). The paper prints no equations; where it is silent the
- * following readings are taken (each is listed in the design notes):
+ * following readings are taken:
  *   - Neo-Hookean: the compressible form
  *       Psi(F) = mu/2 (tr F^T F - 3) - mu ln J + lam/2 (ln J)^2,  J = det F,
  *     whose linearisation at F = I is isotropic Hooke with Lame (mu, lam);

@@ -7,7 +7,7 @@
  * product path; only tests, the smoke check and the CPU-baseline timing of the
  * benchmark use it.
  *
- * Problem (paper Sec. III-A, with the readings stated in the design notes):
+ * Problem (paper Sec. III-A, with readings where the paper is silent):
  * linear tetrahedral FEM of a hyperelastic skin (the compressible Neo-Hookean
  * law that the paper's validated model uses), fixed boundary nodes, and rigid
  * indenters pushed into the skin; contact is a frictionless node-vs-signed-

@@ -282,8 +282,8 @@ void build_layout(const double *X, int n, const int32_t *tets, int m, int max_te
     }
 }
 
-// HIP events around every `every`-th launch of the timed kernels, harvested
-// after stream synchronisations.
+// Start/stop HIP events attached to every `every`-th launch of the timed
+// kernels (hipExtLaunchKernel), harvested after stream synchronisations.
 struct KernelTimer {
     static constexpr int kKinds = 3, kPool = 512;
     int every = 0;
@@ -783,11 +783,6 @@ int enqueue_round(fem_batch *B, int chunk) {
     return launch_check("round");
 }
 
-// Launches a round, replaying a captured graph for its length when graphs are
-// on (lengths rounded up to a multiple of 4, of 8 above 32; at most 64 solver
-// steps). With kernel timing
-// on, rounds are launched kernel by kernel so events can bracket single
-// kernels (event records cannot be captured into the graph here).
 // Kernel instances a round needs, from the host's view of the running jobs
 // (laws present, friction present), as bits 1 (Neo-Hookean), 2
 // (co-rotational), 4 (friction). A job's law and friction are set with its
@@ -803,6 +798,11 @@ int kernel_variant(fem_batch *B) {
     return (B->n_law[0] > 0 ? 1 : 0) | (B->n_law[1] > 0 ? 2 : 0) | (B->n_fric > 0 ? 4 : 0);
 }
 
+// Launches a round, replaying a captured graph for its length when graphs are
+// on (lengths rounded up to a multiple of 4, of 8 above 32; at most 64 solver
+// steps). With kernel timing on, rounds are launched kernel by kernel so
+// single launches can carry events (event records cannot be captured into the
+// graph here).
 template <typename T>
 int launch_round(fem_batch *B, int chunk) {
     if (pad8(B->nwork_tile) == 0 || pad8(B->nwork_node) == 0 || B->nlive == 0) return FEM_OK;
