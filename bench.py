@@ -423,7 +423,7 @@ VARIANTS = {
                      "co-rotational batched indentation: {J} jobs on the synthetic 50k-tet fingertip, E = 1.55 MPa, "
                      "nu = 0.316, seeded indenters at half depth (up to 1.5 mm), 100 quasi-static load steps each"),
     "friction": (0, 0.3e6, 0.45, 1.0, 0.783, 0.0,
-                 "batched indentation with Coulomb friction 0.783 (lagged, smoothed over 1 um): {J} jobs on the "
+                 "batched indentation with Coulomb friction 0.783 (lagged, smoothed over 10 um): {J} jobs on the "
                  "synthetic 50k-tet fingertip, seeded indenters, 100 quasi-static load steps each"),
     "simulator": (1, 1.55e6, 0.316, 0.5, 0.783, 1e-4,
                   "the paper's simulator model: co-rotational skin (E = 1.55 MPa, nu = 0.316), Coulomb friction "
@@ -450,7 +450,7 @@ def bench_variant(args, name):
         ind = W.seat_on_mesh(W.random_indentation(3000 + i), mesh)
         ind.model = law
         ind.depth *= depth_f
-        ind.friction, ind.friction_eps = mu_f, 1e-6
+        ind.friction, ind.friction_eps = mu_f, 1e-5
         ind.dt, ind.density = dt, 1100.0
         inds.append(ind)
     r = run_batched(mesh, inds, "fp32", args.steps, args.warmup, args.timing_every, material=(E, nu))

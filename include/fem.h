@@ -173,7 +173,9 @@ int fem_set_model(fem_mesh *mesh, int32_t model);
  * slip once |s| >= eps. The lag state is the result of the previous fem_step
  * at its indenter pose, or the displacements of fem_set_displacements at the
  * indenter pose set then; before either there is none and the step carries no
- * friction. mu_f = 0 turns friction off (the default).
+ * friction. mu_f = 0 turns friction off (the default). eps = 1e-5 m suits
+ * millimetre indentations in steps of tens of micrometres; smaller values
+ * sharpen the stick-slip transition at the cost of Newton iterations.
  * Errors: FEM_E_INVALID (mu_f < 0, or eps <= 0 with mu_f > 0, non-finite). */
 int fem_set_friction(fem_mesh *mesh, double mu_f, double eps);
 
@@ -305,7 +307,8 @@ typedef struct {
     int32_t model;       /* FEM_MODEL_NEOHOOKEAN or FEM_MODEL_COROTATIONAL */
     double friction;     /* Coulomb coefficient, 0 = frictionless (see fem_set_friction);
                             the lag state of the first step is u = 0 at c0 */
-    double friction_eps; /* slip smoothing length (m), > 0 when friction > 0 */
+    double friction_eps; /* slip smoothing length (m), > 0 when friction > 0;
+                            1e-5 suits millimetre indentations in 100 steps */
 } fem_indentation;
 
 typedef struct {

@@ -275,13 +275,13 @@ class Solver:
         self.dt = 0.0
         self.mass = None
         self.utilde = np.zeros((self.n, 3))
-        self.mu_f, self.eps_f, self.u_lag = 0.0, 1e-6, None
+        self.mu_f, self.eps_f, self.u_lag = 0.0, 1e-5, None
 
     def set_model(self, model):
         """Constitutive law: NEOHOOKEAN (default) or COROTATIONAL."""
         self.p.model = int(model)
 
-    def set_friction(self, mu_f, eps=1e-6):
+    def set_friction(self, mu_f, eps=1e-5):
         """Lagged, smoothed Coulomb friction (mu_f = 0: frictionless)."""
         self.mu_f, self.eps_f = float(mu_f), float(eps)
         self.p.mu_f, self.p.eps_f = self.mu_f, self.eps_f

@@ -360,7 +360,7 @@ struct fem_batch {
 // Friction settings of a job: coefficient, smoothing length and its lag state
 // (lag_ok = 0: none, so the first step has no friction).
 struct FrictionInit {
-    double mu_f = 0.0, eps_f = 1e-6;
+    double mu_f = 0.0, eps_f = 1e-5;
     int lag_ok = 0;
     double c_lag[3] = {0.0, 0.0, 0.0};
 };
@@ -1101,7 +1101,7 @@ int check_params(const fem_solve_params &P) {
 FrictionInit job_friction(const fem_indentation *job) {
     FrictionInit f;
     f.mu_f = job->friction;
-    f.eps_f = job->friction > 0.0 ? job->friction_eps : 1e-6;
+    f.eps_f = job->friction > 0.0 ? job->friction_eps : 1e-5;
     f.lag_ok = 1;
     for (int d = 0; d < 3; d++) f.c_lag[d] = job->c0[d];
     return f;
@@ -1418,7 +1418,7 @@ int fem_set_friction(fem_mesh *M, double mu_f, double eps) {
     if (!M) return fail(FEM_E_INVALID, "null mesh");
     TRY(check_friction(mu_f, eps));
     M->friction.mu_f = mu_f;
-    M->friction.eps_f = mu_f > 0.0 ? eps : 1e-6;
+    M->friction.eps_f = mu_f > 0.0 ? eps : 1e-5;
     return FEM_OK;
 }
 

@@ -367,7 +367,7 @@ class FemMesh:
     def set_model(self, model):
         _check(load().fem_set_model(self.h, int(model)))
 
-    def set_friction(self, mu_f, eps=1e-6):
+    def set_friction(self, mu_f, eps=1e-5):
         _check(load().fem_set_friction(self.h, float(mu_f), float(eps)))
 
     def tet_stress(self):
@@ -466,7 +466,7 @@ def make_indentation(ind) -> fem_indentation:
     j.density = float(getattr(ind, "density", 1100.0))
     j.model = int(getattr(ind, "model", FEM_MODEL_NEOHOOKEAN))
     j.friction = float(getattr(ind, "friction", 0.0))
-    j.friction_eps = float(getattr(ind, "friction_eps", 1e-6))
+    j.friction_eps = float(getattr(ind, "friction_eps", 1e-5))
     return j
 
 

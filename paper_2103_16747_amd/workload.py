@@ -256,7 +256,7 @@ class Indentation:
     density: float = 1100.0   # kg/m^3, lumped masses of implicit steps
     model: int = 0            # 0 Neo-Hookean, 1 co-rotational linear elasticity
     friction: float = 0.0     # Coulomb coefficient (0: frictionless)
-    friction_eps: float = 1e-6  # slip smoothing length (m)
+    friction_eps: float = 1e-5  # slip smoothing length (m)
 
     def center(self, step: int) -> np.ndarray:
         """Indenter centre at load step `step` (0 = initial contact pose)."""
