@@ -43,14 +43,15 @@ FLOPS_PER_TET = {"hv": 417, "element": 464}
 # The co-rotational law (same counting): both passes share G, J - 1, dG or
 # the node blocks, nodal forces and p.q with the Neo-Hookean ones (223 for
 # the Hessian-vector pass, 305 for the element pass). Per tet the law adds
-# the polar rotation, 3 + 83 per Newton iteration, and E = (C - I)(S + I)^-1
-# (243); then the Hessian-vector pass R^T dG, the rotation rate w and dP
-# (184), the element pass tr E, |E|^2, the energy and P = R (2 mu E +
-# lam tr E I) (81). The iteration count is data-dependent: 2.2 per tet on
-# average over the co-rotational fingertip states at 20-100 % of the
-# indentation depth, which gives 836 and 815.
+# the polar rotation, 3 + 83 per Newton iteration; the Hessian-vector pass
+# then forms E = sym(R^T F) - I (102), R^T dG, the rotation rate w and dP
+# (184); the element pass forms E = (C - I)(S + I)^-1 without cancellation
+# (243), tr E, |E|^2, the energy and P = R (2 mu E + lam tr E I) (81). The
+# iteration count is data-dependent: 2.2 per tet on average over the
+# co-rotational fingertip states at 20-100 % of the indentation depth, which
+# gives 695 and 815.
 POLAR_ITERS = 2.2
-FLOPS_PER_TET_CR = {"hv": round(223 + 3 + 83 * POLAR_ITERS + 243 + 184),
+FLOPS_PER_TET_CR = {"hv": round(223 + 3 + 83 * POLAR_ITERS + 102 + 184),
                     "element": round(305 + 3 + 83 * POLAR_ITERS + 243 + 81)}
 FP32_VECTOR_PEAK_TFLOPS = 157.3      # 256 CU x 64 lanes x 2 x 2.4 GHz x 2 (packed FP32)
 FP32_NONPACKED_PEAK_TFLOPS = 78.6    # the same without packed FP32, which the library is compiled without

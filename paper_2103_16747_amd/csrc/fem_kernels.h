@@ -562,11 +562,31 @@ template <typename T> struct Law<T, LAW_CR> {
         beta = lam;
     }
 
+    // R and E = sym(R^T F) - I formed directly: in the tangent E only enters
+    // through tr S I - S = (2 + tr E) I - E and lam tr E dR, where its
+    // rounding (absolute, about the working precision) is negligible.
+    __device__ static __forceinline__ void rotation_strain_direct(const T G[9], T R[9], T E[9]) {
+        polar_rotation(G, R);
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = i; j < 3; j++) {
+                // S_ij = (R^T (I + G))_ij, symmetrised
+                const T sij = R[3 * 0 + i] * G[3 * 0 + j] + R[3 * 1 + i] * G[3 * 1 + j] + R[3 * 2 + i] * G[3 * 2 + j] +
+                              R[3 * j + i];
+                const T sji = R[3 * 0 + j] * G[3 * 0 + i] + R[3 * 1 + j] * G[3 * 1 + i] + R[3 * 2 + j] * G[3 * 2 + i] +
+                              R[3 * i + j];
+                const T e = (T)0.5 * (sij + sji) - (i == j ? (T)1 : (T)0);
+                E[3 * i + j] = e;
+                E[3 * j + i] = e;
+            }
+    }
+
     // dP = 2 mu (dG - dR) + lam tr(R^T dG) R + lam tr E dR, dR = R [w]x with
     // (tr S I - S) w = axial(R^T dG - dG^T R).
     __device__ static __forceinline__ void hessvec(const T G[9], T Jm1, T J, const T dG[9], T mu, T lam, T dP[9]) {
         T R[9], E[9];
-        rotation_strain(G, R, E);
+        rotation_strain_direct(G, R, E);
         T M[9];   // R^T dG
 #pragma unroll
         for (int i = 0; i < 3; i++)
