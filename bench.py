@@ -208,7 +208,10 @@ def measured_traffic():
     return t["traffic_bytes_per_dispatch"]
 
 
-def roofline(r, word, flops_per_tet=FLOPS_PER_TET, kname=None):
+FP64_VECTOR_PEAK_TFLOPS = 78.6      # 256 CU x 64 lanes x 2 x 2.4 GHz (FP64 vector)
+
+
+def roofline(r, word, flops_per_tet=FLOPS_PER_TET, kname=None, peak=FP32_VECTOR_PEAK_TFLOPS):
     """Roofline of the tile kernel (the dominant one) over the timed region:
     algorithmic flops per launch (the passes the jobs made, times the tets per
     pass and FLOPS_PER_TET, over the number of launches) divided by the mean
@@ -233,15 +236,16 @@ def roofline(r, word, flops_per_tet=FLOPS_PER_TET, kname=None):
     byts = tile_bytes(r["layout"], word, r["hv_passes"], r["grad_passes"], t["launches"])
     if kname is None:
         kname = "k_tile<float, LAW_NH>" if word == 4 else "k_tile<double, LAW_NH>"
-    return ({"bound": "alu", "kernel": kname, "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
-             "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(),
-             "frac_of_non_packed_peak": achieved / FP32_NONPACKED_PEAK_TFLOPS,
-             "avg_launch_us": t["avg_us"], "sampled_launches": t["sampled"], "launches": t["launches"],
-             "flops_per_launch": per_launch,
-             "tet_updates_per_launch": m * (r["hv_passes"] + r["grad_passes"]) / t["launches"],
-             "hbm_model": {"algorithmic_bytes_per_launch": byts, "GB_per_s": byts / avg_s / 1e9,
-                           "frac_of_hbm_peak": byts / avg_s / 1e9 / HBM_PEAK_GBS}},
-            {k: v["avg_us"] for k, v in per.items()})
+    out = {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": peak,
+           "unit": "TFLOP/s", "frac": achieved / peak, "traffic": measured_traffic() if word == 4 else None}
+    if word == 4:
+        out["frac_of_non_packed_peak"] = achieved / FP32_NONPACKED_PEAK_TFLOPS
+    out.update({"avg_launch_us": t["avg_us"], "sampled_launches": t["sampled"], "launches": t["launches"],
+                "flops_per_launch": per_launch,
+                "tet_updates_per_launch": m * (r["hv_passes"] + r["grad_passes"]) / t["launches"],
+                "hbm_model": {"algorithmic_bytes_per_launch": byts, "GB_per_s": byts / avg_s / 1e9,
+                              "frac_of_hbm_peak": byts / avg_s / 1e9 / HBM_PEAK_GBS}})
+    return out, {k: v["avg_us"] for k, v in per.items()}
 
 
 RESOLUTIONS = (5000, 20000, 50000, 120000)
@@ -588,11 +592,15 @@ def main():
         out["roofline"] = rl
         out["kernel_avg_us"] = kav
     if not args.no_fp64:
-        r64 = run_batched(mesh, inds, "fp64", 1, 0, 0, track_latency=False)
+        r64 = run_batched(mesh, inds, "fp64", 1, 0, args.timing_every, track_latency=False)
         w64 = sum(r64["walls"])
         out["fp64_batched"] = {"solves_per_s": J / w64, "tet_updates_per_s": r64["tet_updates"] / w64,
                                "ms_per_step": w64 * 1e3, "failed_load_steps": r64["failed_steps"],
                                "floor_load_steps": r64["floor_steps"]}
+        rl64, kav64 = roofline(r64, 8, kname="k_tile<double, LAW_NH>", peak=FP64_VECTOR_PEAK_TFLOPS)
+        if rl64:
+            out["fp64_batched"]["roofline"] = rl64
+            out["fp64_batched"]["kernel_avg_us"] = kav64
         out["e_inf_fp32_vs_fp64"] = [float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
                                      for a, b in zip(r32["finals"], r64["finals"])]
     if not args.no_single:
