@@ -1,17 +1,20 @@
 /*
- * libfem: quasi-static Neo-Hookean indentation of a tetrahedral skin mesh on
- * one AMD Instinct MI355X (gfx950).
+ * libfem: indentation of a tetrahedral skin mesh on one AMD Instinct MI355X
+ * (gfx950).
  *
  * The problem is the finite-element contact simulation of paper Sec. III-A: a
  * volumetric mesh of linear tetrahedra (a soft skin), fixed boundary nodes
  * (bonded to a rigid core / clamped), rigid indenters driven into the skin,
  * and, per step, the nodal positions (displacements) and nodal contact forces
- * with their resultant. The skin is the compressible Neo-Hookean solid that
- * the paper's validated model uses,
+ * with their resultant. By default the skin is the compressible Neo-Hookean
+ * solid that the paper's validated model uses,
  *     Psi(F) = mu/2 (tr F^T F - 3) - mu ln J + lam/2 (ln J)^2,
- * contact is a frictionless per-node penalty k/2 min(0, phi)^2 against the
- * indenter's signed distance phi, and each load step is solved to a
- * stationary point of the total energy by Newton's method with matrix-free
+ * or, per mesh handle or job, the co-rotational law of the paper's own
+ * simulator (fem_set_model). Contact is a per-node penalty k/2 min(0, phi)^2
+ * against the indenter's signed distance phi, optionally with lagged,
+ * smoothed Coulomb friction (fem_set_friction). Each step, quasi-static or a
+ * backward-Euler time step (fem_set_dynamics), is solved to a stationary
+ * point of its energy by Newton's method with matrix-free
  * Jacobi-preconditioned CG and a backtracking line search.
  *
  * Conventions for every call:
