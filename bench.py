@@ -106,13 +106,17 @@ def run_batched(mesh, inds, precision, timed_steps, warm_steps, timing_every=0, 
         t0 = time.perf_counter()
         done_at = {}
         running = len(jobs)
+        pending = list(jobs)
         while running:
+            prev = running
             running = batch.run(P, max_rounds=8 if track_latency else 0)
             now = time.perf_counter() - t0
-            if track_latency:
-                for j in jobs:
-                    if j not in done_at and batch.job_info(j)["done"]:
+            # completions are looked up only when the running count fell
+            if track_latency and running < prev:
+                for j in pending:
+                    if batch.job_info(j)["done"]:
                         done_at[j] = now
+                pending = [j for j in pending if j not in done_at]
         walls.append(time.perf_counter() - t0)
         progress(f"batched {precision}: {len(jobs)} jobs in {walls[-1]:.2f} s")
         infos = [batch.job_info(j) for j in jobs]
@@ -374,12 +378,16 @@ def bench_dynamic(args):
             batch.restart_job(j, ind)
         t0 = time.perf_counter()
         done_at, running = {}, len(jobs)
+        pending = list(jobs)
         while running:
+            prev = running
             running = batch.run(max_rounds=8)
             now = time.perf_counter() - t0
-            for j in jobs:
-                if j not in done_at and batch.job_info(j)["done"]:
-                    done_at[j] = now
+            if running < prev:
+                for j in pending:
+                    if batch.job_info(j)["done"]:
+                        done_at[j] = now
+                pending = [j for j in pending if j not in done_at]
         walls.append(time.perf_counter() - t0)
         progress(f"dynamic batch: {len(jobs)} jobs in {walls[-1]:.2f} s")
         infos = [batch.job_info(j) for j in jobs]
