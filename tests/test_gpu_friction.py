@@ -38,6 +38,17 @@ def e_inf(u, ref):
 MESHES = {"cube8": lambda: W.cube_block_mesh(), "fingertip50k": lambda: W.fingertip_mesh(50000)}
 
 
+def tight(obj, precision):
+    """FP64: both sides converged to 1e-10 relative residual. Stick-slip
+    transitions on the 1 um smoothing scale can take a load step past the
+    default 50 Newton iterations at that tolerance (FP64 LDS sums are
+    order-nondeterministic, so a marginal step may land either side), hence
+    a budget of 100; the comparison is of converged results."""
+    if precision == "fp64":
+        return obj.default_params(newton_rtol=1e-10, cg_rtol=1e-10, max_newton=100)
+    return obj.default_params()
+
+
 @pytest.fixture(scope="module")
 def meshes():
     return {k: f() for k, f in MESHES.items()}
@@ -122,7 +133,7 @@ def test_cube_drag_matches_oracle(oracle_lib, meshes, precision):
     dev.set_friction(MU_F, EPS)
     orc = oracle_lib.Solver(mesh.X, mesh.tets, mesh.fixed, E=E0, nu=NU0)
     orc.set_friction(MU_F, EPS)
-    P = dev.default_params(newton_rtol=1e-10, cg_rtol=1e-10) if precision == "fp64" else dev.default_params()
+    P = tight(dev, precision)
     Po = oracle_lib.default_params(newton_rtol=1e-11, cg_rtol=1e-11)
     u_ref = np.zeros((mesh.n, 3))
     c_prev = None
@@ -172,7 +183,7 @@ def test_batch_jobs_with_friction(oracle_lib, meshes, precision):
     batch = fem.FemBatch(len(jobs), precision)
     mid = batch.add_mesh(mesh.X, mesh.tets, mesh.fixed)
     ids = [batch.add_job(mid, ind, E, nu) for ind, E, nu in jobs]
-    P = batch.default_params(newton_rtol=1e-10, cg_rtol=1e-10) if precision == "fp64" else batch.default_params()
+    P = tight(batch, precision)
     assert batch.run(P) == 0
     Po = oracle_lib.default_params(newton_rtol=1e-11, cg_rtol=1e-11)
     for jid, (ind, E, nu) in zip(ids, jobs):
@@ -226,7 +237,7 @@ def test_switching_law_and_friction_between_steps(oracle_lib, meshes, precision)
     dev = fem.FemMesh(mesh.X, mesh.tets, mesh.fixed, precision=precision)
     dev.set_material(E0, NU0, 1100.0)
     place(dev, c1)
-    P = dev.default_params(newton_rtol=1e-10, cg_rtol=1e-10) if precision == "fp64" else dev.default_params()
+    P = tight(dev, precision)
     assert dev.step(P)["status"] >= 0
     u1 = dev.displacements()
     dev.set_model(fem.FEM_MODEL_COROTATIONAL)
