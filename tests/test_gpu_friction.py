@@ -169,16 +169,18 @@ def test_cube_drag_matches_oracle(oracle_lib, meshes, precision):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_batch_jobs_with_friction(oracle_lib, meshes, precision):
     """Fingertip (50k tets) jobs, first 3 load steps of a 10-step schedule:
-    Neo-Hookean with friction, co-rotational with friction, and one
-    frictionless job, in one batch; each against its own oracle run."""
+    Neo-Hookean with friction, co-rotational with friction, the paper's
+    simulator model (co-rotational, friction, backward-Euler steps of
+    1e-4 s), and one frictionless job, in one batch; each against its own
+    oracle run."""
     mesh = meshes["fingertip50k"]
-    spec = [(2001, 0, E0, NU0, MU_F), (2004, 0, E0, NU0, MU_F), (2003, 1, 1.55e6, 0.316, MU_F),
-            (2002, 0, E0, NU0, 0.0)]
+    spec = [(2001, 0, E0, NU0, MU_F, 0.0), (2004, 0, E0, NU0, MU_F, 0.0), (2003, 1, 1.55e6, 0.316, MU_F, 0.0),
+            (2005, 1, 1.55e6, 0.316, MU_F, 1e-4), (2002, 0, E0, NU0, 0.0, 0.0)]
     jobs = []
-    for seed, model, E, nu, mu_f in spec:
+    for seed, model, E, nu, mu_f, dt in spec:
         base = W.seat_on_mesh(W.random_indentation(seed, steps=10), mesh)
         ind = W.Indentation(base.kind, base.shape, base.R, base.c0, base.direction, base.depth * 3 / 10, 3,
-                            base.k_penalty, seed=seed, model=model, friction=mu_f, friction_eps=EPS)
+                            base.k_penalty, seed=seed, model=model, friction=mu_f, friction_eps=EPS, dt=dt)
         jobs.append((ind, E, nu))
     batch = fem.FemBatch(len(jobs), precision)
     mid = batch.add_mesh(mesh.X, mesh.tets, mesh.fixed)
@@ -192,12 +194,15 @@ def test_batch_jobs_with_friction(oracle_lib, meshes, precision):
         orc = oracle_lib.Solver(mesh.X, mesh.tets, mesh.fixed, E=E, nu=nu)
         orc.set_model(ind.model)
         orc.set_friction(ind.friction, EPS)
-        ref = orc.solve_indentation(ind, params=Po)
+        if ind.dt > 0:
+            ref = [(u, i) for u, v, i in orc.solve_dynamic(ind, ind.dt, ind.density, params=Po)]
+        else:
+            ref = orc.solve_indentation(ind, params=Po)
         assert all(r[1]["status"] == 0 for r in ref)
         err = e_inf(batch.displacements(jid), ref[-1][0])
         ids_d, f_d, _, Ft_d = batch.contact_patch(jid)
         ids_r, f_r, _, Ft_r = orc.contact_patch(ref[-1][0])
-        say(ind.seed, W.KIND_NAMES[ind.kind], "model", ind.model, "mu", ind.friction, "e_inf %.3e" % err,
+        say(ind.seed, W.KIND_NAMES[ind.kind], "model", ind.model, "mu", ind.friction, "dt", ind.dt, "e_inf %.3e" % err,
             "newton", info["newton_iters"], "cg", info["cg_iters"], "patch", len(ids_d), len(ids_r))
         assert err <= SOLVE[precision]
         if precision == "fp64":
