@@ -1,0 +1,73 @@
+"""CPU checks of bench.py's contract: it refuses more than one GPU before
+touching the device, its roofline arithmetic, and the gating of the committed
+HBM traffic figure on the kernel source it was measured on."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def fake_run(timing, hv, grad, word_tets=49584):
+    return {"timing": timing, "hv_passes": hv, "grad_passes": grad,
+            "layout": {"n_tets": word_tets, "n_nodes": 11249, "n_entries": 21652, "n_eligible": 3757}}
+
+
+def test_roofline_arithmetic(monkeypatch):
+    monkeypatch.setattr(bench, "measured_traffic", lambda: 1.0e8)
+    # 100 tile launches, 10 of them sampled for 1 ms in all (100 us each)
+    r = fake_run({0: (10, 1.0, 100), 1: (10, 0.5, 100), 2: (10, 0.05, 100)}, hv=900, grad=100)
+    rl, kav = bench.roofline(r, 4)
+    flops = 49584 * (900 * bench.FLOPS_PER_TET["hv"] + 100 * bench.FLOPS_PER_TET["element"]) / 100
+    assert rl["flops_per_launch"] == pytest.approx(flops)
+    assert rl["avg_launch_us"] == pytest.approx(100.0)
+    assert rl["achieved"] == pytest.approx(flops / 100e-6 / 1e12)
+    assert rl["frac"] == pytest.approx(rl["achieved"] / 157.3)
+    assert rl["frac_of_non_packed_peak"] == pytest.approx(rl["achieved"] / 78.6)
+    assert rl["bound"] == "alu" and rl["unit"] == "TFLOP/s" and rl["traffic"] == 1.0e8
+    assert kav == {"tile": pytest.approx(100.0), "node": pytest.approx(50.0), "finalize": pytest.approx(5.0)}
+    # the FP64 instance: its own peak, no FP32 traffic figure
+    rl64, _ = bench.roofline(r, 8, kname="k_tile<double, LAW_NH>", peak=bench.FP64_VECTOR_PEAK_TFLOPS)
+    assert rl64["frac"] == pytest.approx(rl64["achieved"] / 78.6) and rl64["traffic"] is None
+    # no sampled launches: no roofline
+    assert bench.roofline(fake_run(None, 1, 1), 4) == (None, None)
+
+
+def test_corotational_flop_counts():
+    assert bench.FLOPS_PER_TET_CR == {"hv": round(223 + 3 + 83 * 2.2 + 102 + 184),
+                                      "element": round(305 + 3 + 83 * 2.2 + 243 + 81)}
+
+
+def test_traffic_figure_follows_the_kernel_source(monkeypatch, tmp_path):
+    from paper_2103_16747_amd import profiling
+
+    f = tmp_path / "traffic.json"
+    f.write_text(json.dumps({"kernel_source_sha256": profiling.kernel_source_hash(),
+                             "traffic_bytes_per_dispatch": 123.0}))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.measured_traffic() == 123.0
+    f.write_text(json.dumps({"kernel_source_sha256": "0" * 64, "traffic_bytes_per_dispatch": 123.0}))
+    assert bench.measured_traffic() is None
+
+
+def test_kernel_source_hash_ignores_comments():
+    from paper_2103_16747_amd.profiling import kernel_source_hash
+
+    a = "int f() {\n  return 1; // one\n}\n"
+    b = "// header\nint f() {\n\n  return 1;\n}\n"
+    assert kernel_source_hash(a) == kernel_source_hash(b)
+    assert kernel_source_hash(a) != kernel_source_hash(a.replace("1", "2"))
