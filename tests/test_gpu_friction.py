@@ -194,11 +194,19 @@ def test_batch_jobs_with_friction(oracle_lib, meshes, precision):
         orc = oracle_lib.Solver(mesh.X, mesh.tets, mesh.fixed, E=E, nu=nu)
         orc.set_model(ind.model)
         orc.set_friction(ind.friction, EPS)
+        v_ref = None
         if ind.dt > 0:
-            ref = [(u, i) for u, v, i in orc.solve_dynamic(ind, ind.dt, ind.density, params=Po)]
+            dyn = orc.solve_dynamic(ind, ind.dt, ind.density, params=Po)
+            ref = [(u, i) for u, v, i in dyn]
+            v_ref = dyn[-1][1]
         else:
             ref = orc.solve_indentation(ind, params=Po)
         assert all(r[1]["status"] == 0 for r in ref)
+        if v_ref is not None:
+            # a velocity is a difference of displacements over dt: 10x the bound
+            ev = e_inf(batch.velocities(jid), v_ref)
+            say("velocity e_inf %.3e" % ev)
+            assert ev <= 10 * SOLVE[precision]
         err = e_inf(batch.displacements(jid), ref[-1][0])
         ids_d, f_d, _, Ft_d = batch.contact_patch(jid)
         ids_r, f_r, _, Ft_r = orc.contact_patch(ref[-1][0])
