@@ -270,10 +270,11 @@ int fem_eval_hessvec(fem_mesh *mesh, const fem_solve_params *params, const doubl
  * Hessian-vector product during CG, the element + contact pass of a gradient
  * or line-search trial otherwise), the node pass (CG update, Newton init,
  * line-search directional derivative) and the finalize. With every > 0,
- * every every-th launch of each is made with a start and a stop HIP event
- * (hipExtLaunchKernel on the handle's stream: the dispatch's own start and
- * end), and rounds are launched kernel by kernel rather than from a captured
- * graph; every = 0 turns timing off. Counters are cleared on each call. */
+ * every every-th round of solver steps is launched kernel by kernel, each
+ * launch with a start and a stop HIP event (hipExtLaunchKernel on the
+ * handle's stream: the dispatch's own start and end); the other rounds
+ * replay captured graphs as without timing. every = 0 turns timing off.
+ * Counters are cleared on each call. */
 #define FEM_KERNEL_TILE 0
 #define FEM_KERNEL_NODE 1
 #define FEM_KERNEL_FINALIZE 2

@@ -282,12 +282,14 @@ void build_layout(const double *X, int n, const int32_t *tets, int m, int max_te
     }
 }
 
-// Start/stop HIP events attached to every `every`-th launch of the timed
-// kernels (hipExtLaunchKernel), harvested after stream synchronisations.
+// Start/stop HIP events attached to every launch of every `every`-th round
+// (hipExtLaunchKernel; the other rounds replay captured graphs), harvested
+// after stream synchronisations.
 struct KernelTimer {
     static constexpr int kKinds = 3, kPool = 512;
     int every = 0;
-    long long seen[kKinds] = {0, 0, 0};
+    long long rounds = 0;                     // rounds launched since timing was set
+    long long seen[kKinds] = {0, 0, 0};       // launches of each kernel kind
     long long count[kKinds] = {0, 0, 0};
     double total_ms[kKinds] = {0, 0, 0};
     hipEvent_t ev[kPool][2] = {};
@@ -393,14 +395,13 @@ int stage(fem_batch *B, size_t bytes) {
     return FEM_OK;
 }
 
-// Sampling: every `every`-th launch of a kernel kind gets a timer slot; the
-// launch then goes through hipExtLaunchKernel with the slot's events, which
-// take the dispatch's own start and end timestamps (no marker packets or
-// cache maintenance of separate event records inside the measured span).
-int timer_slot(fem_batch *B, int kind) {
+// Sampling: in a sampled round every launch gets a timer slot; the launch
+// then goes through hipExtLaunchKernel with the slot's events, which take the
+// dispatch's own start and end timestamps (no marker packets or cache
+// maintenance of separate event records inside the measured span).
+int timer_slot(fem_batch *B, int kind, bool sample) {
     KernelTimer &t = B->timer;
-    if (t.every <= 0) return -1;
-    if ((t.seen[kind]++ % t.every) != 0 || t.used >= KernelTimer::kPool) return -1;
+    if (!sample || t.used >= KernelTimer::kPool) return -1;
     const int slot = t.used++;
     t.kind_of[slot] = kind;
     return slot;
@@ -749,11 +750,11 @@ int write_state(fem_batch *B, int slot) {
 }
 
 // One round: C solver steps, each a tile pass, a node pass and a finalize
-// over every live instance. With kernel timing on, sampled launches carry
-// events (a sampled tile pass with both laws present is timed from the start
-// of the first launch to the end of the second).
+// over every live instance. In a sampled round every launch carries events
+// (a tile pass with both laws present is timed from the start of the first
+// launch to the end of the second).
 template <typename T>
-int enqueue_round(fem_batch *B, int chunk) {
+int enqueue_round(fem_batch *B, int chunk, bool sample) {
     const Topo<T> *tp = (const Topo<T> *)B->d_topos;
     const InstBufs<T> *bf = (const InstBufs<T> *)B->d_bufs;
     const int gt = pad8(B->nwork_tile), gn = pad8(B->nwork_node), nl = B->nlive;
@@ -761,7 +762,7 @@ int enqueue_round(fem_batch *B, int chunk) {
     for (int c = 0; c < chunk; c++) {
         // one tile launch per constitutive law present (blocks of jobs on the
         // other law return at once)
-        int slot = timer_slot(B, FEM_KERNEL_TILE);
+        int slot = timer_slot(B, FEM_KERNEL_TILE, sample);
         if (nh)
             launch_timed(B, slot, true, !cr, k_tile<T, LAW_NH>, dim3(gt), dim3(kBlock), tp, bf,
                          (const int2 *)B->d_work_tile, B->nwork_tile, (const SolveParams *)B->d_params);
@@ -769,14 +770,14 @@ int enqueue_round(fem_batch *B, int chunk) {
             launch_timed(B, slot, !nh, true, k_tile<T, LAW_CR>, dim3(gt), dim3(kBlock), tp, bf,
                          (const int2 *)B->d_work_tile, B->nwork_tile, (const SolveParams *)B->d_params);
         // the node pass with the friction phases only when a job needs them
-        slot = timer_slot(B, FEM_KERNEL_NODE);
+        slot = timer_slot(B, FEM_KERNEL_NODE, sample);
         if (fric)
             launch_timed(B, slot, true, true, k_node<T, true>, dim3(gn), dim3(kBlock), tp, bf,
                          (const int2 *)B->d_work_node, B->nwork_node, (const SolveParams *)B->d_params);
         else
             launch_timed(B, slot, true, true, k_node<T, false>, dim3(gn), dim3(kBlock), tp, bf,
                          (const int2 *)B->d_work_node, B->nwork_node, (const SolveParams *)B->d_params);
-        slot = timer_slot(B, FEM_KERNEL_FINALIZE);
+        slot = timer_slot(B, FEM_KERNEL_FINALIZE, sample);
         launch_timed(B, slot, true, true, k_finalize<T>, dim3(nl), dim3(64), tp, bf, (const int *)B->d_live, nl,
                      (const SolveParams *)B->d_params);
     }
@@ -800,14 +801,23 @@ int kernel_variant(fem_batch *B) {
 
 // Launches a round, replaying a captured graph for its length when graphs are
 // on (lengths rounded up to a multiple of 4, of 8 above 32; at most 64 solver
-// steps). With kernel timing on, rounds are launched kernel by kernel so
-// single launches can carry events (event records cannot be captured into the
-// graph here).
+// steps). With kernel timing on, every `every`-th round is launched kernel by
+// kernel so its launches can carry events (event records cannot be captured
+// into the graph here); the others replay graphs as without timing.
 template <typename T>
 int launch_round(fem_batch *B, int chunk) {
     if (pad8(B->nwork_tile) == 0 || pad8(B->nwork_node) == 0 || B->nlive == 0) return FEM_OK;
     const int variant = kernel_variant(B);
-    if (!B->use_graphs || B->timer.every > 0) return enqueue_round<T>(B, std::max(1, std::min(64, chunk)));
+    KernelTimer &tm = B->timer;
+    const bool timing = tm.every > 0;
+    const bool sample = timing && (tm.rounds++ % tm.every) == 0;
+    if (!B->use_graphs || sample) {
+        const int c = std::max(1, std::min(64, chunk));
+        TRY(enqueue_round<T>(B, c, sample));
+        if (timing)
+            for (int k = 0; k < KernelTimer::kKinds; k++) tm.seen[k] += c;
+        return FEM_OK;
+    }
     // graph lengths: multiples of 4 up to 32, of 8 up to 64
     int c = std::max(4, std::min(64, chunk));
     c = c <= 32 ? (c + 3) / 4 * 4 : (c + 7) / 8 * 8;
@@ -820,7 +830,7 @@ int launch_round(fem_batch *B, int chunk) {
         G.variant = variant;
         hipGraph_t graph = nullptr;
         HIP_TRY(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
-        const int rc = enqueue_round<T>(B, c);
+        const int rc = enqueue_round<T>(B, c, false);
         const hipError_t ec = hipStreamEndCapture(B->stream, &graph);
         if (rc) return rc;
         if (ec != hipSuccess) return fail(FEM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
@@ -831,6 +841,8 @@ int launch_round(fem_batch *B, int chunk) {
         gi = (int)B->graphs.size() - 1;
     }
     HIP_TRY(hipGraphLaunch(B->graphs[gi].exec, B->stream));
+    if (timing)
+        for (int k = 0; k < KernelTimer::kKinds; k++) tm.seen[k] += c;
     return FEM_OK;
 }
 
@@ -1776,6 +1788,7 @@ int fem_batch_set_kernel_timing(fem_batch *B, int32_t every) {
     TRY(sync(B));
     t.used = 0;
     t.every = every;
+    t.rounds = 0;
     for (int k = 0; k < KernelTimer::kKinds; k++) {
         t.seen[k] = 0;
         t.count[k] = 0;

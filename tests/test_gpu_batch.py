@@ -143,8 +143,8 @@ def test_layout_covers_mesh():
 def test_graph_replay_matches_stream_launches(precision):
     """Rounds replayed from captured graphs (many replays, with host state
     writes and synchronisations between them) give the results of rounds
-    launched kernel by kernel; kernel timing (which launches kernel by
-    kernel) records events for each of the three kernels."""
+    launched kernel by kernel; kernel timing records events for each of the
+    three kernels."""
     mesh = W.cube_block_mesh()
     jobs = cube_jobs()
     out = {}
@@ -161,7 +161,7 @@ def test_graph_replay_matches_stream_launches(precision):
             for k in (fem.FEM_KERNEL_TILE, fem.FEM_KERNEL_NODE, fem.FEM_KERNEL_FINALIZE):
                 cnt, ms = batch.kernel_timing(k)
                 launches = batch.kernel_launches(k)
-                assert cnt > 0 and ms > 0 and launches >= 4 * (cnt - 1) + 1
+                assert cnt > 0 and ms > 0 and launches >= cnt
         batch.close()
     tol = 1e-9 if precision == "fp64" else 1e-5
     for a, b in zip(out[1], out[0]):
