@@ -363,6 +363,16 @@ int fem_batch_run(fem_batch *batch, const fem_solve_params *params, int32_t max_
 /* Progress and counters of a job (as of the end of the last run). */
 int fem_batch_job_info(const fem_batch *batch, int32_t job_id, fem_job_info *info);
 
+/* Status of each load step the job has taken so far (as of the end of the
+ * last run), in order: status[k] is the outcome of load step k + 1 (paper
+ * Sec. III-A: the indenter is driven in step by step), FEM_OK, FEM_W_FLOOR,
+ * FEM_E_NOT_CONVERGED or FEM_E_INVERSION. *n_steps receives the number of
+ * steps taken; the first 1024 load steps of a job are recorded. status may be
+ * NULL to query the count. Errors: FEM_E_INVALID (null n_steps, unknown job),
+ * FEM_E_BUFFER (capacity < *n_steps). */
+int fem_batch_job_step_status(const fem_batch *batch, int32_t job_id, int32_t *status, int32_t capacity,
+                              int32_t *n_steps);
+
 /* A job's per-tet stress and displacement statistics, as the single-mesh calls. */
 int fem_batch_get_tet_stress(fem_batch *batch, int32_t job_id, double *sigma, double *von_mises, int64_t capacity);
 int fem_batch_get_displacement_stats(fem_batch *batch, int32_t job_id, double *max_norm, double *mean_norm);

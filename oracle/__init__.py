@@ -17,7 +17,10 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# ORACLE_SANITIZED=1 loads the build with the address and undefined-behaviour
+# sanitizers (build(sanitize=True); the process needs libasan preloaded).
+SANITIZED = os.environ.get("ORACLE_SANITIZED", "0") == "1"
+LIB_PATH = os.path.join(HERE, "liboracle_san.so" if SANITIZED else "liboracle.so")
 SRC = os.path.join(HERE, "oracle.c")
 
 SPHERE, CYLINDER, BOX, RING = 0, 1, 2, 3
@@ -25,15 +28,21 @@ NEOHOOKEAN, COROTATIONAL = 0, 1
 OK, NOT_CONVERGED, INVERSION, NOT_SPD = 0, -6, -7, -9
 
 
-def build(force: bool = True) -> str:
+def build(force: bool = True, sanitize: bool | None = None) -> str:
     """Compile oracle.c into liboracle.so (plain IEEE double: no fast-math,
-    no FMA contraction)."""
-    if force or not os.path.exists(LIB_PATH):
-        cmd = ["gcc", "-O3", "-march=x86-64-v3", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
-               "-Wall", "-fPIC", "-shared", "-o", LIB_PATH + ".tmp", SRC, "-lm"]
+    no FMA contraction), or with sanitize into liboracle_san.so, instrumented
+    by the address and undefined-behaviour sanitizers (host code only)."""
+    if sanitize is None:
+        sanitize = SANITIZED
+    path = os.path.join(HERE, "liboracle_san.so" if sanitize else "liboracle.so")
+    if force or not os.path.exists(path):
+        opt = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+               "-fno-sanitize-recover=all"] if sanitize else ["-O3"]
+        cmd = ["gcc", *opt, "-march=x86-64-v3", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+               "-Wall", "-fPIC", "-shared", "-o", path + ".tmp", SRC, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(LIB_PATH + ".tmp", LIB_PATH)
-    return LIB_PATH
+        os.replace(path + ".tmp", path)
+    return path
 
 
 class Indenter(C.Structure):

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfem.so")
 SOURCES = [os.path.join(HERE, "csrc", "fem_lib.hip")]
-DEPS = SOURCES + [os.path.join(HERE, "csrc", "fem_kernels.h"), os.path.join(HERE, "..", "include", "fem.h")]
+DEPS = SOURCES + [os.path.join(HERE, "csrc", "fem_kernels.h"), os.path.join(HERE, "csrc", "layout.h"), os.path.join(HERE, "..", "include", "fem.h")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

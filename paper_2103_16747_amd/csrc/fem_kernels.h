@@ -38,6 +38,7 @@ constexpr int kBlock = 256;       // 4 wavefronts of 64
 constexpr int kWaves = kBlock / 64;
 constexpr int kTileTets = 512;    // tets per tile (2 per thread)
 constexpr int kTileNodes = 256;   // distinct nodes per tile (8-bit local ids)
+constexpr int kHistSteps = 1024;  // load steps whose status a job records
 
 enum Phase : int {
     PH_IDLE = 0,
@@ -55,8 +56,10 @@ enum Phase : int {
 enum : int { ST_OK = 0, ST_FLOOR = 1, ST_NOT_CONVERGED = -6, ST_INVERSION = -7 };
 
 // Partial-sum streams of an instance (each red_stride doubles).
-// RS_EN: inertial energy of implicit time steps (node blocks).
-enum : int { RS_PQ = 0, RS_RZ, RS_RR, RS_GD, RS_E, RS_MAG, RS_MINJ, RS_GG, RS_IRZ, RS_EN, RS_COUNT };
+// RS_EN: inertial energy of implicit time steps (node blocks). RS_PQN: slot 0
+// holds p.q as every node block summed it (written by node block 0), which the
+// finalize takes, so the CG decision and the update applied always agree.
+enum : int { RS_PQ = 0, RS_RZ, RS_RR, RS_GD, RS_E, RS_MAG, RS_MINJ, RS_GG, RS_IRZ, RS_EN, RS_PQN, RS_COUNT };
 
 struct Indenter {
     int kind;            // 0 sphere, 1 cylinder, 2 box, 3 ring
@@ -147,6 +150,7 @@ struct InstBufs {
     double *fr;                         // nc x 8: friction lag data (w, normal, displacement relative to
                                         // the indenter since the lag state, pad)
     double *red;                        // RS_COUNT x red_stride
+    signed char *hist;                  // kHistSteps: status of each load step taken (ST_*)
     InstState *s;
 };
 
@@ -748,8 +752,9 @@ __device__ inline void sdf_eval(const Indenter &ind, const double x[3], bool wan
 // End of a load step (called by the finalising thread): bookkeeping, then the
 // next load step's pose c = c0 + depth * step / steps * dir, or done.
 // ---------------------------------------------------------------------------
-__device__ inline void end_step(InstState *s, int status) {
+__device__ inline void end_step(InstState *s, signed char *hist, int status) {
     s->last_status = status;
+    if (s->step >= 1 && s->step <= kHistSteps) hist[s->step - 1] = (signed char)status;
     s->st_g = sqrt(s->gg);
     s->tot_newton += s->st_newton;
     s->tot_cg += s->st_cg;
@@ -1268,7 +1273,8 @@ __device__ __forceinline__ void node_init(const Topo<T> &tp, const InstBufs<T> &
 
 // ---------------------------------------------------------------------------
 // CG update of one node block (phases CG, EVAL_HV). Every block sums the tile
-// pass's p.q partials (fixed order, so all blocks agree) and forms
+// pass's p.q partials (fixed order, so all blocks agree; block 0 records the
+// sum for the finalize) and forms
 // alpha = r.z / p.q; then it gathers q from the tile partials plus the contact
 // block times p and, on free nodes, sets p = z + beta p_prev, dx += alpha p,
 // r -= alpha q, z = M^-1 r, with partial sums of r.z and r.r. At p.q <= 0 CG
@@ -1283,6 +1289,7 @@ __device__ __forceinline__ void node_update(const Topo<T> &tp, const InstBufs<T>
     const T beta = (T)s->beta;
     const int cg_first = s->cg_it == 0;
     const double pq = block_sum_partials(B.red + RS_PQ * B.red_stride, tp.ntile + tp.ncb);
+    if (blk == 0 && threadIdx.x == 0) B.red[RS_PQN * B.red_stride] = pq;
     const bool negcurv = !(pq > 0.0);
     const T alpha = negcurv ? (T)0 : (T)(rz / pq);
     double acc[2] = {0.0, 0.0};   // r.z, r.r
@@ -1427,7 +1434,7 @@ __global__ __launch_bounds__(kBlock) void k_node(const Topo<T> *topos, const Ins
 // in a row whose predicted energy change lies within rounding have not halved
 // the smallest residual of the step, the working precision cannot take it
 // lower and the step ends with ST_FLOOR.
-__device__ inline void newton_test(InstState *s, const SolveParams *P, double gg, double rz) {
+__device__ inline void newton_test(InstState *s, signed char *hist, const SolveParams *P, double gg, double rz) {
     s->gg = gg;
     const double gn = sqrt(gg);
     if (s->step_started) {
@@ -1457,11 +1464,11 @@ __device__ inline void newton_test(InstState *s, const SolveParams *P, double gg
         s->apply = 0;
     }
     if (gn <= fmax(P->newton_rtol * s->r0, P->newton_atol)) {
-        end_step(s, ST_OK);
+        end_step(s, hist, ST_OK);
     } else if (s->stall >= 2 && gn <= P->floor_rtol * s->r0) {
-        end_step(s, ST_FLOOR);
+        end_step(s, hist, ST_FLOOR);
     } else if (s->newton_it >= P->max_newton) {
-        end_step(s, ST_NOT_CONVERGED);
+        end_step(s, hist, ST_NOT_CONVERGED);
     } else {
         // inexact Newton: forcing term (|g| / |g_start|)^p, p = 1/2 by default
         // (superlinear of order 1 + p, without tight solves late in a step)
@@ -1515,7 +1522,7 @@ __global__ __launch_bounds__(64) void k_finalize(const Topo<T> *topos, const Ins
         return;
     }
     if (phase == PH_CG || phase == PH_EVAL_HV) {
-        const double pq = wave_sum_partials(B.red + RS_PQ * S, nt);
+        const double pq = B.red[RS_PQN * S];   // the node pass's sum, as it applied it
         const double rz = wave_sum_partials(B.red + RS_RZ * S, nn);
         const double rr = wave_sum_partials(B.red + RS_RR * S, nn);
         if (threadIdx.x != 0) return;
@@ -1561,7 +1568,7 @@ __global__ __launch_bounds__(64) void k_finalize(const Topo<T> *topos, const Ins
                 s->gg = gg;
                 s->phase = PH_IDLE;
             } else {
-                newton_test(s, P, gg, rz);
+                newton_test(s, B.hist, P, gg, rz);
             }
             return;
         }
@@ -1578,7 +1585,7 @@ __global__ __launch_bounds__(64) void k_finalize(const Topo<T> *topos, const Ins
             s->apply = 1;
             s->phase = PH_INIT;
         } else if (s->halvings >= P->max_halvings) {
-            end_step(s, mn > 0.0 ? ST_NOT_CONVERGED : ST_INVERSION);
+            end_step(s, B.hist, mn > 0.0 ? ST_NOT_CONVERGED : ST_INVERSION);
         } else {
             s->halvings++;
             s->alpha_ls *= 0.5;
@@ -1587,7 +1594,7 @@ __global__ __launch_bounds__(64) void k_finalize(const Topo<T> *topos, const Ins
         const double gg = wave_sum_partials(B.red + RS_GG * S, nn);
         const double rz = wave_sum_partials(B.red + RS_IRZ * S, nn);
         if (threadIdx.x != 0) return;
-        newton_test(s, P, gg, rz);
+        newton_test(s, B.hist, P, gg, rz);
     }
 }
 
@@ -1857,6 +1864,8 @@ __device__ __forceinline__ unsigned long long face_key(const int *tet, int e, in
     return ((unsigned long long)a << 42) | ((unsigned long long)b << 21) | (unsigned long long)c;
 }
 
+// Slot hash of a face key: the 64-bit finaliser (fmix64) of Austin Appleby's
+// public-domain MurmurHash3, with its published shift and multiplier constants.
 __device__ __forceinline__ unsigned face_hash(unsigned long long k) {
     k ^= k >> 33;
     k *= 0xff51afd7ed558ccdull;

@@ -30,6 +30,7 @@ EXPORTS = ("fem_create_mesh", "fem_destroy_mesh", "fem_set_material", "fem_set_i
            "fem_get_mesh_info", "fem_get_tet_stress", "fem_get_displacement_stats", "fem_set_model", "fem_set_friction", "fem_set_dynamics", "fem_get_velocities", "fem_set_velocities", "fem_eval_gradient", "fem_eval_hessvec", "fem_set_kernel_timing",
            "fem_get_kernel_timing", "fem_batch_create", "fem_batch_destroy", "fem_batch_add_mesh",
            "fem_batch_mesh_info", "fem_batch_add_job", "fem_batch_restart_job", "fem_batch_remove_job", "fem_batch_run", "fem_batch_job_info",
+           "fem_batch_job_step_status",
            "fem_batch_get_displacements", "fem_batch_get_velocities", "fem_batch_get_tet_stress",
            "fem_batch_get_displacement_stats", "fem_batch_get_contact_patch", "fem_batch_set_kernel_timing",
            "fem_batch_get_kernel_timing", "fem_batch_get_kernel_launches", "fem_set_graphs", "fem_batch_set_graphs", "fem_batch_set_option",
@@ -137,6 +138,7 @@ def load(path: str = LIB_PATH):
     L.fem_batch_remove_job.argtypes = [vp, C.c_int32]
     L.fem_batch_run.argtypes = [vp, C.POINTER(fem_solve_params), C.c_int32, i32p]
     L.fem_batch_job_info.argtypes = [vp, C.c_int32, C.POINTER(fem_job_info)]
+    L.fem_batch_job_step_status.argtypes = [vp, C.c_int32, i32p, C.c_int32, i32p]
     L.fem_batch_get_displacements.argtypes = [vp, C.c_int32, dp, C.c_int64]
     L.fem_batch_get_contact_patch.argtypes = [vp, C.c_int32, i32p, dp, dp, C.c_int32, i32p, dp]
     L.fem_batch_set_kernel_timing.argtypes = [vp, C.c_int32]
@@ -499,6 +501,17 @@ def fem_batch_job_info(h, job: int) -> dict:
     return info.as_dict()
 
 
+def fem_batch_job_step_status(h, job: int) -> np.ndarray:
+    """Status of each load step the job has taken (FEM_OK, FEM_W_FLOOR,
+    FEM_E_NOT_CONVERGED, FEM_E_INVERSION), in step order."""
+    cnt = C.c_int32()
+    _check(load().fem_batch_job_step_status(h, int(job), None, 0, C.byref(cnt)))
+    st = np.zeros(max(cnt.value, 1), dtype=np.int32)
+    _check(load().fem_batch_job_step_status(h, int(job), st.ctypes.data_as(C.POINTER(C.c_int32)), st.size,
+                                            C.byref(cnt)))
+    return st[:cnt.value]
+
+
 def fem_batch_get_displacements(h, job: int, n: int) -> np.ndarray:
     u = np.zeros((n, 3))
     _check(load().fem_batch_get_displacements(h, int(job), _dp(u), u.size))
@@ -592,6 +605,9 @@ class FemBatch:
 
     def job_info(self, job):
         return fem_batch_job_info(self.h, job)
+
+    def step_status(self, job):
+        return fem_batch_job_step_status(self.h, job)
 
     def displacements(self, job):
         return fem_batch_get_displacements(self.h, job, self.mesh_nodes[self.job_mesh[job]])

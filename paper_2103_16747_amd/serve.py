@@ -53,8 +53,15 @@ class Result:
         return self.done - self.arrival
 
 
+# Result.status of a request refused at arrival: its job's device footprint
+# exceeds the whole HBM budget, so it could never be admitted (the C ABI's
+# out-of-memory code).
+REJECTED_FOOTPRINT = -3
+
+
 @dataclass
 class ServerStats:
+    rejected: int = 0
     admitted: int = 0
     restarted_in_place: int = 0
     allocated: int = 0
@@ -128,7 +135,18 @@ class IndentationServer:
 
     def _admit(self, now: float):
         while self.queue and self.queue[0].arrival <= now:
-            if not self._admit_one(self.queue[0], now):
+            req = self.queue[0]
+            if self.footprint[req.mesh] > self.budget:
+                # never admissible: refused with an error result, not queued forever
+                self.queue.popleft()
+                self.stats.rejected += 1
+                self.results.append(Result(req.rid, req.mesh, req.arrival, now, now, REJECTED_FOOTPRINT, 0, 0, 0, 0))
+                continue
+            if not self._admit_one(req, now):
+                if not self.running:
+                    # with nothing running every idle slot could be released,
+                    # so a request within the budget always fits
+                    raise RuntimeError(f"request {req.rid} cannot be admitted with no job running")
                 break
             self.queue.popleft()
 
@@ -170,6 +188,7 @@ class IndentationServer:
 
 
 def latency_summary(results) -> dict:
+    results = [r for r in results if r.status != REJECTED_FOOTPRINT]
     lat = np.array([r.latency for r in results]) * 1e3
     span = max(r.done for r in results) - min(r.arrival for r in results)
     return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),

@@ -100,8 +100,16 @@ def test_job_slot_count_cap():
     assert len(res) == 3 and srv.stats.peak_running == 1
 
 
-def test_request_that_never_fits_times_out():
+def test_request_that_never_fits_is_rejected():
+    """A job whose footprint exceeds the whole budget is refused at arrival
+    with an error result (no spinning), and the others are still served."""
+    from paper_2103_16747_amd.serve import REJECTED_FOOTPRINT
+
     eng = FakeEngine(capacity=2)
-    srv = IndentationServer(eng, {"a": FakeMesh(100)}, hbm_budget=10, max_jobs=2, rounds_per_poll=1)
-    with pytest.raises(TimeoutError):
-        srv.serve(requests([(0.0, "a", 1)]), timeout=0.2)
+    srv = IndentationServer(eng, {"a": FakeMesh(100), "b": FakeMesh(1)}, hbm_budget=5000, max_jobs=2,
+                            rounds_per_poll=1)
+    res = srv.serve(requests([(0.0, "a", 1), (0.0, "b", 2), (0.01, "a", 1)]), timeout=5)
+    assert [r.status for r in res] == [REJECTED_FOOTPRINT, 0, REJECTED_FOOTPRINT]
+    assert srv.stats.rejected == 2 and srv.stats.admitted == 1
+    assert not any(e[0] == "add" and eng.slots.get(e[1], [None])[0] == 0 for e in eng.events)
+    assert latency_summary(res)["completed"] == 1
