@@ -1515,8 +1515,9 @@ int fem_batch_job_step_status(const fem_batch *B, int32_t job, int32_t *status, 
     const InstState &s = B->h_states[job];
     const int taken = std::min(s.steps_ok + s.steps_failed, kHistSteps);
     *n_steps = taken;
+    if (!status) return FEM_OK;   // count query
     if (capacity < taken) return fail(FEM_E_BUFFER, "capacity below the number of load steps taken");
-    if (taken == 0 || !status) return FEM_OK;
+    if (taken == 0) return FEM_OK;
     fem_batch *W = const_cast<fem_batch *>(B);
     TRY(set_device(W));
     const InstRec &R = B->insts[job];

@@ -1,0 +1,163 @@
+"""Per-instance parity of the 256-job fingertip batch (the benchmark's
+workload: seeds 3000..3255 on the 50k-tet fingertip, 100 quasi-static load
+steps each) against stored FP64 oracle results written by
+tests/golden/make_fingertip_batch_reference.py from the oracle alone:
+
+- a 16-seed stratified subset (four per indenter kind, including deep ring
+  and box jobs and the jobs whose FP32 batch run ends load steps at the
+  Newton cap) with full displacement fields after load steps 50 and 100 and
+  the contact patch at step 100;
+- for every seed and step, the oracle's status and the displacement
+  statistics of the paper's Sec. IV (max_i |u_i|, mean_i |u_i|) and the
+  contact resultant.
+
+The subset runs as one batch in the benchmark's launch configuration; load
+steps the device ends at the rounding floor or the Newton cap are replayed
+as truncated jobs (the same poses, stopped after that step) and compared
+with the oracle's statistics at that step.
+
+Bounds, e_inf = max_i |u_i - u_i^ref| / max_i |u_i^ref|:
+  - steps 50 and 100, where the oracle converged and the device ended the
+    step converged or at the rounding floor: 1e-4 (FP32 path) and 1e-8
+    (FP64 path, both sides solved to 2e-9 relative residual); the contact
+    resultant within the same bounds relative to its largest component, and
+    the contact node sets equal;
+  - a step the device ends at the rounding floor: the oracle converged there
+    and the displacement statistics agree within the same bounds;
+  - a step the device ends at the Newton cap: its last accepted iterate is a
+    usable state, the statistics within 1e-2 of the oracle's converged ones
+    (or of the oracle's own last iterate where it fails too).
+"""
+import hashlib
+import os
+
+import numpy as np
+import pytest
+
+from paper_2103_16747_amd import fem, workload as W
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.join(os.path.dirname(__file__), "golden")
+STRAT = os.path.join(HERE, "fingertip50k_stratified_oracle.npz")
+SUMM = os.path.join(HERE, "fingertip50k_batch_summary.npz")
+ST_OK, ST_FLOOR = 0, 1
+CAP_BOUND = 1e-2
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def e_inf(u, ref):
+    return float(np.abs(u - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=float), np.asarray(b, dtype=float)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def mesh_hash(mesh):
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(mesh.X, dtype=np.float64).tobytes())
+    h.update(np.ascontiguousarray(mesh.tets, dtype=np.int32).tobytes())
+    h.update(np.ascontiguousarray(mesh.fixed, dtype=np.uint8).tobytes())
+    return h.hexdigest()[:16]
+
+
+def truncated(ind, k):
+    """The job's first k load steps (same poses), ending after step k."""
+    return W.Indentation(ind.kind, ind.shape, ind.R, ind.c0, ind.direction, ind.depth * k / ind.steps, k,
+                         ind.k_penalty, seed=ind.seed)
+
+
+@pytest.fixture(scope="module")
+def refs():
+    if not (os.path.exists(STRAT) and os.path.exists(SUMM)):
+        pytest.skip("oracle reference files not generated")
+    strat, summ = np.load(STRAT), np.load(SUMM)
+    mesh = W.fingertip_mesh(50000)
+    assert str(strat["mesh_hash"]) == mesh_hash(mesh) == str(summ["mesh_hash"])
+    return strat, summ, mesh
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_stratified_batch_jobs_match_oracle(refs, precision):
+    strat, summ, mesh = refs
+    seeds = [int(s) for s in strat["seeds"]]
+    row = {int(s): i for i, s in enumerate(summ["seeds"])}
+    bound = 1e-4 if precision == "fp32" else 1e-8
+    P = fem.fem_default_params(fem.FEM_PREC_FP32) if precision == "fp32" else \
+        fem.fem_default_params(fem.FEM_PREC_FP64, newton_rtol=2e-9, cg_rtol=1e-10)
+    inds = {s: W.seat_on_mesh(W.random_indentation(s), mesh) for s in seeds}
+    say("case", precision, "seeds", seeds)
+
+    full = fem.FemBatch(len(seeds), precision)
+    mid = full.add_mesh(mesh.X, mesh.tets, mesh.fixed)
+    ids = {s: full.add_job(mid, inds[s]) for s in seeds}
+    assert full.run(P) == 0
+    dev_status = {s: full.step_status(ids[s]) for s in seeds}
+    for s in seeds:
+        assert len(dev_status[s]) == 100 and full.job_info(ids[s])["done"]
+    # Step 50 of every seed, and every step the device did not end converged,
+    # as truncated jobs of one more batch.
+    trunc = [(s, 50) for s in seeds]
+    trunc += [(s, k + 1) for s in seeds for k in np.nonzero(dev_status[s] != ST_OK)[0] if k + 1 not in (50, 100)]
+    part = fem.FemBatch(len(trunc), precision)
+    pmid = part.add_mesh(mesh.X, mesh.tets, mesh.fixed)
+    tids = [part.add_job(pmid, truncated(inds[s], k)) for s, k in trunc]
+    assert part.run(P) == 0
+    state = {(s, 100): full.displacements(ids[s]) for s in seeds}
+    state.update({(s, k): part.displacements(j) for (s, k), j in zip(trunc, tids)})
+
+    failures = []
+    for s in seeds:
+        i = row[s]
+        orc_st = summ["status"][i]
+        for k in (50, 100):
+            dst = int(dev_status[s][k - 1])
+            if orc_st[k - 1] != 0 or dst not in (ST_OK, ST_FLOOR):
+                say(f"{precision} seed {s} step {k}: device status {dst}, oracle {int(orc_st[k - 1])}: not compared")
+                continue
+            err = e_inf(state[(s, k)], strat[f"u{k}_{s}"])
+            say(f"{precision} seed {s} {W.KIND_NAMES[inds[s].kind]} depth {inds[s].depth * 1e3:.2f} mm "
+                f"step {k}: e_inf {err:.3e}")
+            if err > bound:
+                failures.append((s, k, "e_inf", err))
+        if orc_st[99] == 0 and int(dev_status[s][99]) in (ST_OK, ST_FLOOR):
+            pid, _, _, Ft = full.contact_patch(ids[s])
+            ef = rel(Ft, summ["F"][i][99])
+            say(f"{precision} seed {s} step 100: resultant rel err {ef:.3e}, contact nodes {len(pid)} "
+                f"(oracle {len(strat[f'ids100_{s}'])})")
+            if ef > bound:
+                failures.append((s, 100, "resultant", ef))
+            if not np.array_equal(np.sort(pid), np.sort(strat[f"ids100_{s}"])):
+                failures.append((s, 100, "patch", sorted(set(pid) ^ set(strat[f"ids100_{s}"].tolist()))))
+        for k in np.nonzero(dev_status[s] != ST_OK)[0] + 1:
+            dst, ost = int(dev_status[s][k - 1]), int(orc_st[k - 1])
+            um, un = disp_stats(state[(s, k)])
+            dm, dn = rel(um, summ["umax"][i][k - 1]), rel(un, summ["umean"][i][k - 1])
+            dF = rel(resultant_of(full, part, ids, tids, trunc, s, k), summ["F"][i][k - 1])
+            say(f"{precision} seed {s} step {k}: device status {dst}, oracle status {ost}; "
+                f"max|u| rel err {dm:.3e}, mean|u| {dn:.3e}, resultant {dF:.3e}")
+            if dst == ST_FLOOR:
+                if ost != 0:
+                    failures.append((s, k, "floor step where the oracle fails", ost))
+                elif max(dm, dn) > bound:
+                    failures.append((s, k, "floor step stats", max(dm, dn)))
+            elif max(dm, dn) > CAP_BOUND:
+                failures.append((s, k, "capped step stats", max(dm, dn)))
+    full.close()
+    part.close()
+    assert not failures, failures
+
+
+def disp_stats(u):
+    n = np.linalg.norm(u, axis=1)
+    return float(n.max()), float(n.mean())
+
+
+def resultant_of(full, part, ids, tids, trunc, s, k):
+    if k == 100:
+        return full.contact_patch(ids[s])[3]
+    return part.contact_patch(tids[trunc.index((s, k))])[3]
