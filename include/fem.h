@@ -385,6 +385,24 @@ int fem_batch_get_displacements(fem_batch *batch, int32_t job_id, double *u, int
 int fem_batch_get_contact_patch(fem_batch *batch, int32_t job_id, int32_t *ids, double *f, double *phi,
                                 int32_t capacity, int32_t *n_contact, double F_total[3]);
 
+/* fem_batch_get_contact_patch for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same result in the same caller arrays, with the kernel's
+ * staging in a static device array of the library (about 1.2 MB per device,
+ * held until the process ends) instead of a buffer the batch allocates. It
+ * calls no hipMalloc or hipFree and allocates no host memory either: the
+ * entries are ordered in the caller's arrays. Every call on one device shares
+ * that array, so calls that overlap on one device (from several threads or
+ * batches) race and must be serialised by the caller. Limits and errors, in
+ * addition to those of fem_batch_get_contact_patch: FEM_E_INVALID if the
+ * job's mesh has more than FEM_NOALLOC_MAX_CONTACT contact-eligible nodes, or
+ * if f or phi is requested without ids (the ids order the entries);
+ * FEM_E_STATE if jobs were added, restarted or removed since the last
+ * fem_batch_run (updating the launch tables would allocate). */
+#define FEM_NOALLOC_MAX_CONTACT 32768
+int fem_batch_get_contact_patch_noalloc(fem_batch *batch, int32_t job_id, int32_t *ids, double *f, double *phi,
+                                        int32_t capacity, int32_t *n_contact, double F_total[3]);
+
 /* Kernel timing for a batch (as fem_set_kernel_timing). */
 int fem_batch_set_kernel_timing(fem_batch *batch, int32_t every);
 int fem_batch_get_kernel_timing(const fem_batch *batch, int32_t kernel, int64_t *count, double *total_ms);

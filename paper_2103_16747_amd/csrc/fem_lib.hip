@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -27,9 +28,23 @@
 using namespace fem;
 using namespace fem_layout;
 
+// Staging of fem_batch_get_contact_patch_noalloc: the resultant (4 doubles),
+// the contact count, then per contact node its force (3 doubles), phi and
+// device node id, for at most FEM_NOALLOC_MAX_CONTACT contact-eligible
+// nodes. Each device holds its own copy for the life of the process.
+constexpr size_t kNoAllocBytes = 64 + (size_t)FEM_NOALLOC_MAX_CONTACT * (4 * sizeof(double) + sizeof(int));
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
 namespace {
 
 thread_local std::string g_last_error;
+
+// Device address of `scratch` per device ordinal, resolved once per device
+// by fem_batch_create with that device current (the host-side symbol is not
+// a device address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
 
 int fail(int code, const std::string &msg) {
     g_last_error = msg;
@@ -171,6 +186,18 @@ namespace {
 
 int set_device(const fem_batch *B) {
     HIP_TRY(hipSetDevice(B->device));
+    return FEM_OK;
+}
+
+// With `device` current: the device address of `scratch` on it, once.
+int resolve_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return fail(FEM_E_INVALID, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return FEM_OK;
+    void *ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(FEM_E_DEVICE, "no device address for the static scratch");
+    g_scratch_ptr[device] = ptr;
     return FEM_OK;
 }
 
@@ -797,6 +824,7 @@ int batch_create(const fem_config *cfg, int capacity, fem_batch **out) {
     B->capacity = capacity;
     B->insts.resize(capacity);
     int rc = set_device(B);
+    if (!rc) rc = resolve_scratch(B->device);
     if (!rc) {
         if (c.stream) {
             B->stream = (hipStream_t)c.stream;
@@ -952,6 +980,40 @@ void fill_step_info(const InstState &s, int m, fem_step_info *info) {
     info->tet_updates = (int64_t)m * (int64_t)(s.st_grad + s.st_hv);
 }
 
+// Staging of the contact patch kernel in a buffer of `cap` contact slots:
+// resultant (4 doubles), count, then forces (3 cap doubles), phi (cap
+// doubles) and device node ids (cap ints).
+struct PatchStage {
+    double *F, *f, *phi;
+    int *count, *ids;
+    PatchStage(void *base, size_t cap) {
+        char *b = (char *)base;
+        F = (double *)b;
+        count = (int *)(b + 32);
+        f = (double *)(b + 64);
+        phi = f + 3 * cap;
+        ids = (int *)(phi + cap);
+    }
+};
+
+// Runs the contact patch kernel of one instance into `st` and reads the
+// count and resultant back (the kernel writes every slot it reports and
+// clears the count and resultant itself).
+int contact_patch_launch(fem_batch *B, int slot, const PatchStage &st, int *count, double Ft[3]) {
+    if (B->precision == FEM_PREC_FP32)
+        k_contact_patch<float><<<1, 1024, 0, B->stream>>>((const Topo<float> *)B->d_topos,
+                                                            (const InstBufs<float> *)B->d_bufs, slot, st.ids, st.f,
+                                                            st.phi, st.count, st.F);
+    else
+        k_contact_patch<double><<<1, 1024, 0, B->stream>>>((const Topo<double> *)B->d_topos,
+                                                             (const InstBufs<double> *)B->d_bufs, slot, st.ids, st.f,
+                                                             st.phi, st.count, st.F);
+    TRY(launch_check("k_contact_patch"));
+    HIP_TRY(hipMemcpyAsync(count, st.count, sizeof(int), hipMemcpyDeviceToHost, B->stream));
+    HIP_TRY(hipMemcpyAsync(Ft, st.F, 3 * sizeof(double), hipMemcpyDeviceToHost, B->stream));
+    return sync(B);
+}
+
 int contact_patch_impl(fem_batch *B, int slot, int32_t *ids, double *f, double *phi, int32_t capacity,
                        int32_t *n_contact, double F_total[3]) {
     const int n = B->topos[B->insts[slot].topo].n;
@@ -964,26 +1026,12 @@ int contact_patch_impl(fem_batch *B, int slot, int32_t *ids, double *f, double *
         B->patch_bytes = need;
     }
     if (B->tables_dirty) TRY(B->precision == FEM_PREC_FP32 ? rebuild_tables<float>(B) : rebuild_tables<double>(B));
-    char *base = (char *)B->patch;
-    double *d_F = (double *)base;
-    int *d_count = (int *)(base + 32);
-    double *d_f = (double *)(base + 64);
-    double *d_phi = d_f + 3 * (size_t)n;
-    int *d_ids = (int *)(d_phi + n);
-    if (B->precision == FEM_PREC_FP32)
-        k_contact_patch<float><<<1, 1024, 0, B->stream>>>((const Topo<float> *)B->d_topos,
-                                                            (const InstBufs<float> *)B->d_bufs, slot, d_ids, d_f,
-                                                            d_phi, d_count, d_F);
-    else
-        k_contact_patch<double><<<1, 1024, 0, B->stream>>>((const Topo<double> *)B->d_topos,
-                                                             (const InstBufs<double> *)B->d_bufs, slot, d_ids, d_f,
-                                                             d_phi, d_count, d_F);
-    TRY(launch_check("k_contact_patch"));
+    const PatchStage st(B->patch, (size_t)n);
+    double *d_f = st.f, *d_phi = st.phi;
+    int *d_ids = st.ids;
     int count = 0;
     double Ft[3];
-    HIP_TRY(hipMemcpyAsync(&count, d_count, sizeof(int), hipMemcpyDeviceToHost, B->stream));
-    HIP_TRY(hipMemcpyAsync(Ft, d_F, sizeof Ft, hipMemcpyDeviceToHost, B->stream));
-    TRY(sync(B));
+    TRY(contact_patch_launch(B, slot, st, &count, Ft));
     *n_contact = count;
     if (F_total) std::memcpy(F_total, Ft, sizeof Ft);
     if (capacity < count) return fail(FEM_E_BUFFER, "capacity below the contact count");
@@ -1006,6 +1054,57 @@ int contact_patch_impl(fem_batch *B, int slot, int32_t *ids, double *f, double *
                 for (int d = 0; d < 3; d++) f[3 * (size_t)k + d] = hf[3 * (size_t)src + d];
             if (phi) phi[k] = hphi[src];
         }
+    }
+    return FEM_OK;
+}
+
+// The contact patch staged in the device's static scratch: the same kernel
+// and the same caller-visible result as contact_patch_impl, with the caller's
+// arrays as the only host storage (the device ids are mapped to caller ids
+// and the entries ordered by a heap sort in place).
+int contact_patch_noalloc_impl(fem_batch *B, int slot, int32_t *ids, double *f, double *phi, int32_t capacity,
+                               int32_t *n_contact, double F_total[3]) {
+    const TopoRec &tp = B->topos[B->insts[slot].topo];
+    if (tp.nc > FEM_NOALLOC_MAX_CONTACT)
+        return fail(FEM_E_INVALID, "mesh has " + std::to_string(tp.nc) + " contact-eligible nodes, above the " +
+                                       std::to_string(FEM_NOALLOC_MAX_CONTACT) + " the static scratch holds");
+    if (B->tables_dirty) return fail(FEM_E_STATE, "jobs changed since the last fem_batch_run (run the batch first)");
+    if ((f || phi) && !ids) return fail(FEM_E_INVALID, "ids is needed to order f and phi");
+    void *base = g_scratch_ptr[B->device];
+    if (!base) return fail(FEM_E_STATE, "static scratch not resolved on this device");
+    const PatchStage st(base, (size_t)FEM_NOALLOC_MAX_CONTACT);
+    int count = 0;
+    double Ft[3];
+    TRY(contact_patch_launch(B, slot, st, &count, Ft));
+    *n_contact = count;
+    if (F_total) std::memcpy(F_total, Ft, sizeof Ft);
+    if (capacity < count) return fail(FEM_E_BUFFER, "capacity below the contact count");
+    if (count == 0 || !ids) return FEM_OK;
+    HIP_TRY(hipMemcpyAsync(ids, st.ids, count * sizeof(int), hipMemcpyDeviceToHost, B->stream));
+    if (f) HIP_TRY(hipMemcpyAsync(f, st.f, 3 * (size_t)count * sizeof(double), hipMemcpyDeviceToHost, B->stream));
+    if (phi) HIP_TRY(hipMemcpyAsync(phi, st.phi, count * sizeof(double), hipMemcpyDeviceToHost, B->stream));
+    TRY(sync(B));
+    for (int k = 0; k < count; k++) ids[k] = tp.perm[ids[k]];
+    auto swap_entries = [&](int a, int b) {
+        std::swap(ids[a], ids[b]);
+        if (f)
+            for (int d = 0; d < 3; d++) std::swap(f[3 * (size_t)a + d], f[3 * (size_t)b + d]);
+        if (phi) std::swap(phi[a], phi[b]);
+    };
+    auto sift_down = [&](int root, int end) {
+        for (;;) {
+            int child = 2 * root + 1;
+            if (child >= end) return;
+            if (child + 1 < end && ids[child + 1] > ids[child]) child++;
+            if (ids[root] >= ids[child]) return;
+            swap_entries(root, child);
+            root = child;
+        }
+    };
+    for (int k = count / 2 - 1; k >= 0; k--) sift_down(k, count);
+    for (int end = count - 1; end > 0; end--) {
+        swap_entries(0, end);
+        sift_down(0, end);
     }
     return FEM_OK;
 }
@@ -1589,6 +1688,14 @@ int fem_batch_get_contact_patch(fem_batch *B, int32_t job, int32_t *ids, double 
     if (!n_contact || !job_ok(B, job)) return fail(FEM_E_INVALID, "unknown job");
     TRY(set_device(B));
     return contact_patch_impl(B, job, ids, f, phi, capacity, n_contact, F_total);
+}
+
+int fem_batch_get_contact_patch_noalloc(fem_batch *B, int32_t job, int32_t *ids, double *f, double *phi,
+                                        int32_t capacity, int32_t *n_contact, double F_total[3]) {
+    g_last_error.clear();
+    if (!n_contact || !job_ok(B, job)) return fail(FEM_E_INVALID, "unknown job");
+    TRY(set_device(B));
+    return contact_patch_noalloc_impl(B, job, ids, f, phi, capacity, n_contact, F_total);
 }
 
 int fem_batch_set_kernel_timing(fem_batch *B, int32_t every) {

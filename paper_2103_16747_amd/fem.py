@@ -32,7 +32,8 @@ EXPORTS = ("fem_create_mesh", "fem_destroy_mesh", "fem_set_material", "fem_set_i
            "fem_batch_mesh_info", "fem_batch_add_job", "fem_batch_restart_job", "fem_batch_remove_job", "fem_batch_run", "fem_batch_job_info",
            "fem_batch_job_step_status",
            "fem_batch_get_displacements", "fem_batch_get_velocities", "fem_batch_get_tet_stress",
-           "fem_batch_get_displacement_stats", "fem_batch_get_contact_patch", "fem_batch_set_kernel_timing",
+           "fem_batch_get_displacement_stats", "fem_batch_get_contact_patch", "fem_batch_get_contact_patch_noalloc",
+           "fem_batch_set_kernel_timing",
            "fem_batch_get_kernel_timing", "fem_batch_get_kernel_launches", "fem_set_graphs", "fem_batch_set_graphs", "fem_batch_set_option",
            "fem_batch_job_footprint", "fem_status_string",
            "fem_last_error")
@@ -141,6 +142,7 @@ def load(path: str = LIB_PATH):
     L.fem_batch_job_step_status.argtypes = [vp, C.c_int32, i32p, C.c_int32, i32p]
     L.fem_batch_get_displacements.argtypes = [vp, C.c_int32, dp, C.c_int64]
     L.fem_batch_get_contact_patch.argtypes = [vp, C.c_int32, i32p, dp, dp, C.c_int32, i32p, dp]
+    L.fem_batch_get_contact_patch_noalloc.argtypes = [vp, C.c_int32, i32p, dp, dp, C.c_int32, i32p, dp]
     L.fem_batch_set_kernel_timing.argtypes = [vp, C.c_int32]
     L.fem_batch_get_kernel_timing.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
     L.fem_batch_get_kernel_launches.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64)]
@@ -539,6 +541,20 @@ def fem_batch_get_contact_patch(h, job: int):
     return ids[:c], f[:c], phi[:c], Ft
 
 
+def fem_batch_get_contact_patch_noalloc(h, job: int, ids, f, phi, F_total):
+    """Allocation-free contact patch into caller arrays (ids int32, f n x 3,
+    phi, F_total 3; f and phi need ids; with ids None only the count and the
+    resultant are read); returns the contact count."""
+    cnt = C.c_int32()
+    cap = 0 if ids is None else int(ids.shape[0])
+    i32 = None if ids is None else ids.ctypes.data_as(C.POINTER(C.c_int32))
+    _check(load().fem_batch_get_contact_patch_noalloc(h, int(job), i32, None if f is None else _dp(f),
+                                                      None if phi is None else _dp(phi), cap, C.byref(cnt),
+                                                      None if F_total is None else _dp(F_total)),
+           allow=(FEM_E_BUFFER,) if ids is None else ())
+    return cnt.value
+
+
 def fem_batch_set_kernel_timing(h, every: int):
     _check(load().fem_batch_set_kernel_timing(h, int(every)))
 
@@ -623,6 +639,9 @@ class FemBatch:
 
     def contact_patch(self, job):
         return fem_batch_get_contact_patch(self.h, job)
+
+    def contact_patch_noalloc(self, job, ids, f, phi, F_total):
+        return fem_batch_get_contact_patch_noalloc(self.h, job, ids, f, phi, F_total)
 
     def set_kernel_timing(self, every):
         fem_batch_set_kernel_timing(self.h, every)
