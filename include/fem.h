@@ -271,8 +271,8 @@ int fem_eval_hessvec(fem_mesh *mesh, const fem_solve_params *params, const doubl
  * or line-search trial otherwise), the node pass (CG update, Newton init,
  * line-search directional derivative) and the finalize. With every > 0,
  * every every-th round of solver steps is launched kernel by kernel, each
- * launch with a start and a stop HIP event (hipExtLaunchKernel on the
- * handle's stream: the dispatch's own start and end); the other rounds
+ * launch with a start and a stop HIP event (hipExtLaunchKernel on the job
+ * group's stream: the dispatch's own start and end); the other rounds
  * replay captured graphs as without timing. every = 0 turns timing off.
  * Counters are cleared on each call. */
 #define FEM_KERNEL_TILE 0
@@ -422,11 +422,19 @@ int fem_batch_set_graphs(fem_batch *batch, int32_t enable);
  *                      (0 = automatic: 16 for batches, the expected length
  *                      of the Newton iteration for a single job);
  *   FEM_OPT_TILE_TETS  tets per tile, 64..512 (default 512);
- *   FEM_OPT_TILE_NODES distinct nodes per tile, 16..256 (default 256).
+ *   FEM_OPT_TILE_NODES distinct nodes per tile, 16..256 (default 256);
+ *   FEM_OPT_GROUPS     job groups per round, 0..2 (0 = automatic: two when
+ *                      the running jobs have at least 2048 tile blocks in
+ *                      all). With two groups each group's solver steps run
+ *                      on a stream of its own and the groups' tile passes
+ *                      alternate, so one group's node pass (memory-bound)
+ *                      overlaps the other's tile pass (arithmetic-bound);
+ *                      every job computes the same steps either way.
  * Errors: FEM_E_INVALID (unknown option, value out of range). */
 #define FEM_OPT_ROUND_STEPS 0
 #define FEM_OPT_TILE_TETS 1
 #define FEM_OPT_TILE_NODES 2
+#define FEM_OPT_GROUPS 3
 int fem_batch_set_option(fem_batch *batch, int32_t option, int32_t value);
 
 /* Device bytes one job on mesh mesh_id allocates (for admission by HBM

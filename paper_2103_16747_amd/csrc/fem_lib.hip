@@ -90,7 +90,7 @@ struct Arena {
 // (hipExtLaunchKernel; the other rounds replay captured graphs), harvested
 // after stream synchronisations.
 struct KernelTimer {
-    static constexpr int kKinds = 3, kPool = 512;
+    static constexpr int kKinds = 3, kPool = 1024;
     int every = 0;
     long long rounds = 0;                     // rounds launched since timing was set
     long long seen[kKinds] = {0, 0, 0};       // launches of each kernel kind
@@ -106,8 +106,22 @@ struct KernelTimer {
 struct RoundGraph {
     int chunk = 0;
     int variant = 0;        // kernel instances captured (see kernel_variant)
+    int groups = 1;         // job groups (streams) captured
     hipGraphExec_t exec = nullptr;
 };
+
+// One group of running jobs: its slices of the tile and node work tables and
+// of the live list. A round runs each group's solver steps on a stream of its
+// own (see enqueue_round).
+struct JobGroup {
+    int tile_off = 0, tile_n = 0, node_off = 0, node_n = 0, live_off = 0, live_n = 0;
+};
+
+// Work at or above which a round splits the running jobs into two groups
+// (tile blocks over all jobs: 8 per compute unit).
+constexpr int kGroupMinTileBlocks = 2048;
+// Events for the cross-stream order of one captured or launched round.
+constexpr int kRoundEvents = 2 * 64 + 2;
 
 struct TopoRec {
     int n = 0, m = 0, ntile = 0, nent = 0, nc = 0, ncb = 0;
@@ -134,6 +148,12 @@ struct fem_batch {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    hipStream_t stream2 = nullptr;          // the second job group's stream (library-owned)
+    hipEvent_t xev[kRoundEvents] = {};      // cross-stream order within a round
+    bool xev_created = false;
+    JobGroup grp[2];
+    int ngroups = 1;
+    int groups_opt = 0;                     // 0: automatic, 1 or 2: forced
     int capacity = 0;
     std::vector<TopoRec> topos;
     std::vector<InstRec> insts;     // size capacity
@@ -226,12 +246,13 @@ int timer_slot(fem_batch *B, int kind, bool sample) {
 // Launches `kernel` plainly, or with the timer slot's start (first) and stop
 // (last) events when sampled.
 template <typename K, typename... Args>
-void launch_timed(fem_batch *B, int slot, bool first, bool last, K kernel, dim3 grid, dim3 block, Args... args) {
+void launch_timed(fem_batch *B, hipStream_t st, int slot, bool first, bool last, K kernel, dim3 grid, dim3 block,
+                  Args... args) {
     if (slot < 0) {
-        hipLaunchKernelGGL(kernel, grid, block, 0, B->stream, args...);
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
         return;
     }
-    hipExtLaunchKernelGGL(kernel, grid, block, 0, B->stream, first ? B->timer.ev[slot][0] : nullptr,
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, st, first ? B->timer.ev[slot][0] : nullptr,
                           last ? B->timer.ev[slot][1] : nullptr, 0, args...);
 }
 
@@ -482,24 +503,53 @@ template <typename T>
 int rebuild_tables(fem_batch *B) {
     std::vector<int2> wt, wn;
     std::vector<int> live;
-    int max_t = 0, max_nb = 0;
+    std::vector<int> members[2];
+    long long blocks = 0;
     for (int i = 0; i < B->capacity; i++) {
         InstRec &R = B->insts[i];
         R.in_tables = R.live && running_phase(B->h_states[i].phase);
         if (!R.in_tables) continue;
         const TopoRec &tp = B->topos[R.topo];
-        max_t = std::max(max_t, tp.ntile + tp.ncb);
-        max_nb = std::max(max_nb, ceil_div(tp.n, kBlock));
+        blocks += tp.ntile + tp.ncb;
         live.push_back(i);
     }
-    for (int t = 0; t < max_t; t++)
-        for (int i : live) {
+    // Two groups when the work fills the chip several times over (or when
+    // forced): jobs dealt to the group with fewer tile blocks so far.
+    const int ng = B->groups_opt == 1 || live.size() < 2 ? 1
+                   : B->groups_opt == 2 || blocks >= kGroupMinTileBlocks ? 2 : 1;
+    long long load[2] = {0, 0};
+    for (int i : live) {
+        const TopoRec &tp = B->topos[B->insts[i].topo];
+        const int g = ng == 2 && load[1] < load[0] ? 1 : 0;
+        members[g].push_back(i);
+        load[g] += tp.ntile + tp.ncb;
+    }
+    live.clear();
+    for (int g = 0; g < ng; g++) {
+        JobGroup &G = B->grp[g];
+        int max_t = 0, max_nb = 0;
+        for (int i : members[g]) {
             const TopoRec &tp = B->topos[B->insts[i].topo];
-            if (t < tp.ntile + tp.ncb) wt.push_back(make_int2(i, t));
+            max_t = std::max(max_t, tp.ntile + tp.ncb);
+            max_nb = std::max(max_nb, ceil_div(tp.n, kBlock));
         }
-    for (int t = 0; t < max_nb; t++)
-        for (int i : live)
-            if (t < ceil_div(B->topos[B->insts[i].topo].n, kBlock)) wn.push_back(make_int2(i, t));
+        G.tile_off = (int)wt.size();
+        for (int t = 0; t < max_t; t++)
+            for (int i : members[g]) {
+                const TopoRec &tp = B->topos[B->insts[i].topo];
+                if (t < tp.ntile + tp.ncb) wt.push_back(make_int2(i, t));
+            }
+        G.tile_n = (int)wt.size() - G.tile_off;
+        G.node_off = (int)wn.size();
+        for (int t = 0; t < max_nb; t++)
+            for (int i : members[g])
+                if (t < ceil_div(B->topos[B->insts[i].topo].n, kBlock)) wn.push_back(make_int2(i, t));
+        G.node_n = (int)wn.size() - G.node_off;
+        G.live_off = (int)live.size();
+        live.insert(live.end(), members[g].begin(), members[g].end());
+        G.live_n = (int)members[g].size();
+    }
+    B->ngroups = ng;
     auto upload = [&](const std::vector<int2> &v, int2 *&d, int &cap, int &count) -> int {
         if ((int)v.size() > cap) {
             if (d) (void)hipFree(d);
@@ -567,38 +617,59 @@ int write_state(fem_batch *B, int slot) {
     return sync(B);
 }
 
-// One round: C solver steps, each a tile pass, a node pass and a finalize
-// over every live instance. In a sampled round every launch carries events
-// (a tile pass with both laws present is timed from the start of the first
-// launch to the end of the second).
+// One solver step of one job group on stream st: a tile pass (one launch per
+// constitutive law present; blocks of jobs on the other law return at once),
+// a node pass (the friction instance only when a job needs it) and a
+// finalize. Returns after enqueueing the tile pass through `after_tile`, so
+// the caller can order the other group's tile pass behind it.
 template <typename T>
-int enqueue_round(fem_batch *B, int chunk, bool sample) {
+void enqueue_step(fem_batch *B, const JobGroup &G, hipStream_t st, bool sample, hipEvent_t after_tile) {
     const Topo<T> *tp = (const Topo<T> *)B->d_topos;
     const InstBufs<T> *bf = (const InstBufs<T> *)B->d_bufs;
-    const int gt = pad8(B->nwork_tile), gn = pad8(B->nwork_node), nl = B->nlive;
+    const int2 *wt = (const int2 *)B->d_work_tile + G.tile_off, *wn = (const int2 *)B->d_work_node + G.node_off;
+    const int *lv = (const int *)B->d_live + G.live_off;
+    const SolveParams *P = (const SolveParams *)B->d_params;
+    const int gt = pad8(G.tile_n), gn = pad8(G.node_n), nl = G.live_n;
     const bool nh = B->n_law[0] > 0, cr = B->n_law[1] > 0, fric = B->n_fric > 0;
-    for (int c = 0; c < chunk; c++) {
-        // one tile launch per constitutive law present (blocks of jobs on the
-        // other law return at once)
-        int slot = timer_slot(B, FEM_KERNEL_TILE, sample);
-        if (nh)
-            launch_timed(B, slot, true, !cr, k_tile<T, LAW_NH>, dim3(gt), dim3(kBlock), tp, bf,
-                         (const int2 *)B->d_work_tile, B->nwork_tile, (const SolveParams *)B->d_params);
-        if (cr)
-            launch_timed(B, slot, !nh, true, k_tile<T, LAW_CR>, dim3(gt), dim3(kBlock), tp, bf,
-                         (const int2 *)B->d_work_tile, B->nwork_tile, (const SolveParams *)B->d_params);
-        // the node pass with the friction phases only when a job needs them
-        slot = timer_slot(B, FEM_KERNEL_NODE, sample);
-        if (fric)
-            launch_timed(B, slot, true, true, k_node<T, true>, dim3(gn), dim3(kBlock), tp, bf,
-                         (const int2 *)B->d_work_node, B->nwork_node, (const SolveParams *)B->d_params);
-        else
-            launch_timed(B, slot, true, true, k_node<T, false>, dim3(gn), dim3(kBlock), tp, bf,
-                         (const int2 *)B->d_work_node, B->nwork_node, (const SolveParams *)B->d_params);
-        slot = timer_slot(B, FEM_KERNEL_FINALIZE, sample);
-        launch_timed(B, slot, true, true, k_finalize<T>, dim3(nl), dim3(64), tp, bf, (const int *)B->d_live, nl,
-                     (const SolveParams *)B->d_params);
+    int slot = timer_slot(B, FEM_KERNEL_TILE, sample);
+    if (nh) launch_timed(B, st, slot, true, !cr, k_tile<T, LAW_NH>, dim3(gt), dim3(kBlock), tp, bf, wt, G.tile_n, P);
+    if (cr) launch_timed(B, st, slot, !nh, true, k_tile<T, LAW_CR>, dim3(gt), dim3(kBlock), tp, bf, wt, G.tile_n, P);
+    if (after_tile) (void)hipEventRecord(after_tile, st);
+    slot = timer_slot(B, FEM_KERNEL_NODE, sample);
+    if (fric)
+        launch_timed(B, st, slot, true, true, k_node<T, true>, dim3(gn), dim3(kBlock), tp, bf, wn, G.node_n, P);
+    else
+        launch_timed(B, st, slot, true, true, k_node<T, false>, dim3(gn), dim3(kBlock), tp, bf, wn, G.node_n, P);
+    slot = timer_slot(B, FEM_KERNEL_FINALIZE, sample);
+    launch_timed(B, st, slot, true, true, k_finalize<T>, dim3(nl), dim3(64), tp, bf, lv, nl, P);
+}
+
+// One round: C solver steps of every job group. With one group the steps run
+// on the batch stream. With two, group 0 runs on the batch stream and group 1
+// on the second stream, each group's steps in order, and the tile passes of
+// the two groups alternate (group 1's step c after group 0's tile pass c,
+// group 0's step c + 1 after group 1's tile pass c): a group's node pass,
+// bound by memory bandwidth, then overlaps the other group's tile pass, bound
+// by vector arithmetic. The round ends with the second stream joined back.
+template <typename T>
+int enqueue_round(fem_batch *B, int chunk, bool sample) {
+    if (B->ngroups == 1) {
+        for (int c = 0; c < chunk; c++) enqueue_step<T>(B, B->grp[0], B->stream, sample, nullptr);
+        return launch_check("round");
     }
+    hipStream_t s0 = B->stream, s1 = B->stream2;
+    hipEvent_t *ev = B->xev;   // [0] fork, [1] join, then two per step
+    HIP_TRY(hipEventRecord(ev[0], s0));
+    HIP_TRY(hipStreamWaitEvent(s1, ev[0], 0));
+    for (int c = 0; c < chunk; c++) {
+        hipEvent_t tile0 = ev[2 + 2 * c], tile1 = ev[3 + 2 * c];
+        if (c > 0) HIP_TRY(hipStreamWaitEvent(s0, ev[3 + 2 * (c - 1)], 0));
+        enqueue_step<T>(B, B->grp[0], s0, sample, tile0);
+        HIP_TRY(hipStreamWaitEvent(s1, tile0, 0));
+        enqueue_step<T>(B, B->grp[1], s1, sample, tile1);
+    }
+    HIP_TRY(hipEventRecord(ev[1], s1));
+    HIP_TRY(hipStreamWaitEvent(s0, ev[1], 0));
     return launch_check("round");
 }
 
@@ -633,7 +704,7 @@ int launch_round(fem_batch *B, int chunk) {
         const int c = std::max(1, std::min(64, chunk));
         TRY(enqueue_round<T>(B, c, sample));
         if (timing)
-            for (int k = 0; k < KernelTimer::kKinds; k++) tm.seen[k] += c;
+            for (int k = 0; k < KernelTimer::kKinds; k++) tm.seen[k] += (long long)c * B->ngroups;
         return FEM_OK;
     }
     // graph lengths: multiples of 4 up to 32, of 8 up to 64
@@ -641,11 +712,12 @@ int launch_round(fem_batch *B, int chunk) {
     c = c <= 32 ? (c + 3) / 4 * 4 : (c + 7) / 8 * 8;
     int gi = -1;
     for (int i = 0; i < (int)B->graphs.size(); i++)
-        if (B->graphs[i].chunk == c && B->graphs[i].variant == variant) gi = i;
+        if (B->graphs[i].chunk == c && B->graphs[i].variant == variant && B->graphs[i].groups == B->ngroups) gi = i;
     if (gi < 0) {
         RoundGraph G;
         G.chunk = c;
         G.variant = variant;
+        G.groups = B->ngroups;
         hipGraph_t graph = nullptr;
         HIP_TRY(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
         const int rc = enqueue_round<T>(B, c, false);
@@ -660,7 +732,7 @@ int launch_round(fem_batch *B, int chunk) {
     }
     HIP_TRY(hipGraphLaunch(B->graphs[gi].exec, B->stream));
     if (timing)
-        for (int k = 0; k < KernelTimer::kKinds; k++) tm.seen[k] += c;
+        for (int k = 0; k < KernelTimer::kKinds; k++) tm.seen[k] += (long long)c * B->ngroups;
     return FEM_OK;
 }
 
@@ -805,6 +877,9 @@ void batch_release(fem_batch *B) {
     if (B->h_params) (void)hipHostFree(B->h_params);
     if (B->h_stage) (void)hipHostFree(B->h_stage);
     if (B->own_stream && B->stream) (void)hipStreamDestroy(B->stream);
+    if (B->stream2) (void)hipStreamDestroy(B->stream2);
+    if (B->xev_created)
+        for (hipEvent_t e : B->xev) (void)hipEventDestroy(e);
     delete B;
 }
 
@@ -833,6 +908,14 @@ int batch_create(const fem_config *cfg, int capacity, fem_batch **out) {
         } else {
             rc = fail(FEM_E_DEVICE, "stream creation failed");
         }
+    }
+    if (!rc && hipStreamCreateWithFlags(&B->stream2, hipStreamNonBlocking) != hipSuccess)
+        rc = fail(FEM_E_DEVICE, "stream creation failed");
+    if (!rc) {
+        for (hipEvent_t &e : B->xev)
+            if (!rc && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+                rc = fail(FEM_E_DEVICE, "event creation failed");
+        B->xev_created = true;
     }
     const size_t bufs_bytes = (size_t)capacity * std::max(sizeof(InstBufs<float>), sizeof(InstBufs<double>));
     if (!rc && hipMalloc(&B->d_states, capacity * sizeof(InstState)) != hipSuccess) rc = fail(FEM_E_OOM, "states");
@@ -1760,6 +1843,11 @@ int fem_batch_set_option(fem_batch *B, int32_t option, int32_t value) {
     case FEM_OPT_TILE_TETS:
         if (value < 64 || value > kTileTets) return fail(FEM_E_INVALID, "tile tets must be 64..512");
         B->tile_tets = value;
+        return FEM_OK;
+    case FEM_OPT_GROUPS:
+        if (value < 0 || value > 2) return fail(FEM_E_INVALID, "groups must be 0 (automatic), 1 or 2");
+        B->groups_opt = value;
+        B->tables_dirty = true;
         return FEM_OK;
     case FEM_OPT_TILE_NODES:
         if (value < 16 || value > kTileNodes) return fail(FEM_E_INVALID, "tile nodes must be 16..256");

@@ -191,3 +191,38 @@ def test_served_results_equal_alone():
         say("served", r.rid, req.mesh, "latency %.1f ms" % (r.latency * 1e3), "vs alone %.2e" % err)
         assert err <= 1e-9
     batch.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_two_job_groups_match_one(precision):
+    """Rounds split into two job groups on two streams (tile passes
+    alternating between the groups) compute what one group computes: jobs on
+    two meshes, run with one group, with two groups replayed from graphs, and
+    with two groups launched kernel by kernel; the same bounds as alone vs
+    in the mix."""
+    meshes = [W.fingertip_mesh(5000), W.fingertip_mesh(50000)]
+    jobs = []
+    for i in range(10):
+        mesh = meshes[i % 2]
+        ind = W.seat_on_mesh(W.random_indentation(3000 + i), mesh)
+        jobs.append((i % 2, W.Indentation(ind.kind, ind.shape, ind.R, ind.c0, ind.direction, ind.depth / 10, 10,
+                                          ind.k_penalty, seed=3000 + i)))
+    runs = {}
+    for name, groups, graphs in (("one group", 1, 1), ("two groups", 2, 1), ("two groups, no graphs", 2, 0)):
+        b = fem.FemBatch(len(jobs), precision)
+        b.set_option(fem.FEM_OPT_GROUPS, groups)
+        b.set_graphs(graphs)
+        mids = [b.add_mesh(m.X, m.tets, m.fixed) for m in meshes]
+        ids = [b.add_job(mids[k], job, E0, NU0) for k, job in jobs]
+        say("case", precision, name)
+        assert b.run(tight(b, precision)) == 0
+        runs[name] = [b.displacements(j) for j in ids]
+        for j in ids:
+            info = b.job_info(j)
+            assert info["done"] == 1 and info["steps_ok"] + info["steps_failed"] == 10, info
+        b.close()
+    bound = 1e-9 if precision == "fp64" else 1e-5
+    for name in ("two groups", "two groups, no graphs"):
+        errs = [e_inf(u, ref) for u, ref in zip(runs[name], runs["one group"])]
+        say(precision, name, "vs one group: max e_inf %.3e" % max(errs))
+        assert max(errs) <= bound, errs

@@ -16,6 +16,14 @@ steps the device ends at the rounding floor or the Newton cap are replayed
 as truncated jobs (the same poses, stopped after that step) and compared
 with the oracle's statistics at that step.
 
+Stationary points need not be unique: a deep punch can snap the shell
+through, and two correct solves can continue on different branches from
+there. Where a device state misses the stored oracle result, the oracle's
+own Newton iteration is started from the device state (FP64, to 1e-6 of the
+device state's residual): if it stays within the bound of the device state,
+the device result is an equilibrium of the problem on another branch (a
+bifurcation, reported) and not an error; otherwise the case fails.
+
 Bounds, e_inf = max_i |u_i - u_i^ref| / max_i |u_i^ref|:
   - steps 50 and 100, where the oracle converged and the device ended the
     step converged or at the rounding floor: 1e-4 (FP32 path) and 1e-8
@@ -24,9 +32,10 @@ Bounds, e_inf = max_i |u_i - u_i^ref| / max_i |u_i^ref|:
     the contact node sets equal;
   - a step the device ends at the rounding floor: the oracle converged there
     and the displacement statistics agree within the same bounds;
-  - a step the device ends at the Newton cap: its last accepted iterate is a
-    usable state, the statistics within 1e-2 of the oracle's converged ones
-    (or of the oracle's own last iterate where it fails too).
+  - a step the device ends at the Newton cap: either the oracle fails that
+    step too (both report it; two unconverged iterates are not compared), or
+    the device's last accepted iterate is a usable state, its statistics
+    within 1e-2 of the oracle's converged ones.
 """
 import hashlib
 import os
@@ -34,6 +43,7 @@ import os
 import numpy as np
 import pytest
 
+import oracle
 from paper_2103_16747_amd import fem, workload as W
 
 pytestmark = pytest.mark.gpu
@@ -110,7 +120,24 @@ def test_stratified_batch_jobs_match_oracle(refs, precision):
     state = {(s, 100): full.displacements(ids[s]) for s in seeds}
     state.update({(s, k): part.displacements(j) for (s, k), j in zip(trunc, tids)})
 
-    failures = []
+    failures, branches = [], []
+    orc = oracle.Solver(mesh.X, mesh.tets, mesh.fixed, E=0.3e6, nu=0.45)
+    relax_prm = oracle.default_params(newton_rtol=1e-6, newton_atol=1e-12, cg_rtol=1e-10)
+
+    def on_other_branch(s, k, u):
+        """The device state relaxed by the oracle's Newton iteration at load
+        step k: True if it is within the bound of an exact equilibrium."""
+        ind = inds[s]
+        orc.set_indenter(ind.kind, ind.shape, ind.R, ind.center(k), ind.k_penalty)
+        u_rel, info = orc.step(u, relax_prm)
+        d = e_inf(u, u_rel)
+        say(f"{precision} seed {s} step {k}: oracle Newton from the device state: status {info['status']}, "
+            f"|g| {info['g0_norm']:.3e} -> {info['g_norm']:.3e}, e_inf to the relaxed state {d:.3e}")
+        if info["status"] == 0 and d <= bound:
+            branches.append((s, int(k)))
+            return True
+        return False
+
     for s in seeds:
         i = row[s]
         orc_st = summ["status"][i]
@@ -122,9 +149,9 @@ def test_stratified_batch_jobs_match_oracle(refs, precision):
             err = e_inf(state[(s, k)], strat[f"u{k}_{s}"])
             say(f"{precision} seed {s} {W.KIND_NAMES[inds[s].kind]} depth {inds[s].depth * 1e3:.2f} mm "
                 f"step {k}: e_inf {err:.3e}")
-            if err > bound:
+            if err > bound and not on_other_branch(s, k, state[(s, k)]):
                 failures.append((s, k, "e_inf", err))
-        if orc_st[99] == 0 and int(dev_status[s][99]) in (ST_OK, ST_FLOOR):
+        if orc_st[99] == 0 and int(dev_status[s][99]) in (ST_OK, ST_FLOOR) and (s, 100) not in branches:
             pid, _, _, Ft = full.contact_patch(ids[s])
             ef = rel(Ft, summ["F"][i][99])
             say(f"{precision} seed {s} step 100: resultant rel err {ef:.3e}, contact nodes {len(pid)} "
@@ -143,12 +170,14 @@ def test_stratified_batch_jobs_match_oracle(refs, precision):
             if dst == ST_FLOOR:
                 if ost != 0:
                     failures.append((s, k, "floor step where the oracle fails", ost))
-                elif max(dm, dn) > bound:
+                elif max(dm, dn) > bound and (s, k) not in branches and not on_other_branch(s, k, state[(s, k)]):
                     failures.append((s, k, "floor step stats", max(dm, dn)))
-            elif max(dm, dn) > CAP_BOUND:
-                failures.append((s, k, "capped step stats", max(dm, dn)))
+            elif ost == 0 and max(dm, dn) > CAP_BOUND:
+                failures.append((s, k, "capped step where the oracle converged", max(dm, dn)))
     full.close()
     part.close()
+    if branches:
+        say(f"{precision}: device states on another equilibrium branch than the oracle's: {branches}")
     assert not failures, failures
 
 
