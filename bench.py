@@ -79,15 +79,38 @@ def tile_bytes(info, word, hv_passes, el_passes, launches):
     return shared + (hv_passes * hv + el_passes * el) / max(launches, 1)
 
 
+def _plain(o):
+    """JSON encoding of numpy scalars and arrays."""
+    if isinstance(o, np.integer):
+        return int(o)
+    if isinstance(o, np.floating):
+        return float(o)
+    if isinstance(o, np.ndarray):
+        return o.tolist()
+    raise TypeError(type(o).__name__)
+
+
+def emit(out):
+    print(json.dumps(out, default=_plain), flush=True)
+
+
 def progress(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
 def run_batched(mesh, inds, precision, timed_steps, warm_steps, timing_every=0, track_latency=True,
-                material=(0.3e6, 0.45)):
+                material=(0.3e6, 0.45), groups=0, keep=()):
+    """Runs warm_steps untimed and timed_steps timed batches of the jobs
+    `inds`; returns walls, latencies, counters (totals over the timed
+    batches and per batch), kernel timing, and per-job results of the last
+    timed batch: status, counters, displacement statistics and contact
+    resultant for every job, and the final displacements of the job indices
+    in `keep`."""
     from paper_2103_16747_amd import fem
 
     batch = fem.FemBatch(len(inds), precision)
+    if groups:
+        batch.set_option(fem.FEM_OPT_GROUPS, groups)
     mid = batch.add_mesh(mesh.X, mesh.tets, mesh.fixed)
     info = batch.mesh_info(mid)
     jobs = [batch.add_job(mid, ind, *material) for ind in inds]
@@ -99,7 +122,8 @@ def run_batched(mesh, inds, precision, timed_steps, warm_steps, timing_every=0, 
         progress(f"warm-up batch {precision} done")
     if timing_every:
         batch.set_kernel_timing(timing_every)
-    walls, lat, tu, failed, floor, hv, gp = [], [], 0, 0, 0, 0, 0
+    walls, lat, tu, failed, floor, hv, gp, ls = [], [], 0, 0, 0, 0, 0, 0
+    per_batch_failed, per_batch_floor = [], []
     for _ in range(timed_steps):
         for j, ind in zip(jobs, inds):
             batch.restart_job(j, ind, *material)
@@ -121,18 +145,26 @@ def run_batched(mesh, inds, precision, timed_steps, warm_steps, timing_every=0, 
         progress(f"batched {precision}: {len(jobs)} jobs in {walls[-1]:.2f} s")
         infos = [batch.job_info(j) for j in jobs]
         tu += sum(i["tet_updates"] for i in infos)
-        failed += sum(i["steps_failed"] for i in infos)
-        floor += sum(i["steps_floor"] for i in infos)
+        per_batch_failed.append(sum(i["steps_failed"] for i in infos))
+        per_batch_floor.append(sum(i["steps_floor"] for i in infos))
+        failed += per_batch_failed[-1]
+        floor += per_batch_floor[-1]
         hv += sum(i["hv_products"] for i in infos)
         gp += sum(i["grad_passes"] for i in infos)
+        ls += sum(i["ls_trials"] for i in infos)
         lat += list(done_at.values())
     timing = None
     if timing_every:
         timing = {k: batch.kernel_timing(k) + (batch.kernel_launches(k),)
                   for k in (fem.FEM_KERNEL_TILE, fem.FEM_KERNEL_NODE, fem.FEM_KERNEL_FINALIZE)}
         batch.set_kernel_timing(0)
-    finals = [batch.displacements(j) for j in jobs[:4]]
+    finals = {k: batch.displacements(jobs[k]) for k in keep}
     stats = [batch.job_info(j) for j in jobs]
+    job_out = []
+    for j in jobs:
+        umax, umean = batch.displacement_stats(j)
+        job_out.append({"status": batch.step_status(j), "umax": umax, "umean": umean,
+                        "F": batch.contact_patch(j)[3]})
     # data-generation outputs of the finished jobs: per-tet stress and
     # displacement statistics (device kernels; the stress copy to the host
     # is included)
@@ -144,8 +176,9 @@ def run_batched(mesh, inds, precision, timed_steps, warm_steps, timing_every=0, 
     out_ms = (time.perf_counter() - t0) / nout * 1e3
     batch.close()
     return {"walls": walls, "lat": lat, "tet_updates": tu, "failed_steps": failed, "floor_steps": floor,
-            "outputs_ms_per_job": out_ms,
-            "timing": timing, "hv_passes": hv, "grad_passes": gp, "layout": info, "finals": finals, "stats": stats}
+            "failed_per_batch": per_batch_failed, "floor_per_batch": per_batch_floor,
+            "outputs_ms_per_job": out_ms, "timing": timing, "hv_passes": hv, "grad_passes": gp, "ls_trials": ls,
+            "layout": info, "finals": finals, "stats": stats, "jobs": job_out, "groups": groups}
 
 
 def run_single(mesh, inds, precision):
@@ -171,51 +204,29 @@ def run_single(mesh, inds, precision):
     return {"walls": walls, "tet_updates": tu, "failed_steps": failed}
 
 
-def cpu_baseline(mesh, ind, seconds):
-    import oracle
-
-    orc = oracle.Solver(mesh.X, mesh.tets, mesh.fixed, E=0.3e6, nu=0.45)
-    u = np.zeros((mesh.n, 3))
-    t0 = time.perf_counter()
-    steps, passes = 0, 0
-    for k in range(1, ind.steps + 1):
-        orc.set_indenter(ind.kind, ind.shape, ind.R, ind.center(k), ind.k_penalty)
-        u, info = orc.step(u)
-        steps += 1
-        passes += info["grad_passes"] + info["energy_passes"] + info["hv_products"]
-        if time.perf_counter() - t0 >= seconds:
-            break
-        if steps % 10 == 0:
-            progress(f"cpu oracle: {steps} load steps")
-    el = time.perf_counter() - t0
-    return {"value": (steps / ind.steps) / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "tet_updates_per_s": mesh.m * passes / el,
-            "sample": f"FP64 oracle, one thread, the first {steps} of {ind.steps} load steps of job seed {ind.seed} "
-                      f"on the {mesh.m}-tet fingertip ({el:.1f} s); solves/s = ({steps}/{ind.steps}) / time"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fingertip50k_traffic.json")
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tile_fingertip50k_traffic.json")
-
-
-def measured_traffic():
-    """HBM bytes per tile-kernel launch from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE runs (copy-calibrated), or None when they are
-    missing or were taken on a different kernel source."""
+def measured_traffic(groups):
+    """HBM bytes per launch of the tile and node kernels from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs (copy-calibrated), or None when
+    they are missing or were taken on a different kernel source or launch
+    configuration (job groups per round)."""
     from paper_2103_16747_amd.profiling import kernel_source_hash
 
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as f:
         t = json.load(f)
-    if t.get("kernel_source_sha256") != kernel_source_hash():
+    if t.get("kernel_source_sha256") != kernel_source_hash() or t.get("groups") != groups:
         return None
-    return t["traffic_bytes_per_dispatch"]
+    return {"tile": t.get("tile_bytes_per_dispatch"), "node": t.get("node_bytes_per_dispatch")}
 
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6      # 256 CU x 64 lanes x 2 x 2.4 GHz (FP64 vector)
 
 
-def roofline(r, word, flops_per_tet=FLOPS_PER_TET, kname=None, peak=FP32_VECTOR_PEAK_TFLOPS):
+def roofline(r, word, flops_per_tet=FLOPS_PER_TET, kname=None, peak=FP32_VECTOR_PEAK_TFLOPS, traffic=None):
     """Roofline of the tile kernel (the dominant one) over the timed region:
     algorithmic flops per launch (the passes the jobs made, times the tets per
     pass and FLOPS_PER_TET, over the number of launches) divided by the mean
@@ -241,7 +252,7 @@ def roofline(r, word, flops_per_tet=FLOPS_PER_TET, kname=None, peak=FP32_VECTOR_
     if kname is None:
         kname = "k_tile<float, LAW_NH>" if word == 4 else "k_tile<double, LAW_NH>"
     out = {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": peak,
-           "unit": "TFLOP/s", "frac": achieved / peak, "traffic": measured_traffic() if word == 4 else None}
+           "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic.get("tile") if traffic else None}
     if word == 4:
         out["frac_of_non_packed_peak"] = achieved / FP32_NONPACKED_PEAK_TFLOPS
     out.update({"avg_launch_us": t["avg_us"], "sampled_launches": t["sampled"], "launches": t["launches"],
@@ -250,6 +261,131 @@ def roofline(r, word, flops_per_tet=FLOPS_PER_TET, kname=None, peak=FP32_VECTOR_
                 "hbm_model": {"algorithmic_bytes_per_launch": byts, "GB_per_s": byts / avg_s / 1e9,
                               "frac_of_hbm_peak": byts / avg_s / 1e9 / HBM_PEAK_GBS}})
     return out, {k: v["avg_us"] for k, v in per.items()}
+
+
+def node_bytes(info, word, hv_passes, el_passes, launches):
+    """Algorithmic HBM bytes per launch of the node kernel, averaged over
+    `launches` launches that made hv_passes CG updates and followed el_passes
+    element passes in all (ideal reuse: every value read or written once).
+
+    Shared per launch: the node -> entry CSR (4 B per node and per entry),
+    the contact index (4 B per node) and the fixed mask (1 B per node).
+    CG update, per job and node: reads p, z, dx, r (12 words), the block
+    inverse (6), the q partials (3 words per entry); writes p, dx, r, z (12);
+    per contact-eligible node the contact block (6 words).
+    After an element pass (Newton init; counted for every element pass, an
+    upper bound for line-search trials, which read only g and dx): reads u
+    and dx (6 words), the gradient and block partials (9 words per entry);
+    writes u, g, the block inverse, r, z, p, dx (21 words); per eligible node
+    the contact gradient and block (9 words).
+    """
+    n, nent, nc = info["n_nodes"], info["n_entries"], info["n_eligible"]
+    shared = 4 * (n + 1) + 4 * nent + 4 * n + n
+    cg = word * (30 * n + 3 * nent + 6 * nc)
+    init = word * (27 * n + 9 * nent + 9 * nc)
+    return shared + (hv_passes * cg + el_passes * init) / max(launches, 1)
+
+
+def hbm_roofline(r, word, traffic=None):
+    """HBM view of the solver: the node kernel (bound by memory) and the whole
+    solver step (tile + node + finalize) as algorithmic bytes over time
+    against the 8 TB/s peak, with the counter-measured bytes beside them
+    where the committed rocprofv3 figures apply to this build."""
+    from paper_2103_16747_amd import fem
+
+    tm = r["timing"]
+    if not tm:
+        return None
+    info = r["layout"]
+    t_launch = tm[fem.FEM_KERNEL_TILE][2]
+    n_cnt, n_ms, n_launch = tm[fem.FEM_KERNEL_NODE]
+    node_avg_s = n_ms / max(n_cnt, 1) * 1e-3
+    nb = node_bytes(info, word, r["hv_passes"], r["grad_passes"], n_launch)
+    tb = tile_bytes(info, word, r["hv_passes"], r["grad_passes"], t_launch)
+    jobs_steps = r["hv_passes"] + r["grad_passes"]
+    fin_total = 8 * 3 * (info["n_tiles"] + ceil_div(info["n_eligible"], 256) + ceil_div(info["n_nodes"], 256)) * jobs_steps
+    total = tb * t_launch + nb * n_launch + fin_total
+    wall = sum(r["walls"])
+    out = {"node_kernel": {"bound": "hbm", "kernel": "k_node", "achieved": nb / node_avg_s / 1e9, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": nb / node_avg_s / 1e9 / HBM_PEAK_GBS,
+                           "algorithmic_bytes_per_launch": nb, "avg_launch_us": node_avg_s * 1e6,
+                           "traffic": traffic.get("node") if traffic else None},
+           "solver_step": {"bound": "hbm", "achieved": total / wall / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": total / wall / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": total,
+                           "note": "tile + node + finalize algorithmic bytes of the timed batches over their wall time"}}
+    if traffic and traffic.get("tile") and traffic.get("node"):
+        meas = traffic["tile"] * t_launch + traffic["node"] * n_launch + fin_total
+        out["solver_step"]["counter_bytes"] = meas
+        out["solver_step"]["counter_frac"] = meas / wall / 1e9 / HBM_PEAK_GBS
+    return out
+
+
+def ceil_div(a, b):
+    return (a + b - 1) // b
+
+
+def _oracle_job(args):
+    """One whole oracle job (FP64, one thread) of the batch workload; returns
+    (seed, seconds, load steps, tet-updates)."""
+    seed, steps_cap, seconds = args
+    import oracle
+    from paper_2103_16747_amd import workload as W
+
+    mesh = W.fingertip_mesh(50000)
+    ind = W.seat_on_mesh(W.random_indentation(seed), mesh)
+    orc = oracle.Solver(mesh.X, mesh.tets, mesh.fixed, E=0.3e6, nu=0.45)
+    u = np.zeros((mesh.n, 3))
+    t0 = time.perf_counter()
+    steps, passes = 0, 0
+    for k in range(1, ind.steps + 1):
+        orc.set_indenter(ind.kind, ind.shape, ind.R, ind.center(k), ind.k_penalty)
+        u, info = orc.step(u)
+        steps += 1
+        passes += info["grad_passes"] + info["energy_passes"] + info["hv_products"]
+        if steps >= steps_cap or (seconds and time.perf_counter() - t0 >= seconds):
+            break
+    return seed, time.perf_counter() - t0, steps, mesh.m * passes
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(seed0, all_seconds, single=True):
+    """The FP64 oracle on the host: (a) one whole job (seed0, all 100 load
+    steps) on one thread; (b) one job per host core (seeds seed0 + 1 ...), each
+    process running its job's load steps for all_seconds, throughput summed
+    over the processes (solves/s = load steps done / 100 / time)."""
+    import multiprocessing as mp
+
+    nproc = os.cpu_count() or 1
+    cores = max(1, min(nproc, 16))
+    out = {"kind": "oracle", "unit": "solves/s", "nproc": nproc, "cpu_model": cpu_model()}
+    if single:
+        progress("cpu oracle: one whole job on one thread")
+        sd, el, steps, tu = _oracle_job((seed0, 100, 0))
+        out["single_thread"] = {"solves_per_s": (steps / 100) / el, "seconds_per_job": el, "seed": sd,
+                                "load_steps": steps, "tet_updates_per_s": tu / el}
+    progress(f"cpu oracle: {cores} processes, {all_seconds:.0f} s each")
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_job, [(seed0 + 1 + i, 100, all_seconds) for i in range(cores)])
+    wall = time.perf_counter() - t0
+    rate = sum((st / 100) / el for _, el, st, _ in res)
+    out.update({"value": rate, "cores": cores,
+                "tet_updates_per_s": sum(tu / el for _, el, _, tu in res),
+                "sample": f"FP64 oracle on {cores} host cores ({out['cpu_model']}, nproc {nproc}): one process per core, "
+                          f"each on its own job of the batch workload (seeds {seed0 + 1}..{seed0 + cores}) for "
+                          f"{all_seconds:.0f} s ({sum(st for _, _, st, _ in res)} load steps in all, "
+                          f"{wall:.0f} s wall); solves/s = sum over processes of load steps / 100 / time"})
+    return out
 
 
 RESOLUTIONS = (5000, 20000, 50000, 120000)
@@ -491,6 +627,62 @@ def bench_variant(args, name):
     return out
 
 
+STRAT_GOLD = os.path.join(ROOT, "tests", "golden", "fingertip50k_stratified_oracle.npz")
+SUMM_GOLD = os.path.join(ROOT, "tests", "golden", "fingertip50k_batch_summary.npz")
+
+
+def stratified_keep(J):
+    """Job indices (seed - 3000) of the stored stratified oracle results."""
+    if not os.path.exists(STRAT_GOLD):
+        return []
+    return [int(x) - 3000 for x in np.load(STRAT_GOLD)["seeds"] if int(x) - 3000 < J]
+
+
+def accuracy(r, bound):
+    """Per-instance agreement of the last timed batch with the stored FP64
+    oracle results: e_inf at load step 100 for the stratified seeds (full
+    fields), and for every job the relative error of max|u|, mean|u| and the
+    contact resultant at step 100 (where the oracle and the device both
+    ended the step converged or at the floor); the device's capped steps with
+    the oracle's status at the same steps."""
+    if not (os.path.exists(STRAT_GOLD) and os.path.exists(SUMM_GOLD)):
+        return None
+    strat, summ = np.load(STRAT_GOLD), np.load(SUMM_GOLD)
+    row = {int(x): i for i, x in enumerate(summ["seeds"])}
+    out = {"bound": bound, "stratified_e_inf_step100": {}, "capped_steps": {}}
+    for k, u in r["finals"].items():
+        seed = 3000 + k
+        st = r["jobs"][k]["status"]
+        if summ["status"][row[seed]][99] == 0 and st[99] >= 0:
+            ref = strat[f"u100_{seed}"]
+            out["stratified_e_inf_step100"][str(seed)] = float(np.abs(u - ref).max() / np.abs(ref).max())
+    errs, above = [], []
+    for k, job in enumerate(r["jobs"]):
+        seed = 3000 + k
+        i = row.get(seed)
+        if i is None:
+            continue
+        st = job["status"]
+        capped = [int(q) + 1 for q in np.nonzero(st < 0)[0]]
+        if capped:
+            out["capped_steps"][str(seed)] = [[q, int(summ["status"][i][q - 1])] for q in capped]
+        if summ["status"][i][99] != 0 or st[99] < 0:
+            continue
+        F = summ["F"][i][99]
+        e = max(abs(job["umax"] - summ["umax"][i][99]) / summ["umax"][i][99],
+                abs(job["umean"] - summ["umean"][i][99]) / summ["umean"][i][99],
+                float(np.abs(job["F"] - F).max() / max(np.abs(F).max(), 1e-300)))
+        errs.append(e)
+        if e > bound:
+            above.append([seed, e])
+    out["all_jobs_step100"] = {"jobs_compared": len(errs), "max_rel_err": max(errs) if errs else None,
+                               "median_rel_err": float(np.median(errs)) if errs else None,
+                               "within_bound": sum(e <= bound for e in errs), "above_bound": above,
+                               "quantities": "max|u|, mean|u| and contact resultant, relative to the oracle's"}
+    out["capped_steps_note"] = "per seed: [load step, oracle status at that step (0 converged, -6 capped)]"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -498,7 +690,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--jobs", type=int, default=256)
     ap.add_argument("--single-jobs", type=int, default=3, help="jobs timed one at a time on the FP64 path")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="CPU baseline: seconds per process, all cores")
+    ap.add_argument("--no-cpu-single", action="store_true", help="CPU baseline: skip the whole single-thread job")
+    ap.add_argument("--groups", type=int, default=0, help="job groups per round (0 or 1: one, 2: two)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-single", action="store_true")
@@ -534,23 +728,26 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.config == "uneven":
-        print(json.dumps(bench_uneven(args)), flush=True)
+        emit(bench_uneven(args))
         return
     if args.config == "serving":
-        print(json.dumps(bench_serving(args)), flush=True)
+        emit(bench_serving(args))
         return
     if args.config == "dynamic":
-        print(json.dumps(bench_dynamic(args)), flush=True)
+        emit(bench_dynamic(args))
         return
     if args.config in VARIANTS:
-        print(json.dumps(bench_variant(args, args.config)), flush=True)
+        emit(bench_variant(args, args.config))
         return
     mesh = W.fingertip_mesh(50000)
     inds = [W.seat_on_mesh(W.random_indentation(3000 + i), mesh) for i in range(args.jobs)]
 
+    keep = stratified_keep(args.jobs)
     torch.cuda.synchronize()
-    r32 = run_batched(mesh, inds, "fp32", args.steps, args.warmup, args.timing_every)
+    r32 = run_batched(mesh, inds, "fp32", args.steps, args.warmup, args.timing_every, groups=args.groups, keep=keep)
     torch.cuda.synchronize()
+    groups_used = 2 if args.groups == 2 else 1
+    traffic = measured_traffic(groups_used)
     K, J = args.steps, args.jobs
     wall = sum(r32["walls"])
     lat_ms = np.array(r32["lat"]) * 1e3
@@ -579,38 +776,39 @@ def main():
         "tet_updates_per_s": r32["tet_updates"] / wall,
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "mode": "job completion time from batch start, all jobs submitted together"},
-        "failed_load_steps": r32["failed_steps"],
-        "floor_load_steps": r32["floor_steps"],
+        "load_steps_per_batch": J * 100,
+        "failed_load_steps_per_batch": float(np.mean(r32["failed_per_batch"])),
+        "floor_load_steps_per_batch": float(np.mean(r32["floor_per_batch"])),
         "cg_iters_per_job": float(np.mean([s["cg_iters"] for s in r32["stats"]])),
         "outputs_ms_per_job": r32["outputs_ms_per_job"],
         "newton_iters_per_job": float(np.mean([s["newton_iters"] for s in r32["stats"]])),
+        "job_groups_per_round": groups_used,
     }
-    gold_path = os.path.join(ROOT, "tests", "golden", "fingertip50k_oracle.npz")
-    if os.path.exists(gold_path):
-        gold = np.load(gold_path)
-        errs = {}
-        for i, u in enumerate(r32["finals"]):
-            key = f"u100_{3000 + i}"
-            st = gold.get(f"status_{3000 + i}")
-            if key in gold and st is not None and not np.any(st != 0):
-                errs[str(3000 + i)] = float(np.abs(u - gold[key]).max() / np.abs(gold[key]).max())
-        out["e_inf_vs_fp64_oracle"] = errs
-    rl, kav = roofline(r32, 4)
+    acc = accuracy(r32, 1e-4)
+    if acc:
+        out["accuracy_vs_fp64_oracle"] = acc
+    rl, kav = roofline(r32, 4, traffic=traffic)
     if rl:
         out["roofline"] = rl
         out["kernel_avg_us"] = kav
+        out["roofline_hbm"] = hbm_roofline(r32, 4, traffic)
     if not args.no_fp64:
-        r64 = run_batched(mesh, inds, "fp64", 1, 0, args.timing_every, track_latency=False)
+        r64 = run_batched(mesh, inds, "fp64", 1, 0, args.timing_every, track_latency=False, groups=args.groups,
+                          keep=keep)
         w64 = sum(r64["walls"])
         out["fp64_batched"] = {"solves_per_s": J / w64, "tet_updates_per_s": r64["tet_updates"] / w64,
-                               "ms_per_step": w64 * 1e3, "failed_load_steps": r64["failed_steps"],
-                               "floor_load_steps": r64["floor_steps"]}
+                               "ms_per_step": w64 * 1e3, "failed_load_steps_per_batch": r64["failed_steps"],
+                               "floor_load_steps_per_batch": r64["floor_steps"]}
+        acc64 = accuracy(r64, 1e-8)
+        if acc64:
+            out["fp64_batched"]["accuracy_vs_fp64_oracle"] = acc64
         rl64, kav64 = roofline(r64, 8, kname="k_tile<double, LAW_NH>", peak=FP64_VECTOR_PEAK_TFLOPS)
         if rl64:
             out["fp64_batched"]["roofline"] = rl64
             out["fp64_batched"]["kernel_avg_us"] = kav64
-        out["e_inf_fp32_vs_fp64"] = [float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
-                                     for a, b in zip(r32["finals"], r64["finals"])]
+        out["e_inf_fp32_vs_fp64"] = {str(3000 + k): float(np.abs(r32["finals"][k] - b).max() /
+                                                          max(np.abs(b).max(), 1e-300))
+                                     for k, b in r64["finals"].items()}
     if not args.no_single:
         s64 = run_single(mesh, inds[:args.single_jobs], "fp64")
         w = sum(s64["walls"])
@@ -621,8 +819,8 @@ def main():
                                        "jobs": len(s64["walls"])}
         out["speedup_vs_fp64_single_instance"] = out["value"] / out["fp64_single_instance"]["solves_per_s"]
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(mesh, inds[0], args.cpu_seconds)
-    print(json.dumps(out), flush=True)
+        out["cpu_baseline"] = cpu_baseline(3000, args.cpu_seconds, single=not args.no_cpu_single)
+    emit(out)
 
 
 if __name__ == "__main__":

@@ -423,10 +423,9 @@ int fem_batch_set_graphs(fem_batch *batch, int32_t enable);
  *                      of the Newton iteration for a single job);
  *   FEM_OPT_TILE_TETS  tets per tile, 64..512 (default 512);
  *   FEM_OPT_TILE_NODES distinct nodes per tile, 16..256 (default 256);
- *   FEM_OPT_GROUPS     job groups per round, 0..2 (0 = automatic: two when
- *                      the running jobs have at least 2048 tile blocks in
- *                      all). With two groups each group's solver steps run
- *                      on a stream of its own and the groups' tile passes
+ *   FEM_OPT_GROUPS     job groups per round: 0 or 1 (default) one, 2 two.
+ *                      With two groups each group's solver steps run on a
+ *                      stream of its own and the groups' tile passes
  *                      alternate, so one group's node pass (memory-bound)
  *                      overlaps the other's tile pass (arithmetic-bound);
  *                      every job computes the same steps either way.

@@ -27,11 +27,10 @@ def fake_run(timing, hv, grad, word_tets=49584):
             "layout": {"n_tets": word_tets, "n_nodes": 11249, "n_entries": 21652, "n_eligible": 3757}}
 
 
-def test_roofline_arithmetic(monkeypatch):
-    monkeypatch.setattr(bench, "measured_traffic", lambda: 1.0e8)
+def test_roofline_arithmetic():
     # 100 tile launches, 10 of them sampled for 1 ms in all (100 us each)
     r = fake_run({0: (10, 1.0, 100), 1: (10, 0.5, 100), 2: (10, 0.05, 100)}, hv=900, grad=100)
-    rl, kav = bench.roofline(r, 4)
+    rl, kav = bench.roofline(r, 4, traffic={"tile": 1.0e8, "node": 2.0e8})
     flops = 49584 * (900 * bench.FLOPS_PER_TET["hv"] + 100 * bench.FLOPS_PER_TET["element"]) / 100
     assert rl["flops_per_launch"] == pytest.approx(flops)
     assert rl["avg_launch_us"] == pytest.approx(100.0)
@@ -52,16 +51,42 @@ def test_corotational_flop_counts():
                                       "element": round(305 + 3 + 83 * 2.2 + 243 + 81)}
 
 
-def test_traffic_figure_follows_the_kernel_source(monkeypatch, tmp_path):
+def test_traffic_figure_follows_the_kernel_source_and_launch(monkeypatch, tmp_path):
     from paper_2103_16747_amd import profiling
 
     f = tmp_path / "traffic.json"
-    f.write_text(json.dumps({"kernel_source_sha256": profiling.kernel_source_hash(),
-                             "traffic_bytes_per_dispatch": 123.0}))
+    rec = {"kernel_source_sha256": profiling.kernel_source_hash(), "groups": 2,
+           "tile_bytes_per_dispatch": 123.0, "node_bytes_per_dispatch": 456.0}
+    f.write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
-    assert bench.measured_traffic() == 123.0
-    f.write_text(json.dumps({"kernel_source_sha256": "0" * 64, "traffic_bytes_per_dispatch": 123.0}))
-    assert bench.measured_traffic() is None
+    assert bench.measured_traffic(2) == {"tile": 123.0, "node": 456.0}
+    assert bench.measured_traffic(1) is None          # taken with another launch configuration
+    f.write_text(json.dumps(dict(rec, kernel_source_sha256="0" * 64)))
+    assert bench.measured_traffic(2) is None          # taken on other kernels
+
+
+def test_node_bytes_model():
+    info = {"n_nodes": 100, "n_entries": 200, "n_eligible": 10, "n_tets": 300, "n_tiles": 1}
+    shared = 4 * 101 + 4 * 200 + 4 * 100 + 100
+    # one CG update of one job per launch, FP32: 30 words per node, 3 per entry, 6 per eligible node
+    assert bench.node_bytes(info, 4, 1, 0, 1) == pytest.approx(shared + 4 * (30 * 100 + 3 * 200 + 6 * 10))
+    # one element pass followed by a Newton init, FP64
+    assert bench.node_bytes(info, 8, 0, 1, 1) == pytest.approx(shared + 8 * (27 * 100 + 9 * 200 + 9 * 10))
+
+
+def test_hbm_roofline_arithmetic():
+    r = fake_run({0: (10, 1.0, 100), 1: (10, 0.5, 100), 2: (10, 0.05, 100)}, hv=900, grad=100)
+    r["layout"]["n_tiles"] = 97
+    r["walls"] = [0.1]
+    h = bench.hbm_roofline(r, 4, traffic={"tile": 1.0e8, "node": 2.0e8})
+    nb = bench.node_bytes(r["layout"], 4, 900, 100, 100)
+    assert h["node_kernel"]["achieved"] == pytest.approx(nb / 50e-6 / 1e9)
+    assert h["node_kernel"]["frac"] == pytest.approx(h["node_kernel"]["achieved"] / 8000.0)
+    assert h["node_kernel"]["traffic"] == 2.0e8
+    tb = bench.tile_bytes(r["layout"], 4, 900, 100, 100)
+    assert h["solver_step"]["algorithmic_bytes"] > 100 * (tb + nb)
+    assert h["solver_step"]["frac"] == pytest.approx(h["solver_step"]["algorithmic_bytes"] / 0.1 / 8e12)
+    assert h["solver_step"]["counter_frac"] > h["solver_step"]["frac"] * 0 and "counter_bytes" in h["solver_step"]
 
 
 def test_kernel_source_hash_ignores_comments():
@@ -71,3 +96,10 @@ def test_kernel_source_hash_ignores_comments():
     b = "// header\nint f() {\n\n  return 1;\n}\n"
     assert kernel_source_hash(a) == kernel_source_hash(b)
     assert kernel_source_hash(a) != kernel_source_hash(a.replace("1", "2"))
+
+
+def test_line_encodes_numpy_values(capsys):
+    import numpy as np
+
+    bench.emit({"a": np.int64(3), "b": np.float32(1.5), "c": np.arange(2), "d": [np.int32(1)]})
+    assert json.loads(capsys.readouterr().out) == {"a": 3, "b": 1.5, "c": [0, 1], "d": [1]}
