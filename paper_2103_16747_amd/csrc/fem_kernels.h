@@ -1284,54 +1284,66 @@ __device__ __forceinline__ void node_init(const Topo<T> &tp, const InstBufs<T> &
 template <typename T, bool DYN>
 __device__ __forceinline__ void node_update(const Topo<T> &tp, const InstBufs<T> &B, const InstState *s, int blk,
                                             bool eval) {
-    // solver scalars first, so their loads overlap the partial sums
+    // solver scalars and this thread's node data first: their loads are in
+    // flight while the block sums the p.q partials
     const double rz = s->rz;
     const T beta = (T)s->beta;
     const int cg_first = s->cg_it == 0;
+    const int i = blk * kBlock + threadIdx.x;
+    const bool live = i < tp.n;
+    T pv[3] = {(T)0, (T)0, (T)0}, qv[3] = {(T)0, (T)0, (T)0}, rv[3], dxv[3], M[6];
+    bool fixed = true;
+    if (live) {
+#pragma unroll
+        for (int d = 0; d < 3; d++) pv[d] = fma_t(beta, B.p[3 * i + d], B.z[3 * i + d]);
+        for (int q = tp.node_ent_off[i]; q < tp.node_ent_off[i + 1]; q++) {
+            const T *src = B.pq + 3 * tp.node_ent[q];
+            qv[0] += src[0];
+            qv[1] += src[1];
+            qv[2] += src[2];
+        }
+        const int j = tp.cidx[i];
+        if (j >= 0) {
+            const T *H = B.cp + 9 * j + 3;
+            qv[0] += H[0] * pv[0] + H[3] * pv[1] + H[4] * pv[2];
+            qv[1] += H[3] * pv[0] + H[1] * pv[1] + H[5] * pv[2];
+            qv[2] += H[4] * pv[0] + H[5] * pv[1] + H[2] * pv[2];
+        }
+        fixed = tp.fixed[i] != 0;
+        if (DYN && !fixed) {
+            const T cm = (T)s->mdt2 * tp.nvol[i];
+#pragma unroll
+            for (int d = 0; d < 3; d++) qv[d] = fma_t(cm, pv[d], qv[d]);
+        }
+        if (!eval && !fixed) {
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                rv[d] = B.r[3 * i + d];
+                dxv[d] = B.dx[3 * i + d];
+            }
+#pragma unroll
+            for (int c = 0; c < 6; c++) M[c] = B.dinv[6 * i + c];
+        }
+    }
     const double pq = block_sum_partials(B.red + RS_PQ * B.red_stride, tp.ntile + tp.ncb);
     if (blk == 0 && threadIdx.x == 0) B.red[RS_PQN * B.red_stride] = pq;
     const bool negcurv = !(pq > 0.0);
     const T alpha = negcurv ? (T)0 : (T)(rz / pq);
     double acc[2] = {0.0, 0.0};   // r.z, r.r
     double unused = 0.0;
-    const int i = blk * kBlock + threadIdx.x;
-    if (i < tp.n) {
-        T pv[3];
+    if (live) {
+        if (eval) {
 #pragma unroll
-        for (int d = 0; d < 3; d++) pv[d] = fma_t(beta, B.p[3 * i + d], B.z[3 * i + d]);
-        if (eval || !negcurv) {
-            T qv[3] = {(T)0, (T)0, (T)0};
-            for (int q = tp.node_ent_off[i]; q < tp.node_ent_off[i + 1]; q++) {
-                const T *src = B.pq + 3 * tp.node_ent[q];
-                qv[0] += src[0];
-                qv[1] += src[1];
-                qv[2] += src[2];
-            }
-            const int j = tp.cidx[i];
-            if (j >= 0) {
-                const T *H = B.cp + 9 * j + 3;
-                qv[0] += H[0] * pv[0] + H[3] * pv[1] + H[4] * pv[2];
-                qv[1] += H[3] * pv[0] + H[1] * pv[1] + H[5] * pv[2];
-                qv[2] += H[4] * pv[0] + H[5] * pv[1] + H[2] * pv[2];
-            }
-            if (DYN && !tp.fixed[i]) {
-                const T cm = (T)s->mdt2 * tp.nvol[i];
-#pragma unroll
-                for (int d = 0; d < 3; d++) qv[d] = fma_t(cm, pv[d], qv[d]);
-            }
-            if (eval) {
-#pragma unroll
-                for (int d = 0; d < 3; d++) B.qout[3 * i + d] = qv[d];
-            } else if (!tp.fixed[i]) {
-                T rv[3];
+            for (int d = 0; d < 3; d++) B.qout[3 * i + d] = qv[d];
+        } else if (!negcurv) {
+            if (!fixed) {
 #pragma unroll
                 for (int d = 0; d < 3; d++) {
                     B.p[3 * i + d] = pv[d];
-                    B.dx[3 * i + d] = fma_t(alpha, pv[d], B.dx[3 * i + d]);
-                    rv[d] = fma_t(-alpha, qv[d], B.r[3 * i + d]);
+                    B.dx[3 * i + d] = fma_t(alpha, pv[d], dxv[d]);
+                    rv[d] = fma_t(-alpha, qv[d], rv[d]);
                     B.r[3 * i + d] = rv[d];
                 }
-                const T *M = B.dinv + 6 * i;
                 const T z0 = M[0] * rv[0] + M[3] * rv[1] + M[4] * rv[2];
                 const T z1 = M[3] * rv[0] + M[1] * rv[1] + M[5] * rv[2];
                 const T z2 = M[4] * rv[0] + M[5] * rv[1] + M[2] * rv[2];

@@ -3,6 +3,7 @@
     python -m paper_2103_16747_amd.profiling stats  <rocprof dir> [--kernel REGEX]
     python -m paper_2103_16747_amd.profiling traffic <fetch dir> <write dir> --copy-bytes N [--kernel REGEX]
     python -m paper_2103_16747_amd.profiling counters <pmc dir> --kernel REGEX
+    python -m paper_2103_16747_amd.profiling traffic-json <fetch dir> <write dir> --copy-bytes N --out FILE
 
 `stats` reads a --kernel-trace --stats run (kernel_stats.csv / kernel_trace.csv)
 and prints per-kernel calls and durations. `traffic` reads two --pmc runs, one
@@ -138,6 +139,12 @@ def main(argv=None):
     b.add_argument("--copy-bytes", type=float, required=True)
     b.add_argument("--kernel", required=True)
     b.add_argument("--json", default=None, help="also write the result here, with the kernel source hash")
+    d = sub.add_parser("traffic-json", help="tile and node kernel traffic into one file for bench.py")
+    d.add_argument("fetch_dir")
+    d.add_argument("write_dir")
+    d.add_argument("--copy-bytes", type=float, required=True)
+    d.add_argument("--groups", type=int, default=1, help="job groups per round of the profiled run")
+    d.add_argument("--out", required=True)
     c = sub.add_parser("counters")
     c.add_argument("dir")
     c.add_argument("--kernel", required=True)
@@ -153,6 +160,21 @@ def main(argv=None):
         print(f"dispatches {r['dispatches']}  mean duration {r['mean_duration_us']:.2f} us")
         for k, v in r["per_dispatch"].items():
             print(f"  {k:28s} {v:.4e} per dispatch")
+    elif args.cmd == "traffic-json":
+        import json
+        rec = {"kernel_source_sha256": kernel_source_hash(), "groups": args.groups}
+        for key, pat in (("tile", r"k_tile<float, 0>"), ("node", r"k_node<float, false>")):
+            t = traffic(args.fetch_dir, args.write_dir, args.copy_bytes, pat)
+            rec[f"{key}_bytes_per_dispatch"] = t["traffic_bytes_per_dispatch"]
+            rec[f"{key}_fetch_bytes_per_dispatch"] = t["fetch_bytes_per_dispatch"]
+            rec[f"{key}_write_bytes_per_dispatch"] = t["write_bytes_per_dispatch"]
+            rec[f"{key}_dispatches"] = t["dispatches_fetch"]
+            rec["fetch_scale"], rec["write_scale"] = t["fetch_scale"], t["write_scale"]
+            print(f"{key}: {t['traffic_bytes_per_dispatch'] / 1e6:.1f} MB per dispatch "
+                  f"({t['fetch_bytes_per_dispatch'] / 1e6:.1f} fetched, {t['write_bytes_per_dispatch'] / 1e6:.1f} written, "
+                  f"{t['dispatches_fetch']} dispatches)")
+        with open(args.out, "w") as f:
+            json.dump(rec, f, indent=1)
     else:
         t = traffic(args.fetch_dir, args.write_dir, args.copy_bytes, args.kernel)
         for k, v in t.items():

@@ -243,14 +243,19 @@ def test_friction_arguments_are_validated():
 def test_switching_law_and_friction_between_steps(oracle_lib, meshes, precision):
     """One single-mesh handle: a frictionless Neo-Hookean step, then the
     co-rotational law with friction for the next step (the kernels a round
-    launches follow the jobs' current settings)."""
+    launches follow the jobs' current settings). The first step presses the
+    flat punch 0.3 mm from rest in one go: its starting residual is the
+    penalty force of some 80 contact nodes, each 27 times stiffer than a
+    node's elastic stiffness, so the FP32 path's default relative test
+    (3e-6) bounds the displacement error only to about 1e-4 there (measured
+    0.9e-4 to 1.03e-4); the FP32 solve here runs to 1e-6."""
     say("case switch law and friction", precision)
     mesh = meshes["cube8"]
     c1, c2 = punch_path()[2], punch_path()[5]
     dev = fem.FemMesh(mesh.X, mesh.tets, mesh.fixed, precision=precision)
     dev.set_material(E0, NU0, 1100.0)
     place(dev, c1)
-    P = tight(dev, precision)
+    P = tight(dev, precision) if precision == "fp64" else dev.default_params(newton_rtol=1e-6)
     assert dev.step(P)["status"] >= 0
     u1 = dev.displacements()
     dev.set_model(fem.FEM_MODEL_COROTATIONAL)
