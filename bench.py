@@ -406,34 +406,56 @@ def uneven_jobs(count, seed0):
 
 
 def bench_uneven(args):
-    """64 jobs at mixed resolution in one batch, shapes from the autotuner,
-    against the same jobs solved one at a time (FP32 path both)."""
+    """64 jobs at mixed resolution in one batch, tile shapes tuned per mesh
+    and the round length for the mix by the autotuner, against the same 64
+    jobs solved one at a time through the single-mesh API (FP32 path both);
+    the tile kernel's roofline over the timed batch."""
     from paper_2103_16747_amd import autotune, fem
 
     meshes, jobs = uneven_jobs(64, 4000)
-    tuned = autotune.tune([meshes[r] for r in RESOLUTIONS], "fp32", log=progress)
-    progress(f"autotune: tile {tuned['tile_tets']} chunk {tuned['chunk']}")
+    mesh_list = [meshes[r] for r in RESOLUTIONS]
+    tuned = autotune.tune(mesh_list, "fp32", cache=args.autotune_cache, log=progress)
+    shape_of = dict(zip(RESOLUTIONS, tuned["shapes"]))
+    progress(f"autotune: shapes {shape_of}, round length {tuned['chunk']}")
     batch = fem.FemBatch(len(jobs), "fp32")
-    batch.set_option(fem.FEM_OPT_TILE_TETS, tuned["tile_tets"])
     batch.set_option(fem.FEM_OPT_ROUND_STEPS, tuned["chunk"])
-    mids = {r: batch.add_mesh(meshes[r].X, meshes[r].tets, meshes[r].fixed) for r in RESOLUTIONS}
+    mids = {}
+    for r in RESOLUTIONS:
+        autotune.apply_shape(batch, shape_of[r])
+        mids[r] = batch.add_mesh(meshes[r].X, meshes[r].tets, meshes[r].fixed)
+    layouts = {r: batch.mesh_info(mids[r]) for r in RESOLUTIONS}
     ids = [batch.add_job(mids[r], ind) for r, ind in jobs]
     batch.run()
     for j, (r, ind) in zip(ids, jobs):
         batch.restart_job(j, ind)
+    batch.set_kernel_timing(args.timing_every)
     t0 = time.perf_counter()
     batch.run()
     wall = time.perf_counter() - t0
     infos = [batch.job_info(j) for j in ids]
+    tm = {k: batch.kernel_timing(k) + (batch.kernel_launches(k),)
+          for k in (fem.FEM_KERNEL_TILE, fem.FEM_KERNEL_NODE, fem.FEM_KERNEL_FINALIZE)}
     batch.close()
     progress(f"uneven batch: {len(jobs)} jobs in {wall:.2f} s")
-    # unbatched reference: the first job of each resolution, one at a time
-    solo = {}
+    # the tile kernel's roofline: algorithmic flops of the passes the jobs made
+    cnt, ms, launches = tm[fem.FEM_KERNEL_TILE]
+    flops = sum(meshes[r].m * (i["hv_products"] * FLOPS_PER_TET["hv"] + i["grad_passes"] * FLOPS_PER_TET["element"])
+                for (r, _), i in zip(jobs, infos))
+    avg_s = ms / max(cnt, 1) * 1e-3
+    achieved = flops / max(launches, 1) / avg_s / 1e12 if cnt else None
+    rl = {"bound": "alu", "kernel": "k_tile<float, LAW_NH>", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+          "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS if achieved else None, "traffic": None,
+          "frac_of_non_packed_peak": achieved / FP32_NONPACKED_PEAK_TFLOPS if achieved else None,
+          "avg_launch_us": avg_s * 1e6, "sampled_launches": cnt, "launches": launches}
+    # every job one at a time through the single-mesh API (one fem_step per load step)
+    solo_walls, solo_tu = [], 0
     for r in RESOLUTIONS:
-        ind = next(ind for rr, ind in jobs if rr == r)
-        single = run_single(meshes[r], [ind], "fp32")
-        solo[r] = single["walls"][0]
-    per_job_solo = sum(solo[r] for r, _ in jobs)
+        mine = [ind for rr, ind in jobs if rr == r]
+        if mine:
+            single = run_single(meshes[r], mine, "fp32")
+            solo_walls += single["walls"]
+            solo_tu += single["tet_updates"]
+    solo = sum(solo_walls)
     tu = sum(i["tet_updates"] for i in infos)
     return {"metric": METRIC, "value": len(jobs) / wall, "unit": "solves/s", "n_gpus": 1, "steps": 1,
             "warmup": 1, "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -441,47 +463,62 @@ def bench_uneven(args):
             "config": {"workload": "uneven batch: 64 synthetic-fingertip jobs at 5k/20k/50k/120k tets (uniform mix), "
                                    "seeded indenters, 100 load steps each",
                        "mix": {str(r): sum(1 for rr, _ in jobs if rr == r) for r in RESOLUTIONS},
-                       "autotuned": {"tile_tets": tuned["tile_tets"], "chunk": tuned["chunk"]}},
+                       "autotuned": {"tile_shape_per_mesh": {str(r): shape_of[r] for r in RESOLUTIONS},
+                                     "round_steps": tuned["chunk"]},
+                       "layouts": {str(r): layouts[r] for r in RESOLUTIONS}},
             "tet_updates_per_s": tu / wall, "failed_load_steps": sum(i["steps_failed"] for i in infos),
-            "unbatched_estimate": {"solves_per_s": len(jobs) / per_job_solo,
-                                   "per_resolution_s": {str(r): solo[r] for r in RESOLUTIONS},
-                                   "note": "one job per resolution timed alone; the batch's jobs summed at those times"},
-            "speedup_vs_unbatched": per_job_solo / wall,
-            "autotune_table": tuned["table"]}
+            "floor_load_steps": sum(i["steps_floor"] for i in infos),
+            "roofline": rl,
+            "unbatched": {"solves_per_s": len(jobs) / solo, "tet_updates_per_s": solo_tu / solo, "wall_s": solo,
+                          "jobs": len(solo_walls),
+                          "note": "all 64 jobs one at a time through the single-mesh API, FP32 path"},
+            "speedup_vs_unbatched": solo / wall,
+            "autotune": {"per_mesh": tuned["per_mesh"], "round_length_table": tuned["table"]}}
 
 
 def bench_serving(args):
     """Poisson streams of mixed-resolution jobs through the serving loop
-    (admission by HBM footprint, continuous batching); p50/p99 latency and
-    solves/s per arrival rate, against one-at-a-time FP64 solves."""
+    (admission by HBM footprint, continuous batching): per arrival rate,
+    args.warmup_requests requests warm the server up and the next
+    args.requests are measured (p50/p99 latency from arrival to the result
+    on the host, solves/s); against the one-at-a-time FP64 path timed on a
+    sample of the same jobs."""
     from paper_2103_16747_amd import fem, workload as W
     from paper_2103_16747_amd.serve import IndentationServer, Request, latency_summary
 
-    meshes, jobs = uneven_jobs(args.requests, 5000)
+    warm = args.warmup_requests
+    meshes, jobs = uneven_jobs(warm + args.requests, 5000)
     keyed = {str(r): meshes[r] for r in RESOLUTIONS}
     out = {"metric": METRIC, "unit": "ms", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
-           "dtype": "f32", "config": {"workload": f"serving: Poisson arrivals of {args.requests} mixed-resolution "
-                                                  "fingertip jobs per rate, 100 load steps each",
+           "dtype": "f32", "config": {"workload": f"serving: Poisson arrivals of {warm} warm-up and {args.requests} "
+                                                  "measured mixed-resolution fingertip jobs (5k-120k tets) per rate, "
+                                                  "100 load steps each",
                                       "hbm_budget_GiB": 64}, "rates": {}}
     for rate in [float(x) for x in args.rates.split(",")]:
         arrivals = W.poisson_arrivals(int(rate * 1000), rate, len(jobs))
         reqs = [Request(i, float(t), str(r), ind) for i, (t, (r, ind)) in enumerate(zip(arrivals, jobs))]
         batch = fem.FemBatch(len(jobs), "fp32")
         srv = IndentationServer(batch, keyed, hbm_budget=64 << 30, max_jobs=len(jobs), rounds_per_poll=2)
-        res = srv.serve(reqs, timeout=600)
-        summ = latency_summary(res)
+        res = srv.serve(reqs, timeout=1500, progress=progress)
+        summ = latency_summary(res, skip=warm)
         summ["peak_running"] = srv.stats.peak_running
+        summ["warmup_requests"] = warm
         out["rates"][str(rate)] = summ
         batch.close()
         progress(f"serving rate {rate}: p50 {summ['p50_ms']:.0f} ms p99 {summ['p99_ms']:.0f} ms "
                  f"{summ['solves_per_s']:.1f} solves/s")
-    # one-at-a-time FP64 reference on the first job of each resolution
+    # one-at-a-time FP64 reference on a sample of the measured jobs, per resolution
     ref = {}
     for r in RESOLUTIONS:
-        ind = next(ind for rr, ind in jobs if rr == r)
-        ref[str(r)] = run_single(meshes[r], [ind], "fp64")["walls"][0]
-    mean_one = sum(ref[str(r)] for r, _ in jobs) / len(jobs)
-    out["fp64_one_at_a_time"] = {"solves_per_s": 1.0 / mean_one, "per_resolution_s": ref}
+        sample = [ind for rr, ind in jobs[warm:] if rr == r][:args.fp64_sample]
+        if sample:
+            w = run_single(meshes[r], sample, "fp64")["walls"]
+            ref[str(r)] = sum(w) / len(w)
+    measured = [r for r, _ in jobs[warm:]]
+    mean_one = sum(ref[str(r)] for r in measured) / len(measured)
+    out["fp64_one_at_a_time"] = {"solves_per_s": 1.0 / mean_one, "mean_s_per_job": ref,
+                                 "note": f"the first {args.fp64_sample} measured jobs of each resolution one at a time "
+                                         "(single-mesh API, FP64), weighted by the stream's resolution mix"}
     last = out["rates"][max(out["rates"], key=float)]
     out["value"] = last["p99_ms"]
     return out
@@ -693,6 +730,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="CPU baseline: seconds per process, all cores")
     ap.add_argument("--no-cpu-single", action="store_true", help="CPU baseline: skip the whole single-thread job")
     ap.add_argument("--groups", type=int, default=0, help="job groups per round (0 or 1: one, 2: two)")
+    ap.add_argument("--autotune-cache", default=None, help="uneven: JSON cache of the autotuner's results")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-single", action="store_true")
@@ -705,8 +743,10 @@ def main():
                          "the batched workload as implicit time steps of 1e-4 s; corotational: the batched workload under the "
                          "co-rotational law; friction: with Coulomb friction 0.783; simulator: co-rotational, "
                          "friction and implicit steps together")
-    ap.add_argument("--rates", default="10,50,200,500", help="serving: arrival rates (req/s)")
-    ap.add_argument("--requests", type=int, default=160, help="serving: requests per rate")
+    ap.add_argument("--rates", default="10,20,50,100,200,500", help="serving: arrival rates (req/s)")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: measured requests per rate")
+    ap.add_argument("--warmup-requests", type=int, default=200, help="serving: warm-up requests per rate")
+    ap.add_argument("--fp64-sample", type=int, default=8, help="serving: FP64 one-at-a-time jobs per resolution")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="before the solves, one device copy of this many MiB (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()

@@ -165,15 +165,21 @@ class IndentationServer:
             self.idle[req.mesh].append(slot)
 
     # -- main loop -------------------------------------------------------------
-    def serve(self, requests, timeout: float | None = None):
-        """Serves `requests` (sorted by arrival) until all are done."""
+    def serve(self, requests, timeout: float | None = None, progress=None, progress_every: float = 30.0):
+        """Serves `requests` (sorted by arrival) until all are done; with
+        `progress`, calls it with a status line every progress_every seconds."""
         self.queue.extend(sorted(requests, key=lambda r: r.arrival))
         total = len(self.queue)
         self.t0 = self.clock()
+        next_report = progress_every
         while len(self.results) < total:
             now = self.clock() - self.t0
             if timeout is not None and now > timeout:
                 raise TimeoutError(f"{len(self.results)} of {total} requests done after {now:.1f} s")
+            if progress and now >= next_report:
+                progress(f"serving: {len(self.results)} of {total} done at {now:.0f} s, {len(self.running)} running, "
+                         f"{len(self.queue)} queued")
+                next_report += progress_every
             self._admit(now)
             if not self.running:
                 if self.queue:
@@ -187,8 +193,12 @@ class IndentationServer:
         return sorted(self.results, key=lambda r: r.rid)
 
 
-def latency_summary(results) -> dict:
-    results = [r for r in results if r.status != REJECTED_FOOTPRINT]
+def latency_summary(results, skip: int = 0) -> dict:
+    """p50/p99/mean/max latency and solves/s of the served requests with rid
+    >= skip (the first `skip` requests warm the server up): solves/s counts
+    those requests over the span from the first one's arrival to the last
+    completion."""
+    results = [r for r in results if r.status != REJECTED_FOOTPRINT and r.rid >= skip]
     lat = np.array([r.latency for r in results]) * 1e3
     span = max(r.done for r in results) - min(r.arrival for r in results)
     return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),

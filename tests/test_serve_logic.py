@@ -113,3 +113,14 @@ def test_request_that_never_fits_is_rejected():
     assert srv.stats.rejected == 2 and srv.stats.admitted == 1
     assert not any(e[0] == "add" and eng.slots.get(e[1], [None])[0] == 0 for e in eng.events)
     assert latency_summary(res)["completed"] == 1
+
+
+def test_latency_summary_skips_warmup_requests():
+    from paper_2103_16747_amd.serve import Result, latency_summary
+
+    res = [Result(i, "m", float(i), float(i), float(i) + (10.0 if i < 2 else 1.0), 0, 1, 0, 0, 0) for i in range(6)]
+    all_ = latency_summary(res)
+    meas = latency_summary(res, skip=2)
+    assert all_["completed"] == 6 and meas["completed"] == 4
+    assert meas["max_ms"] == 1000.0 and all_["max_ms"] == 10000.0
+    assert meas["solves_per_s"] == 4 / (6.0 - 2.0)
