@@ -423,6 +423,15 @@ int fem_batch_set_graphs(fem_batch *batch, int32_t enable);
  *                      of the Newton iteration for a single job);
  *   FEM_OPT_TILE_TETS  tets per tile, 64..512 (default 512);
  *   FEM_OPT_TILE_NODES distinct nodes per tile, 16..256 (default 256);
+ *   FEM_OPT_DETERMINISTIC 0 (default) or 1: the tile passes sum element
+ *                      contributions into the tile partials in a fixed
+ *                      order (each chunk of tets stores its contributions,
+ *                      then every tile entry adds its incident ones in
+ *                      ascending tet order) instead of with LDS atomics, so
+ *                      a job's result is bitwise independent of the other
+ *                      jobs in the batch and of the launch configuration;
+ *                      slower, a cross-check of the default mode, whose
+ *                      atomic sums depend on the order of wavefronts;
  *   FEM_OPT_GROUPS     job groups per round: 0 or 1 (default) one, 2 two.
  *                      With two groups each group's solver steps run on a
  *                      stream of its own and the groups' tile passes
@@ -434,6 +443,7 @@ int fem_batch_set_graphs(fem_batch *batch, int32_t enable);
 #define FEM_OPT_TILE_TETS 1
 #define FEM_OPT_TILE_NODES 2
 #define FEM_OPT_GROUPS 3
+#define FEM_OPT_DETERMINISTIC 4
 int fem_batch_set_option(fem_batch *batch, int32_t option, int32_t value);
 
 /* Device bytes one job on mesh mesh_id allocates (for admission by HBM

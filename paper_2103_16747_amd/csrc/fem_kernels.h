@@ -38,6 +38,7 @@ constexpr int kBlock = 256;       // 4 wavefronts of 64
 constexpr int kWaves = kBlock / 64;
 constexpr int kTileTets = 512;    // tets per tile (2 per thread)
 constexpr int kTileNodes = 256;   // distinct nodes per tile (8-bit local ids)
+constexpr int kDetElemChunk = 128; // deterministic element pass: tets per chunk of contributions
 constexpr int kHistSteps = 1024;  // load steps whose status a job records
 
 enum Phase : int {
@@ -128,6 +129,8 @@ struct Topo {
     const TetRec<T> *rec;               // m, tile order
     const int *node_ent_off;            // n + 1
     const int *node_ent;                // nent
+    const int *inc_off;                 // nent + 1: each tile entry's incident (tet, slot) pairs
+    const uint16_t *inc;                // 4 m: (local tet << 2 | slot), ascending tet per entry
     const uint8_t *fixed;               // n
     const int *cnodes;                  // nc
     const int *cidx;                    // n: contact slot or -1
@@ -797,11 +800,15 @@ __device__ __forceinline__ void store_partials(double *red, int stride, const in
 // LDS of a tile block, shared by the two tile paths (doubles): the element
 // path keeps 9 FP64 accumulators and one staged vector per entry, the
 // Hessian path 3 accumulators and two staged vectors.
-template <typename T>
+// In the deterministic mode (DET) the accumulators are replaced by a buffer of
+// one chunk of tets' contributions in the path precision: 9 values per node
+// and tet (element path, chunks of kDetElemChunk tets) or 3 (Hessian path,
+// chunks of kBlock tets).
+template <typename T, bool DET = false>
 struct TileLds {
     static constexpr int kVec = kSw * kTileNodes * (int)sizeof(T) / 8;
-    static constexpr int kElem = 9 * kTileNodes + kVec;
-    static constexpr int kHv = 3 * kTileNodes + 2 * kVec;
+    static constexpr int kElem = DET ? kVec + kDetElemChunk * 36 * (int)sizeof(T) / 8 : 9 * kTileNodes + kVec;
+    static constexpr int kHv = DET ? 2 * kVec + kBlock * 12 * (int)sizeof(T) / 8 : 3 * kTileNodes + 2 * kVec;
     static constexpr int kDoubles = kElem > kHv ? kElem : kHv;
 };
 
@@ -887,14 +894,15 @@ __device__ inline void friction_rel(const double fr[8], const double inc[3], dou
 // penalty energy, gradient k phi n and block k n n^T (+ k phi Hess(phi) with
 // the exact contact Hessian) per eligible node.
 // ---------------------------------------------------------------------------
-template <typename T, int LAW>
+template <typename T, int LAW, bool DET>
 __device__ __forceinline__ void tile_element(const Topo<T> &tp, const InstBufs<T> &B, const InstState *s, int blk,
                                              T alpha, int contact_full, double *pool) {
     const T mu = (T)s->mu, lam = (T)s->lam;
     double acc[3] = {0.0, 0.0, INFINITY};   // energy, magnitude, min J
     if (blk < tp.ntile) {
-        double *sa = pool;                          // 9 per entry, FP64 in both precisions
-        T *su = (T *)(pool + 9 * kTileNodes);       // kSw per entry
+        double *sa = pool;                                    // 9 per entry, FP64 in both precisions
+        T *su = (T *)(pool + (DET ? 0 : 9 * kTileNodes));     // kSw per entry
+        T *cf = su + kSw * kTileNodes;                        // DET: 36 per tet of a chunk
         const int t = blk;
         const int e0 = tp.tile_ent[t], ne = tp.tile_ent[t + 1] - e0;
         const int k0 = tp.tile_tet[t], nk = tp.tile_tet[t + 1] - k0;
@@ -911,11 +919,14 @@ __device__ __forceinline__ void tile_element(const Topo<T> &tp, const InstBufs<T
                 su[kSw * l + d] = uu;
             }
             su[kSw * l + 3] = (T)0;
+            if (!DET)
 #pragma unroll
-            for (int c = 0; c < 9; c++) sa[9 * l + c] = 0.0;
+                for (int c = 0; c < 9; c++) sa[9 * l + c] = 0.0;
         }
         __syncthreads();
-        for (int k = threadIdx.x; k < nk; k += kBlock) {
+        // One tet: its energy into acc, and per node a the gradient (c = 0..2)
+        // and diagonal block (c = 3..8) contributions to put(l, a, c, value).
+        auto tet = [&](int k, auto &&put) {
             int l[4];
             if (k != (int)threadIdx.x) fetch_tet(tp, k0 + k, tw);
             const ElemGeo<T> geo = unpack_tet(tw, l);
@@ -928,7 +939,7 @@ __device__ __forceinline__ void tile_element(const Topo<T> &tp, const InstBufs<T
             acc[2] = fmin(acc[2], (double)J);
             if (!(J > (T)0)) {
                 acc[0] = INFINITY;
-                continue;
+                return;
             }
             T psi, mag, Pk[9], FiT[9], kI, kc;   // FiT: the block's c = Mb b
             Law<T, LAW>::element(G, Jm1, J, mu, lam, psi, mag, Pk, FiT, kI, kc);
@@ -938,10 +949,9 @@ __device__ __forceinline__ void tile_element(const Topo<T> &tp, const InstBufs<T
             element_nodal(Pk, geo.Bm, geo.V, f);
 #pragma unroll
             for (int a = 0; a < 4; a++) {
-                double *dst = sa + 9 * l[a];
-                atomicAdd(dst + 0, (double)f[a][0]);
-                atomicAdd(dst + 1, (double)f[a][1]);
-                atomicAdd(dst + 2, (double)f[a][2]);
+                put(l, a, 0, f[a][0]);
+                put(l, a, 1, f[a][1]);
+                put(l, a, 2, f[a][2]);
                 T bb[3];
                 if (a == 0) {
                     bb[0] = -(geo.Bm[0] + geo.Bm[3] + geo.Bm[6]);
@@ -957,16 +967,48 @@ __device__ __forceinline__ void tile_element(const Topo<T> &tp, const InstBufs<T
                 const T cz = FiT[6] * bb[0] + FiT[7] * bb[1] + FiT[8] * bb[2];
                 const T sI = geo.V * kI * (bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2]);
                 const T Vk = geo.V * kc;
-                atomicAdd(dst + 3, (double)(sI + Vk * cx * cx));
-                atomicAdd(dst + 4, (double)(sI + Vk * cy * cy));
-                atomicAdd(dst + 5, (double)(sI + Vk * cz * cz));
-                atomicAdd(dst + 6, (double)(Vk * cx * cy));
-                atomicAdd(dst + 7, (double)(Vk * cx * cz));
-                atomicAdd(dst + 8, (double)(Vk * cy * cz));
+                put(l, a, 3, sI + Vk * cx * cx);
+                put(l, a, 4, sI + Vk * cy * cy);
+                put(l, a, 5, sI + Vk * cz * cz);
+                put(l, a, 6, Vk * cx * cy);
+                put(l, a, 7, Vk * cx * cz);
+                put(l, a, 8, Vk * cy * cz);
             }
+        };
+        if constexpr (!DET) {
+            for (int k = threadIdx.x; k < nk; k += kBlock)
+                tet(k, [&](const int *l, int a, int c, T v) { atomicAdd(sa + 9 * l[a] + c, (double)v); });
+            __syncthreads();
+            for (int i = threadIdx.x; i < 9 * ne; i += kBlock) B.pg[9 * e0 + i] = (T)sa[i];
+        } else {
+            // Deterministic: a chunk of tets stores its contributions, then
+            // each entry sums its incident ones in ascending tet order.
+            double ga[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            const bool mine = (int)threadIdx.x < ne;
+            int ip = mine ? tp.inc_off[e0 + threadIdx.x] : 0;
+            const int ie = mine ? tp.inc_off[e0 + threadIdx.x + 1] : 0;
+            for (int c0 = 0; c0 < nk; c0 += kDetElemChunk) {
+                const int k = c0 + (int)threadIdx.x;
+                if ((int)threadIdx.x < kDetElemChunk && k < nk) {
+                    T *dst = cf + 36 * threadIdx.x;
+#pragma unroll
+                    for (int q = 0; q < 36; q++) dst[q] = (T)0;
+                    tet(k, [&](const int *, int a, int c, T v) { dst[9 * a + c] = v; });
+                }
+                __syncthreads();
+                for (; ip < ie; ip++) {
+                    const int code = tp.inc[ip];
+                    if ((code >> 2) >= c0 + kDetElemChunk) break;
+                    const T *src = cf + 36 * ((code >> 2) - c0) + 9 * (code & 3);
+#pragma unroll
+                    for (int c = 0; c < 9; c++) ga[c] += (double)src[c];
+                }
+                __syncthreads();
+            }
+            if (mine)
+#pragma unroll
+                for (int c = 0; c < 9; c++) B.pg[9 * (e0 + threadIdx.x) + c] = (T)ga[c];
         }
-        __syncthreads();
-        for (int i = threadIdx.x; i < 9 * ne; i += kBlock) B.pg[9 * e0 + i] = (T)sa[i];
     } else {
         const int j = (blk - tp.ntile) * kBlock + threadIdx.x;
         if (j < tp.nc) {
@@ -1033,7 +1075,7 @@ __device__ __forceinline__ void tile_element(const Topo<T> &tp, const InstBufs<T
 // p.q is accumulated element by element (and over contact blocks), so alpha
 // is known to the node pass without a pass over q.
 // ---------------------------------------------------------------------------
-template <typename T, int LAW>
+template <typename T, int LAW, bool DET>
 __device__ __forceinline__ void tile_hessvec(const Topo<T> &tp, const InstBufs<T> &B, const InstState *s, int blk,
                                              double *pool) {
     const T beta = (T)s->beta;
@@ -1041,9 +1083,10 @@ __device__ __forceinline__ void tile_hessvec(const Topo<T> &tp, const InstBufs<T
     double acc[1] = {0.0};
     double unused = 0.0;
     if (blk < tp.ntile) {
-        double *sa = pool;                          // 3 per entry, FP64 in both precisions
-        T *su = (T *)(pool + 3 * kTileNodes);       // kSw per entry
-        T *sp = su + kSw * kTileNodes;              // kSw per entry
+        double *sa = pool;                                    // 3 per entry, FP64 in both precisions
+        T *su = (T *)(pool + (DET ? 0 : 3 * kTileNodes));     // kSw per entry
+        T *sp = su + kSw * kTileNodes;                        // kSw per entry
+        T *cf = sp + kSw * kTileNodes;                        // DET: 12 per tet of a chunk
         const int t = blk;
         const int e0 = tp.tile_ent[t], ne = tp.tile_ent[t + 1] - e0;
         const int k0 = tp.tile_tet[t], nk = tp.tile_tet[t + 1] - k0;
@@ -1063,7 +1106,7 @@ __device__ __forceinline__ void tile_hessvec(const Topo<T> &tp, const InstBufs<T
                 su[kSw * l + d] = B.u[3 * gid + d];
                 pv[d] = fma_t(beta, B.p[3 * gid + d], B.z[3 * gid + d]);
                 sp[kSw * l + d] = pv[d];
-                sa[3 * l + d] = 0.0;
+                if (!DET) sa[3 * l + d] = 0.0;
             }
             su[kSw * l + 3] = (T)0;
             sp[kSw * l + 3] = (T)0;
@@ -1072,7 +1115,8 @@ __device__ __forceinline__ void tile_hessvec(const Topo<T> &tp, const InstBufs<T
                       ((double)pv[0] * (double)pv[0] + (double)pv[1] * (double)pv[1] + (double)pv[2] * (double)pv[2]);
         }
         __syncthreads();
-        for (int k = threadIdx.x; k < nk; k += kBlock) {
+        // One tet: its p.q into pq and its nodal vectors to put(l, a, d, value).
+        auto tet = [&](int k, auto &&put) {
             int l[4];
             if (k != (int)threadIdx.x) fetch_tet(tp, k0 + k, tw);
             const ElemGeo<T> geo = unpack_tet(tw, l);
@@ -1083,7 +1127,7 @@ __device__ __forceinline__ void tile_hessvec(const Topo<T> &tp, const InstBufs<T
             edge_gradient(wu, geo.Bm, G);
             const T Jm1 = det_minus_one(G);
             const T J = (T)1 + Jm1;
-            if (!(J > (T)0)) continue;
+            if (!(J > (T)0)) return;
             T dG[9];
             edge_gradient(wp, geo.Bm, dG);
             T dP[9];
@@ -1093,17 +1137,50 @@ __device__ __forceinline__ void tile_hessvec(const Topo<T> &tp, const InstBufs<T
             T e_pq = (T)0;
 #pragma unroll
             for (int a = 0; a < 4; a++) {
-                double *dst = sa + 3 * l[a];
-                atomicAdd(dst + 0, (double)f[a][0]);
-                atomicAdd(dst + 1, (double)f[a][1]);
-                atomicAdd(dst + 2, (double)f[a][2]);
+                put(l, a, 0, f[a][0]);
+                put(l, a, 1, f[a][1]);
+                put(l, a, 2, f[a][2]);
                 e_pq += wp[a][0] * f[a][0] + wp[a][1] * f[a][1] + wp[a][2] * f[a][2];
             }
             pq += (double)e_pq;
+        };
+        if constexpr (!DET) {
+            for (int k = threadIdx.x; k < nk; k += kBlock)
+                tet(k, [&](const int *l, int a, int d, T v) { atomicAdd(sa + 3 * l[a] + d, (double)v); });
+            acc[0] = pq;
+            __syncthreads();
+            for (int i = threadIdx.x; i < 3 * ne; i += kBlock) B.pq[3 * e0 + i] = (T)sa[i];
+        } else {
+            // Deterministic: each chunk of kBlock tets stores its nodal
+            // vectors, then each entry sums its incident ones in ascending
+            // tet order.
+            double qa[3] = {0.0, 0.0, 0.0};
+            const bool mine = (int)threadIdx.x < ne;
+            int ip = mine ? tp.inc_off[e0 + threadIdx.x] : 0;
+            const int ie = mine ? tp.inc_off[e0 + threadIdx.x + 1] : 0;
+            for (int c0 = 0; c0 < nk; c0 += kBlock) {
+                const int k = c0 + (int)threadIdx.x;
+                if (k < nk) {
+                    T *dst = cf + 12 * threadIdx.x;
+#pragma unroll
+                    for (int q = 0; q < 12; q++) dst[q] = (T)0;
+                    tet(k, [&](const int *, int a, int d, T v) { dst[3 * a + d] = v; });
+                }
+                __syncthreads();
+                for (; ip < ie; ip++) {
+                    const int code = tp.inc[ip];
+                    if ((code >> 2) >= c0 + kBlock) break;
+                    const T *src = cf + 12 * ((code >> 2) - c0) + 3 * (code & 3);
+#pragma unroll
+                    for (int d = 0; d < 3; d++) qa[d] += (double)src[d];
+                }
+                __syncthreads();
+            }
+            acc[0] = pq;
+            if (mine)
+#pragma unroll
+                for (int d = 0; d < 3; d++) B.pq[3 * (e0 + threadIdx.x) + d] = (T)qa[d];
         }
-        acc[0] = pq;
-        __syncthreads();
-        for (int i = threadIdx.x; i < 3 * ne; i += kBlock) B.pq[3 * e0 + i] = (T)sa[i];
     } else {
         const int j = (blk - tp.ntile) * kBlock + threadIdx.x;
         if (j < tp.nc) {
@@ -1132,10 +1209,10 @@ __device__ __forceinline__ void tile_hessvec(const Topo<T> &tp, const InstBufs<T
 // paths share one LDS pool (their register needs are alike, so the union
 // does not lower occupancy).
 // ---------------------------------------------------------------------------
-template <typename T, int LAW>
+template <typename T, int LAW, bool DET>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 1 : 3))) void k_tile(const Topo<T> *topos, const InstBufs<T> *bufs, const int2 *work,
                                                  int nwork, const SolveParams *P) {
-    __shared__ __attribute__((aligned(32))) double pool[TileLds<T>::kDoubles];
+    __shared__ __attribute__((aligned(32))) double pool[TileLds<T, DET>::kDoubles];
     const int L = logical_block();
     if (L >= nwork) return;
     const int2 w = work[L];
@@ -1148,10 +1225,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T
     const int phase = s->phase;
     if (s->model != LAW) return;   // served by the other law's launch
     if (phase == PH_CG || phase == PH_EVAL_HV) {
-        tile_hessvec<T, LAW>(tp, B, s, w.y, pool);
+        tile_hessvec<T, LAW, DET>(tp, B, s, w.y, pool);
     } else if (phase == PH_GRAD || phase == PH_EVAL_GRAD || phase == PH_TRIAL) {
         const T alpha = phase == PH_TRIAL ? (T)s->alpha_ls : (T)0;
-        tile_element<T, LAW>(tp, B, s, w.y, alpha, contact_full, pool);
+        tile_element<T, LAW, DET>(tp, B, s, w.y, alpha, contact_full, pool);
     }
 }
 

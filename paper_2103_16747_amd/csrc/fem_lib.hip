@@ -151,6 +151,7 @@ struct fem_batch {
     JobGroup grp[2];
     int ngroups = 1;
     int groups_opt = 0;                     // 2: two job groups per round; 0 or 1: one
+    bool deterministic = false;             // tile partials summed in a fixed order
     int capacity = 0;
     std::vector<TopoRec> topos;
     std::vector<InstRec> insts;     // size capacity
@@ -316,6 +317,10 @@ int add_topology(fem_batch *B, const double *X_in, int n, const int32_t *tets_in
     const size_t o_fixed = A.take<uint8_t>(n), o_cn = A.take<int>(n), o_cidx = A.take<int>(n);
     const size_t o_X = A.take<double>(3 * (size_t)n), o_elig = A.take<uint8_t>(n);
     const size_t o_nvol = A.take<T>(n), o_owner = A.take<uint8_t>(L.nent), o_tid = A.take<int>(m);
+    std::vector<int> inc_off;
+    std::vector<uint16_t> inc;
+    build_incidence(L, inc_off, inc);
+    const size_t o_inc_off = A.take<int>(L.nent + 1), o_inc = A.take<uint16_t>(4 * (size_t)m);
     // Lumped volume share per node (sum over its tets of V_e / 4, FP64 on the
     // host) and each node's first tile entry.
     std::vector<T> nvol(n, (T)0);
@@ -352,6 +357,8 @@ int add_topology(fem_batch *B, const double *X_in, int n, const int32_t *tets_in
     if (!rc) rc = up(o_nvol, nvol.data(), (size_t)n * sizeof(T));
     if (!rc) rc = up(o_owner, owner.data(), (size_t)L.nent);
     if (!rc) rc = up(o_tid, L.order.data(), (size_t)m * sizeof(int));
+    if (!rc) rc = up(o_inc_off, inc_off.data(), inc_off.size() * sizeof(int));
+    if (!rc) rc = up(o_inc, inc.data(), inc.size() * sizeof(uint16_t));
     // Rest volumes and boundary faces from the original connectivity.
     unsigned slots = 1;
     while (slots < 8u * (unsigned)m) slots <<= 1;
@@ -419,6 +426,8 @@ int add_topology(fem_batch *B, const double *X_in, int n, const int32_t *tets_in
     v.rec = (const TetRec<T> *)(base + o_rec);
     v.node_ent_off = (const int *)(base + o_neo);
     v.node_ent = (const int *)(base + o_ne);
+    v.inc_off = (const int *)(base + o_inc_off);
+    v.inc = (const uint16_t *)(base + o_inc);
     v.fixed = (const uint8_t *)(base + o_fixed);
     v.cnodes = (const int *)(base + o_cn);
     v.cidx = (const int *)(base + o_cidx);
@@ -627,8 +636,13 @@ void enqueue_step(fem_batch *B, const JobGroup &G, hipStream_t st, bool sample, 
     const int gt = pad8(G.tile_n), gn = pad8(G.node_n), nl = G.live_n;
     const bool nh = B->n_law[0] > 0, cr = B->n_law[1] > 0, fric = B->n_fric > 0;
     int slot = timer_slot(B, FEM_KERNEL_TILE, sample);
-    if (nh) launch_timed(B, st, slot, true, !cr, k_tile<T, LAW_NH>, dim3(gt), dim3(kBlock), tp, bf, wt, G.tile_n, P);
-    if (cr) launch_timed(B, st, slot, !nh, true, k_tile<T, LAW_CR>, dim3(gt), dim3(kBlock), tp, bf, wt, G.tile_n, P);
+    if (B->deterministic) {
+        if (nh) launch_timed(B, st, slot, true, !cr, k_tile<T, LAW_NH, true>, dim3(gt), dim3(kBlock), tp, bf, wt, G.tile_n, P);
+        if (cr) launch_timed(B, st, slot, !nh, true, k_tile<T, LAW_CR, true>, dim3(gt), dim3(kBlock), tp, bf, wt, G.tile_n, P);
+    } else {
+        if (nh) launch_timed(B, st, slot, true, !cr, k_tile<T, LAW_NH, false>, dim3(gt), dim3(kBlock), tp, bf, wt, G.tile_n, P);
+        if (cr) launch_timed(B, st, slot, !nh, true, k_tile<T, LAW_CR, false>, dim3(gt), dim3(kBlock), tp, bf, wt, G.tile_n, P);
+    }
     if (after_tile) (void)hipEventRecord(after_tile, st);
     slot = timer_slot(B, FEM_KERNEL_NODE, sample);
     if (fric)
@@ -680,7 +694,8 @@ int kernel_variant(fem_batch *B) {
         B->n_law[B->h_states[i].model == LAW_CR ? 1 : 0]++;
         if (B->h_states[i].mu_f > 0.0) B->n_fric++;
     }
-    return (B->n_law[0] > 0 ? 1 : 0) | (B->n_law[1] > 0 ? 2 : 0) | (B->n_fric > 0 ? 4 : 0);
+    return (B->n_law[0] > 0 ? 1 : 0) | (B->n_law[1] > 0 ? 2 : 0) | (B->n_fric > 0 ? 4 : 0) |
+           (B->deterministic ? 8 : 0);
 }
 
 // Launches a round, replaying a captured graph for its length when graphs are
@@ -1838,6 +1853,13 @@ int fem_batch_set_option(fem_batch *B, int32_t option, int32_t value) {
     case FEM_OPT_TILE_TETS:
         if (value < 64 || value > kTileTets) return fail(FEM_E_INVALID, "tile tets must be 64..512");
         B->tile_tets = value;
+        return FEM_OK;
+    case FEM_OPT_DETERMINISTIC:
+        if (value < 0 || value > 1) return fail(FEM_E_INVALID, "deterministic must be 0 or 1");
+        TRY(set_device(B));
+        TRY(sync(B));
+        drop_graphs(B);
+        B->deterministic = value != 0;
         return FEM_OK;
     case FEM_OPT_GROUPS:
         if (value < 0 || value > 2) return fail(FEM_E_INVALID, "groups must be 0, 1 or 2");

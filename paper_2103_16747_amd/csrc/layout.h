@@ -226,4 +226,25 @@ inline void build_layout(const double *X, int n, const int32_t *tets, int m, int
     }
 }
 
+// Incident (tet, slot) pairs of every tile entry, for the deterministic
+// accumulation of tile partials: entry e's pairs are inc[off[e] .. off[e+1]),
+// coded (tet position within the tile << 2) | slot, in ascending tet order.
+inline void build_incidence(const HostLayout &L, std::vector<int> &off, std::vector<uint16_t> &inc) {
+    off.assign(L.nent + 1, 0);
+    inc.assign(4 * (size_t)L.m, 0);
+    for (int t = 0; t < L.ntile; t++) {
+        const int e0 = L.tile_ent[t];
+        for (int k = L.tile_tet[t]; k < L.tile_tet[t + 1]; k++)
+            for (int a = 0; a < 4; a++) off[e0 + ((L.tet_loc[k] >> (8 * a)) & 0xff) + 1]++;
+    }
+    for (int e = 0; e < L.nent; e++) off[e + 1] += off[e];
+    std::vector<int> fill(off.begin(), off.end() - 1);
+    for (int t = 0; t < L.ntile; t++) {
+        const int e0 = L.tile_ent[t], k0 = L.tile_tet[t];
+        for (int k = k0; k < L.tile_tet[t + 1]; k++)
+            for (int a = 0; a < 4; a++)
+                inc[fill[e0 + ((L.tet_loc[k] >> (8 * a)) & 0xff)]++] = (uint16_t)(((k - k0) << 2) | a);
+    }
+}
+
 }  // namespace fem_layout

@@ -38,7 +38,7 @@ EXPORTS = ("fem_create_mesh", "fem_destroy_mesh", "fem_set_material", "fem_set_i
            "fem_batch_job_footprint", "fem_status_string",
            "fem_last_error")
 FEM_KERNEL_TILE, FEM_KERNEL_NODE, FEM_KERNEL_FINALIZE = 0, 1, 2
-FEM_OPT_ROUND_STEPS, FEM_OPT_TILE_TETS, FEM_OPT_TILE_NODES, FEM_OPT_GROUPS = 0, 1, 2, 3
+FEM_OPT_ROUND_STEPS, FEM_OPT_TILE_TETS, FEM_OPT_TILE_NODES, FEM_OPT_GROUPS, FEM_OPT_DETERMINISTIC = 0, 1, 2, 3, 4
 
 
 class FemError(RuntimeError):

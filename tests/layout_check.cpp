@@ -102,6 +102,24 @@ int main(int argc, char **argv) {
             if (L.ent_node[ent] != v) return bad("entry under the wrong node", v, ent);
             eseen[ent] = 1;
         }
+    // incidence lists: every (tet, slot) of a tile exactly once, under the
+    // entry of that slot, in ascending tet order
+    std::vector<int> ioff;
+    std::vector<uint16_t> inc;
+    build_incidence(L, ioff, inc);
+    if ((int)ioff.size() != L.nent + 1 || ioff[L.nent] != 4 * m) return bad("incidence offsets", L.nent, m);
+    for (int t = 0; t < L.ntile; t++) {
+        const int e0 = L.tile_ent[t], k0 = L.tile_tet[t];
+        for (int e = e0; e < L.tile_ent[t + 1]; e++) {
+            int last = -1;
+            for (int q = ioff[e]; q < ioff[e + 1]; q++) {
+                const int k = inc[q] >> 2, a = inc[q] & 3;
+                if (k < last || k0 + k >= L.tile_tet[t + 1]) return bad("incidence order", e, k);
+                if ((int)((L.tet_loc[k0 + k] >> (8 * a)) & 0xff) != e - e0) return bad("incidence slot", e, k);
+                last = k;
+            }
+        }
+    }
     std::printf("ok tiles=%d entries=%d\n", L.ntile, L.nent);
     return 0;
 }

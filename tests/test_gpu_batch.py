@@ -228,3 +228,57 @@ def test_two_job_groups_match_one(precision):
         errs = [e_inf(u, ref) for u, ref in zip(runs[name], runs["one group"])]
         say(precision, name, "vs one group: max e_inf %.3e" % max(errs))
         assert max(errs) <= bound, errs
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_deterministic_mode_is_bitwise(precision):
+    """The fixed-order tile sums (FEM_OPT_DETERMINISTIC): each job's result is
+    bitwise the same alone, in a mix of meshes, laws and indenters replayed
+    from graphs, and in the same mix split into two job groups launched
+    kernel by kernel; and the default mode (LDS atomics, whose sums follow
+    the order of wavefronts) agrees with it within the alone-vs-mix bounds."""
+    cube = W.cube_block_mesh()
+    tip = W.fingertip_mesh(5000)
+    mix = [(cube, j, E0, NU0) for j in cube_jobs()[:2]]
+    for s, model in ((4200, 0), (4201, 1), (4202, 0)):
+        base = W.seat_on_mesh(W.random_indentation(s, steps=6), tip)
+        ind = W.Indentation(base.kind, base.shape, base.R, base.c0, base.direction, base.depth * 0.6, 6,
+                            base.k_penalty, seed=s, model=model, friction=0.3 if model else 0.0,
+                            friction_eps=1e-5)
+        mix.append((tip, ind, 1.55e6 if model else E0, 0.316 if model else NU0))
+
+    def run(jobs, det, groups=1, graphs=1):
+        b = fem.FemBatch(len(jobs), precision)
+        b.set_option(fem.FEM_OPT_DETERMINISTIC, det)
+        b.set_option(fem.FEM_OPT_GROUPS, groups)
+        b.set_graphs(graphs)
+        mids = {}
+        ids = []
+        for mesh, ind, E, nu in jobs:
+            if mesh.name not in mids:
+                mids[mesh.name] = b.add_mesh(mesh.X, mesh.tets, mesh.fixed)
+            ids.append(b.add_job(mids[mesh.name], ind, E, nu))
+        assert b.run(tight(b, precision)) == 0
+        for j, (_, ind, _, _) in zip(ids, jobs):
+            info = b.job_info(j)
+            assert info["done"] == 1 and info["steps_ok"] + info["steps_failed"] == ind.steps, info
+        out = [b.displacements(j) for j in ids]
+        b.close()
+        return out
+
+    say("case", precision, "deterministic, mix")
+    det_mix = run(mix, 1)
+    say("case", precision, "deterministic, two groups, no graphs")
+    det_groups = run(mix, 1, groups=2, graphs=0)
+    say("case", precision, "default mode, mix")
+    atomic_mix = run(mix, 0)
+    bound = 1e-9 if precision == "fp64" else 1e-5
+    for i, job in enumerate(mix):
+        say("case", precision, "deterministic, alone", i)
+        alone = run([job], 1)[0]
+        np.testing.assert_array_equal(det_mix[i], alone)
+        np.testing.assert_array_equal(det_groups[i], alone)
+        err = e_inf(atomic_mix[i], alone)
+        say(precision, job[0].name, W.KIND_NAMES[job[1].kind], "model", job[1].model,
+            "default vs deterministic %.3e" % err)
+        assert err <= bound
