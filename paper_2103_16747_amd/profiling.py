@@ -163,7 +163,7 @@ def main(argv=None):
     elif args.cmd == "traffic-json":
         import json
         rec = {"kernel_source_sha256": kernel_source_hash(), "groups": args.groups}
-        for key, pat in (("tile", r"k_tile<float, 0>"), ("node", r"k_node<float, false>")):
+        for key, pat in (("tile", r"k_tile<float, 0, false>"), ("node", r"k_node<float, false>")):
             t = traffic(args.fetch_dir, args.write_dir, args.copy_bytes, pat)
             rec[f"{key}_bytes_per_dispatch"] = t["traffic_bytes_per_dispatch"]
             rec[f"{key}_fetch_bytes_per_dispatch"] = t["fetch_bytes_per_dispatch"]
