@@ -1909,10 +1909,11 @@ __global__ __launch_bounds__(kBlock) void k_check_volumes(const double *X, const
 }
 
 // Rest constants per tet in tile order (FP64, stored in the path precision):
-// D_m = [X1-X0, X2-X0, X3-X0], D_m^-1 by cofactors, V = det D_m / 6, from the
-// tet's nodes in device vertex order (tnodes, 4 per tet in tile order; an
-// even reordering of the input, so det D_m keeps its sign); with the tet's
-// packed local node slots.
+// D_m = [X1-X0, X2-X0, X3-X0], D_m^-1 by cofactors, V = |det D_m| / 6, from
+// the tet's nodes in device vertex order (tnodes, 4 per tet in tile order;
+// any reordering of the input's vertices: F = D_s D_m^-1 does not depend on
+// it, and the input orientation is checked by k_check_volumes); with the
+// tet's packed local node slots.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_rest_constants(const double *X, const int *tnodes, const uint32_t *loc,
                                                            int m, TetRec<T> *rec) {
@@ -1936,7 +1937,7 @@ __global__ __launch_bounds__(kBlock) void k_rest_constants(const double *X, cons
     TetRec<T> r{};
 #pragma unroll
     for (int c = 0; c < 9; c++) r.Bm[c] = (T)inv[c];
-    r.V = (T)(det / 6.0);
+    r.V = (T)(fabs(det) / 6.0);
     r.loc = loc[k];
     rec[k] = r;
 }

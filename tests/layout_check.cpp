@@ -6,6 +6,8 @@
 // checks every invariant the device kernels rely on. Prints one line
 // "ok tiles=<T> entries=<E>" and exits 0, or names the first broken
 // invariant and exits 1.
+#include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -70,13 +72,17 @@ int main(int argc, char **argv) {
         const int k0 = L.tile_tet[t], k1 = L.tile_tet[t + 1], e0 = L.tile_ent[t], e1 = L.tile_ent[t + 1];
         if (k1 <= k0 || k1 - k0 > max_tets) return bad("tets per tile", t, k1 - k0);
         if (e1 <= e0 || e1 - e0 > max_nodes) return bad("nodes per tile", t, e1 - e0);
-        for (int q = e0 + 1; q < e1; q++)
-            if (L.ent_node[q] <= L.ent_node[q - 1]) return bad("entries not ascending", t, q);
+        {
+            std::vector<int> en(L.ent_node.begin() + e0, L.ent_node.begin() + e1);
+            std::sort(en.begin(), en.end());
+            for (size_t q = 1; q < en.size(); q++)
+                if (en[q] == en[q - 1]) return bad("node repeated in a tile", t, en[q]);
+        }
         for (int k = k0; k < k1; k++) {
             const int e = L.order[k];
             if (e < 0 || e >= m || tseen[e]) return bad("tile order not a permutation", k, e);
             tseen[e] = 1;
-            // device vertex order: the same node set, an even reordering (orientation kept)
+            // device vertex order: a reordering of the tet's vertices
             const int *dn = &L.tet_nodes[4 * (size_t)k];
             const int *in = &T[4 * (size_t)e];
             for (int a = 0; a < 4; a++) {
@@ -88,8 +94,11 @@ int main(int argc, char **argv) {
                 if (slot >= e1 - e0) return bad("local slot beyond the tile", k, slot);
                 if (L.ent_node[e0 + slot] != dn[a]) return bad("local slot names another node", k, slot);
             }
+            for (int a = 0; a < 4; a++)
+                for (int b = a + 1; b < 4; b++)
+                    if (dn[a] == dn[b]) return bad("device vertex repeated", k, a);
             const double d0 = det_dm(X.data(), in), d1 = det_dm(X.data(), dn);
-            if ((d0 > 0) != (d1 > 0)) return bad("vertex reordering flipped the orientation", k, e);
+            if (std::fabs(std::fabs(d0) - std::fabs(d1)) > 1e-9 * std::fabs(d0)) return bad("reordering changed |det D_m|", k, e);
         }
     }
     // node -> entry lists: each entry exactly once, under its own node
@@ -120,6 +129,20 @@ int main(int argc, char **argv) {
             }
         }
     }
-    std::printf("ok tiles=%d entries=%d\n", L.ntile, L.nent);
+    // dealing: largest number of lanes sharing a residue (local id mod 16) in
+    // one slot of a group of 16 consecutive positions, averaged (1 = no LDS
+    // bank repeats)
+    long long groups = 0, passes = 0;
+    for (int t = 0; t < L.ntile; t++) {
+        const int k0 = L.tile_tet[t], nk = L.tile_tet[t + 1] - k0;
+        for (int q0 = 0; q0 < nk; q0 += 16)
+            for (int a = 0; a < 4; a++) {
+                int h[16] = {0}, mx = 0;
+                for (int j = q0; j < std::min(nk, q0 + 16); j++) mx = std::max(mx, ++h[(L.tet_loc[k0 + j] >> (8 * a)) & 15]);
+                groups++;
+                passes += mx;
+            }
+    }
+    std::printf("ok tiles=%d entries=%d passes=%.4f\n", L.ntile, L.nent, (double)passes / (double)groups);
     return 0;
 }

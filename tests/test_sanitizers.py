@@ -5,7 +5,8 @@
   lists; paper_2103_16747_amd/csrc/layout.h) is compiled with g++
   -fsanitize=address,undefined into tests/layout_check.cpp's checker and run
   on the block and fingertip meshes at several tile limits; the checker also
-  asserts the layout's invariants.
+  asserts the layout's invariants and reports how well the dealing spreads
+  each 16-lane group's LDS accesses over the banks.
 - The FP64 oracle (oracle/oracle.c) is compiled with the same sanitizers and
   its pin tests run against that build in a child process with the sanitizer
   runtime preloaded.
@@ -41,7 +42,7 @@ def _env():
 @pytest.fixture(scope="module")
 def layout_checker(tmp_path_factory):
     exe = str(tmp_path_factory.mktemp("san") / "layout_check")
-    subprocess.run(["g++", "-std=c++17", *SAN, "-o", exe, os.path.join(ROOT, "tests", "layout_check.cpp")],
+    subprocess.run(["g++", "-std=c++17", "-pthread", *SAN, "-o", exe, os.path.join(ROOT, "tests", "layout_check.cpp")],
                    check=True)
     return exe
 
@@ -72,6 +73,10 @@ def test_layout_construction_under_sanitizers(layout_checker, tmp_path, name, li
                        env=_env(), timeout=300)
     assert p.returncode == 0 and p.stdout.startswith("ok"), (p.stdout, p.stderr[-2000:])
     assert "runtime error" not in p.stderr and "AddressSanitizer" not in p.stderr
+    if name.startswith("fingertip") and limits[1] >= 128:
+        # the dealing leaves (almost) no repeated LDS bank in a 16-lane group
+        passes = float(p.stdout.split("passes=")[1].split()[0])
+        assert passes <= 1.05, p.stdout
 
 
 def test_oracle_pins_under_sanitizers():
