@@ -32,6 +32,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace fem {
 
 constexpr int kBlock = 256;       // 4 wavefronts of 64
@@ -120,42 +122,65 @@ template <> struct alignas(16) TetRec<double> {
 };
 static_assert(sizeof(TetRec<float>) == 48 && sizeof(TetRec<double>) == 96, "tet record layout");
 
-template <typename T>
+// Buffer pointers of the descriptors below. The host fills them as plain
+// pointers; kernels read them through a device view (DEV = true, same
+// layout) whose pointers are in the global address space, so accesses
+// compile to global memory instructions instead of flat ones (a flat
+// instruction also counts against the LDS counter, which makes every wait
+// for an LDS result wait for the outstanding memory loads as well).
+#ifdef __HIP_DEVICE_COMPILE__
+template <class U> using glob_ptr = U __attribute__((address_space(1))) *;
+#else
+template <class U> using glob_ptr = U *;
+#endif
+template <class U, bool DEV> using buf_ptr = std::conditional_t<DEV, glob_ptr<U>, U *>;
+
+template <typename T, bool DEV = false>
 struct Topo {
-    int n, m, ntile, nent, nc, ncb;     // ncb = contact blocks
-    const int *tile_tet;                // ntile + 1
-    const int *tile_ent;                // ntile + 1
-    const int *ent_node;                // nent
-    const TetRec<T> *rec;               // m, tile order
-    const int *node_ent_off;            // n + 1
-    const int *node_ent;                // nent
-    const int *inc_off;                 // nent + 1: each tile entry's incident (tet, slot) pairs
-    const uint16_t *inc;                // 4 m: (local tet << 2 | slot), ascending tet per entry
-    const uint8_t *fixed;               // n
-    const int *cnodes;                  // nc
-    const int *cidx;                    // n: contact slot or -1
-    const double *X;                    // n x 3
-    const T *nvol;                      // n: lumped volume share sum_e V_e / 4
-    const uint8_t *owner;               // nent: 1 on each node's first entry
-    const int *tet_id;                  // m: input index of the tet at each tile position
+    int n, m, ntile, nent, nc, ncb;                 // ncb = contact blocks
+    buf_ptr<const int, DEV> tile_tet;               // ntile + 1
+    buf_ptr<const int, DEV> tile_ent;               // ntile + 1
+    buf_ptr<const int, DEV> ent_node;               // nent
+    buf_ptr<const TetRec<T>, DEV> rec;              // m, tile order
+    buf_ptr<const int, DEV> node_ent_off;           // n + 1
+    buf_ptr<const int, DEV> node_ent;               // nent
+    buf_ptr<const int, DEV> inc_off;                // nent + 1: each tile entry's incident (tet, slot) pairs
+    buf_ptr<const uint16_t, DEV> inc;               // 4 m: (local tet << 2 | slot), ascending tet per entry
+    buf_ptr<const uint8_t, DEV> fixed;              // n
+    buf_ptr<const int, DEV> cnodes;                 // nc
+    buf_ptr<const int, DEV> cidx;                   // n: contact slot or -1
+    buf_ptr<const double, DEV> X;                   // n x 3
+    buf_ptr<const T, DEV> nvol;                     // n: lumped volume share sum_e V_e / 4
+    buf_ptr<const uint8_t, DEV> owner;              // nent: 1 on each node's first entry
+    buf_ptr<const int, DEV> tet_id;                 // m: input index of the tet at each tile position
 };
 
-template <typename T>
+template <typename T, bool DEV = false>
 struct InstBufs {
     int topo;
-    int red_stride;                     // partial slots per reduction stream
-    T *u, *dx, *g, *r, *z, *p, *dinv;   // dinv n x 6, others n x 3
-    T *pg;                              // nent x 9: gradient (3) + node block (6) partials
-    T *pq;                              // nent x 3: Hv partials
-    T *cp;                              // nc x 9: contact gradient (3) + block (6)
-    T *qout;                            // n x 3 (diagnostics)
-    T *v, *ut;                          // n x 3: velocity of the last completed step, inertial predictor
-    double *fr;                         // nc x 8: friction lag data (w, normal, displacement relative to
-                                        // the indenter since the lag state, pad)
-    double *red;                        // RS_COUNT x red_stride
-    signed char *hist;                  // kHistSteps: status of each load step taken (ST_*)
-    InstState *s;
+    int red_stride;                                 // partial slots per reduction stream
+    buf_ptr<T, DEV> u, dx, g, r, z, p, dinv;        // dinv n x 6, others n x 3
+    buf_ptr<T, DEV> pg;                             // nent x 9: gradient (3) + node block (6) partials
+    buf_ptr<T, DEV> pq;                             // nent x 3: Hv partials
+    buf_ptr<T, DEV> cp;                             // nc x 9: contact gradient (3) + block (6)
+    buf_ptr<T, DEV> qout;                           // n x 3 (diagnostics)
+    buf_ptr<T, DEV> v, ut;                          // n x 3: velocity of the last completed step, inertial predictor
+    buf_ptr<double, DEV> fr;                        // nc x 8: friction lag data (w, normal, displacement
+                                                    // relative to the indenter since the lag state, pad)
+    buf_ptr<double, DEV> red;                       // RS_COUNT x red_stride
+    buf_ptr<signed char, DEV> hist;                 // kHistSteps: status of each load step taken (ST_*)
+    buf_ptr<InstState, DEV> s;
 };
+
+// Device views of descriptors read from device memory.
+template <typename T> using TopoD = Topo<T, true>;
+template <typename T> using BufsD = InstBufs<T, true>;
+template <typename T> __device__ __forceinline__ TopoD<T> dev_view(const Topo<T> &t) {
+    return __builtin_bit_cast(TopoD<T>, t);
+}
+template <typename T> __device__ __forceinline__ BufsD<T> dev_view(const InstBufs<T> &b) {
+    return __builtin_bit_cast(BufsD<T>, b);
+}
 
 // ---------------------------------------------------------------------------
 // Work mapping: blocks are dealt to the 8 XCDs round-robin, so logical work
@@ -283,7 +308,7 @@ template <typename T> struct TetWords {
 };
 
 template <typename T>
-__device__ __forceinline__ void fetch_tet(const Topo<T> &tp, int k, TetWords<T> &tw) {
+__device__ __forceinline__ void fetch_tet(const TopoD<T> &tp, int k, TetWords<T> &tw) {
     const uint4 *src = reinterpret_cast<const uint4 *>(tp.rec + k);
 #pragma unroll
     for (int i = 0; i < (int)(sizeof(TetRec<T>) / 16); i++) tw.w[i] = src[i];
@@ -895,7 +920,7 @@ __device__ inline void friction_rel(const double fr[8], const double inc[3], dou
 // the exact contact Hessian) per eligible node.
 // ---------------------------------------------------------------------------
 template <typename T, int LAW, bool DET>
-__device__ __forceinline__ void tile_element(const Topo<T> &tp, const InstBufs<T> &B, const InstState *s, int blk,
+__device__ __forceinline__ void tile_element(const TopoD<T> &tp, const BufsD<T> &B, const InstState *s, int blk,
                                              T alpha, int contact_full, double *pool) {
     const T mu = (T)s->mu, lam = (T)s->lam;
     double acc[3] = {0.0, 0.0, INFINITY};   // energy, magnitude, min J
@@ -1076,7 +1101,7 @@ __device__ __forceinline__ void tile_element(const Topo<T> &tp, const InstBufs<T
 // is known to the node pass without a pass over q.
 // ---------------------------------------------------------------------------
 template <typename T, int LAW, bool DET>
-__device__ __forceinline__ void tile_hessvec(const Topo<T> &tp, const InstBufs<T> &B, const InstState *s, int blk,
+__device__ __forceinline__ void tile_hessvec(const TopoD<T> &tp, const BufsD<T> &B, const InstState *s, int blk,
                                              double *pool) {
     const T beta = (T)s->beta;
     const T mu = (T)s->mu, lam = (T)s->lam;
@@ -1218,8 +1243,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T
     const int2 w = work[L];
     // Descriptors copied up front, before any store of the kernel, so they
     // are fetched once as uniform (scalar) loads.
-    const InstBufs<T> B = bufs[w.x];
-    const Topo<T> tp = topos[B.topo];
+    const BufsD<T> B = dev_view(bufs[w.x]);
+    const TopoD<T> tp = dev_view(topos[B.topo]);
     const int contact_full = P->contact_full;
     const InstState *s = B.s;
     const int phase = s->phase;
@@ -1245,7 +1270,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T
 // energy (m/2dt^2)|u - ut|^2 to its own partial sum.
 // ---------------------------------------------------------------------------
 template <typename T, bool FRIC>
-__device__ __forceinline__ void node_init(const Topo<T> &tp, const InstBufs<T> &B, const InstState *s, int blk,
+__device__ __forceinline__ void node_init(const TopoD<T> &tp, const BufsD<T> &B, const InstState *s, int blk,
                                           bool apply, bool step_start, int block_jacobi) {
     const T alpha = (T)s->alpha_ls;
     const double dt = s->dt, mdt2 = s->mdt2;
@@ -1359,7 +1384,7 @@ __device__ __forceinline__ void node_init(const Topo<T> &tp, const InstBufs<T> &
 // Newton direction). EVAL_HV writes q instead.
 // ---------------------------------------------------------------------------
 template <typename T, bool DYN>
-__device__ __forceinline__ void node_update(const Topo<T> &tp, const InstBufs<T> &B, const InstState *s, int blk,
+__device__ __forceinline__ void node_update(const TopoD<T> &tp, const BufsD<T> &B, const InstState *s, int blk,
                                             bool eval) {
     // solver scalars and this thread's node data first: their loads are in
     // flight while the block sums the p.q partials
@@ -1444,7 +1469,7 @@ __device__ __forceinline__ void node_update(const Topo<T> &tp, const InstBufs<T>
 // line search) and, for implicit steps, of the inertial energy
 // (m/2dt^2)|u + alpha dx - ut|^2 at the trial point.
 template <typename T>
-__device__ __forceinline__ void node_trial(const Topo<T> &tp, const InstBufs<T> &B, const InstState *s, int blk) {
+__device__ __forceinline__ void node_trial(const TopoD<T> &tp, const BufsD<T> &B, const InstState *s, int blk) {
     double acc[2] = {0.0, 0.0};
     double unused = 0.0;
     const int i = blk * kBlock + threadIdx.x;
@@ -1476,7 +1501,7 @@ __device__ __forceinline__ void node_trial(const Topo<T> &tp, const InstBufs<T> 
 // ---------------------------------------------------------------------------
 // Friction lag data of the contact-eligible nodes of one node block.
 template <typename T>
-__device__ __forceinline__ void node_lag(const Topo<T> &tp, const InstBufs<T> &B, const InstState *s, int blk) {
+__device__ __forceinline__ void node_lag(const TopoD<T> &tp, const BufsD<T> &B, const InstState *s, int blk) {
     const int i = blk * kBlock + threadIdx.x;
     if (i >= tp.n) return;
     const int j = tp.cidx[i];
@@ -1497,8 +1522,8 @@ __global__ __launch_bounds__(kBlock) void k_node(const Topo<T> *topos, const Ins
     const int2 w = work[L];
     // Descriptors copied up front, before any store of the kernel, so they
     // are fetched once as uniform (scalar) loads.
-    const InstBufs<T> B = bufs[w.x];
-    const Topo<T> tp = topos[B.topo];
+    const BufsD<T> B = dev_view(bufs[w.x]);
+    const TopoD<T> tp = dev_view(topos[B.topo]);
     const InstState *s = B.s;
     const int phase = s->phase;
     if (phase == PH_CG || phase == PH_EVAL_HV) {
@@ -1523,7 +1548,8 @@ __global__ __launch_bounds__(kBlock) void k_node(const Topo<T> *topos, const Ins
 // in a row whose predicted energy change lies within rounding have not halved
 // the smallest residual of the step, the working precision cannot take it
 // lower and the step ends with ST_FLOOR.
-__device__ inline void newton_test(InstState *s, signed char *hist, const SolveParams *P, double gg, double rz) {
+template <class StatePtr, class HistPtr>   // global-address-space pointers on the device
+__device__ inline void newton_test(StatePtr s, HistPtr hist, const SolveParams *P, double gg, double rz) {
     s->gg = gg;
     const double gn = sqrt(gg);
     if (s->step_started) {
@@ -1600,9 +1626,9 @@ template <typename T>
 __global__ __launch_bounds__(64) void k_finalize(const Topo<T> *topos, const InstBufs<T> *bufs, const int *live,
                                                  int nlive, const SolveParams *P) {
     if ((int)blockIdx.x >= nlive) return;
-    const InstBufs<T> B = bufs[live[blockIdx.x]];
-    const Topo<T> tp = topos[B.topo];
-    InstState *s = B.s;
+    const BufsD<T> B = dev_view(bufs[live[blockIdx.x]]);
+    const TopoD<T> tp = dev_view(topos[B.topo]);
+    const auto s = B.s;   // global-address-space pointer on the device
     const int phase = s->phase;
     const int S = B.red_stride;
     const int nt = tp.ntile + tp.ncb, nn = (tp.n + kBlock - 1) / kBlock;
@@ -1702,8 +1728,8 @@ __global__ __launch_bounds__(1024) void k_contact_patch(const Topo<T> *topos, co
     __shared__ double wave_f[16][3];
     __shared__ int base_s;
     __shared__ double F_s[3];
-    const InstBufs<T> &B = bufs[inst];
-    const Topo<T> &tp = topos[B.topo];
+    const BufsD<T> B = dev_view(bufs[inst]);
+    const TopoD<T> tp = dev_view(topos[B.topo]);
     const Indenter ind = B.s->ind;
     const bool fric = B.s->mu_f > 0.0;
     const double eps_f = B.s->eps_f;
@@ -1790,8 +1816,8 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_tet_stress(const Topo<T> *topos, const InstBufs<T> *bufs, int inst,
                                                        double *sigma, double *vm) {
     __shared__ __attribute__((aligned(32))) T su[kSw * kTileNodes];
-    const InstBufs<T> B = bufs[inst];
-    const Topo<T> tp = topos[B.topo];
+    const BufsD<T> B = dev_view(bufs[inst]);
+    const TopoD<T> tp = dev_view(topos[B.topo]);
     const int t = blockIdx.x;
     if (t >= tp.ntile) return;
     const T mu = (T)B.s->mu, lam = (T)B.s->lam;
@@ -1859,7 +1885,7 @@ template <typename T>
 __global__ __launch_bounds__(1024) void k_disp_stats(const Topo<T> *topos, const InstBufs<T> *bufs, int inst,
                                                      double *out) {
     __shared__ double smax[16], ssum[16];
-    const InstBufs<T> B = bufs[inst];
+    const BufsD<T> B = dev_view(bufs[inst]);
     const int n = topos[B.topo].n;
     double mx = 0.0, sum = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
