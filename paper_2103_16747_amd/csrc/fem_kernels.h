@@ -40,6 +40,7 @@ constexpr int kBlock = 256;       // 4 wavefronts of 64
 constexpr int kWaves = kBlock / 64;
 constexpr int kTileTets = 512;    // tets per tile (2 per thread)
 constexpr int kTileNodes = 256;   // distinct nodes per tile (8-bit local ids)
+static_assert(kTileNodes <= kBlock, "the tile passes stage one entry per thread");
 constexpr int kDetElemChunk = 128; // deterministic element pass: tets per chunk of contributions
 constexpr int kHistSteps = 1024;  // load steps whose status a job records
 
@@ -140,7 +141,8 @@ struct Topo {
     int n, m, ntile, nent, nc, ncb;                 // ncb = contact blocks
     buf_ptr<const int, DEV> tile_tet;               // ntile + 1
     buf_ptr<const int, DEV> tile_ent;               // ntile + 1
-    buf_ptr<const int, DEV> ent_node;               // nent
+    buf_ptr<const int, DEV> ent_node;               // nent: node of each entry (ascending within a tile)
+    buf_ptr<const uint8_t, DEV> ent_slot;           // nent: LDS slot of each entry (local id in the tet records)
     buf_ptr<const TetRec<T>, DEV> rec;              // m, tile order
     buf_ptr<const int, DEV> node_ent_off;           // n + 1
     buf_ptr<const int, DEV> node_ent;               // nent
@@ -935,18 +937,20 @@ __device__ __forceinline__ void tile_element(const TopoD<T> &tp, const BufsD<T> 
         // barrier, so its latency overlaps the staging loads.
         TetWords<T> tw;
         if ((int)threadIdx.x < nk) fetch_tet(tp, k0 + (int)threadIdx.x, tw);
-        for (int l = threadIdx.x; l < ne; l += kBlock) {
-            const int gid = tp.ent_node[e0 + l];
+        // entry threadIdx.x (ne <= kTileNodes <= kBlock), staged at its slot
+        const int sl = (int)threadIdx.x < ne ? tp.ent_slot[e0 + threadIdx.x] : 0;
+        if ((int)threadIdx.x < ne) {
+            const int gid = tp.ent_node[e0 + threadIdx.x];
 #pragma unroll
             for (int d = 0; d < 3; d++) {
                 T uu = B.u[3 * gid + d];
                 if (alpha != (T)0) uu = fma_t(alpha, B.dx[3 * gid + d], uu);
-                su[kSw * l + d] = uu;
+                su[kSw * sl + d] = uu;
             }
-            su[kSw * l + 3] = (T)0;
+            su[kSw * sl + 3] = (T)0;
             if (!DET)
 #pragma unroll
-                for (int c = 0; c < 9; c++) sa[9 * l + c] = 0.0;
+                for (int c = 0; c < 9; c++) sa[9 * sl + c] = 0.0;
         }
         __syncthreads();
         // One tet: its energy into acc, and per node a the gradient (c = 0..2)
@@ -1004,7 +1008,9 @@ __device__ __forceinline__ void tile_element(const TopoD<T> &tp, const BufsD<T> 
             for (int k = threadIdx.x; k < nk; k += kBlock)
                 tet(k, [&](const int *l, int a, int c, T v) { atomicAdd(sa + 9 * l[a] + c, (double)v); });
             __syncthreads();
-            for (int i = threadIdx.x; i < 9 * ne; i += kBlock) B.pg[9 * e0 + i] = (T)sa[i];
+            if ((int)threadIdx.x < ne)
+#pragma unroll
+                for (int c = 0; c < 9; c++) B.pg[9 * (e0 + threadIdx.x) + c] = (T)sa[9 * sl + c];
         } else {
             // Deterministic: a chunk of tets stores its contributions, then
             // each entry sums its incident ones in ascending tet order.
@@ -1123,19 +1129,21 @@ __device__ __forceinline__ void tile_hessvec(const TopoD<T> &tp, const BufsD<T> 
         // barrier, so its latency overlaps the staging loads.
         TetWords<T> tw;
         if ((int)threadIdx.x < nk) fetch_tet(tp, k0 + (int)threadIdx.x, tw);
-        for (int l = threadIdx.x; l < ne; l += kBlock) {
-            const int gid = tp.ent_node[e0 + l];
+        // entry threadIdx.x (ne <= kTileNodes <= kBlock), staged at its slot
+        const int sl = (int)threadIdx.x < ne ? tp.ent_slot[e0 + threadIdx.x] : 0;
+        if ((int)threadIdx.x < ne) {
+            const int gid = tp.ent_node[e0 + threadIdx.x];
             T pv[3];
 #pragma unroll
             for (int d = 0; d < 3; d++) {
-                su[kSw * l + d] = B.u[3 * gid + d];
+                su[kSw * sl + d] = B.u[3 * gid + d];
                 pv[d] = fma_t(beta, B.p[3 * gid + d], B.z[3 * gid + d]);
-                sp[kSw * l + d] = pv[d];
-                if (!DET) sa[3 * l + d] = 0.0;
+                sp[kSw * sl + d] = pv[d];
+                if (!DET) sa[3 * sl + d] = 0.0;
             }
-            su[kSw * l + 3] = (T)0;
-            sp[kSw * l + 3] = (T)0;
-            if (cm > 0.0 && tp.owner[e0 + l])
+            su[kSw * sl + 3] = (T)0;
+            sp[kSw * sl + 3] = (T)0;
+            if (cm > 0.0 && tp.owner[e0 + threadIdx.x])
                 pq += cm * (double)tp.nvol[gid] *
                       ((double)pv[0] * (double)pv[0] + (double)pv[1] * (double)pv[1] + (double)pv[2] * (double)pv[2]);
         }
@@ -1174,7 +1182,9 @@ __device__ __forceinline__ void tile_hessvec(const TopoD<T> &tp, const BufsD<T> 
                 tet(k, [&](const int *l, int a, int d, T v) { atomicAdd(sa + 3 * l[a] + d, (double)v); });
             acc[0] = pq;
             __syncthreads();
-            for (int i = threadIdx.x; i < 3 * ne; i += kBlock) B.pq[3 * e0 + i] = (T)sa[i];
+            if ((int)threadIdx.x < ne)
+#pragma unroll
+                for (int d = 0; d < 3; d++) B.pq[3 * (e0 + threadIdx.x) + d] = (T)sa[3 * sl + d];
         } else {
             // Deterministic: each chunk of kBlock tets stores its nodal
             // vectors, then each entry sums its incident ones in ascending
@@ -1825,10 +1835,10 @@ __global__ __launch_bounds__(kBlock) void k_tet_stress(const Topo<T> *topos, con
     const int e0 = tp.tile_ent[t], ne = tp.tile_ent[t + 1] - e0;
     const int k0 = tp.tile_tet[t], nk = tp.tile_tet[t + 1] - k0;
     for (int l = threadIdx.x; l < ne; l += kBlock) {
-        const int gid = tp.ent_node[e0 + l];
+        const int gid = tp.ent_node[e0 + l], sl = tp.ent_slot[e0 + l];
 #pragma unroll
-        for (int d = 0; d < 3; d++) su[kSw * l + d] = B.u[3 * gid + d];
-        su[kSw * l + 3] = (T)0;
+        for (int d = 0; d < 3; d++) su[kSw * sl + d] = B.u[3 * gid + d];
+        su[kSw * sl + 3] = (T)0;
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nk; k += kBlock) {

@@ -317,6 +317,7 @@ int add_topology(fem_batch *B, const double *X_in, int n, const int32_t *tets_in
     const size_t o_fixed = A.take<uint8_t>(n), o_cn = A.take<int>(n), o_cidx = A.take<int>(n);
     const size_t o_X = A.take<double>(3 * (size_t)n), o_elig = A.take<uint8_t>(n);
     const size_t o_nvol = A.take<T>(n), o_owner = A.take<uint8_t>(L.nent), o_tid = A.take<int>(m);
+    const size_t o_ent_slot = A.take<uint8_t>(L.nent);
     std::vector<int> inc_off;
     std::vector<uint16_t> inc;
     build_incidence(L, inc_off, inc);
@@ -350,6 +351,7 @@ int add_topology(fem_batch *B, const double *X_in, int n, const int32_t *tets_in
     if (!rc) rc = up(o_tile_tet, L.tile_tet.data(), L.tile_tet.size() * sizeof(int));
     if (!rc) rc = up(o_tile_ent, L.tile_ent.data(), L.tile_ent.size() * sizeof(int));
     if (!rc) rc = up(o_ent_node, L.ent_node.data(), L.ent_node.size() * sizeof(int));
+    if (!rc) rc = up(o_ent_slot, L.ent_slot.data(), L.ent_slot.size());
     if (!rc) rc = up(o_neo, L.node_ent_off.data(), L.node_ent_off.size() * sizeof(int));
     if (!rc) rc = up(o_ne, L.node_ent.data(), L.node_ent.size() * sizeof(int));
     if (!rc) rc = up(o_fixed, fixed, n);
@@ -423,6 +425,7 @@ int add_topology(fem_batch *B, const double *X_in, int n, const int32_t *tets_in
     v.tile_tet = (const int *)(base + o_tile_tet);
     v.tile_ent = (const int *)(base + o_tile_ent);
     v.ent_node = (const int *)(base + o_ent_node);
+    v.ent_slot = (const uint8_t *)(base + o_ent_slot);
     v.rec = (const TetRec<T> *)(base + o_rec);
     v.node_ent_off = (const int *)(base + o_neo);
     v.node_ent = (const int *)(base + o_ne);

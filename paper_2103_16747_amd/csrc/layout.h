@@ -20,6 +20,7 @@ namespace fem_layout {
 struct HostLayout {
     int n = 0, m = 0, ntile = 0, nent = 0;
     std::vector<int> tile_tet, tile_ent, ent_node, node_ent_off, node_ent;
+    std::vector<uint8_t> ent_slot;      // nent: LDS slot (local id in tet_loc) of each entry
     std::vector<uint32_t> tet_loc;
     std::vector<int> order;             // tile position -> input tet index
     std::vector<int> tet_nodes;         // 4 x m: global node ids per tet in tile order and device vertex order
@@ -427,6 +428,7 @@ inline void build_layout(const double *X, int n, const int32_t *tets, int m, int
     for (int t = 0; t < L.ntile; t++) L.tile_ent[t + 1] = L.tile_ent[t] + (int)tnodes[t].size();
     L.nent = L.tile_ent[L.ntile];
     L.ent_node.assign(L.nent, 0);
+    L.ent_slot.assign(L.nent, 0);
     L.tet_loc.assign(m, 0);
     L.order.assign(m, 0);
     L.tet_nodes.assign(4 * (size_t)m, 0);
@@ -448,7 +450,12 @@ inline void build_layout(const double *X, int n, const int32_t *tets, int m, int
         }
         std::vector<int> newid, placed;
         deal_tile(words, ne, newid, placed, (uint32_t)t);
-        for (int l = 0; l < ne; l++) L.ent_node[e0 + newid[l]] = nodes[l];
+        // entries stay in ascending node order (the node pass reads a
+        // node's partials at consecutive addresses); slots follow the dealing
+        for (int l = 0; l < ne; l++) {
+            L.ent_node[e0 + l] = nodes[l];
+            L.ent_slot[e0 + l] = (uint8_t)newid[l];
+        }
         for (int k = k0; k < k1; k++) {
             const int src = placed[k - k0] >> 5, r = placed[k - k0] & 31;
             const int e = order[k0 + src];
@@ -491,18 +498,25 @@ inline void build_layout(const double *X, int n, const int32_t *tets, int m, int
 inline void build_incidence(const HostLayout &L, std::vector<int> &off, std::vector<uint16_t> &inc) {
     off.assign(L.nent + 1, 0);
     inc.assign(4 * (size_t)L.m, 0);
-    for (int t = 0; t < L.ntile; t++) {
-        const int e0 = L.tile_ent[t];
-        for (int k = L.tile_tet[t]; k < L.tile_tet[t + 1]; k++)
-            for (int a = 0; a < 4; a++) off[e0 + ((L.tet_loc[k] >> (8 * a)) & 0xff) + 1]++;
-    }
-    for (int e = 0; e < L.nent; e++) off[e + 1] += off[e];
-    std::vector<int> fill(off.begin(), off.end() - 1);
-    for (int t = 0; t < L.ntile; t++) {
-        const int e0 = L.tile_ent[t], k0 = L.tile_tet[t];
-        for (int k = k0; k < L.tile_tet[t + 1]; k++)
-            for (int a = 0; a < 4; a++)
-                inc[fill[e0 + ((L.tet_loc[k] >> (8 * a)) & 0xff)]++] = (uint16_t)(((k - k0) << 2) | a);
+    std::vector<int> ent_of(256, 0);   // tile entry of each LDS slot
+    for (int pass = 0; pass < 2; pass++) {
+        std::vector<int> fill;
+        if (pass == 1) {
+            for (int e = 0; e < L.nent; e++) off[e + 1] += off[e];
+            fill.assign(off.begin(), off.end() - 1);
+        }
+        for (int t = 0; t < L.ntile; t++) {
+            const int e0 = L.tile_ent[t], k0 = L.tile_tet[t];
+            for (int e = e0; e < L.tile_ent[t + 1]; e++) ent_of[L.ent_slot[e]] = e;
+            for (int k = k0; k < L.tile_tet[t + 1]; k++)
+                for (int a = 0; a < 4; a++) {
+                    const int e = ent_of[(L.tet_loc[k] >> (8 * a)) & 0xff];
+                    if (pass == 0)
+                        off[e + 1]++;
+                    else
+                        inc[fill[e]++] = (uint16_t)(((k - k0) << 2) | a);
+                }
+        }
     }
 }
 

@@ -72,11 +72,15 @@ int main(int argc, char **argv) {
         const int k0 = L.tile_tet[t], k1 = L.tile_tet[t + 1], e0 = L.tile_ent[t], e1 = L.tile_ent[t + 1];
         if (k1 <= k0 || k1 - k0 > max_tets) return bad("tets per tile", t, k1 - k0);
         if (e1 <= e0 || e1 - e0 > max_nodes) return bad("nodes per tile", t, e1 - e0);
-        {
-            std::vector<int> en(L.ent_node.begin() + e0, L.ent_node.begin() + e1);
-            std::sort(en.begin(), en.end());
-            for (size_t q = 1; q < en.size(); q++)
-                if (en[q] == en[q - 1]) return bad("node repeated in a tile", t, en[q]);
+        for (int q = e0 + 1; q < e1; q++)
+            if (L.ent_node[q] <= L.ent_node[q - 1]) return bad("entries not ascending", t, q);
+        // LDS slots: a permutation of 0 .. ne-1; ent_of[slot] = entry
+        if ((int)L.ent_slot.size() != L.nent) return bad("slot array", (long long)L.ent_slot.size(), L.nent);
+        std::vector<int> ent_of(e1 - e0, -1);
+        for (int q = e0; q < e1; q++) {
+            const int sl = L.ent_slot[q];
+            if (sl >= e1 - e0 || ent_of[sl] >= 0) return bad("slots not a permutation", t, sl);
+            ent_of[sl] = q;
         }
         for (int k = k0; k < k1; k++) {
             const int e = L.order[k];
@@ -92,7 +96,7 @@ int main(int argc, char **argv) {
                 // the packed local slot names this vertex's entry in the tile
                 const int slot = (int)((L.tet_loc[k] >> (8 * a)) & 0xffu);
                 if (slot >= e1 - e0) return bad("local slot beyond the tile", k, slot);
-                if (L.ent_node[e0 + slot] != dn[a]) return bad("local slot names another node", k, slot);
+                if (L.ent_node[ent_of[slot]] != dn[a]) return bad("local slot names another node", k, slot);
             }
             for (int a = 0; a < 4; a++)
                 for (int b = a + 1; b < 4; b++)
@@ -124,7 +128,7 @@ int main(int argc, char **argv) {
             for (int q = ioff[e]; q < ioff[e + 1]; q++) {
                 const int k = inc[q] >> 2, a = inc[q] & 3;
                 if (k < last || k0 + k >= L.tile_tet[t + 1]) return bad("incidence order", e, k);
-                if ((int)((L.tet_loc[k0 + k] >> (8 * a)) & 0xff) != e - e0) return bad("incidence slot", e, k);
+                if ((int)((L.tet_loc[k0 + k] >> (8 * a)) & 0xff) != L.ent_slot[e]) return bad("incidence slot", e, k);
                 last = k;
             }
         }
