@@ -38,6 +38,8 @@ namespace fem {
 
 constexpr int kBlock = 256;       // 4 wavefronts of 64
 constexpr int kWaves = kBlock / 64;
+constexpr int kGather = 4;        // node pass: tile entries per node held with the node (node_ent4)
+static_assert(kGather == 4, "node_ent4 holds four entries");
 constexpr int kTileTets = 512;    // tets per tile (2 per thread)
 constexpr int kTileNodes = 256;   // distinct nodes per tile (8-bit local ids)
 static_assert(kTileNodes <= kBlock, "the tile passes stage one entry per thread");
@@ -139,6 +141,7 @@ template <class U, bool DEV> using buf_ptr = std::conditional_t<DEV, glob_ptr<U>
 template <typename T, bool DEV = false>
 struct Topo {
     int n, m, ntile, nent, nc, ncb;                 // ncb = contact blocks
+    int n_free, pad0;                               // nodes 0 .. n_free-1 are free, the rest fixed
     buf_ptr<const int, DEV> tile_tet;               // ntile + 1
     buf_ptr<const int, DEV> tile_ent;               // ntile + 1
     buf_ptr<const int, DEV> ent_node;               // nent: node of each entry (ascending within a tile)
@@ -146,6 +149,7 @@ struct Topo {
     buf_ptr<const TetRec<T>, DEV> rec;              // m, tile order
     buf_ptr<const int, DEV> node_ent_off;           // n + 1
     buf_ptr<const int, DEV> node_ent;               // nent
+    buf_ptr<const int4, DEV> node_ent4;             // n: each node's first kGather entries (-1 past its last)
     buf_ptr<const int, DEV> inc_off;                // nent + 1: each tile entry's incident (tet, slot) pairs
     buf_ptr<const uint16_t, DEV> inc;               // 4 m: (local tet << 2 | slot), ascending tet per entry
     buf_ptr<const uint8_t, DEV> fixed;              // n
@@ -254,10 +258,13 @@ __device__ __forceinline__ double block_sum_partials(const double *part, int nb)
     return r;
 }
 
-// Wavefront sum / min of nb partials in a fixed order (finalize kernel).
+// Wavefront sum / min of nb partials in a fixed order: lane l adds partials
+// l, l + 64, ..., then the wavefront tree. Every wavefront that calls it gets
+// the same value (finalize kernel; the node pass's p.q, formed by each of its
+// wavefronts without a block barrier).
 __device__ __forceinline__ double wave_sum_partials(const double *part, int nb) {
     double v = 0.0;
-    for (int b = threadIdx.x; b < nb; b += 64) v += part[b];
+    for (int b = threadIdx.x & 63; b < nb; b += 64) v += part[b];
     v = wave_sum(v);
     return __shfl(v, 0, 64);
 }
@@ -1403,30 +1410,18 @@ __device__ __forceinline__ void node_update(const TopoD<T> &tp, const BufsD<T> &
     const int cg_first = s->cg_it == 0;
     const int i = blk * kBlock + threadIdx.x;
     const bool live = i < tp.n;
-    T pv[3] = {(T)0, (T)0, (T)0}, qv[3] = {(T)0, (T)0, (T)0}, rv[3], dxv[3], M[6];
+    T pv[3] = {(T)0, (T)0, (T)0}, qv[3] = {(T)0, (T)0, (T)0}, rv[3] = {(T)0, (T)0, (T)0}, dxv[3] = {(T)0, (T)0, (T)0};
+    T M[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
     bool fixed = true;
     if (live) {
+        // every load that depends only on i is issued first (r, dx and the
+        // block inverse after the fixed flag: fixed nodes are numbered last,
+        // so the test is uniform across almost every wavefront)
+        const int4 e4 = tp.node_ent4[i];
+        const int j = tp.cidx[i];
+        fixed = tp.fixed[i] != 0;
 #pragma unroll
         for (int d = 0; d < 3; d++) pv[d] = fma_t(beta, B.p[3 * i + d], B.z[3 * i + d]);
-        for (int q = tp.node_ent_off[i]; q < tp.node_ent_off[i + 1]; q++) {
-            const T *src = B.pq + 3 * tp.node_ent[q];
-            qv[0] += src[0];
-            qv[1] += src[1];
-            qv[2] += src[2];
-        }
-        const int j = tp.cidx[i];
-        if (j >= 0) {
-            const T *H = B.cp + 9 * j + 3;
-            qv[0] += H[0] * pv[0] + H[3] * pv[1] + H[4] * pv[2];
-            qv[1] += H[3] * pv[0] + H[1] * pv[1] + H[5] * pv[2];
-            qv[2] += H[4] * pv[0] + H[5] * pv[1] + H[2] * pv[2];
-        }
-        fixed = tp.fixed[i] != 0;
-        if (DYN && !fixed) {
-            const T cm = (T)s->mdt2 * tp.nvol[i];
-#pragma unroll
-            for (int d = 0; d < 3; d++) qv[d] = fma_t(cm, pv[d], qv[d]);
-        }
         if (!eval && !fixed) {
 #pragma unroll
             for (int d = 0; d < 3; d++) {
@@ -1436,13 +1431,44 @@ __device__ __forceinline__ void node_update(const TopoD<T> &tp, const BufsD<T> &
 #pragma unroll
             for (int c = 0; c < 6; c++) M[c] = B.dinv[6 * i + c];
         }
+        // the node's tile partials, summed in entry order: the first kGather
+        // entries come with the node (their loads are in flight together; an
+        // absent entry, -1, reads entry 0 and is dropped), the rest from the
+        // node -> entry lists (1.92 entries per node on the 50k fingertip)
+        const int ent[kGather] = {e4.x, e4.y, e4.z, e4.w};
+        T part[kGather][3];
+#pragma unroll
+        for (int k = 0; k < kGather; k++)
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                const T v = B.pq[3 * (ent[k] >= 0 ? ent[k] : 0) + d];
+                part[k][d] = ent[k] >= 0 ? v : (T)0;
+            }
+#pragma unroll
+        for (int k = 0; k < kGather; k++)
+#pragma unroll
+            for (int d = 0; d < 3; d++) qv[d] += part[k][d];
+        if (e4.w >= 0)
+            for (int q = tp.node_ent_off[i] + kGather; q < tp.node_ent_off[i + 1]; q++)
+#pragma unroll
+                for (int d = 0; d < 3; d++) qv[d] += B.pq[3 * tp.node_ent[q] + d];
+        if (j >= 0) {
+            const T *H = B.cp + 9 * j + 3;
+            qv[0] += H[0] * pv[0] + H[3] * pv[1] + H[4] * pv[2];
+            qv[1] += H[3] * pv[0] + H[1] * pv[1] + H[5] * pv[2];
+            qv[2] += H[4] * pv[0] + H[5] * pv[1] + H[2] * pv[2];
+        }
+        if (DYN && !fixed) {
+            const T cm = (T)s->mdt2 * tp.nvol[i];
+#pragma unroll
+            for (int d = 0; d < 3; d++) qv[d] = fma_t(cm, pv[d], qv[d]);
+        }
     }
-    const double pq = block_sum_partials(B.red + RS_PQ * B.red_stride, tp.ntile + tp.ncb);
+    const double pq = wave_sum_partials(B.red + RS_PQ * B.red_stride, tp.ntile + tp.ncb);
     if (blk == 0 && threadIdx.x == 0) B.red[RS_PQN * B.red_stride] = pq;
     const bool negcurv = !(pq > 0.0);
     const T alpha = negcurv ? (T)0 : (T)(rz / pq);
     double acc[2] = {0.0, 0.0};   // r.z, r.r
-    double unused = 0.0;
     if (live) {
         if (eval) {
 #pragma unroll
@@ -1470,9 +1496,14 @@ __device__ __forceinline__ void node_update(const TopoD<T> &tp, const BufsD<T> &
             for (int d = 0; d < 3; d++) B.dx[3 * i + d] = pv[d];
         }
     }
-    block_reduce<2, false>(acc, unused);
-    const int streams[2] = {RS_RZ, RS_RR};
-    store_partials<2>(B.red, B.red_stride, streams, blk, acc);
+    // per-wavefront partials (kWaves per block), summed by the finalize
+    acc[0] = wave_sum(acc[0]);
+    acc[1] = wave_sum(acc[1]);
+    if ((threadIdx.x & 63) == 0) {
+        const int slot = kWaves * blk + (int)(threadIdx.x >> 6);
+        B.red[RS_RZ * B.red_stride + slot] = acc[0];
+        B.red[RS_RR * B.red_stride + slot] = acc[1];
+    }
 }
 
 // Line-search trial, node part: partial sums of g . dx (first trial of a
@@ -1537,6 +1568,9 @@ __global__ __launch_bounds__(kBlock) void k_node(const Topo<T> *topos, const Ins
     const InstState *s = B.s;
     const int phase = s->phase;
     if (phase == PH_CG || phase == PH_EVAL_HV) {
+        // a CG update changes free nodes only: blocks of fixed nodes (numbered
+        // last) have nothing to do; block 0 always runs (it records p.q)
+        if (phase == PH_CG && w.y > 0 && w.y * kBlock >= tp.n_free) return;
         // the inertial term as a separate instance keeps it out of the
         // quasi-static CG update
         if (s->mdt2 > 0.0)
@@ -1648,8 +1682,10 @@ __global__ __launch_bounds__(64) void k_finalize(const Topo<T> *topos, const Ins
     }
     if (phase == PH_CG || phase == PH_EVAL_HV) {
         const double pq = B.red[RS_PQN * S];   // the node pass's sum, as it applied it
-        const double rz = wave_sum_partials(B.red + RS_RZ * S, nn);
-        const double rr = wave_sum_partials(B.red + RS_RR * S, nn);
+        // the node pass's per-wavefront partials of its blocks with free nodes
+        const int ncg = tp.n_free > kBlock ? (tp.n_free + kBlock - 1) / kBlock : 1;
+        const double rz = wave_sum_partials(B.red + RS_RZ * S, kWaves * ncg);
+        const double rr = wave_sum_partials(B.red + RS_RR * S, kWaves * ncg);
         if (threadIdx.x != 0) return;
         s->pq = pq;
         if (phase == PH_EVAL_HV) {

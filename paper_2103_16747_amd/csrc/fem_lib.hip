@@ -288,9 +288,14 @@ template <> Topo<double> &topo_view<double>(TopoRec &R) { return R.v64; }
 template <typename T>
 int add_topology(fem_batch *B, const double *X_in, int n, const int32_t *tets_in, int m, const uint8_t *fixed_in,
                  int *id) {
-    // Everything on the device uses the node numbering of node_order().
+    // Everything on the device uses the node numbering of node_order(), with
+    // the fixed nodes moved after the free ones (in the same order), so a CG
+    // update skips whole blocks of fixed nodes.
     TopoRec R;
     R.perm = node_order(X_in, n, tets_in, m);
+    std::stable_partition(R.perm.begin(), R.perm.end(), [&](int v) { return fixed_in[v] == 0; });
+    int n_free = 0;
+    for (int i = 0; i < n; i++) n_free += fixed_in[i] == 0;
     std::vector<int> inv(n);
     for (int i = 0; i < n; i++) inv[R.perm[i]] = i;
     std::vector<double> Xv(3 * (size_t)n);
@@ -317,7 +322,16 @@ int add_topology(fem_batch *B, const double *X_in, int n, const int32_t *tets_in
     const size_t o_fixed = A.take<uint8_t>(n), o_cn = A.take<int>(n), o_cidx = A.take<int>(n);
     const size_t o_X = A.take<double>(3 * (size_t)n), o_elig = A.take<uint8_t>(n);
     const size_t o_nvol = A.take<T>(n), o_owner = A.take<uint8_t>(L.nent), o_tid = A.take<int>(m);
-    const size_t o_ent_slot = A.take<uint8_t>(L.nent);
+    const size_t o_ent_slot = A.take<uint8_t>(L.nent), o_ne4 = A.take<int4>(n);
+    std::vector<int4> ne4(n);
+    for (int i = 0; i < n; i++) {
+        int e[kGather];
+        for (int k = 0; k < kGather; k++) {
+            const int q = L.node_ent_off[i] + k;
+            e[k] = q < L.node_ent_off[i + 1] ? L.node_ent[q] : -1;
+        }
+        ne4[i] = make_int4(e[0], e[1], e[2], e[3]);
+    }
     std::vector<int> inc_off;
     std::vector<uint16_t> inc;
     build_incidence(L, inc_off, inc);
@@ -352,6 +366,7 @@ int add_topology(fem_batch *B, const double *X_in, int n, const int32_t *tets_in
     if (!rc) rc = up(o_tile_ent, L.tile_ent.data(), L.tile_ent.size() * sizeof(int));
     if (!rc) rc = up(o_ent_node, L.ent_node.data(), L.ent_node.size() * sizeof(int));
     if (!rc) rc = up(o_ent_slot, L.ent_slot.data(), L.ent_slot.size());
+    if (!rc) rc = up(o_ne4, ne4.data(), ne4.size() * sizeof(int4));
     if (!rc) rc = up(o_neo, L.node_ent_off.data(), L.node_ent_off.size() * sizeof(int));
     if (!rc) rc = up(o_ne, L.node_ent.data(), L.node_ent.size() * sizeof(int));
     if (!rc) rc = up(o_fixed, fixed, n);
@@ -417,6 +432,7 @@ int add_topology(fem_batch *B, const double *X_in, int n, const int32_t *tets_in
     R.elig = (uint8_t *)(base + o_elig);
     Topo<T> &v = topo_view<T>(R);
     v.n = n;
+    v.n_free = n_free;
     v.m = m;
     v.ntile = L.ntile;
     v.nent = L.nent;
@@ -429,6 +445,7 @@ int add_topology(fem_batch *B, const double *X_in, int n, const int32_t *tets_in
     v.rec = (const TetRec<T> *)(base + o_rec);
     v.node_ent_off = (const int *)(base + o_neo);
     v.node_ent = (const int *)(base + o_ne);
+    v.node_ent4 = (const int4 *)(base + o_ne4);
     v.inc_off = (const int *)(base + o_inc_off);
     v.inc = (const uint16_t *)(base + o_inc);
     v.fixed = (const uint8_t *)(base + o_fixed);
@@ -455,7 +472,7 @@ template <typename T>
 int alloc_instance(fem_batch *B, int slot, int topo) {
     const TopoRec &tp = B->topos[topo];
     const int n = tp.n;
-    const int stride = std::max(tp.ntile + tp.ncb, ceil_div(n, kBlock));
+    const int stride = std::max(tp.ntile + tp.ncb, kWaves * ceil_div(n, kBlock));   // node pass: partials per wavefront
     Arena A;
     size_t o[7];
     for (int k = 0; k < 6; k++) o[k] = A.take<T>(3 * (size_t)n);
@@ -1883,7 +1900,7 @@ int fem_batch_job_footprint(const fem_batch *B, int32_t mesh_id, int64_t *bytes)
     if (!B || !bytes || mesh_id < 0 || mesh_id >= (int)B->topos.size()) return fail(FEM_E_INVALID, "unknown mesh");
     const TopoRec &tp = B->topos[mesh_id];
     const size_t w = B->elem();
-    const size_t stride = std::max(tp.ntile + tp.ncb, ceil_div(tp.n, kBlock));
+    const size_t stride = std::max(tp.ntile + tp.ncb, kWaves * ceil_div(tp.n, kBlock));
     // the arena of alloc_instance, with its 256-byte alignment padding
     size_t total = 0;
     auto add = [&](size_t b) { total += (b + 255) & ~size_t(255); };
