@@ -92,22 +92,25 @@ def traffic(fetch_dir, write_dir, copy_bytes, pattern, copy_pattern=r"copy|eleme
             "traffic_bytes_per_dispatch": fetch + write}
 
 
-def counter_means(d, pattern):
+def counter_means(d, pattern, busy_floor_us=0.0):
     """Per-dispatch means of every counter of a --pmc run for the kernels
     matching `pattern`, with the number of dispatches and their mean
-    duration (us, from the dispatch timestamps)."""
-    tot, cnt, dur = {}, {}, {}
+    duration (us, from the dispatch timestamps); with busy_floor_us > 0,
+    over the dispatches that lasted longer than that only."""
+    per, dur = {}, {}
     for r in csv.DictReader(open(_find(d, "counter_collection.csv"))):
         if not re.search(pattern, r["Kernel_Name"]):
             continue
-        name = r["Counter_Name"]
-        tot[name] = tot.get(name, 0.0) + float(r["Counter_Value"])
-        cnt[name] = cnt.get(name, 0) + 1
-        dur[r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
-    if not dur:
+        i = r["Dispatch_Id"]
+        c = per.setdefault(i, {})
+        c[r["Counter_Name"]] = c.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        dur[i] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+    sel = [i for i in dur if dur[i] > busy_floor_us]
+    if not sel:
         raise RuntimeError("no counters for " + pattern)
-    return {"dispatches": len(dur), "mean_duration_us": statistics.mean(dur.values()),
-            "per_dispatch": {k: tot[k] / cnt[k] for k in sorted(tot)}}
+    names = sorted({k for i in sel for k in per[i]})
+    return {"dispatches": len(sel), "mean_duration_us": statistics.mean(dur[i] for i in sel),
+            "per_dispatch": {k: sum(per[i].get(k, 0.0) for i in sel) / len(sel) for k in names}}
 
 
 def kernel_source_hash(text=None):
@@ -148,6 +151,7 @@ def main(argv=None):
     c = sub.add_parser("counters")
     c.add_argument("dir")
     c.add_argument("--kernel", required=True)
+    c.add_argument("--busy-floor-us", type=float, default=0.0)
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         for r in kernel_stats(args.dir, args.kernel):
@@ -156,7 +160,7 @@ def main(argv=None):
         if args.kernel and args.busy_floor_us > 0:
             print("busy dispatches:", busy_kernel_stats(args.dir, args.kernel, args.busy_floor_us))
     elif args.cmd == "counters":
-        r = counter_means(args.dir, args.kernel)
+        r = counter_means(args.dir, args.kernel, args.busy_floor_us)
         print(f"dispatches {r['dispatches']}  mean duration {r['mean_duration_us']:.2f} us")
         for k, v in r["per_dispatch"].items():
             print(f"  {k:28s} {v:.4e} per dispatch")
