@@ -243,21 +243,6 @@ __device__ __forceinline__ void block_reduce(double (&v)[NS], double &mn) {
     __syncthreads();
 }
 
-// Sum of nb partials (stride 1) in a fixed order, valid in every thread of
-// the block (all threads take part).
-__device__ __forceinline__ double block_sum_partials(const double *part, int nb) {
-    double v[1] = {0.0};
-    double unused = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kBlock) v[0] += part[b];
-    block_reduce<1, false>(v, unused);
-    __shared__ double bcast;
-    if (threadIdx.x == 0) bcast = v[0];
-    __syncthreads();
-    const double r = bcast;
-    __syncthreads();
-    return r;
-}
-
 // Wavefront sum / min of nb partials in a fixed order: lane l adds partials
 // l, l + 64, ..., then the wavefront tree. Every wavefront that calls it gets
 // the same value (finalize kernel; the node pass's p.q, formed by each of its
