@@ -202,16 +202,43 @@ __device__ __forceinline__ int logical_block() {
 // ---------------------------------------------------------------------------
 // Reductions
 // ---------------------------------------------------------------------------
+// Wavefront reductions with DPP lane moves (vector ALU, no LDS traffic): a
+// prefix sum within each row of 16 lanes (row_shr 1, 2, 4, 8), then the row
+// totals carried across rows (row_bcast 15 and 31), so lane 63 holds the
+// result, which is broadcast. The order is fixed: every wavefront that
+// reduces the same values gets the same bits. Lanes without a source take
+// the identity (`empty`, as two 32-bit halves).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_move(double v, int empty_lo, int empty_hi) {
+    const int lo = __builtin_amdgcn_update_dpp(empty_lo, __double2loint(v), CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(empty_hi, __double2hiint(v), CTRL, ROWMASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane63(double v) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                            __builtin_amdgcn_readlane(__double2loint(v), 63));
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    return v;
+    v += dpp_move<0x111, 0xf>(v, 0, 0);   // row_shr:1
+    v += dpp_move<0x112, 0xf>(v, 0, 0);   // row_shr:2
+    v += dpp_move<0x114, 0xf>(v, 0, 0);   // row_shr:4
+    v += dpp_move<0x118, 0xf>(v, 0, 0);   // row_shr:8
+    v += dpp_move<0x142, 0xa>(v, 0, 0);   // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xc>(v, 0, 0);   // row_bcast:31 into rows 2 and 3
+    return lane63(v);
 }
 
 __device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_down(v, o, 64));
-    return v;
+    const int ilo = 0, ihi = 0x7ff00000;  // +inf
+    v = fmin(v, dpp_move<0x111, 0xf>(v, ilo, ihi));
+    v = fmin(v, dpp_move<0x112, 0xf>(v, ilo, ihi));
+    v = fmin(v, dpp_move<0x114, 0xf>(v, ilo, ihi));
+    v = fmin(v, dpp_move<0x118, 0xf>(v, ilo, ihi));
+    v = fmin(v, dpp_move<0x142, 0xa>(v, ilo, ihi));
+    v = fmin(v, dpp_move<0x143, 0xc>(v, ilo, ihi));
+    return lane63(v);
 }
 
 template <int NS, bool MIN>
@@ -250,15 +277,13 @@ __device__ __forceinline__ void block_reduce(double (&v)[NS], double &mn) {
 __device__ __forceinline__ double wave_sum_partials(const double *part, int nb) {
     double v = 0.0;
     for (int b = threadIdx.x & 63; b < nb; b += 64) v += part[b];
-    v = wave_sum(v);
-    return __shfl(v, 0, 64);
+    return wave_sum(v);
 }
 
 __device__ __forceinline__ double wave_min_partials(const double *part, int nb) {
     double v = INFINITY;
     for (int b = threadIdx.x; b < nb; b += 64) v = fmin(v, part[b]);
-    v = wave_min(v);
-    return __shfl(v, 0, 64);
+    return wave_min(v);
 }
 
 // ---------------------------------------------------------------------------
@@ -1926,8 +1951,7 @@ __global__ __launch_bounds__(1024) void k_disp_stats(const Topo<T> *topos, const
         sum += a;
     }
     sum = wave_sum(sum);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_down(mx, o, 64));
+    mx = -wave_min(-mx);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (lane == 0) {
         smax[wv] = mx;
