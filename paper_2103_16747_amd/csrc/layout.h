@@ -264,10 +264,17 @@ inline int deal_tile(const std::vector<uint32_t> &words, int ne, std::vector<int
         std::replace(mem[qj].begin(), mem[qj].end(), bj, bi);
     }
     // 3. per group: slot c of each tet = colour c of a 4-edge-colouring of the
-    // tets x residues multigraph, by alternating-path recolouring
+    // tets x residues multigraph, by alternating-path recolouring; the
+    // colours of a group are then renamed (one of the 24 orders) so that as
+    // few of its nodes as possible take a slot in which an earlier group of
+    // the same wavefront (4 groups) already has them: lanes of one atomic
+    // instruction that add into the same address are serialised
     placed.assign(nk, 0);
     std::vector<std::pair<int, int>> path;
+    std::array<std::vector<char>, 4> used;
     for (int q = 0; q < nq; q++) {
+        if (q % 4 == 0)
+            for (auto &u : used) u.assign(ne, 0);
         const std::vector<int> &M = mem[q];
         const int nt = (int)M.size();
         std::vector<std::array<int, 4>> slot(nt), at_t(nt);   // slot of (tet, vertex); vertex of (tet, colour)
@@ -322,6 +329,23 @@ inline int deal_tile(const std::vector<uint32_t> &words, int ne, std::vector<int
                     at_rv[r][al] = a;
                 }
             }
+        int best_r = 0, best_c = 1 << 30;
+        for (int r = 0; r < 24; r++) {
+            int c = 0;
+            for (int t = 0; t < nt; t++)
+                for (int a = 0; a < 4; a++)
+                    if (slot[t][a] >= 0) c += used[kPerm24[r][slot[t][a]]][loc[M[t]][a]];
+            if (c < best_c) {
+                best_c = c;
+                best_r = r;
+            }
+        }
+        for (int t = 0; t < nt; t++)
+            for (int a = 0; a < 4; a++)
+                if (slot[t][a] >= 0) {
+                    slot[t][a] = kPerm24[best_r][slot[t][a]];
+                    used[slot[t][a]][loc[M[t]][a]] = 1;
+                }
         for (int t = 0; t < nt; t++) {
             int p[4] = {-1, -1, -1, -1};
             for (int a = 0; a < 4; a++)
