@@ -99,16 +99,18 @@ def progress(*a):
 
 
 def run_batched(mesh, inds, precision, timed_steps, warm_steps, timing_every=0, track_latency=True,
-                material=(0.3e6, 0.45), groups=0, keep=()):
+                material=(0.3e6, 0.45), groups=0, keep=(), round_steps=64):
     """Runs warm_steps untimed and timed_steps timed batches of the jobs
     `inds`; returns walls, latencies, counters (totals over the timed
     batches and per batch), kernel timing, and per-job results of the last
     timed batch: status, counters, displacement statistics and contact
     resultant for every job, and the final displacements of the job indices
-    in `keep`."""
+    in `keep`. round_steps: solver steps per captured round (the host polls
+    the jobs between rounds; the solve itself does not depend on it)."""
     from paper_2103_16747_amd import fem
 
     batch = fem.FemBatch(len(inds), precision)
+    batch.set_option(fem.FEM_OPT_ROUND_STEPS, round_steps)
     if groups:
         batch.set_option(fem.FEM_OPT_GROUPS, groups)
     mid = batch.add_mesh(mesh.X, mesh.tets, mesh.fixed)
@@ -133,7 +135,8 @@ def run_batched(mesh, inds, precision, timed_steps, warm_steps, timing_every=0, 
         pending = list(jobs)
         while running:
             prev = running
-            running = batch.run(P, max_rounds=8 if track_latency else 0)
+            # completion times are taken every 128 solver steps
+            running = batch.run(P, max_rounds=max(1, 128 // round_steps) if track_latency else 0)
             now = time.perf_counter() - t0
             # completions are looked up only when the running count fell
             if track_latency and running < prev:

@@ -26,7 +26,7 @@ from . import fem, workload as W
 # (tets per tile, distinct nodes per tile); the library's limits are
 # 64..512 tets and 16..256 nodes (8-bit local slots)
 SHAPE_CANDIDATES = ((512, 256), (384, 256), (256, 256), (256, 128), (128, 128))
-CHUNK_CANDIDATES = (8, 16, 32)
+CHUNK_CANDIDATES = (8, 16, 32, 64)
 
 
 def mesh_key(mesh, precision):
