@@ -121,8 +121,11 @@ struct JobGroup {
 constexpr int kRoundEvents = 2 * 64 + 2;
 
 struct TopoRec {
-    int n = 0, m = 0, ntile = 0, nent = 0, nc = 0, ncb = 0;
+    int n = 0, n_free = 0, m = 0, ntile = 0, nent = 0, nc = 0, ncb = 0;
     std::vector<int> perm;     // device node id -> caller's node id (node_order())
+    // order of the mesh's tile-pass and node-pass blocks in the work tables
+    // (spread_order())
+    std::vector<int> tile_cols, node_cols;
     void *arena = nullptr;
     uint8_t *elig = nullptr;   // device, n
     Topo<float> v32{};
@@ -429,6 +432,13 @@ int add_topology(fem_batch *B, const double *X_in, int n, const int32_t *tets_in
     }
     R.nc = host[1];
     R.ncb = ceil_div(R.nc, kBlock);
+    R.n_free = n_free;
+    R.tile_cols = spread_order(R.ntile, R.ncb);
+    {
+        // node blocks with free nodes (block 0 always runs a CG update)
+        const int nb = ceil_div(n, kBlock), ncg = n_free > kBlock ? ceil_div(n_free, kBlock) : 1;
+        R.node_cols = spread_order(ncg, nb - ncg);
+    }
     R.elig = (uint8_t *)(base + o_elig);
     Topo<T> &v = topo_view<T>(R);
     v.n = n;
@@ -521,7 +531,8 @@ inline bool running_phase(int ph) { return ph != PH_IDLE && ph != PH_DONE; }
 // Work tables: tile (+ contact) blocks and node blocks of every running
 // instance (as of the host's last view of the states), ordered tile-major so
 // one tile of consecutive instances is processed back to back (on one XCD,
-// see logical_block()). Finished instances are left out, so their blocks
+// see logical_block()), the tiles of each mesh taken in spread_order(), so
+// that every XCD's share holds its share of the heavy blocks. Finished instances are left out, so their blocks
 // cost nothing; one made to run again (restart) is put back by the next run.
 // Mesh and buffer descriptors are uploaded again only after a structural
 // change (mesh or job added or removed).
@@ -558,16 +569,18 @@ int rebuild_tables(fem_batch *B) {
             max_nb = std::max(max_nb, ceil_div(tp.n, kBlock));
         }
         G.tile_off = (int)wt.size();
-        for (int t = 0; t < max_t; t++)
+        for (int c = 0; c < max_t; c++)
             for (int i : members[g]) {
                 const TopoRec &tp = B->topos[B->insts[i].topo];
-                if (t < tp.ntile + tp.ncb) wt.push_back(make_int2(i, t));
+                if (c < tp.ntile + tp.ncb) wt.push_back(make_int2(i, tp.tile_cols[c]));
             }
         G.tile_n = (int)wt.size() - G.tile_off;
         G.node_off = (int)wn.size();
-        for (int t = 0; t < max_nb; t++)
-            for (int i : members[g])
-                if (t < ceil_div(B->topos[B->insts[i].topo].n, kBlock)) wn.push_back(make_int2(i, t));
+        for (int c = 0; c < max_nb; c++)
+            for (int i : members[g]) {
+                const TopoRec &tp = B->topos[B->insts[i].topo];
+                if (c < ceil_div(tp.n, kBlock)) wn.push_back(make_int2(i, tp.node_cols[c]));
+            }
         G.node_n = (int)wn.size() - G.node_off;
         G.live_off = (int)live.size();
         live.insert(live.end(), members[g].begin(), members[g].end());

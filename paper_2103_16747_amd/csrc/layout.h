@@ -544,4 +544,25 @@ inline void build_incidence(const HostLayout &L, std::vector<int> &off, std::vec
     }
 }
 
+// Order of `heavy` blocks 0..heavy-1 and `light` blocks heavy..heavy+light-1
+// with the light ones spread evenly among the heavy ones (block h sits at
+// (h + 1/2) / heavy of the way, block l at (l + 1/2) / light). Each XCD runs
+// a contiguous share of a work table (blocks are dealt to the XCDs
+// round-robin and renumbered so that consecutive work items share one); in
+// plain index order the light blocks (the contact blocks of the tile pass;
+// the node blocks holding only fixed nodes, which a CG update skips) would
+// all fall to the last XCDs, which then idle while the others carry the
+// heavy work.
+inline std::vector<int> spread_order(int heavy, int light) {
+    std::vector<int> o;
+    o.reserve(heavy + light);
+    int h = 0, l = 0;
+    while (h < heavy || l < light) {
+        const bool take_light =
+            l < light && (h >= heavy || (2LL * l + 1) * heavy < (2LL * h + 1) * light);
+        o.push_back(take_light ? heavy + l++ : h++);
+    }
+    return o;
+}
+
 }  // namespace fem_layout

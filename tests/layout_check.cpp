@@ -147,6 +147,30 @@ int main(int argc, char **argv) {
                 passes += mx;
             }
     }
+    // work-table column order of this mesh's tile and contact blocks (and of
+    // a range of other counts): a permutation keeping each kind in ascending
+    // order, with every prefix holding its proportional share of light blocks
+    // to within one
+    {
+        const int nc_blocks = std::max(1, L.ntile / 6);
+        const int cases[][2] = {{L.ntile, nc_blocks}, {1, 0}, {0, 3}, {36, 8}, {97, 15}, {5, 40}, {1, 1}, {300, 7}};
+        for (const auto &c : cases) {
+            const int heavy = c[0], light = c[1];
+            const std::vector<int> o = spread_order(heavy, light);
+            if ((int)o.size() != heavy + light) return bad("spread size", (long long)o.size(), heavy + light);
+            int h = 0, l = 0;
+            for (int k = 0; k < (int)o.size(); k++) {
+                if (o[k] < heavy) {
+                    if (o[k] != h++) return bad("spread heavy order", o[k], h - 1);
+                } else if (o[k] != heavy + l++) {
+                    return bad("spread light order", o[k], heavy + l - 1);
+                }
+                // light blocks among the first k + 1, against (k + 1) light / total
+                const double share = (double)(k + 1) * light / (double)(heavy + light);
+                if (std::fabs(l - share) > 1.0) return bad("spread share", l, (long long)std::lround(share));
+            }
+        }
+    }
     std::printf("ok tiles=%d entries=%d passes=%.4f\n", L.ntile, L.nent, (double)passes / (double)groups);
     return 0;
 }
