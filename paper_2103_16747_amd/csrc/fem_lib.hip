@@ -547,8 +547,8 @@ int rebuild_tables(fem_batch *B) {
         if (!R.in_tables) continue;
         live.push_back(i);
     }
-    // Two groups only on request (measured on the 256-job fingertip batch:
-    // 44.9 against 44.8 solves/s with one group, the node pass of one group
+    // Two groups only on request (on the 256-job fingertip batch they run
+    // within the run-to-run spread of one group, the node pass of one group
     // taking wave slots from the other's tile pass): jobs dealt to the group
     // with fewer tile blocks so far.
     const int ng = B->groups_opt == 2 && live.size() >= 2 ? 2 : 1;
