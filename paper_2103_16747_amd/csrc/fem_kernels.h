@@ -169,6 +169,7 @@ struct InstBufs {
     buf_ptr<T, DEV> pg;                             // nent x 9: gradient (3) + node block (6) partials
     buf_ptr<T, DEV> pq;                             // nent x 3: Hv partials
     buf_ptr<T, DEV> cp;                             // nc x 9: contact gradient (3) + block (6)
+    buf_ptr<uint8_t, DEV> cact;                     // nc: 1 where that block is nonzero
     buf_ptr<T, DEV> qout;                           // n x 3 (diagnostics)
     buf_ptr<T, DEV> v, ut;                          // n x 3: velocity of the last completed step, inertial predictor
     buf_ptr<double, DEV> fr;                        // nc x 8: friction lag data (w, normal, displacement
@@ -1103,8 +1104,15 @@ __device__ __forceinline__ void tile_element(const TopoD<T> &tp, const BufsD<T> 
                     for (int c = 0; c < 6; c++) od[3 + c] += Hf[c];
                 }
             }
+            // the Hessian-vector passes read a node's contact block only
+            // where it is nonzero (most eligible nodes are out of contact)
+            bool act = false;
 #pragma unroll
-            for (int c = 0; c < 9; c++) B.cp[9 * j + c] = (T)od[c];
+            for (int c = 0; c < 9; c++) {
+                B.cp[9 * j + c] = (T)od[c];
+                if (c >= 3) act = act || (T)od[c] != (T)0;
+            }
+            B.cact[j] = act ? 1 : 0;
         }
     }
     double sums[2] = {acc[0], acc[1]};
@@ -1235,18 +1243,16 @@ __device__ __forceinline__ void tile_hessvec(const TopoD<T> &tp, const BufsD<T> 
         }
     } else {
         const int j = (blk - tp.ntile) * kBlock + threadIdx.x;
-        if (j < tp.nc) {
+        if (j < tp.nc && B.cact[j]) {
             const T *H = B.cp + 9 * j + 3;
-            if (H[0] != (T)0 || H[1] != (T)0 || H[2] != (T)0 || H[3] != (T)0 || H[4] != (T)0 || H[5] != (T)0) {
-                const int i = tp.cnodes[j];
-                T pv[3];
+            const int i = tp.cnodes[j];
+            T pv[3];
 #pragma unroll
-                for (int d = 0; d < 3; d++) pv[d] = fma_t(beta, B.p[3 * i + d], B.z[3 * i + d]);
-                const T q0 = H[0] * pv[0] + H[3] * pv[1] + H[4] * pv[2];
-                const T q1 = H[3] * pv[0] + H[1] * pv[1] + H[5] * pv[2];
-                const T q2 = H[4] * pv[0] + H[5] * pv[1] + H[2] * pv[2];
-                acc[0] = (double)(pv[0] * q0 + pv[1] * q1 + pv[2] * q2);
-            }
+            for (int d = 0; d < 3; d++) pv[d] = fma_t(beta, B.p[3 * i + d], B.z[3 * i + d]);
+            const T q0 = H[0] * pv[0] + H[3] * pv[1] + H[4] * pv[2];
+            const T q1 = H[3] * pv[0] + H[1] * pv[1] + H[5] * pv[2];
+            const T q2 = H[4] * pv[0] + H[5] * pv[1] + H[2] * pv[2];
+            acc[0] = (double)(pv[0] * q0 + pv[1] * q1 + pv[2] * q2);
         }
     }
     block_reduce<1, false>(acc, unused);
@@ -1462,7 +1468,7 @@ __device__ __forceinline__ void node_update(const TopoD<T> &tp, const BufsD<T> &
             for (int q = tp.node_ent_off[i] + kGather; q < tp.node_ent_off[i + 1]; q++)
 #pragma unroll
                 for (int d = 0; d < 3; d++) qv[d] += B.pq[3 * tp.node_ent[q] + d];
-        if (j >= 0) {
+        if (j >= 0 && B.cact[j]) {
             const T *H = B.cp + 9 * j + 3;
             qv[0] += H[0] * pv[0] + H[3] * pv[1] + H[4] * pv[2];
             qv[1] += H[3] * pv[0] + H[1] * pv[1] + H[5] * pv[2];

@@ -493,6 +493,7 @@ int alloc_instance(fem_batch *B, int slot, int topo) {
     const size_t o_v = A.take<T>(3 * (size_t)n), o_ut = A.take<T>(3 * (size_t)n);
     const size_t o_fr = A.take<double>(8 * (size_t)std::max(tp.nc, 1));
     const size_t o_hist = A.take<signed char>(kHistSteps);
+    const size_t o_cact = A.take<uint8_t>(std::max(tp.nc, 1));
     InstRec &R = B->insts[slot];
     HIP_TRY(hipMalloc(&R.arena, A.off));
     HIP_TRY(hipMemsetAsync(R.arena, 0, A.off, B->stream));
@@ -512,6 +513,7 @@ int alloc_instance(fem_batch *B, int slot, int topo) {
     b.ut = (T *)(base + o_ut);
     b.fr = (double *)(base + o_fr);
     b.hist = (signed char *)(base + o_hist);
+    b.cact = (uint8_t *)(base + o_cact);
     b.s = B->d_states + slot;
     R.topo = topo;
     R.live = true;
@@ -1927,6 +1929,7 @@ int fem_batch_job_footprint(const fem_batch *B, int32_t mesh_id, int64_t *bytes)
     add(3 * (size_t)tp.n * w);
     add(8 * (size_t)std::max(tp.nc, 1) * sizeof(double));
     add(kHistSteps);
+    add(std::max(tp.nc, 1));   // contact-block flags
     *bytes = (int64_t)total;
     return FEM_OK;
 }
