@@ -57,7 +57,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3      # 256 CU x 64 lanes x 2 x 2.4 GHz x 2 (pack
 FP32_NONPACKED_PEAK_TFLOPS = 78.6    # the same without packed FP32, which the library is compiled without
 
 
-def tile_bytes(info, word, hv_passes, el_passes, launches):
+def tile_bytes(info, word, hv_passes, el_passes, launches, n_act=None):
     """Algorithmic HBM bytes per launch of the tile kernel, averaged over
     `launches` launches that made hv_passes Hessian-vector passes and
     el_passes element passes in all (ideal reuse: every value read or written
@@ -66,16 +66,19 @@ def tile_bytes(info, word, hv_passes, el_passes, launches):
     Shared per launch: packed local ids (4 B/tet), D_m^-1 and V (10 words per
     tet), the entry -> node map (4 B per entry).
     Hessian-vector pass, per job: reads of u, z, p_prev (9 words per node),
-    write of the q partials (3 words per entry), contact blocks (6 words per
-    eligible node).
+    write of the q partials (3 words per entry), the contact-block flags (1 B
+    per eligible node) and the contact blocks of the nodes in contact (6
+    words each; n_act of them, the job's final contact patch, which bounds
+    the patch of every earlier step of the deepening indentation).
     Element pass, per job: reads of u and dx (6 words per node), write of the
     gradient + block partials (9 words per entry), contact node coordinates
     (3 doubles) and contact outputs (9 words) per eligible node.
     """
     n, m, nent, nc = info["n_nodes"], info["n_tets"], info["n_entries"], info["n_eligible"]
+    na = nc if n_act is None else n_act
     shared = m * (4 + 10 * word) + 4 * nent
-    hv = 9 * word * n + 3 * word * nent + 6 * word * nc
-    el = 6 * word * n + 9 * word * nent + (24 + 9 * word) * nc
+    hv = 9 * word * n + 3 * word * nent + nc + 6 * word * na
+    el = 6 * word * n + 9 * word * nent + (24 + 9 * word + 1) * nc
     return shared + (hv_passes * hv + el_passes * el) / max(launches, 1)
 
 
@@ -166,8 +169,9 @@ def run_batched(mesh, inds, precision, timed_steps, warm_steps, timing_every=0, 
     job_out = []
     for j in jobs:
         umax, umean = batch.displacement_stats(j)
-        job_out.append({"status": batch.step_status(j), "umax": umax, "umean": umean,
-                        "F": batch.contact_patch(j)[3]})
+        ids, _, _, Fr = batch.contact_patch(j)
+        job_out.append({"status": batch.step_status(j), "umax": umax, "umean": umean, "F": Fr,
+                        "patch": int(len(ids))})
     # data-generation outputs of the finished jobs: per-tet stress and
     # displacement statistics (device kernels; the stress copy to the host
     # is included)
@@ -251,7 +255,7 @@ def roofline(r, word, flops_per_tet=FLOPS_PER_TET, kname=None, peak=FP32_VECTOR_
     per_launch = flops / t["launches"]
     avg_s = t["avg_us"] * 1e-6
     achieved = per_launch / avg_s / 1e12
-    byts = tile_bytes(r["layout"], word, r["hv_passes"], r["grad_passes"], t["launches"])
+    byts = tile_bytes(r["layout"], word, r["hv_passes"], r["grad_passes"], t["launches"], contact_nodes(r))
     if kname is None:
         kname = "k_tile<float, LAW_NH>" if word == 4 else "k_tile<double, LAW_NH>"
     out = {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": peak,
@@ -266,7 +270,7 @@ def roofline(r, word, flops_per_tet=FLOPS_PER_TET, kname=None, peak=FP32_VECTOR_
     return out, {k: v["avg_us"] for k, v in per.items()}
 
 
-def node_bytes(info, word, hv_passes, el_passes, launches):
+def node_bytes(info, word, hv_passes, el_passes, launches, n_act=None):
     """Algorithmic HBM bytes per launch of the node kernel, averaged over
     `launches` launches that made hv_passes CG updates and followed el_passes
     element passes in all (ideal reuse: every value read or written once).
@@ -275,7 +279,8 @@ def node_bytes(info, word, hv_passes, el_passes, launches):
     the contact index (4 B per node) and the fixed mask (1 B per node).
     CG update, per job and node: reads p, z, dx, r (12 words), the block
     inverse (6), the q partials (3 words per entry); writes p, dx, r, z (12);
-    per contact-eligible node the contact block (6 words).
+    per contact-eligible node its contact-block flag (1 B), and the contact
+    block (6 words) of the n_act nodes in contact (as for tile_bytes).
     After an element pass (Newton init; counted for every element pass, an
     upper bound for line-search trials, which read only g and dx): reads u
     and dx (6 words), the gradient and block partials (9 words per entry);
@@ -283,8 +288,9 @@ def node_bytes(info, word, hv_passes, el_passes, launches):
     the contact gradient and block (9 words).
     """
     n, nent, nc = info["n_nodes"], info["n_entries"], info["n_eligible"]
+    na = nc if n_act is None else n_act
     shared = 4 * (n + 1) + 4 * nent + 4 * n + n
-    cg = word * (30 * n + 3 * nent + 6 * nc)
+    cg = word * (30 * n + 3 * nent + 6 * na) + nc
     init = word * (27 * n + 9 * nent + 9 * nc)
     return shared + (hv_passes * cg + el_passes * init) / max(launches, 1)
 
@@ -303,8 +309,8 @@ def hbm_roofline(r, word, traffic=None):
     t_launch = tm[fem.FEM_KERNEL_TILE][2]
     n_cnt, n_ms, n_launch = tm[fem.FEM_KERNEL_NODE]
     node_avg_s = n_ms / max(n_cnt, 1) * 1e-3
-    nb = node_bytes(info, word, r["hv_passes"], r["grad_passes"], n_launch)
-    tb = tile_bytes(info, word, r["hv_passes"], r["grad_passes"], t_launch)
+    nb = node_bytes(info, word, r["hv_passes"], r["grad_passes"], n_launch, contact_nodes(r))
+    tb = tile_bytes(info, word, r["hv_passes"], r["grad_passes"], t_launch, contact_nodes(r))
     jobs_steps = r["hv_passes"] + r["grad_passes"]
     fin_total = 8 * 3 * (info["n_tiles"] + ceil_div(info["n_eligible"], 256) + ceil_div(info["n_nodes"], 256)) * jobs_steps
     total = tb * t_launch + nb * n_launch + fin_total
@@ -325,6 +331,13 @@ def hbm_roofline(r, word, traffic=None):
 
 def ceil_div(a, b):
     return (a + b - 1) // b
+
+
+def contact_nodes(r):
+    """Mean final contact-patch size of the timed batch's jobs (nodes whose
+    contact block the Hessian-vector passes read), or None when unknown."""
+    sizes = [j["patch"] for j in r.get("jobs", []) if "patch" in j]
+    return float(np.mean(sizes)) if sizes else None
 
 
 def _oracle_job(args):

@@ -68,10 +68,26 @@ def test_traffic_figure_follows_the_kernel_source_and_launch(monkeypatch, tmp_pa
 def test_node_bytes_model():
     info = {"n_nodes": 100, "n_entries": 200, "n_eligible": 10, "n_tets": 300, "n_tiles": 1}
     shared = 4 * 101 + 4 * 200 + 4 * 100 + 100
-    # one CG update of one job per launch, FP32: 30 words per node, 3 per entry, 6 per eligible node
-    assert bench.node_bytes(info, 4, 1, 0, 1) == pytest.approx(shared + 4 * (30 * 100 + 3 * 200 + 6 * 10))
+    # one CG update of one job per launch, FP32: 30 words per node, 3 per entry, a flag byte per
+    # eligible node and 6 words per node in contact (all eligible ones when the patch is unknown)
+    assert bench.node_bytes(info, 4, 1, 0, 1) == pytest.approx(shared + 4 * (30 * 100 + 3 * 200 + 6 * 10) + 10)
+    assert bench.node_bytes(info, 4, 1, 0, 1, n_act=3) == pytest.approx(shared + 4 * (30 * 100 + 3 * 200 + 6 * 3) + 10)
     # one element pass followed by a Newton init, FP64
     assert bench.node_bytes(info, 8, 0, 1, 1) == pytest.approx(shared + 8 * (27 * 100 + 9 * 200 + 9 * 10))
+
+
+def test_tile_bytes_model():
+    info = {"n_nodes": 100, "n_entries": 200, "n_eligible": 10, "n_tets": 300, "n_tiles": 1}
+    shared = 300 * (4 + 10 * 4) + 4 * 200
+    # one Hessian-vector pass: u, z, p_prev per node, q partials per entry, flags, blocks in contact
+    assert bench.tile_bytes(info, 4, 1, 0, 1, n_act=2) == pytest.approx(shared + 4 * (9 * 100 + 3 * 200 + 6 * 2) + 10)
+    # one element pass: u, dx per node, 9 partials per entry, contact coordinates, outputs and flag
+    assert bench.tile_bytes(info, 4, 0, 1, 1) == pytest.approx(shared + 4 * (6 * 100 + 9 * 200) + (24 + 36 + 1) * 10)
+
+
+def test_contact_nodes_mean_patch():
+    assert bench.contact_nodes({"jobs": [{"patch": 10}, {"patch": 30}]}) == pytest.approx(20.0)
+    assert bench.contact_nodes({"jobs": []}) is None
 
 
 def test_hbm_roofline_arithmetic():
