@@ -1411,7 +1411,8 @@ __device__ __forceinline__ void node_init(const TopoD<T> &tp, const BufsD<T> &B,
 // pass's p.q partials (fixed order, so all blocks agree; block 0 records the
 // sum for the finalize) and forms
 // alpha = r.z / p.q; then it gathers q from the tile partials plus the contact
-// block times p and, on free nodes, sets p = z + beta p_prev, dx += alpha p,
+// block times p (read only where the element pass flagged the block nonzero)
+// and, on free nodes, sets p = z + beta p_prev, dx += alpha p,
 // r -= alpha q, z = M^-1 r, with partial sums of r.z and r.r. At p.q <= 0 CG
 // stops (on its first iteration the preconditioned residual becomes the
 // Newton direction). EVAL_HV writes q instead.
